@@ -1,0 +1,316 @@
+"""Plain FP64 CPU oracle of the DPM score-estimation path.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product library imports, links or
+runs this module; only the tests, the smoke check and the benchmark's CPU
+baseline leg call it.  It shares no code with the GPU path (the only common
+import is the seeded input generator in ``workloads``, which holds none of the
+method's arithmetic).
+
+Every function works in float64 on numpy arrays, written for readability, not
+speed.  Conventions (each one is a reading of the paper, see the notes):
+
+* Feature level X: (H, W, 32), channel innermost.  Filter f: (h, w, 32).
+* Correlation, not convolution (Section 4, the operator written as a small
+  circle is a correlation), over valid placements only:
+  resp(y, x) = sum_{n<h, m<w, l<32} f[n, m, l] * X[y+n, x+m, l],
+  0 <= y <= H-h, 0 <= x <= W-w.
+* Deformation feature psi = (dx, dx^2, dy, dy^2) with dx = x' - x_anchor,
+  dy = y' - y_anchor; the cost d . psi is subtracted (Section 2, the score
+  formula and the placement argmax).  Coefficient order d = (d_x, d_xx, d_y, d_yy).
+* The part placement maximises over every position of the part map
+  (Section 2: "all possible part positions").  Exact ties go to the
+  lexicographically smallest (y', x').
+* Score (Section 2): s(p0) = resp_root(p0) + sum_i D_i(2*p0 + v_i); the parts
+  live one octave below the root (twice the resolution), v_i is the anchor of
+  part i.  No bias term.  An anchor outside the part map gives -inf.
+* Tensor form: one feature-mode basis U_R (32 x R) shared by the whole bank,
+  taken from the leading eigenvectors of the Gram matrix of the mode-3
+  unfolding (the Frobenius-optimal truncation of Section 4's criterion applied
+  to the feature mode); per-filter factors G_k = f_k x_3 U_R^T; projected
+  features Z = X x_3 U_R^T; response = correlation of Z with G_k over R
+  channels (Section 4, feature contraction first, then the spatial sums).
+
+Parity status of each function is pinned by tests/test_oracle_pins.py.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+NEG_INF = -np.inf
+
+
+# --------------------------------------------------------------------------
+# O1: direct correlation  (Section 4, multiplication count alpha = N'M'NML)
+# --------------------------------------------------------------------------
+def correlate(X: np.ndarray, f: np.ndarray) -> np.ndarray:
+    """Valid-placement correlation of one level with one filter, float64.
+
+    Sums taps in (n, m) order; the inner channel contraction is a library
+    matrix-vector product.  Returns (H-h+1, W-w+1), or an empty array when the
+    filter does not fit.
+    """
+    X = np.asarray(X, dtype=np.float64)
+    f = np.asarray(f, dtype=np.float64)
+    H, W, C = X.shape
+    h, w, C2 = f.shape
+    assert C == C2
+    Ho, Wo = H - h + 1, W - w + 1
+    if Ho <= 0 or Wo <= 0:
+        return np.zeros((max(Ho, 0), max(Wo, 0)))
+    out = np.zeros((Ho, Wo))
+    for n in range(h):
+        for m in range(w):
+            out += X[n:n + Ho, m:m + Wo, :] @ f[n, m, :]
+    return out
+
+
+# --------------------------------------------------------------------------
+# O2: shared feature-mode basis (Section 4, Frobenius criterion)
+# --------------------------------------------------------------------------
+@dataclass
+class Decomposition:
+    sigma: np.ndarray       # (32,) singular values of the mode-3 unfolding, descending
+    U: np.ndarray           # (32, R) leading feature-mode basis vectors
+    rank: int
+
+    @property
+    def gap(self) -> float:
+        """(sigma_R - sigma_{R+1}) / sigma_1; zero gap means U_R is not unique."""
+        s = self.sigma
+        nxt = s[self.rank] if self.rank < len(s) else 0.0
+        return float((s[self.rank - 1] - nxt) / s[0])
+
+
+def unfold_mode3(filters: Sequence[np.ndarray]) -> np.ndarray:
+    """Rows = every cell vector f_k[n, m, :] of every filter (mode-3 unfolding, transposed)."""
+    return np.concatenate([np.asarray(f, np.float64).reshape(-1, f.shape[2]) for f in filters], axis=0)
+
+
+def decompose(filters: Sequence[np.ndarray], rank: int) -> Decomposition:
+    """Leading ``rank`` eigenvectors of C = M^T M, M the mode-3 unfolding.
+
+    The eigen-solve is the library symmetric eigensolver; eigenvalues are
+    sorted in descending order and clipped at zero; sigma = sqrt(lambda).
+    Sign convention: the largest-magnitude entry of each column is positive.
+    """
+    M = unfold_mode3(filters)
+    C = M.T @ M
+    lam, V = np.linalg.eigh(C)
+    order = np.argsort(lam)[::-1]
+    lam = np.clip(lam[order], 0.0, None)
+    V = V[:, order]
+    for j in range(V.shape[1]):
+        i = np.argmax(np.abs(V[:, j]))
+        if V[i, j] < 0:
+            V[:, j] = -V[:, j]
+    return Decomposition(np.sqrt(lam), V[:, :rank].copy(), rank)
+
+
+def factor(f: np.ndarray, U: np.ndarray) -> np.ndarray:
+    """G = f x_3 U^T: per-cell projection of the filter onto the basis, (h, w, R)."""
+    return np.asarray(f, np.float64) @ U
+
+
+def project(X: np.ndarray, U: np.ndarray) -> np.ndarray:
+    """Z = X x_3 U^T: per-cell projection of a feature level, (H, W, R)."""
+    return np.asarray(X, np.float64) @ U
+
+
+def tensor_response(X: np.ndarray, f: np.ndarray, U: np.ndarray) -> np.ndarray:
+    """Shortened correlation: feature contraction first (projection), then the
+    spatial correlation over R channels with the factor G = f x_3 U^T."""
+    return correlate(project(X, U), factor(f, U))
+
+
+# --------------------------------------------------------------------------
+# O4: generalized distance transform, brute force, separable
+#     (Section 2, placement argmax over all part positions)
+# --------------------------------------------------------------------------
+@dataclass
+class DTResult:
+    D: np.ndarray        # best value  resp(y', x') - cost(y'-y, x'-x)
+    arg_y: np.ndarray    # argmax y'  (-1 where the target is outside the map)
+    arg_x: np.ndarray    # argmax x'
+    margin: np.ndarray   # best minus the best value over positions != argmax
+
+
+def _row_pass(resp: np.ndarray, d: np.ndarray, tx: np.ndarray):
+    """For every row y' and target column x_t: max over x' of
+    resp[y', x'] - (d_x (x'-x_t) + d_xx (x'-x_t)^2); first argmax; runner-up."""
+    Hp, Wp = resp.shape
+    dx = np.arange(Wp)[None, :] - tx[:, None]                    # (nT, Wp)
+    cost = d[0] * dx + d[1] * dx * dx                            # (nT, Wp)
+    V = resp[:, None, :] - cost[None, :, :]                       # (Hp, nT, Wp)
+    arg = np.argmax(V, axis=2)                                   # first maximum
+    best = np.take_along_axis(V, arg[..., None], axis=2)[..., 0]
+    V2 = V.copy()
+    np.put_along_axis(V2, arg[..., None], NEG_INF, axis=2)
+    second = V2.max(axis=2) if Wp > 1 else np.full(best.shape, NEG_INF)
+    return best, arg, second
+
+
+def distance_transform(resp: np.ndarray, d: Sequence[float],
+                       ty: Optional[np.ndarray] = None,
+                       tx: Optional[np.ndarray] = None) -> DTResult:
+    """D(y_t, x_t) = max_{y', x'} resp[y', x'] - d . (dx, dx^2, dy, dy^2),
+    dx = x' - x_t, dy = y' - y_t, for targets on the grid ty x tx (default:
+    every cell).  Row pass over x', then column pass over y', both brute force
+    (quadratic per line).  Ties: smallest x' within a row, then smallest y'.
+    Targets outside [0, Hp) x [0, Wp) give -inf with arg -1.
+    """
+    resp = np.asarray(resp, np.float64)
+    d = np.asarray(d, np.float64)
+    Hp, Wp = resp.shape
+    ty = np.arange(Hp) if ty is None else np.asarray(ty, np.int64)
+    tx = np.arange(Wp) if tx is None else np.asarray(tx, np.int64)
+    nY, nX = len(ty), len(tx)
+    D = np.full((nY, nX), NEG_INF)
+    AY = np.full((nY, nX), -1, dtype=np.int64)
+    AX = np.full((nY, nX), -1, dtype=np.int64)
+    MG = np.full((nY, nX), np.inf)
+    if Hp <= 0 or Wp <= 0 or nY == 0 or nX == 0:
+        return DTResult(D, AY, AX, MG)
+    okx = (tx >= 0) & (tx < Wp)
+    oky = (ty >= 0) & (ty < Hp)
+    if not okx.any() or not oky.any():
+        return DTResult(D, AY, AX, MG)
+    txv, tyv = tx[okx], ty[oky]
+    rbest, rarg, rsecond = _row_pass(resp, d, txv)               # (Hp, nTx)
+    dy = np.arange(Hp)[None, :] - tyv[:, None]                    # (nTy, Hp)
+    cy = d[2] * dy + d[3] * dy * dy
+    Vc = rbest.T[None, :, :] - cy[:, None, :]                     # (nTy, nTx, Hp)
+    ay = np.argmax(Vc, axis=2)
+    best = np.take_along_axis(Vc, ay[..., None], axis=2)[..., 0]
+    Vc2 = Vc.copy()
+    np.put_along_axis(Vc2, ay[..., None], NEG_INF, axis=2)
+    other_rows = Vc2.max(axis=2) if Hp > 1 else np.full(best.shape, NEG_INF)
+    # runner-up inside the winning row, with that row's vertical cost
+    rs = rsecond.T[np.arange(len(txv))[None, :], ay]              # (nTy, nTx)
+    cy_win = cy[np.arange(len(tyv))[:, None], ay]
+    second = np.maximum(other_rows, rs - cy_win)
+    ax = rarg.T[np.arange(len(txv))[None, :], ay]
+    iy = np.nonzero(oky)[0]
+    ix = np.nonzero(okx)[0]
+    D[np.ix_(iy, ix)] = best
+    AY[np.ix_(iy, ix)] = ay
+    AX[np.ix_(iy, ix)] = ax
+    MG[np.ix_(iy, ix)] = best - second
+    return DTResult(D, AY, AX, MG)
+
+
+def distance_transform_2d_bruteforce(resp: np.ndarray, d: Sequence[float],
+                                     ty: Optional[np.ndarray] = None,
+                                     tx: Optional[np.ndarray] = None) -> DTResult:
+    """Same as ``distance_transform`` but by a direct search over all (y', x')
+    for every target: pure Python loops, for tiny maps only."""
+    resp = np.asarray(resp, np.float64)
+    Hp, Wp = resp.shape
+    ty = list(range(Hp)) if ty is None else list(ty)
+    tx = list(range(Wp)) if tx is None else list(tx)
+    D = np.full((len(ty), len(tx)), NEG_INF)
+    AY = np.full((len(ty), len(tx)), -1, dtype=np.int64)
+    AX = np.full((len(ty), len(tx)), -1, dtype=np.int64)
+    MG = np.full((len(ty), len(tx)), np.inf)
+    for a, yt in enumerate(ty):
+        for b, xt in enumerate(tx):
+            if not (0 <= yt < Hp and 0 <= xt < Wp):
+                continue
+            vals = []
+            for yp in range(Hp):
+                for xp in range(Wp):
+                    ddx, ddy = xp - xt, yp - yt
+                    c = d[0] * ddx + d[1] * ddx * ddx + d[2] * ddy + d[3] * ddy * ddy
+                    vals.append((resp[yp, xp] - c, yp, xp))
+            best = max(v[0] for v in vals)
+            first = min((v for v in vals if v[0] == best), key=lambda v: (v[1], v[2]))
+            rest = [v[0] for v in vals if (v[1], v[2]) != (first[1], first[2])]
+            D[a, b] = best
+            AY[a, b], AX[a, b] = first[1], first[2]
+            MG[a, b] = best - (max(rest) if rest else NEG_INF)
+    return DTResult(D, AY, AX, MG)
+
+
+# --------------------------------------------------------------------------
+# O5: star-model score (Section 2 score formula)
+# --------------------------------------------------------------------------
+@dataclass
+class ScoreMap:
+    score: np.ndarray          # (Ho, Wo) root-position scores, -inf where an anchor is outside
+    offsets: np.ndarray        # (n_parts, Ho, Wo, 2) int (dy, dx) = placement - anchor
+    margin: np.ndarray         # (n_parts, Ho, Wo) DT margin at the anchor
+    root: np.ndarray           # (Ho, Wo) root response
+    D: np.ndarray              # (n_parts, Ho, Wo) deformed part scores at the anchors
+
+
+def score_component(root_resp: np.ndarray, part_resps: Sequence[np.ndarray],
+                    anchors: np.ndarray, deform: np.ndarray) -> ScoreMap:
+    """s(y0, x0) = root(y0, x0) + sum_i D_i(2 y0 + v_iy, 2 x0 + v_ix)."""
+    Ho, Wo = root_resp.shape
+    n = len(part_resps)
+    score = np.array(root_resp, dtype=np.float64, copy=True)
+    offs = np.zeros((n, Ho, Wo, 2), dtype=np.int64)
+    marg = np.full((n, Ho, Wo), np.inf)
+    Dall = np.full((n, Ho, Wo), NEG_INF)
+    for i, resp in enumerate(part_resps):
+        vy, vx = int(anchors[i][0]), int(anchors[i][1])
+        ty = 2 * np.arange(Ho) + vy
+        tx = 2 * np.arange(Wo) + vx
+        r = distance_transform(resp, deform[i], ty, tx)
+        score = score + r.D
+        inside = r.arg_y >= 0
+        offs[i, :, :, 0] = np.where(inside, r.arg_y - ty[:, None], 0)
+        offs[i, :, :, 1] = np.where(inside, r.arg_x - tx[None, :], 0)
+        marg[i] = r.margin
+        Dall[i] = r.D
+    return ScoreMap(score, offs, marg, np.asarray(root_resp, np.float64), Dall)
+
+
+def score_pyramid(levels: Sequence[np.ndarray], filters: Sequence[np.ndarray],
+                  components, octave: int, U: Optional[np.ndarray] = None
+                  ) -> List[List[ScoreMap]]:
+    """Scores of every component at every root level l >= octave of one image.
+
+    ``levels``: list of (H, W, 32) feature levels.  ``components``: objects with
+    ``root``, ``parts``, ``anchors``, ``deform``.  With ``U`` given, every
+    response is the shortened (tensor-form) correlation; otherwise direct.
+    Returns out[l - octave][c].
+    """
+    resp_of = (lambda X, f: correlate(X, f)) if U is None else \
+              (lambda X, f: tensor_response(X, f, U))
+    out = []
+    for l in range(octave, len(levels)):
+        Xr, Xp = levels[l], levels[l - octave]
+        per_comp = []
+        for c in components:
+            rr = resp_of(Xr, filters[c.root])
+            prs = [resp_of(Xp, filters[k]) for k in c.parts]
+            per_comp.append(score_component(rr, prs, c.anchors, c.deform))
+        out.append(per_comp)
+    return out
+
+
+# --------------------------------------------------------------------------
+# Section 4 accounting: multiplication counts and formula (1)
+# --------------------------------------------------------------------------
+def mults_direct(Np: int, Mp: int, N: int, M: int, L: int) -> int:
+    """alpha = N' M' N M L multiplications for one filter on one image."""
+    return Np * Mp * N * M * L
+
+
+def mults_cp(Np: int, Mp: int, N: int, M: int, L: int, R: int) -> int:
+    """R N' M' (L + M + N) multiplications for the rank-R separable form."""
+    return R * Np * Mp * (L + M + N)
+
+
+def gain_formula1(N: int, M: int, L: int, R: int) -> float:
+    """Formula (1): N M L / (R (N + M + L)), speed and memory gain of rank R."""
+    return N * M * L / (R * (N + M + L))
+
+
+def mults_shared_basis(Np: int, Mp: int, N: int, M: int, L: int, R: int) -> int:
+    """Shortened correlation over R projected channels: N' M' N M R per filter
+    (the projection, N' M' L R per level, is shared by the whole bank)."""
+    return Np * Mp * N * M * R

@@ -1,0 +1,282 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself.
+
+Each test ties one oracle function to something fixed independently: a
+hand-derived example (tests/golden), a textbook library routine, a closed
+form, an invariant of the mathematics, or a direct search on tiny inputs.
+All CPU-only.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.signal
+
+import oracle
+import workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _load(name):
+    with open(os.path.join(GOLDEN, name)) as fh:
+        return json.load(fh)
+
+
+# ---------------------------------------------------------------- worked example
+def test_worked_example_score_map():
+    g = _load("worked_example.json")
+    X0 = np.zeros((3, 4, 32))
+    X0[:, :, 0] = np.array(g["root_level_ch0"])
+    f0 = np.zeros((2, 2, 32))
+    f0[:, :, 0] = np.array(g["root_filter_ch0"])
+    X1 = np.zeros(tuple(g["part_level_shape"]) + (32,))
+    for y, x, v in g["part_level_ch1_nonzero"]:
+        X1[y, x, 1] = v
+    f1 = np.zeros((1, 1, 32))
+    f1[0, 0, 1] = g["part_filter_ch1"][0][0]
+    rr = oracle.correlate(X0, f0)
+    np.testing.assert_array_equal(rr, np.array(g["root_response"], float))
+    pr = oracle.correlate(X1, f1)
+    sm = oracle.score_component(rr, [pr], np.array([g["anchor"]]), np.array([g["deform"]], float))
+    np.testing.assert_array_equal(sm.score, np.array(g["score"], float))
+    np.testing.assert_array_equal(sm.D[0], np.array(g["D"], float))
+    np.testing.assert_array_equal(sm.margin[0], np.array(g["margin"], float))
+    place = np.array(g["placement"])
+    Ho, Wo = rr.shape
+    anchor_y = 2 * np.arange(Ho)[:, None] + g["anchor"][0]
+    anchor_x = 2 * np.arange(Wo)[None, :] + g["anchor"][1]
+    np.testing.assert_array_equal(sm.offsets[0, :, :, 0], place[:, :, 0] - anchor_y)
+    np.testing.assert_array_equal(sm.offsets[0, :, :, 1], place[:, :, 1] - anchor_x)
+
+
+def test_dt_1d_golden():
+    for case in _load("dt_1d.json")["cases"]:
+        resp = np.array([case["resp"]], float)
+        r = oracle.distance_transform(resp, case["deform"])
+        np.testing.assert_array_equal(r.D[0], np.array(case["D"], float))
+        np.testing.assert_array_equal(r.arg_x[0], np.array(case["arg_x"]))
+        np.testing.assert_array_equal(r.arg_y[0], np.zeros(len(case["D"]), int))
+        np.testing.assert_array_equal(r.margin[0], np.array(case["margin"], float))
+
+
+# ---------------------------------------------------------------- correlation
+def test_correlate_matches_scipy_valid_correlation():
+    rng = np.random.default_rng(0)
+    for (H, W, h, w) in [(7, 9, 3, 2), (6, 11, 6, 11), (10, 8, 1, 1), (5, 5, 2, 4)]:
+        X = rng.standard_normal((H, W, 32))
+        f = rng.standard_normal((h, w, 32))
+        ref = scipy.signal.correlate(X, f, mode="valid", method="direct")[:, :, 0]
+        np.testing.assert_allclose(oracle.correlate(X, f), ref, rtol=1e-12, atol=1e-12)
+
+
+def test_correlate_is_not_a_convolution():
+    # A one-hot filter at tap (n, m) must read X[y+n, x+m]: a flipped
+    # (convolution) implementation would read X[y+h-1-n, x+w-1-m].
+    X = np.arange(5 * 6 * 32, dtype=float).reshape(5, 6, 32)
+    f = np.zeros((2, 3, 32))
+    f[0, 2, 4] = 1.0
+    out = oracle.correlate(X, f)
+    np.testing.assert_array_equal(out, X[0:4, 2:6, 4])
+
+
+def test_correlate_linearity():
+    rng = np.random.default_rng(1)
+    X1, X2 = rng.standard_normal((2, 9, 12, 32))
+    f1, f2 = rng.standard_normal((2, 4, 5, 32))
+    a, b = 0.7, -1.3
+    lhs = oracle.correlate(a * X1 + b * X2, f1)
+    rhs = a * oracle.correlate(X1, f1) + b * oracle.correlate(X2, f1)
+    np.testing.assert_allclose(lhs, rhs, rtol=1e-12, atol=1e-12)
+    lhs = oracle.correlate(X1, a * f1 + b * f2)
+    rhs = a * oracle.correlate(X1, f1) + b * oracle.correlate(X1, f2)
+    np.testing.assert_allclose(lhs, rhs, rtol=1e-12, atol=1e-12)
+
+
+def test_correlate_filter_larger_than_level_is_empty():
+    assert oracle.correlate(np.zeros((4, 4, 32)), np.zeros((5, 2, 32))).shape == (0, 3)
+
+
+# ---------------------------------------------------------------- decomposition
+def _planted_bank(rng, sigmas, shapes):
+    """Filters whose stacked cell vectors are A diag(sigmas) Q^T with A, Q orthonormal:
+    the mode-3 singular values are exactly ``sigmas`` and the leading subspace is Q."""
+    n_rows = sum(h * w for h, w in shapes)
+    k = len(sigmas)
+    A, _ = np.linalg.qr(rng.standard_normal((n_rows, k)))
+    Q, _ = np.linalg.qr(rng.standard_normal((32, k)))
+    M = A @ np.diag(sigmas) @ Q.T
+    filters, r = [], 0
+    for h, w in shapes:
+        filters.append(M[r:r + h * w].reshape(h, w, 32))
+        r += h * w
+    return filters, Q
+
+
+def test_decompose_recovers_planted_spectrum_and_subspace():
+    rng = np.random.default_rng(2)
+    sig = np.array([5.0, 3.0, 2.0, 1.0, 0.5, 0.25])
+    filters, Q = _planted_bank(rng, sig, [(6, 11), (6, 6), (7, 13), (6, 6), (8, 15)])
+    for R in (1, 3, 6):
+        dec = oracle.decompose(filters, R)
+        np.testing.assert_allclose(dec.sigma[:6], sig, rtol=1e-10)
+        np.testing.assert_allclose(dec.sigma[6:], 0.0, atol=1e-7)
+        P = dec.U @ dec.U.T
+        Pq = Q[:, :R] @ Q[:, :R].T
+        np.testing.assert_allclose(P, Pq, atol=1e-10)
+
+
+def test_decompose_orthonormal_and_eckart_young():
+    wl = workloads.config2()
+    fs = wl.bank.filters
+    for R in (4, 8, 16, 32):
+        dec = oracle.decompose(fs, R)
+        np.testing.assert_allclose(dec.U.T @ dec.U, np.eye(R), atol=1e-12)
+        P = dec.U @ dec.U.T
+        resid = sum(np.sum((f.astype(np.float64) - f.astype(np.float64) @ P) ** 2) for f in fs)
+        np.testing.assert_allclose(resid, np.sum(dec.sigma[R:] ** 2), rtol=1e-9, atol=1e-13)
+        assert np.all(np.diff(dec.sigma) <= 1e-12)
+
+
+def test_decompose_singular_values_of_unfolding():
+    # the singular values of the stacked matrix, independently of the Gram route
+    rng = np.random.default_rng(3)
+    fs = [rng.standard_normal((h, w, 32)) for h, w in [(6, 6), (6, 11), (3, 4)]]
+    dec = oracle.decompose(fs, 8)
+    M = np.concatenate([f.reshape(-1, 32) for f in fs])
+    sv = np.linalg.svd(M, compute_uv=False)
+    np.testing.assert_allclose(dec.sigma, sv, rtol=1e-10)
+
+
+# ---------------------------------------------------------------- tensor form
+def test_full_rank_tensor_form_reproduces_direct():
+    wl = workloads.config1()
+    X = wl.level_features(0, 1).astype(np.float64)
+    dec = oracle.decompose(wl.bank.filters, 32)
+    for f in wl.bank.filters:
+        d = oracle.correlate(X, f)
+        t = oracle.tensor_response(X, f, dec.U)
+        np.testing.assert_allclose(t, d, rtol=0, atol=1e-10)
+
+
+def test_tensor_form_closed_form_and_truncation_bound():
+    wl = workloads.config1()
+    X = wl.level_features(0, 1).astype(np.float64)
+    for R in (2, 4, 8, 16):
+        dec = oracle.decompose(wl.bank.filters, R)
+        P = dec.U @ dec.U.T
+        for f in wl.bank.filters[:3]:
+            f64 = f.astype(np.float64)
+            t = oracle.tensor_response(X, f, dec.U)
+            np.testing.assert_allclose(t, oracle.correlate(X, f64 @ P), atol=1e-12)
+            # |R_ten - R_dir| <= ||X window||_F ||f - f P||_F  (Cauchy-Schwarz)
+            d = oracle.correlate(X, f)
+            h, w, _ = f.shape
+            wn = np.sqrt(oracle.correlate(X * X, np.ones((h, w, 32))))
+            bound = wn * np.linalg.norm(f64 - f64 @ P)
+            assert np.all(np.abs(t - d) <= bound + 1e-12)
+
+
+# ---------------------------------------------------------------- distance transform
+@pytest.mark.parametrize("seed", range(6))
+def test_dt_separable_equals_2d_bruteforce(seed):
+    rng = np.random.default_rng(100 + seed)
+    Hp, Wp = rng.integers(1, 7, size=2)
+    if seed % 2 == 0:
+        resp = rng.integers(-3, 4, size=(Hp, Wp)).astype(float)   # exact ties likely
+        d = rng.integers(-1, 3, size=4).astype(float)
+        d[1] = max(d[1], 1.0)
+        d[3] = max(d[3], 1.0)
+    else:
+        resp = rng.standard_normal((Hp, Wp))
+        d = np.array([rng.uniform(-0.5, 0.5), rng.uniform(0.01, 1), rng.uniform(-0.5, 0.5), rng.uniform(0.01, 1)])
+    ty = np.arange(-1, Hp + 1)
+    tx = np.arange(-2, Wp + 1)
+    a = oracle.distance_transform(resp, d, ty, tx)
+    b = oracle.distance_transform_2d_bruteforce(resp, d, ty, tx)
+    np.testing.assert_array_equal(a.arg_y, b.arg_y)
+    np.testing.assert_array_equal(a.arg_x, b.arg_x)
+    np.testing.assert_allclose(a.D, b.D, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(a.margin, b.margin, rtol=0, atol=1e-12)
+
+
+def test_dt_invariants():
+    rng = np.random.default_rng(7)
+    resp = rng.standard_normal((9, 13))
+    d = np.array([0.05, 0.03, -0.02, 0.07])
+    r = oracle.distance_transform(resp, d)
+    # D >= resp (the target itself is a candidate with zero cost)
+    assert np.all(r.D >= resp - 1e-15)
+    # D equals the deformed score of its own argmax
+    yy, xx = np.meshgrid(np.arange(9), np.arange(13), indexing="ij")
+    dy, dx = r.arg_y - yy, r.arg_x - xx
+    np.testing.assert_allclose(r.D, resp[r.arg_y, r.arg_x] - (d[0] * dx + d[1] * dx * dx + d[2] * dy + d[3] * dy * dy), atol=1e-14)
+    # shift invariance: D(resp + c) = D(resp) + c, same argmax
+    r2 = oracle.distance_transform(resp + 3.25, d)
+    np.testing.assert_allclose(r2.D, r.D + 3.25, atol=1e-12)
+    np.testing.assert_array_equal(r2.arg_y, r.arg_y)
+    np.testing.assert_array_equal(r2.arg_x, r.arg_x)
+    # 1-Lipschitz in the sup norm
+    pert = resp + rng.uniform(-0.1, 0.1, resp.shape)
+    r3 = oracle.distance_transform(pert, d)
+    assert np.max(np.abs(r3.D - r.D)) <= np.max(np.abs(pert - resp)) + 1e-14
+    # a huge quadratic cost pins every part to its anchor
+    r4 = oracle.distance_transform(resp, [0, 1e9, 0, 1e9])
+    np.testing.assert_array_equal(r4.D, resp)
+    np.testing.assert_array_equal(r4.arg_y, yy)
+    np.testing.assert_array_equal(r4.arg_x, xx)
+
+
+def test_dt_targets_outside_give_neg_inf():
+    resp = np.ones((3, 4))
+    r = oracle.distance_transform(resp, [0, 1, 0, 1], np.array([-1, 0, 3]), np.array([0, 4]))
+    assert np.isneginf(r.D[0]).all() and np.isneginf(r.D[2]).all() and np.isneginf(r.D[:, 1]).all()
+    assert r.D[1, 0] == 1.0 and (r.arg_y[0] == -1).all()
+
+
+# ---------------------------------------------------------------- assembly
+def test_score_component_matches_bruteforce_assembly():
+    rng = np.random.default_rng(11)
+    root = rng.standard_normal((3, 4))
+    parts = [rng.standard_normal((7, 9)) for _ in range(3)]
+    anchors = np.array([[0, 0], [1, 2], [2, 1]])
+    deform = rng.uniform(0.01, 0.5, size=(3, 4))
+    sm = oracle.score_component(root, parts, anchors, deform)
+    for y0 in range(3):
+        for x0 in range(4):
+            s = root[y0, x0]
+            for i, pr in enumerate(parts):
+                ty, tx = 2 * y0 + anchors[i, 0], 2 * x0 + anchors[i, 1]
+                if not (0 <= ty < 7 and 0 <= tx < 9):
+                    s = -np.inf
+                    continue
+                b = oracle.distance_transform_2d_bruteforce(pr, deform[i], [ty], [tx])
+                s += b.D[0, 0]
+                assert sm.offsets[i, y0, x0, 0] == b.arg_y[0, 0] - ty
+                assert sm.offsets[i, y0, x0, 1] == b.arg_x[0, 0] - tx
+            if np.isneginf(s):
+                assert np.isneginf(sm.score[y0, x0])
+            else:
+                assert abs(sm.score[y0, x0] - s) < 1e-12
+
+
+# ---------------------------------------------------------------- Section 4 accounting
+def test_formula1_instance_from_section5():
+    # rank 6, 8 parts of 8x8x32 and a 5x11x32 root: gain "beyond 7"
+    direct = 8 * oracle.mults_direct(1, 1, 8, 8, 32) + oracle.mults_direct(1, 1, 5, 11, 32)
+    cp = 8 * oracle.mults_cp(1, 1, 8, 8, 32, 6) + oracle.mults_cp(1, 1, 5, 11, 32, 6)
+    assert direct / cp == pytest.approx(7.0, abs=1e-12)
+    assert oracle.gain_formula1(8, 8, 32, 6) == pytest.approx(8 * 8 * 32 / (6 * 48))
+
+
+def test_multiplication_counts_by_counting():
+    # count the multiplications of the separable rank-R evaluation, one pass
+    # per 1D factor over an N' x M' grid (borders ignored as in Section 4)
+    Np, Mp, N, M, L, R = 5, 7, 3, 4, 6, 2
+    count = 0
+    for _r in range(R):
+        count += Np * Mp * L      # feature-axis contraction with c_r
+        count += Np * Mp * M      # x-direction 1D correlation with b_r
+        count += Np * Mp * N      # y-direction 1D correlation with a_r
+    assert count == oracle.mults_cp(Np, Mp, N, M, L, R)
+    assert oracle.mults_direct(Np, Mp, N, M, L) == Np * Mp * N * M * L
