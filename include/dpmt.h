@@ -1,0 +1,189 @@
+/*
+ * dpmt.h -- C ABI of libdpmt, DPM score estimation on AMD MI355X (gfx950).
+ *
+ * The library computes, for every root position of every level of a HOG
+ * feature pyramid and every mixture component, the star-model score
+ *     s(p0) = f0 . phi(p0) + sum_i ( f_i . phi(p_i) - d_i . psi(p_i, p0) )
+ * with every part placed at its best position (Section 2, the score formula
+ * and the placement argmax over all part positions).  Filter responses are
+ * computed either directly or in the tensor form of Section 4: the filter
+ * bank is decomposed once into a shared feature-mode basis U_R (the leading
+ * R eigenvectors of the Gram matrix of the bank's mode-3 unfolding, the
+ * Frobenius-optimal truncation of that mode), features are projected onto it
+ * once per level, and rank-R correlations replace the 32-channel ones.
+ *
+ * Conventions used throughout:
+ *   - A feature level is rows x cols cells of 32 float32 channels, channel
+ *     innermost (HWC).  A filter is h x w x 32 float32, HWC.
+ *   - A response is a correlation (not a convolution) over valid placements:
+ *     resp(y, x) = sum_{n<h, m<w, l<32} f[n][m][l] * X[y+n][x+m][l],
+ *     0 <= y <= rows-h, 0 <= x <= cols-w.
+ *   - Deformation coefficients d = (d_x, d_xx, d_y, d_yy); the cost of a part
+ *     at (y', x') for anchor (ya, xa) is
+ *     d_x*(x'-xa) + d_xx*(x'-xa)^2 + d_y*(y'-ya) + d_yy*(y'-ya)^2.
+ *   - Parts of a root at pyramid level l live on level l - octave, at twice
+ *     the resolution: the anchor of part i for root position (y0, x0) is
+ *     (2*y0 + v_y, 2*x0 + v_x).  An anchor outside the part response map
+ *     gives score -inf.  Ties in the placement argmax go to the smallest
+ *     (y', x') in lexicographic order.
+ *
+ * Memory: every pointer argument is owned by the caller and never freed by
+ * the library.  "_host" pointers are host memory, read during the call and
+ * copied where kept.  "_dev" pointers are device memory on the context's
+ * GPU.  Calls that take a hip_stream (a hipStream_t, NULL = the context's
+ * stream) enqueue work asynchronously on it; validation happens before
+ * anything is enqueued, and a failed validation leaves outputs untouched.
+ * A context is not thread-safe; different contexts are independent.
+ */
+#ifndef DPMT_H
+#define DPMT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dpmt_ctx dpmt_ctx;
+
+typedef enum {
+    DPMT_OK = 0,
+    DPMT_E_INVALID = -1,      /* bad argument: NULL pointer, bad size, bad coefficient  */
+    DPMT_E_STATE = -2,        /* call out of order (e.g. score before plan)              */
+    DPMT_E_RANK = -3,         /* rank outside [1, 32]                                    */
+    DPMT_E_NOMEM = -4,        /* device or host allocation failed                        */
+    DPMT_E_DEVICE = -5,       /* a HIP call failed; dpmt_last_error names it             */
+    DPMT_E_UNSUPPORTED = -6   /* valid request this build does not handle                */
+} dpmt_status;
+
+typedef enum {
+    DPMT_DIRECT_FP32 = 0,     /* 32-channel correlation, FP32 MFMA, FP32 accumulation    */
+    DPMT_TENSOR_FP32 = 1,     /* rank-R tensor form, FP32 projection and MFMA            */
+    DPMT_TENSOR_BF16 = 2,     /* rank-R tensor form, BF16 operands, FP32 accumulation    */
+    DPMT_TENSOR_FP8 = 3       /* rank-R tensor form, FP8 e4m3 operands with per-channel
+                                 scales, FP32 accumulation                               */
+} dpmt_mode;
+
+typedef struct { int32_t h, w; } dpmt_shape;          /* filter rows, cols; 32 channels */
+
+/* One mixture component (Section 2: a root filter f0, n > 0 part filters f_i
+ * and deformation coefficients d_i). */
+typedef struct {
+    int32_t        root;       /* filter index of the root filter                       */
+    int32_t        n_parts;    /* >= 1                                                   */
+    const int32_t* parts;      /* [n_parts] filter indices (host)                        */
+    const int32_t* anchors;    /* [n_parts][2] (v_y, v_x), part-level cells (host);
+                                  0 <= v_y <= 2*h0 - h_i, 0 <= v_x <= 2*w0 - w_i         */
+    const float*   deform;     /* [n_parts][4] (d_x, d_xx, d_y, d_yy) (host); d_xx > 0,
+                                  d_yy > 0, all finite                                   */
+} dpmt_component;
+
+typedef struct {
+    int64_t cell_offset;       /* first cell of the level in the packed feature buffer  */
+    int32_t rows, cols;        /* >= 1                                                   */
+} dpmt_level;
+
+typedef struct {
+    int32_t           n_levels;
+    const dpmt_level* levels;  /* [n_levels] (host)                                      */
+    int32_t           octave;  /* levels per octave: parts of root level l use l-octave  */
+} dpmt_pyramid;
+
+/* Output layout, computed by dpmt_plan and owned by the context (valid until
+ * the next dpmt_plan or dpmt_destroy).  One score map per (image, root level
+ * l >= octave, component), in that nesting order; map k has map_rows[k] x
+ * map_cols[k] = (rows_l - h0 + 1) x (cols_l - w0 + 1) float32 scores, row
+ * major, at scores_dev + map_score_off[k] (0 x 0 when the root filter does not
+ * fit), and n_parts int16 (dy, dx) placement offsets per position at
+ * offsets_dev + map_offs_off[k], laid out [part][row][col][2]. */
+typedef struct {
+    int64_t        n_score;        /* float32 elements scores_dev must hold            */
+    int64_t        n_offsets;      /* int16 elements offsets_dev must hold             */
+    int32_t        n_maps;
+    const int32_t* map_image;      /* [n_maps]                                         */
+    const int32_t* map_level;      /* [n_maps] root level                              */
+    const int32_t* map_comp;       /* [n_maps] component index                         */
+    const int32_t* map_rows;       /* [n_maps]                                         */
+    const int32_t* map_cols;       /* [n_maps]                                         */
+    const int64_t* map_score_off;  /* [n_maps] element offsets into scores_dev         */
+    const int64_t* map_offs_off;   /* [n_maps] element offsets into offsets_dev        */
+    int64_t        n_cells;        /* cells (x32 floats) the feature buffer must hold  */
+    int64_t        n_resp;         /* filter-response cells per dpmt_score_pyramid     */
+    int64_t        n_resp_root;    /*   of which root filters on levels >= octave      */
+    int64_t        n_resp_part;    /*   of which part filters one octave below         */
+    int64_t        workspace_bytes;/* device workspace the context holds for the plan  */
+} dpmt_layout;
+
+/* Create a context on HIP device `device` (>= 0), or a host-only context
+ * (device = -1) that can load, decompose and plan but not score.  The stream
+ * (a hipStream_t, may be NULL) becomes the default for calls that get NULL. */
+dpmt_status dpmt_create(dpmt_ctx** out, int32_t device, void* hip_stream);
+void        dpmt_destroy(dpmt_ctx* ctx);
+
+/* Load the filter bank and the mixture components (Section 2 model).
+ * weights_host: all filters concatenated, filter k is shapes[k].h x
+ * shapes[k].w x 32 float32 HWC; copied.  Every weight must be finite, every
+ * shape >= 1 x 1, every component index in range, d_xx > 0 and d_yy > 0,
+ * anchors inside [0, 2*h0 - h_i] x [0, 2*w0 - w_i].  Replaces any previous
+ * bank and drops any decomposition and plan. */
+dpmt_status dpmt_load_filters(dpmt_ctx* ctx, int32_t n_filters, const dpmt_shape* shapes,
+                              const float* weights_host, int32_t n_components,
+                              const dpmt_component* comps);
+
+/* Decompose the loaded bank for the tensor modes (Section 4 criterion applied
+ * to the feature mode): FP64 Gram matrix C = M^T M of the mode-3 unfolding M
+ * (one row per filter cell), cyclic Jacobi eigen-solve, U_R = leading `rank`
+ * eigenvectors (largest-magnitude entry of each column positive), factors
+ * G_k = f_k x_3 U_R^T.  sigma_out (host, may be NULL) receives the 32 singular
+ * values sqrt(lambda) in descending order; basis_out (host, may be NULL)
+ * receives U_R as 32 x rank row-major float64.  Uploads the quantised factors
+ * when the context has a device. */
+dpmt_status dpmt_decompose(dpmt_ctx* ctx, int32_t rank, double* sigma_out, double* basis_out);
+
+/* Plan a batch of n_images pyramids (host descriptors, copied): output layout,
+ * work lists and device workspace.  *out points at the context-owned layout. */
+dpmt_status dpmt_plan(dpmt_ctx* ctx, int32_t n_images, const dpmt_pyramid* pyrs,
+                      const dpmt_layout** out);
+
+/* Score the planned batch.  features_dev: packed float32 HWC cells (at least
+ * layout->n_cells x 32).  scores_dev: layout->n_score float32.  offsets_dev:
+ * layout->n_offsets int16 (may be NULL to skip placements).  Tensor modes need
+ * dpmt_decompose first (else DPMT_E_STATE). */
+dpmt_status dpmt_score_pyramid(dpmt_ctx* ctx, dpmt_mode mode, const float* features_dev,
+                               float* scores_dev, int16_t* offsets_dev, void* hip_stream);
+
+/* Filter responses of every filter of the bank on one planned level (for
+ * checking the correlation stage on its own).  out_dev receives, for filter
+ * k = 0 .. n_filters-1 in order, its (rows - h_k + 1) x (cols - w_k + 1)
+ * row-major float32 map (nothing for a filter that does not fit); capacity is
+ * out_dev's size in elements (DPMT_E_INVALID if too small).  n_written (host,
+ * may be NULL) receives the element count. */
+dpmt_status dpmt_level_responses(dpmt_ctx* ctx, dpmt_mode mode, const float* features_dev,
+                                 int32_t image, int32_t level, float* out_dev,
+                                 int64_t capacity, int64_t* n_written, void* hip_stream);
+
+/* Generalised distance transform of one map (Section 2 placement argmax for
+ * every target cell): d_dev[y][x] = max over all (y', x') of
+ * resp[y'][x'] - cost(y'-y, x'-x), with arg_y_dev / arg_x_dev the maximiser
+ * (int32, may both be NULL).  resp_dev is rows x cols float32 with row pitch
+ * ld >= cols elements; outputs are rows x cols, pitch cols.  deform_host is
+ * (d_x, d_xx, d_y, d_yy) with d_xx > 0, d_yy > 0.  FP32 arithmetic. */
+dpmt_status dpmt_distance_transform(const float* resp_dev, int32_t rows, int32_t cols, int32_t ld,
+                                    const float* deform_host, float* d_dev, int32_t* arg_y_dev,
+                                    int32_t* arg_x_dev, void* hip_stream);
+
+/* Per-stage timing of the last dpmt_score_pyramid call, in milliseconds, from
+ * HIP events recorded on the launch stream around each stage.  Enable with
+ * dpmt_set_profiling(ctx, 1) (adds event records; off by default).  Stages:
+ * 0 projection, 1 correlation (all filters), 2 DT row pass, 3 DT column pass,
+ * 4 score assembly, 5 whole call.  Returns the number of stages written. */
+dpmt_status dpmt_set_profiling(dpmt_ctx* ctx, int32_t on);
+int32_t     dpmt_stage_times(dpmt_ctx* ctx, float* ms_out, int32_t n);
+
+const char* dpmt_status_string(dpmt_status s);
+const char* dpmt_last_error(const dpmt_ctx* ctx);     /* detail of the last failure */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DPMT_H */

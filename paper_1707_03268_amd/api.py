@@ -1,0 +1,253 @@
+"""Python binding of libdpmt: argument marshalling over the C ABI.
+
+Every step of the scoring path runs in the library's HIP kernels; this module
+only converts numpy arrays and torch tensors into the pointers and structs the
+C ABI takes.  PyTorch provides device memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes
+from ctypes import POINTER, byref, c_double, c_float, c_int32, c_int64, c_void_p
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from . import _abi
+
+
+class DpmtError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        self.status = status
+        super().__init__(f"{message} (status {status})")
+
+
+def _lib():
+    return _abi.load()
+
+
+def _check(status: int, ctx=None, what: str = "") -> None:
+    if status != _abi.DPMT_OK:
+        lib = _lib()
+        detail = lib.dpmt_last_error(ctx)
+        detail = detail.decode() if detail else ""
+        name = lib.dpmt_status_string(status).decode()
+        raise DpmtError(status, f"{what}: {name}: {detail}")
+
+
+def _stream_ptr(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dev_ptr(t, dtype, name: str) -> int:
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) torch tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+@dataclass
+class Layout:
+    """Output layout of a plan (copied out of the context-owned dpmt_layout)."""
+    n_score: int
+    n_offsets: int
+    n_maps: int
+    map_image: np.ndarray
+    map_level: np.ndarray
+    map_comp: np.ndarray
+    map_rows: np.ndarray
+    map_cols: np.ndarray
+    map_score_off: np.ndarray
+    map_offs_off: np.ndarray
+    n_cells: int
+    n_resp: int
+    n_resp_root: int
+    n_resp_part: int
+    workspace_bytes: int
+
+    @staticmethod
+    def from_c(lay: _abi.Layout) -> "Layout":
+        n = lay.n_maps
+
+        def arr(p, dt):
+            return np.ctypeslib.as_array(p, shape=(n,)).astype(dt).copy() if n else np.zeros(0, dt)
+        return Layout(lay.n_score, lay.n_offsets, n, arr(lay.map_image, np.int32),
+                      arr(lay.map_level, np.int32), arr(lay.map_comp, np.int32),
+                      arr(lay.map_rows, np.int32), arr(lay.map_cols, np.int32),
+                      arr(lay.map_score_off, np.int64), arr(lay.map_offs_off, np.int64),
+                      lay.n_cells, lay.n_resp, lay.n_resp_root, lay.n_resp_part,
+                      lay.workspace_bytes)
+
+    def find(self, image: int, level: int, comp: int) -> int:
+        hit = np.nonzero((self.map_image == image) & (self.map_level == level) & (self.map_comp == comp))[0]
+        if len(hit) != 1:
+            raise KeyError((image, level, comp))
+        return int(hit[0])
+
+
+class Context:
+    """A libdpmt context on one HIP device (``device=-1``: host-only, can load,
+    decompose and plan but not score)."""
+
+    def __init__(self, device: int = 0, stream=None):
+        lib = _lib()
+        h = c_void_p()
+        sp = None
+        if device >= 0 and stream is not None:
+            sp = _stream_ptr(stream)
+        _check(lib.dpmt_create(byref(h), int(device), sp), None, "dpmt_create")
+        self._h = h
+        self.device = device
+        self.layout: Optional[Layout] = None
+        self.n_filters = 0
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) and self._h.value:
+            _lib().dpmt_destroy(self._h)
+            self._h = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -------------------------------------------------------------- bank
+    def load_filters(self, filters: Sequence[np.ndarray], components) -> None:
+        """filters: list of (h, w, 32) float32 arrays; components: objects with
+        ``root``, ``parts``, ``anchors`` ((n, 2) int) and ``deform`` ((n, 4) float)."""
+        shapes = (_abi.Shape * len(filters))()
+        flat = []
+        for k, f in enumerate(filters):
+            f = np.asarray(f, dtype=np.float32)
+            if f.ndim != 3 or f.shape[2] != 32:
+                raise ValueError(f"filter {k} must be (h, w, 32)")
+            shapes[k].h, shapes[k].w = f.shape[0], f.shape[1]
+            flat.append(np.ascontiguousarray(f).ravel())
+        weights = np.ascontiguousarray(np.concatenate(flat)) if flat else np.zeros(0, np.float32)
+        comps = (_abi.Component * len(components))()
+        keep = []
+        for i, c in enumerate(components):
+            parts = np.ascontiguousarray(np.asarray(c.parts, dtype=np.int32))
+            anchors = np.ascontiguousarray(np.asarray(c.anchors, dtype=np.int32).reshape(-1, 2))
+            deform = np.ascontiguousarray(np.asarray(c.deform, dtype=np.float32).reshape(-1, 4))
+            keep += [parts, anchors, deform]
+            comps[i].root = int(c.root)
+            comps[i].n_parts = len(parts)
+            comps[i].parts = parts.ctypes.data_as(POINTER(c_int32))
+            comps[i].anchors = anchors.ctypes.data_as(POINTER(c_int32))
+            comps[i].deform = deform.ctypes.data_as(POINTER(c_float))
+        _check(_lib().dpmt_load_filters(self._h, len(filters), shapes,
+                                        weights.ctypes.data_as(POINTER(c_float)),
+                                        len(components), comps), self._h, "dpmt_load_filters")
+        self.n_filters = len(filters)
+        self.layout = None
+
+    def decompose(self, rank: int):
+        """Returns (sigma[32], U_R (32, rank)) in float64."""
+        sigma = np.zeros(32, np.float64)
+        basis = np.zeros((32, max(int(rank), 1)), np.float64)
+        _check(_lib().dpmt_decompose(self._h, int(rank), sigma.ctypes.data_as(POINTER(c_double)),
+                                     basis.ctypes.data_as(POINTER(c_double))), self._h,
+               "dpmt_decompose")
+        return sigma, basis
+
+    def plan(self, pyramids) -> Layout:
+        """pyramids: objects with ``levels`` (each with cell_offset, rows, cols) and ``octave``."""
+        arrs = []
+        pyrs = (_abi.PyramidDesc * len(pyramids))()
+        for i, p in enumerate(pyramids):
+            lv = (_abi.LevelDesc * len(p.levels))()
+            for l, L in enumerate(p.levels):
+                lv[l].cell_offset, lv[l].rows, lv[l].cols = int(L.cell_offset), int(L.rows), int(L.cols)
+            arrs.append(lv)
+            pyrs[i].n_levels = len(p.levels)
+            pyrs[i].levels = ctypes.cast(lv, POINTER(_abi.LevelDesc))
+            pyrs[i].octave = int(p.octave)
+        out = POINTER(_abi.Layout)()
+        _check(_lib().dpmt_plan(self._h, len(pyramids), pyrs, byref(out)), self._h, "dpmt_plan")
+        self.layout = Layout.from_c(out.contents)
+        return self.layout
+
+    # -------------------------------------------------------------- scoring
+    def score_pyramid(self, mode, features, scores, offsets=None, stream=None) -> None:
+        """Enqueue the scoring of the planned batch on ``stream`` (default: torch's current)."""
+        import torch
+        m = _abi.MODES[mode] if isinstance(mode, str) else int(mode)
+        _check(_lib().dpmt_score_pyramid(
+            self._h, m, _dev_ptr(features, torch.float32, "features"),
+            _dev_ptr(scores, torch.float32, "scores"),
+            _dev_ptr(offsets, torch.int16, "offsets") if offsets is not None else None,
+            _stream_ptr(stream)), self._h, "dpmt_score_pyramid")
+
+    def level_responses(self, mode, features, image: int, level: int, out=None, stream=None):
+        """Per-filter response maps of every filter on one level.  Returns
+        (flat float32 tensor, [(offset, rows, cols) or None per filter])."""
+        import torch
+        m = _abi.MODES[mode] if isinstance(mode, str) else int(mode)
+        lv = None
+        n = c_int64(0)
+        fp = _dev_ptr(features, torch.float32, "features")
+        if out is None:
+            st = _lib().dpmt_level_responses(self._h, m, fp, int(image), int(level), None, 0,
+                                             byref(n), _stream_ptr(stream))
+            if st not in (_abi.DPMT_OK, _abi.DPMT_E_INVALID):
+                _check(st, self._h, "dpmt_level_responses")
+            out = torch.empty(max(n.value, 1), dtype=torch.float32, device=features.device)
+        _check(_lib().dpmt_level_responses(self._h, m, fp, int(image), int(level),
+                                           _dev_ptr(out, torch.float32, "out"), out.numel(),
+                                           byref(n), _stream_ptr(stream)),
+               self._h, "dpmt_level_responses")
+        return out, n.value
+
+    def set_profiling(self, on: bool) -> None:
+        _check(_lib().dpmt_set_profiling(self._h, 1 if on else 0), self._h, "dpmt_set_profiling")
+
+    def stage_times(self) -> List[float]:
+        buf = (c_float * 6)()
+        n = _lib().dpmt_stage_times(self._h, buf, 6)
+        return [buf[i] for i in range(n)]
+
+
+def distance_transform(resp, deform, out=None, arg_y=None, arg_x=None, stream=None):
+    """Generalised distance transform of one 2D float32 CUDA map for every
+    target cell; returns (D, arg_y, arg_x)."""
+    import torch
+    if resp.dim() != 2:
+        raise ValueError("resp must be 2D")
+    rows, cols = resp.shape
+    ld = resp.stride(0)
+    if resp.stride(1) != 1:
+        raise ValueError("resp rows must be contiguous")
+    if out is None:
+        out = torch.empty((rows, cols), dtype=torch.float32, device=resp.device)
+    if arg_y is None:
+        arg_y = torch.empty((rows, cols), dtype=torch.int32, device=resp.device)
+    if arg_x is None:
+        arg_x = torch.empty((rows, cols), dtype=torch.int32, device=resp.device)
+    d = (c_float * 4)(*[float(v) for v in deform])
+    if not resp.is_cuda or resp.dtype != torch.float32:
+        raise TypeError("resp must be a float32 CUDA tensor")
+    _check(_lib().dpmt_distance_transform(
+        c_void_p(resp.data_ptr()), rows, cols, ld, d,
+        _dev_ptr(out, torch.float32, "out"), _dev_ptr(arg_y, torch.int32, "arg_y"),
+        _dev_ptr(arg_x, torch.int32, "arg_x"), _stream_ptr(stream)), None,
+        "dpmt_distance_transform")
+    return out, arg_y, arg_x

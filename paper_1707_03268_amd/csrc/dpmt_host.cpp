@@ -1,0 +1,1039 @@
+// Host runtime of libdpmt: context, validation, FP64 decomposition of the
+// filter bank, operand packing, planning of work lists, and the launch
+// sequence of dpmt_score_pyramid.  Kernels live in dpmt_kernels.hip.
+#include "dpmt.h"
+#include "dpmt_internal.h"
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+using namespace dpmt;
+
+namespace {
+
+thread_local std::string g_free_error;   // errors of calls without a context
+
+constexpr int TY = 4, BB = 2, WY = 4;     // correlation tile: 16 rows x 32 cols x 64 filters
+constexpr int TYWG = TY * WY;
+constexpr int MAX_FILTER_H = 16;
+constexpr int MAX_FILTER_W = 32;
+
+enum Role { ROLE_ROOT = 0, ROLE_PART = 1, ROLE_ALL = 2 };
+
+struct HostGroup {
+    Role role;
+    int h, w;
+    std::vector<int> filters;   // response-block column order
+};
+
+struct ModeData {
+    bool ready = false;
+    Packing pk{};
+    CorrKind kind = CORR_F32;
+    void* dG = nullptr;         // packed operands of every group
+    GroupDesc* dGroups = nullptr;
+    std::vector<GroupDesc> groups;
+    float* dU = nullptr;        // 32 x RP projection basis (tensor modes)
+    int max_h = 0, max_S = 0;   // over the groups used by score_pyramid
+    // planned correlation tiles of this mode (valid for plan_id)
+    int plan_id = -1;
+    CorrTile* dTiles = nullptr;
+    int n_tiles = 0;
+};
+
+struct LevelInfo {
+    int64_t cell_offset;
+    int rows, cols;
+};
+
+struct BlockKey {
+    int img, level, group;
+    bool operator<(const BlockKey& o) const {
+        return std::tie(img, level, group) < std::tie(o.img, o.level, o.group);
+    }
+};
+
+struct BlockInfo {
+    int64_t off;      // element offset in the response workspace
+    int Ho, Wo;
+};
+
+template <typename T>
+hipError_t upload(T** dptr, const std::vector<T>& v) {
+    if (*dptr) { (void)hipFree(*dptr); *dptr = nullptr; }
+    if (v.empty()) return hipSuccess;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(dptr), v.size() * sizeof(T));
+    if (e != hipSuccess) return e;
+    return hipMemcpy(*dptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+void dfree(void* p) {
+    if (p) (void)hipFree(p);
+}
+
+// float32 -> bfloat16, round to nearest even (finite inputs)
+uint16_t f32_to_bf16(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    const uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7FFFu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+}  // namespace
+
+struct dpmt_ctx {
+    int device = -1;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    // bank
+    bool loaded = false;
+    std::vector<dpmt_shape> shapes;
+    std::vector<int64_t> woff;          // float offset of each filter in `weights`
+    std::vector<float> weights;
+    struct Comp {
+        int root;
+        std::vector<int> parts;
+        std::vector<std::array<int, 2>> anchors;
+        std::vector<std::array<float, 4>> deform;
+    };
+    std::vector<Comp> comps;
+    std::vector<HostGroup> groups;      // root groups, part groups, all groups
+    std::vector<int> comp_root_group, comp_root_col;
+    std::vector<PairDesc> pairs;        // per part group, concatenated
+    std::vector<int> group_pair_base, group_pair_count;
+
+    // decomposition
+    bool decomposed = false;
+    int rank = 0;
+    std::vector<double> sigma;          // 32
+    std::vector<double> Ufull;          // 32 x 32 row major, columns = eigenvectors
+
+    ModeData modes[4];
+
+    // plan
+    int plan_id = 0;
+    bool planned = false;
+    std::vector<std::vector<LevelInfo>> pyr;
+    std::vector<int> octave;
+    std::map<BlockKey, BlockInfo> blocks;
+    int64_t resp_elems = 0;
+    int64_t n_cells = 0;
+    std::vector<int32_t> m_image, m_level, m_comp, m_rows, m_cols;
+    std::vector<int64_t> m_score_off, m_offs_off;
+    std::vector<MapDesc> maps;
+    std::vector<DTItem> dt_items;
+    std::vector<int32_t> row_prefix, col_prefix, asm_prefix;
+    int row_blocks = 0, col_blocks = 0, asm_blocks = 0;
+    int64_t r1_elems = 0, dbuf_elems = 0;
+    dpmt_layout layout{};
+
+    // device workspace
+    float* d_resp = nullptr;
+    float* d_r1v = nullptr;
+    int32_t* d_r1a = nullptr;
+    float* d_dbuf = nullptr;
+    void* d_Z = nullptr;
+    size_t Z_bytes = 0;
+    PairDesc* d_pairs = nullptr;
+    MapDesc* d_maps = nullptr;
+    DTItem* d_items = nullptr;
+    int32_t* d_row_prefix = nullptr;
+    int32_t* d_col_prefix = nullptr;
+    int32_t* d_asm_prefix = nullptr;
+
+    // profiling
+    bool prof = false;
+    hipEvent_t ev[6] = {};
+    float stage_ms[6] = {};
+    bool have_times = false;
+
+    bool has_device() const { return device >= 0; }
+};
+
+namespace {
+
+dpmt_status fail(dpmt_ctx* c, dpmt_status s, const std::string& msg) {
+    if (c) c->err = msg;
+    else g_free_error = msg;
+    return s;
+}
+
+dpmt_status hip_fail(dpmt_ctx* c, hipError_t e, const char* what) {
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(c, e == hipErrorOutOfMemory ? DPMT_E_NOMEM : DPMT_E_DEVICE, m);
+}
+
+#define HIP_TRY(ctx, call, what)                          \
+    do {                                                  \
+        hipError_t e_ = (call);                           \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
+    } while (0)
+
+void free_mode(ModeData& m) {
+    dfree(m.dG);
+    dfree(m.dGroups);
+    dfree(m.dU);
+    dfree(m.dTiles);
+    m = ModeData{};
+}
+
+void free_plan(dpmt_ctx* c) {
+    dfree(c->d_resp); c->d_resp = nullptr;
+    dfree(c->d_r1v); c->d_r1v = nullptr;
+    dfree(c->d_r1a); c->d_r1a = nullptr;
+    dfree(c->d_dbuf); c->d_dbuf = nullptr;
+    dfree(c->d_Z); c->d_Z = nullptr; c->Z_bytes = 0;
+    dfree(c->d_maps); c->d_maps = nullptr;
+    dfree(c->d_items); c->d_items = nullptr;
+    dfree(c->d_row_prefix); c->d_row_prefix = nullptr;
+    dfree(c->d_col_prefix); c->d_col_prefix = nullptr;
+    dfree(c->d_asm_prefix); c->d_asm_prefix = nullptr;
+    for (auto& m : c->modes) {
+        dfree(m.dTiles);
+        m.dTiles = nullptr;
+        m.n_tiles = 0;
+        m.plan_id = -1;
+    }
+    c->planned = false;
+}
+
+// Channels padded to what the operand packing supports.
+int padded_rank(dpmt_mode mode, int R) {
+    if (mode == DPMT_DIRECT_FP32) return 32;
+    if (R <= 4) return 4;
+    if (R <= 8) return 8;
+    if (R <= 16) return 16;
+    if (mode == DPMT_TENSOR_FP32 && R <= 24) return 24;
+    return 32;
+}
+
+Packing packing_for(dpmt_mode mode, int R) {
+    Packing p{};
+    p.RP = padded_rank(mode, R);
+    p.esz = (mode == DPMT_TENSOR_BF16) ? 2 : 4;
+    p.PB = std::min(p.RP * p.esz, 32);
+    p.Q = p.RP * p.esz / p.PB;
+    return p;
+}
+
+// Jacobi eigen-decomposition of a symmetric 32x32 matrix (cyclic sweeps of
+// plane rotations; Golub & Van Loan, Section 8.5).  A is destroyed; on return
+// its diagonal holds the eigenvalues and V (row major) the eigenvectors as
+// columns.
+void jacobi_eigen(std::vector<double>& A, std::vector<double>& V, int n) {
+    V.assign(n * n, 0.0);
+    for (int i = 0; i < n; ++i) V[i * n + i] = 1.0;
+    double fro = 0;
+    for (double x : A) fro += x * x;
+    fro = std::sqrt(fro);
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0;
+        for (int p = 0; p < n; ++p)
+            for (int q = p + 1; q < n; ++q) off += 2 * A[p * n + q] * A[p * n + q];
+        if (std::sqrt(off) <= 1e-15 * fro || fro == 0) break;
+        for (int p = 0; p < n; ++p) {
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = A[p * n + q];
+                if (apq == 0.0) continue;
+                const double app = A[p * n + p], aqq = A[q * n + q];
+                const double theta = (aqq - app) / (2 * apq);
+                const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1));
+                const double cs = 1.0 / std::sqrt(t * t + 1), sn = t * cs;
+                for (int k = 0; k < n; ++k) {        // A <- A J  (columns p, q)
+                    const double akp = A[k * n + p], akq = A[k * n + q];
+                    A[k * n + p] = cs * akp - sn * akq;
+                    A[k * n + q] = sn * akp + cs * akq;
+                }
+                for (int k = 0; k < n; ++k) {        // A <- J^T A  (rows p, q)
+                    const double apk = A[p * n + k], aqk = A[q * n + k];
+                    A[p * n + k] = cs * apk - sn * aqk;
+                    A[q * n + k] = sn * apk + cs * aqk;
+                }
+                for (int k = 0; k < n; ++k) {        // V <- V J
+                    const double vkp = V[k * n + p], vkq = V[k * n + q];
+                    V[k * n + p] = cs * vkp - sn * vkq;
+                    V[k * n + q] = sn * vkp + cs * vkq;
+                }
+            }
+        }
+    }
+}
+
+// Operand weights of filter k for a mode: h x w x RP values in float64
+// (original weights for the direct mode, G_k = f_k x_3 U_R for tensor modes).
+std::vector<double> operand_weights(const dpmt_ctx* c, int k, const Packing& pk, bool tensor) {
+    const int h = c->shapes[k].h, w = c->shapes[k].w;
+    const float* f = c->weights.data() + c->woff[k];
+    std::vector<double> out((size_t)h * w * pk.RP, 0.0);
+    for (int cell = 0; cell < h * w; ++cell) {
+        if (!tensor) {
+            for (int l = 0; l < 32; ++l) out[(size_t)cell * pk.RP + l] = f[cell * 32 + l];
+        } else {
+            for (int r = 0; r < c->rank; ++r) {
+                double s = 0;
+                for (int l = 0; l < 32; ++l) s += (double)f[cell * 32 + l] * c->Ufull[l * 32 + r];
+                out[(size_t)cell * pk.RP + r] = s;
+            }
+        }
+    }
+    return out;
+}
+
+// Pack every group's operand in MFMA B-fragment order:
+// [block][plane q][step s][filter row n][lane 0..63][16 bytes], lane = f + 32*j
+// holding bytes [32 s + 16 j, 32 s + 16 j + 16) of filter (32*block + f)'s
+// flattened plane-q row n (w cells x PB bytes, zero beyond).
+dpmt_status prepare_mode(dpmt_ctx* c, dpmt_mode mode) {
+    ModeData& md = c->modes[mode];
+    if (md.ready) return DPMT_OK;
+    const bool tensor = mode != DPMT_DIRECT_FP32;
+    if (tensor && !c->decomposed) return fail(c, DPMT_E_STATE, "tensor mode needs dpmt_decompose first");
+    if (mode == DPMT_TENSOR_FP8) return fail(c, DPMT_E_UNSUPPORTED, "FP8 tensor mode is not built");
+    md.pk = packing_for(mode, c->rank);
+    md.kind = (mode == DPMT_TENSOR_BF16) ? CORR_BF16 : CORR_F32;
+    const Packing pk = md.pk;
+    std::vector<unsigned char> G;
+    md.groups.clear();
+    md.max_h = md.max_S = 0;
+    std::vector<std::vector<double>> opw(c->shapes.size());
+    for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+        const HostGroup& hg = c->groups[gi];
+        GroupDesc gd{};
+        gd.h = hg.h;
+        gd.w = hg.w;
+        gd.ng = (int)hg.filters.size();
+        gd.S = (hg.w * pk.PB + 31) / 32;
+        gd.g_off = (int64_t)G.size();
+        if (hg.role != ROLE_ALL) {
+            md.max_h = std::max(md.max_h, gd.h);
+            md.max_S = std::max(md.max_S, gd.S);
+        }
+        const int nblk = (gd.ng + 31) / 32;
+        const int nblk_pad = (nblk + BB - 1) / BB * BB;
+        const size_t bytes = (size_t)nblk_pad * pk.Q * gd.S * gd.h * 1024;
+        G.resize(G.size() + bytes, 0);
+        unsigned char* base = G.data() + gd.g_off;
+        for (int fi = 0; fi < gd.ng; ++fi) {
+            const int k = hg.filters[fi];
+            if (opw[k].empty()) opw[k] = operand_weights(c, k, pk, tensor);
+            const std::vector<double>& wv = opw[k];
+            const int blk = fi / 32, f = fi % 32;
+            for (int q = 0; q < pk.Q; ++q)
+                for (int s = 0; s < gd.S; ++s)
+                    for (int n = 0; n < gd.h; ++n)
+                        for (int j = 0; j < 2; ++j) {
+                            unsigned char* dst = base + ((((size_t)blk * pk.Q + q) * gd.S + s) * gd.h + n) * 1024 +
+                                                 (size_t)(f + 32 * j) * 16;
+                            for (int e = 0; e < 16 / pk.esz; ++e) {
+                                const int o = 32 * s + 16 * j + e * pk.esz;   // flattened byte
+                                const int m = o / pk.PB;
+                                const int ch = q * (pk.PB / pk.esz) + (o % pk.PB) / pk.esz;
+                                if (m >= gd.w) continue;
+                                const double v = wv[((size_t)n * gd.w + m) * pk.RP + ch];
+                                if (pk.esz == 4) {
+                                    const float fv = (float)v;
+                                    std::memcpy(dst + e * 4, &fv, 4);
+                                } else {
+                                    const uint16_t bv = f32_to_bf16((float)v);
+                                    std::memcpy(dst + e * 2, &bv, 2);
+                                }
+                            }
+                        }
+        }
+        md.groups.push_back(gd);
+    }
+    if (c->has_device()) {
+        HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
+        std::vector<unsigned char> Gv(G);
+        HIP_TRY(c, upload(reinterpret_cast<unsigned char**>(&md.dG), Gv), "upload packed filters");
+        HIP_TRY(c, upload(&md.dGroups, md.groups), "upload group table");
+        if (tensor) {
+            std::vector<float> U((size_t)32 * pk.RP, 0.f);
+            for (int l = 0; l < 32; ++l)
+                for (int r = 0; r < c->rank; ++r) U[l * pk.RP + r] = (float)c->Ufull[l * 32 + r];
+            HIP_TRY(c, upload(&md.dU, U), "upload basis");
+        }
+    }
+    md.ready = true;
+    return DPMT_OK;
+}
+
+void build_groups(dpmt_ctx* c) {
+    c->groups.clear();
+    c->comp_root_group.assign(c->comps.size(), -1);
+    c->comp_root_col.assign(c->comps.size(), -1);
+    std::map<std::pair<int, int>, int> root_g, part_g, all_g;
+    auto group_for = [&](std::map<std::pair<int, int>, int>& gm, Role role, int k) {
+        const auto key = std::make_pair(c->shapes[k].h, c->shapes[k].w);
+        auto it = gm.find(key);
+        if (it != gm.end()) return it->second;
+        c->groups.push_back(HostGroup{role, key.first, key.second, {}});
+        gm[key] = (int)c->groups.size() - 1;
+        return (int)c->groups.size() - 1;
+    };
+    auto col_of = [&](int g, int k) {
+        auto& fl = c->groups[g].filters;
+        auto it = std::find(fl.begin(), fl.end(), k);
+        if (it != fl.end()) return (int)(it - fl.begin());
+        fl.push_back(k);
+        return (int)fl.size() - 1;
+    };
+    for (size_t ci = 0; ci < c->comps.size(); ++ci) {
+        const int g = group_for(root_g, ROLE_ROOT, c->comps[ci].root);
+        c->comp_root_group[ci] = g;
+        c->comp_root_col[ci] = col_of(g, c->comps[ci].root);
+    }
+    std::vector<std::vector<PairDesc>> gp;
+    for (size_t ci = 0; ci < c->comps.size(); ++ci) {
+        const auto& cm = c->comps[ci];
+        for (size_t s = 0; s < cm.parts.size(); ++s) {
+            const int k = cm.parts[s];
+            const int g = group_for(part_g, ROLE_PART, k);
+            const int col = col_of(g, k);
+            if ((int)gp.size() <= g) gp.resize(g + 1);
+            PairDesc pd{};
+            pd.fcol = col;
+            pd.comp = (int)ci;
+            pd.slot = (int)s;
+            pd.vy = cm.anchors[s][0];
+            pd.vx = cm.anchors[s][1];
+            pd.h0 = c->shapes[cm.root].h;
+            pd.w0 = c->shapes[cm.root].w;
+            for (int t = 0; t < 4; ++t) pd.d[t] = cm.deform[s][t];
+            gp[g].push_back(pd);
+        }
+    }
+    for (size_t k = 0; k < c->shapes.size(); ++k) {
+        const int g = group_for(all_g, ROLE_ALL, (int)k);
+        col_of(g, (int)k);
+    }
+    gp.resize(c->groups.size());
+    c->pairs.clear();
+    c->group_pair_base.assign(c->groups.size(), 0);
+    c->group_pair_count.assign(c->groups.size(), 0);
+    for (size_t g = 0; g < c->groups.size(); ++g) {
+        // pairs ordered by the column of their filter, so that lanes of a
+        // wavefront read neighbouring columns of the response block
+        std::stable_sort(gp[g].begin(), gp[g].end(),
+                         [](const PairDesc& a, const PairDesc& b) { return a.fcol < b.fcol; });
+        c->group_pair_base[g] = (int)c->pairs.size();
+        c->group_pair_count[g] = (int)gp[g].size();
+        c->pairs.insert(c->pairs.end(), gp[g].begin(), gp[g].end());
+    }
+}
+
+void add_tiles(std::vector<CorrTile>& tiles, const GroupDesc& gd, int group, int64_t z_cell,
+               int64_t out_off, int H, int W) {
+    const int Ho = H - gd.h + 1, Wo = W - gd.w + 1;
+    if (Ho <= 0 || Wo <= 0) return;
+    const int nblk = (gd.ng + 31) / 32;
+    for (int y0 = 0; y0 < Ho; y0 += TYWG)
+        for (int x0 = 0; x0 < Wo; x0 += 32)
+            for (int fb = 0; fb < nblk; fb += BB) {
+                CorrTile t{};
+                t.z_cell = z_cell;
+                t.out_off = out_off;
+                t.H = H;
+                t.W = W;
+                t.Ho = Ho;
+                t.Wo = Wo;
+                t.y0 = y0;
+                t.x0 = x0;
+                t.fb0 = fb;
+                t.group = group;
+                tiles.push_back(t);
+            }
+}
+
+dpmt_status prepare_tiles(dpmt_ctx* c, dpmt_mode mode) {
+    ModeData& md = c->modes[mode];
+    if (md.plan_id == c->plan_id && md.dTiles) return DPMT_OK;
+    std::vector<CorrTile> tiles;
+    for (const auto& kv : c->blocks) {
+        const BlockKey& k = kv.first;
+        const LevelInfo& lv = c->pyr[k.img][k.level];
+        add_tiles(tiles, md.groups[k.group], k.group, lv.cell_offset, kv.second.off, lv.rows, lv.cols);
+    }
+    // most expensive groups first so that the tail of the launch is short tiles
+    std::stable_sort(tiles.begin(), tiles.end(), [&](const CorrTile& a, const CorrTile& b) {
+        const GroupDesc& ga = md.groups[a.group];
+        const GroupDesc& gb = md.groups[b.group];
+        return (int64_t)ga.h * ga.S > (int64_t)gb.h * gb.S;
+    });
+    HIP_TRY(c, upload(&md.dTiles, tiles), "upload tiles");
+    md.n_tiles = (int)tiles.size();
+    md.plan_id = c->plan_id;
+    return DPMT_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* dpmt_status_string(dpmt_status s) {
+    switch (s) {
+        case DPMT_OK: return "ok";
+        case DPMT_E_INVALID: return "invalid argument";
+        case DPMT_E_STATE: return "call out of order";
+        case DPMT_E_RANK: return "rank outside [1, 32]";
+        case DPMT_E_NOMEM: return "out of memory";
+        case DPMT_E_DEVICE: return "device error";
+        case DPMT_E_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+const char* dpmt_last_error(const dpmt_ctx* ctx) {
+    return ctx ? ctx->err.c_str() : g_free_error.c_str();
+}
+
+dpmt_status dpmt_create(dpmt_ctx** out, int32_t device, void* hip_stream) {
+    if (!out) return fail(nullptr, DPMT_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (device < -1) return fail(nullptr, DPMT_E_INVALID, "device must be >= -1");
+    dpmt_ctx* c = new dpmt_ctx();
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    if (device >= 0) {
+        int n = 0;
+        hipError_t e = hipGetDeviceCount(&n);
+        if (e != hipSuccess || device >= n) {
+            delete c;
+            return fail(nullptr, DPMT_E_DEVICE, "no such HIP device");
+        }
+        e = hipSetDevice(device);
+        if (e != hipSuccess) {
+            delete c;
+            return fail(nullptr, DPMT_E_DEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e));
+        }
+    }
+    *out = c;
+    return DPMT_OK;
+}
+
+void dpmt_destroy(dpmt_ctx* c) {
+    if (!c) return;
+    if (c->has_device()) {
+        (void)hipSetDevice(c->device);
+        (void)hipDeviceSynchronize();
+        free_plan(c);
+        for (auto& m : c->modes) free_mode(m);
+        dfree(c->d_pairs);
+        for (auto& e : c->ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+    delete c;
+}
+
+dpmt_status dpmt_load_filters(dpmt_ctx* c, int32_t n_filters, const dpmt_shape* shapes,
+                              const float* weights_host, int32_t n_components,
+                              const dpmt_component* comps) {
+    if (!c) return fail(nullptr, DPMT_E_INVALID, "ctx is NULL");
+    if (n_filters <= 0 || !shapes || !weights_host) return fail(c, DPMT_E_INVALID, "need n_filters > 0, shapes and weights");
+    if (n_components <= 0 || !comps) return fail(c, DPMT_E_INVALID, "need n_components > 0 and comps");
+    int64_t total = 0;
+    for (int k = 0; k < n_filters; ++k) {
+        if (shapes[k].h < 1 || shapes[k].w < 1) return fail(c, DPMT_E_INVALID, "filter " + std::to_string(k) + " has an empty shape");
+        if (shapes[k].h > MAX_FILTER_H || shapes[k].w > MAX_FILTER_W)
+            return fail(c, DPMT_E_UNSUPPORTED, "filter " + std::to_string(k) + " larger than 16 x 32 cells");
+        total += (int64_t)shapes[k].h * shapes[k].w * 32;
+    }
+    for (int64_t i = 0; i < total; ++i)
+        if (!std::isfinite(weights_host[i])) return fail(c, DPMT_E_INVALID, "non-finite filter weight at element " + std::to_string(i));
+    for (int ci = 0; ci < n_components; ++ci) {
+        const dpmt_component& cm = comps[ci];
+        const std::string cs = "component " + std::to_string(ci) + ": ";
+        if (cm.root < 0 || cm.root >= n_filters) return fail(c, DPMT_E_INVALID, cs + "root index out of range");
+        if (cm.n_parts < 1 || !cm.parts || !cm.anchors || !cm.deform) return fail(c, DPMT_E_INVALID, cs + "needs n_parts >= 1 with parts, anchors, deform");
+        const int h0 = shapes[cm.root].h, w0 = shapes[cm.root].w;
+        for (int i = 0; i < cm.n_parts; ++i) {
+            const int k = cm.parts[i];
+            if (k < 0 || k >= n_filters) return fail(c, DPMT_E_INVALID, cs + "part index out of range");
+            const float* d = cm.deform + 4 * i;
+            for (int t = 0; t < 4; ++t)
+                if (!std::isfinite(d[t])) return fail(c, DPMT_E_INVALID, cs + "non-finite deformation coefficient");
+            if (!(d[1] > 0.f) || !(d[3] > 0.f)) return fail(c, DPMT_E_INVALID, cs + "quadratic deformation coefficients must be > 0");
+            const int vy = cm.anchors[2 * i], vx = cm.anchors[2 * i + 1];
+            if (vy < 0 || vx < 0 || vy > 2 * h0 - shapes[k].h || vx > 2 * w0 - shapes[k].w)
+                return fail(c, DPMT_E_INVALID, cs + "anchor of part " + std::to_string(i) + " outside [0, 2*h0-h] x [0, 2*w0-w]");
+        }
+    }
+    // accepted: replace the bank
+    if (c->has_device()) {
+        (void)hipSetDevice(c->device);
+        (void)hipDeviceSynchronize();
+        free_plan(c);
+        for (auto& m : c->modes) free_mode(m);
+    }
+    c->planned = false;
+    c->decomposed = false;
+    c->shapes.assign(shapes, shapes + n_filters);
+    c->woff.resize(n_filters);
+    int64_t off = 0;
+    for (int k = 0; k < n_filters; ++k) {
+        c->woff[k] = off;
+        off += (int64_t)shapes[k].h * shapes[k].w * 32;
+    }
+    c->weights.assign(weights_host, weights_host + total);
+    c->comps.clear();
+    for (int ci = 0; ci < n_components; ++ci) {
+        const dpmt_component& cm = comps[ci];
+        dpmt_ctx::Comp cp;
+        cp.root = cm.root;
+        for (int i = 0; i < cm.n_parts; ++i) {
+            cp.parts.push_back(cm.parts[i]);
+            cp.anchors.push_back({cm.anchors[2 * i], cm.anchors[2 * i + 1]});
+            cp.deform.push_back({cm.deform[4 * i], cm.deform[4 * i + 1], cm.deform[4 * i + 2], cm.deform[4 * i + 3]});
+        }
+        c->comps.push_back(cp);
+    }
+    build_groups(c);
+    if (c->has_device()) HIP_TRY(c, upload(&c->d_pairs, c->pairs), "upload pair table");
+    c->loaded = true;
+    c->err.clear();
+    return DPMT_OK;
+}
+
+dpmt_status dpmt_decompose(dpmt_ctx* c, int32_t rank, double* sigma_out, double* basis_out) {
+    if (!c) return fail(nullptr, DPMT_E_INVALID, "ctx is NULL");
+    if (!c->loaded) return fail(c, DPMT_E_STATE, "dpmt_decompose before dpmt_load_filters");
+    if (rank < 1 || rank > 32) return fail(c, DPMT_E_RANK, "rank must be in [1, 32]");
+    // Gram matrix of the mode-3 unfolding: sum over every filter cell of v v^T
+    std::vector<double> C(32 * 32, 0.0);
+    const int64_t n_cells = (int64_t)c->weights.size() / 32;
+    for (int64_t i = 0; i < n_cells; ++i) {
+        const float* v = c->weights.data() + i * 32;
+        for (int a = 0; a < 32; ++a) {
+            const double va = v[a];
+            for (int b = 0; b < 32; ++b) C[a * 32 + b] += va * (double)v[b];
+        }
+    }
+    std::vector<double> V;
+    jacobi_eigen(C, V, 32);
+    std::vector<int> order(32);
+    for (int i = 0; i < 32; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return C[a * 32 + a] > C[b * 32 + b]; });
+    c->sigma.assign(32, 0.0);
+    c->Ufull.assign(32 * 32, 0.0);
+    for (int j = 0; j < 32; ++j) {
+        const int src = order[j];
+        c->sigma[j] = std::sqrt(std::max(C[src * 32 + src], 0.0));
+        int imax = 0;
+        for (int l = 1; l < 32; ++l)
+            if (std::fabs(V[l * 32 + src]) > std::fabs(V[imax * 32 + src])) imax = l;
+        const double sg = V[imax * 32 + src] < 0 ? -1.0 : 1.0;
+        for (int l = 0; l < 32; ++l) c->Ufull[l * 32 + j] = sg * V[l * 32 + src];
+    }
+    c->rank = rank;
+    c->decomposed = true;
+    for (int m = 1; m < 4; ++m) {             // tensor operands depend on U_R
+        ModeData& md = c->modes[m];
+        if (c->has_device()) {
+            (void)hipSetDevice(c->device);
+            (void)hipDeviceSynchronize();
+        }
+        free_mode(md);
+    }
+    if (sigma_out) std::memcpy(sigma_out, c->sigma.data(), 32 * sizeof(double));
+    if (basis_out)
+        for (int l = 0; l < 32; ++l)
+            for (int r = 0; r < rank; ++r) basis_out[l * rank + r] = c->Ufull[l * 32 + r];
+    if (c->has_device()) {
+        // upload the factors of the modes the build supports now, so that the
+        // first score call does not pay for packing
+        dpmt_status s = prepare_mode(c, DPMT_TENSOR_BF16);
+        if (s != DPMT_OK) return s;
+    }
+    c->err.clear();
+    return DPMT_OK;
+}
+
+dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, const dpmt_layout** out) {
+    if (!c) return fail(nullptr, DPMT_E_INVALID, "ctx is NULL");
+    if (!c->loaded) return fail(c, DPMT_E_STATE, "dpmt_plan before dpmt_load_filters");
+    if (n_images <= 0 || !pyrs || !out) return fail(c, DPMT_E_INVALID, "need n_images > 0, pyrs and out");
+    for (int i = 0; i < n_images; ++i) {
+        const dpmt_pyramid& p = pyrs[i];
+        if (p.n_levels < 1 || !p.levels) return fail(c, DPMT_E_INVALID, "image " + std::to_string(i) + ": empty pyramid");
+        if (p.octave < 1) return fail(c, DPMT_E_INVALID, "image " + std::to_string(i) + ": octave must be >= 1");
+        for (int l = 0; l < p.n_levels; ++l) {
+            const dpmt_level& lv = p.levels[l];
+            if (lv.rows < 1 || lv.cols < 1 || lv.cell_offset < 0)
+                return fail(c, DPMT_E_INVALID, "image " + std::to_string(i) + " level " + std::to_string(l) + ": bad size or offset");
+            if ((int64_t)lv.rows * lv.cols > (int64_t)1 << 30)
+                return fail(c, DPMT_E_UNSUPPORTED, "level larger than 2^30 cells");
+        }
+    }
+    if (c->has_device()) {
+        (void)hipSetDevice(c->device);
+        (void)hipDeviceSynchronize();
+    }
+    free_plan(c);
+    c->plan_id++;
+    c->pyr.assign(n_images, {});
+    c->octave.assign(n_images, 0);
+    c->n_cells = 0;
+    for (int i = 0; i < n_images; ++i) {
+        c->octave[i] = pyrs[i].octave;
+        for (int l = 0; l < pyrs[i].n_levels; ++l) {
+            const dpmt_level& lv = pyrs[i].levels[l];
+            c->pyr[i].push_back(LevelInfo{lv.cell_offset, lv.rows, lv.cols});
+            c->n_cells = std::max(c->n_cells, lv.cell_offset + (int64_t)lv.rows * lv.cols);
+        }
+    }
+    // response blocks: root groups on levels >= octave, part groups one octave below
+    c->blocks.clear();
+    c->resp_elems = 0;
+    int64_t n_root = 0, n_part = 0;
+    for (int i = 0; i < n_images; ++i) {
+        const int L = (int)c->pyr[i].size(), oct = c->octave[i];
+        for (size_t g = 0; g < c->groups.size(); ++g) {
+            const HostGroup& hg = c->groups[g];
+            if (hg.role == ROLE_ALL) continue;
+            const int l_lo = hg.role == ROLE_ROOT ? oct : 0;
+            const int l_hi = hg.role == ROLE_ROOT ? L : L - oct;
+            for (int l = l_lo; l < l_hi; ++l) {
+                const LevelInfo& lv = c->pyr[i][l];
+                const int Ho = lv.rows - hg.h + 1, Wo = lv.cols - hg.w + 1;
+                if (Ho <= 0 || Wo <= 0) continue;
+                c->blocks[BlockKey{i, l, (int)g}] = BlockInfo{c->resp_elems, Ho, Wo};
+                const int64_t n = (int64_t)Ho * Wo * hg.filters.size();
+                c->resp_elems += n;
+                (hg.role == ROLE_ROOT ? n_root : n_part) += n;
+            }
+        }
+    }
+    // score maps
+    c->m_image.clear(); c->m_level.clear(); c->m_comp.clear(); c->m_rows.clear(); c->m_cols.clear();
+    c->m_score_off.clear(); c->m_offs_off.clear(); c->maps.clear();
+    int64_t score_off = 0, offs_off = 0, dbuf_off = 0;
+    std::vector<std::vector<int>> map_base(n_images);
+    for (int i = 0; i < n_images; ++i) {
+        const int L = (int)c->pyr[i].size(), oct = c->octave[i];
+        map_base[i].assign(L, -1);
+        for (int l = oct; l < L; ++l) {
+            map_base[i][l] = (int)c->maps.size();
+            const LevelInfo& lv = c->pyr[i][l];
+            for (size_t ci = 0; ci < c->comps.size(); ++ci) {
+                const auto& cm = c->comps[ci];
+                const dpmt_shape rs = c->shapes[cm.root];
+                const int Ho = std::max(lv.rows - rs.h + 1, 0), Wo = std::max(lv.cols - rs.w + 1, 0);
+                const int np = (int)cm.parts.size();
+                MapDesc md{};
+                md.score_off = score_off;
+                md.offs_off = offs_off;
+                md.dbuf_off = dbuf_off;
+                md.Ho = Ho;
+                md.Wo = Wo;
+                md.n_parts = np;
+                const int rg = c->comp_root_group[ci];
+                md.rng = (int)c->groups[rg].filters.size();
+                md.rcol = c->comp_root_col[ci];
+                auto bit = c->blocks.find(BlockKey{i, l, rg});
+                md.rresp_off = bit == c->blocks.end() ? 0 : bit->second.off;
+                c->maps.push_back(md);
+                c->m_image.push_back(i);
+                c->m_level.push_back(l);
+                c->m_comp.push_back((int)ci);
+                c->m_rows.push_back(Ho);
+                c->m_cols.push_back(Wo);
+                c->m_score_off.push_back(score_off);
+                c->m_offs_off.push_back(offs_off);
+                const int64_t plane = (int64_t)Ho * Wo;
+                score_off += plane;
+                offs_off += plane * np * 2;
+                dbuf_off += plane * np;
+            }
+        }
+    }
+    c->dbuf_elems = dbuf_off;
+    // distance-transform items: (image, root level, part group)
+    c->dt_items.clear();
+    c->r1_elems = 0;
+    for (int i = 0; i < n_images; ++i) {
+        const int L = (int)c->pyr[i].size(), oct = c->octave[i];
+        for (int l = oct; l < L; ++l) {
+            const LevelInfo& rl = c->pyr[i][l];
+            const LevelInfo& pl = c->pyr[i][l - oct];
+            for (size_t g = 0; g < c->groups.size(); ++g) {
+                const HostGroup& hg = c->groups[g];
+                if (hg.role != ROLE_PART || c->group_pair_count[g] == 0) continue;
+                int Ht = 0, Wt = 0;
+                for (int p = 0; p < c->group_pair_count[g]; ++p) {
+                    const PairDesc& pd = c->pairs[c->group_pair_base[g] + p];
+                    Ht = std::max(Ht, rl.rows - pd.h0 + 1);
+                    Wt = std::max(Wt, rl.cols - pd.w0 + 1);
+                }
+                if (Ht <= 0 || Wt <= 0) continue;
+                DTItem it{};
+                it.Hp = std::max(pl.rows - hg.h + 1, 0);
+                it.Wp = std::max(pl.cols - hg.w + 1, 0);
+                if (it.Hp == 0 || it.Wp == 0) it.Hp = it.Wp = 0;
+                auto bit = c->blocks.find(BlockKey{i, l - oct, (int)g});
+                it.resp_off = bit == c->blocks.end() ? 0 : bit->second.off;
+                it.r1_off = c->r1_elems;
+                it.Ht = Ht;
+                it.Wt = Wt;
+                it.Hr = rl.rows;
+                it.Wr = rl.cols;
+                it.ng = (int)hg.filters.size();
+                it.np = c->group_pair_count[g];
+                it.pair_base = c->group_pair_base[g];
+                it.map_base = map_base[i][l];
+                c->r1_elems += (int64_t)it.Hp * it.Wt * it.np;
+                c->dt_items.push_back(it);
+            }
+        }
+    }
+    c->row_prefix.clear(); c->col_prefix.clear(); c->asm_prefix.clear();
+    int64_t rb = 0, cb = 0, ab = 0;
+    for (const DTItem& it : c->dt_items) {
+        const int pc = (it.np + 63) / 64;
+        c->row_prefix.push_back((int32_t)rb);
+        c->col_prefix.push_back((int32_t)cb);
+        rb += (int64_t)pc * ((it.Hp + DT_ROWS_PER_BLOCK - 1) / DT_ROWS_PER_BLOCK);
+        cb += (int64_t)pc * ((it.Wt + DT_COLS_PER_BLOCK - 1) / DT_COLS_PER_BLOCK);
+    }
+    for (const MapDesc& md : c->maps) {
+        c->asm_prefix.push_back((int32_t)ab);
+        ab += ((int64_t)md.Ho * md.Wo + ASM_BLOCK - 1) / ASM_BLOCK;
+    }
+    if (rb > INT32_MAX || cb > INT32_MAX || ab > INT32_MAX)
+        return fail(c, DPMT_E_UNSUPPORTED, "batch too large for one launch");
+    c->row_blocks = (int)rb;
+    c->col_blocks = (int)cb;
+    c->asm_blocks = (int)ab;
+
+    dpmt_layout& lay = c->layout;
+    lay = dpmt_layout{};
+    lay.n_score = score_off;
+    lay.n_offsets = offs_off;
+    lay.n_maps = (int32_t)c->maps.size();
+    lay.map_image = c->m_image.data();
+    lay.map_level = c->m_level.data();
+    lay.map_comp = c->m_comp.data();
+    lay.map_rows = c->m_rows.data();
+    lay.map_cols = c->m_cols.data();
+    lay.map_score_off = c->m_score_off.data();
+    lay.map_offs_off = c->m_offs_off.data();
+    lay.n_cells = c->n_cells;
+    lay.n_resp = n_root + n_part;
+    lay.n_resp_root = n_root;
+    lay.n_resp_part = n_part;
+    lay.workspace_bytes = (c->resp_elems + c->dbuf_elems) * 4 + c->r1_elems * 8;
+
+    if (c->has_device()) {
+        auto alloc = [&](void** p, int64_t bytes, const char* what) -> dpmt_status {
+            if (bytes <= 0) return DPMT_OK;
+            hipError_t e = hipMalloc(p, (size_t)bytes);
+            if (e != hipSuccess) return hip_fail(c, e, what);
+            return DPMT_OK;
+        };
+        dpmt_status s;
+        if ((s = alloc((void**)&c->d_resp, c->resp_elems * 4, "allocate responses")) != DPMT_OK) return s;
+        if ((s = alloc((void**)&c->d_r1v, c->r1_elems * 4, "allocate row pass values")) != DPMT_OK) return s;
+        if ((s = alloc((void**)&c->d_r1a, c->r1_elems * 4, "allocate row pass argmax")) != DPMT_OK) return s;
+        if ((s = alloc((void**)&c->d_dbuf, c->dbuf_elems * 4, "allocate part scores")) != DPMT_OK) return s;
+        HIP_TRY(c, upload(&c->d_maps, c->maps), "upload maps");
+        HIP_TRY(c, upload(&c->d_items, c->dt_items), "upload DT items");
+        HIP_TRY(c, upload(&c->d_row_prefix, c->row_prefix), "upload prefix");
+        HIP_TRY(c, upload(&c->d_col_prefix, c->col_prefix), "upload prefix");
+        HIP_TRY(c, upload(&c->d_asm_prefix, c->asm_prefix), "upload prefix");
+    }
+    c->planned = true;
+    *out = &c->layout;
+    c->err.clear();
+    return DPMT_OK;
+}
+
+dpmt_status dpmt_set_profiling(dpmt_ctx* c, int32_t on) {
+    if (!c) return fail(nullptr, DPMT_E_INVALID, "ctx is NULL");
+    if (on && c->has_device() && !c->ev[0]) {
+        (void)hipSetDevice(c->device);
+        for (auto& e : c->ev) HIP_TRY(c, hipEventCreate(&e), "hipEventCreate");
+    }
+    c->prof = on != 0;
+    return DPMT_OK;
+}
+
+int32_t dpmt_stage_times(dpmt_ctx* c, float* ms_out, int32_t n) {
+    if (!c || !ms_out || !c->have_times) return 0;
+    (void)hipSetDevice(c->device);
+    if (hipEventSynchronize(c->ev[5]) != hipSuccess) return 0;
+    float t[6];
+    for (int i = 0; i < 5; ++i)
+        if (hipEventElapsedTime(&t[i], c->ev[i], c->ev[i + 1]) != hipSuccess) return 0;
+    if (hipEventElapsedTime(&t[5], c->ev[0], c->ev[5]) != hipSuccess) return 0;
+    const int m = std::min<int32_t>(n, 6);
+    for (int i = 0; i < m; ++i) ms_out[i] = t[i];
+    return m;
+}
+
+dpmt_status dpmt_score_pyramid(dpmt_ctx* c, dpmt_mode mode, const float* features_dev,
+                               float* scores_dev, int16_t* offsets_dev, void* hip_stream) {
+    if (!c) return fail(nullptr, DPMT_E_INVALID, "ctx is NULL");
+    if (mode < DPMT_DIRECT_FP32 || mode > DPMT_TENSOR_FP8) return fail(c, DPMT_E_INVALID, "unknown mode");
+    if (!c->loaded) return fail(c, DPMT_E_STATE, "dpmt_score_pyramid before dpmt_load_filters");
+    if (mode != DPMT_DIRECT_FP32 && !c->decomposed) return fail(c, DPMT_E_STATE, "tensor mode needs dpmt_decompose first");
+    if (!c->planned) return fail(c, DPMT_E_STATE, "dpmt_score_pyramid before dpmt_plan");
+    if (!c->has_device()) return fail(c, DPMT_E_STATE, "host-only context cannot score");
+    if (!features_dev || (!scores_dev && c->layout.n_score > 0)) return fail(c, DPMT_E_INVALID, "features_dev and scores_dev are required");
+    HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
+    dpmt_status s = prepare_mode(c, mode);
+    if (s != DPMT_OK) return s;
+    if ((s = prepare_tiles(c, mode)) != DPMT_OK) return s;
+    ModeData& md = c->modes[mode];
+    hipStream_t st = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
+    const bool tensor = mode != DPMT_DIRECT_FP32;
+    const void* Zsrc = features_dev;
+    if (tensor) {
+        const size_t need = (size_t)c->n_cells * md.pk.RP * md.pk.esz;
+        if (need > c->Z_bytes) {
+            HIP_TRY(c, hipStreamSynchronize(st), "hipStreamSynchronize");
+            dfree(c->d_Z);
+            c->d_Z = nullptr;
+            c->Z_bytes = 0;
+            HIP_TRY(c, hipMalloc(&c->d_Z, need), "allocate projected features");
+            c->Z_bytes = need;
+        }
+        Zsrc = c->d_Z;
+    }
+    const bool prof = c->prof && c->ev[0];
+    if (prof) HIP_TRY(c, hipEventRecord(c->ev[0], st), "hipEventRecord");
+    if (tensor)
+        HIP_TRY(c, launch_project(md.pk.esz == 2, features_dev, c->n_cells, md.dU, md.pk.RP, c->d_Z, st), "projection launch");
+    if (prof) HIP_TRY(c, hipEventRecord(c->ev[1], st), "hipEventRecord");
+    CorrLaunch cl{md.kind, md.pk, TY, BB, WY};
+    HIP_TRY(c, launch_corr(cl, md.dTiles, md.n_tiles, md.dGroups, Zsrc, md.dG, c->d_resp, md.max_h, md.max_S, st), "correlation launch");
+    if (prof) HIP_TRY(c, hipEventRecord(c->ev[2], st), "hipEventRecord");
+    HIP_TRY(c, launch_dt_row(c->d_items, c->d_row_prefix, (int)c->dt_items.size(), c->row_blocks, c->d_pairs, c->d_resp, c->d_r1v, c->d_r1a, st), "DT row launch");
+    if (prof) HIP_TRY(c, hipEventRecord(c->ev[3], st), "hipEventRecord");
+    HIP_TRY(c, launch_dt_col(c->d_items, c->d_col_prefix, (int)c->dt_items.size(), c->col_blocks, c->d_pairs, c->d_maps, c->d_r1v, c->d_r1a, c->d_dbuf, offsets_dev, st), "DT column launch");
+    if (prof) HIP_TRY(c, hipEventRecord(c->ev[4], st), "hipEventRecord");
+    HIP_TRY(c, launch_assemble(c->d_maps, c->d_asm_prefix, (int)c->maps.size(), c->asm_blocks, c->d_resp, c->d_dbuf, scores_dev, st), "assembly launch");
+    if (prof) HIP_TRY(c, hipEventRecord(c->ev[5], st), "hipEventRecord");
+    c->have_times = prof;
+    return DPMT_OK;
+}
+
+dpmt_status dpmt_level_responses(dpmt_ctx* c, dpmt_mode mode, const float* features_dev,
+                                 int32_t image, int32_t level, float* out_dev, int64_t capacity,
+                                 int64_t* n_written, void* hip_stream) {
+    if (!c) return fail(nullptr, DPMT_E_INVALID, "ctx is NULL");
+    if (mode < DPMT_DIRECT_FP32 || mode > DPMT_TENSOR_FP8) return fail(c, DPMT_E_INVALID, "unknown mode");
+    if (!c->loaded) return fail(c, DPMT_E_STATE, "dpmt_level_responses before dpmt_load_filters");
+    if (mode != DPMT_DIRECT_FP32 && !c->decomposed) return fail(c, DPMT_E_STATE, "tensor mode needs dpmt_decompose first");
+    if (!c->planned) return fail(c, DPMT_E_STATE, "dpmt_level_responses before dpmt_plan");
+    if (!c->has_device()) return fail(c, DPMT_E_STATE, "host-only context cannot compute");
+    if (image < 0 || image >= (int)c->pyr.size()) return fail(c, DPMT_E_INVALID, "image out of range");
+    if (level < 0 || level >= (int)c->pyr[image].size()) return fail(c, DPMT_E_INVALID, "level out of range");
+    if (!features_dev || !out_dev) return fail(c, DPMT_E_INVALID, "features_dev and out_dev are required");
+    const LevelInfo lv = c->pyr[image][level];
+    std::vector<int64_t> map_off(c->shapes.size(), -1);
+    int64_t total = 0;
+    for (size_t k = 0; k < c->shapes.size(); ++k) {
+        const int Ho = lv.rows - c->shapes[k].h + 1, Wo = lv.cols - c->shapes[k].w + 1;
+        if (Ho <= 0 || Wo <= 0) continue;
+        map_off[k] = total;
+        total += (int64_t)Ho * Wo;
+    }
+    if (n_written) *n_written = total;
+    if (capacity < total) return fail(c, DPMT_E_INVALID, "out_dev capacity " + std::to_string(capacity) + " < " + std::to_string(total));
+    HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
+    dpmt_status s = prepare_mode(c, mode);
+    if (s != DPMT_OK) return s;
+    ModeData& md = c->modes[mode];
+    hipStream_t st = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
+    const bool tensor = mode != DPMT_DIRECT_FP32;
+    // per-group blocks in a temporary buffer, then scattered to per-filter maps
+    std::vector<CorrTile> tiles;
+    std::vector<std::pair<int, int64_t>> gblocks;   // (group, block offset)
+    int64_t blk_total = 0;
+    int max_h = 0, max_S = 0;
+    for (size_t g = 0; g < c->groups.size(); ++g) {
+        if (c->groups[g].role != ROLE_ALL) continue;
+        const GroupDesc& gd = md.groups[g];
+        const int Ho = lv.rows - gd.h + 1, Wo = lv.cols - gd.w + 1;
+        if (Ho <= 0 || Wo <= 0) continue;
+        add_tiles(tiles, gd, (int)g, 0, blk_total, lv.rows, lv.cols);
+        gblocks.push_back({(int)g, blk_total});
+        blk_total += (int64_t)Ho * Wo * gd.ng;
+        max_h = std::max(max_h, gd.h);
+        max_S = std::max(max_S, gd.S);
+    }
+    if (tiles.empty()) return DPMT_OK;
+    const int64_t cells = (int64_t)lv.rows * lv.cols;
+    void* dZ = nullptr;
+    float* dblk = nullptr;
+    CorrTile* dtiles = nullptr;
+    int64_t* doff = nullptr;
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(st);
+        dfree(dZ); dfree(dblk); dfree(dtiles); dfree(doff);
+    };
+    hipError_t e = hipSuccess;
+    const void* Zsrc = features_dev + lv.cell_offset * 32;
+    if (tensor) {
+        e = hipMalloc(&dZ, (size_t)cells * md.pk.RP * md.pk.esz);
+        if (e == hipSuccess) e = launch_project(md.pk.esz == 2, features_dev + lv.cell_offset * 32, cells, md.dU, md.pk.RP, dZ, st);
+        Zsrc = dZ;
+    }
+    if (e == hipSuccess) e = hipMalloc((void**)&dblk, (size_t)blk_total * 4);
+    if (e == hipSuccess) e = upload(&dtiles, tiles);
+    CorrLaunch cl{md.kind, md.pk, TY, BB, WY};
+    if (e == hipSuccess) e = launch_corr(cl, dtiles, (int)tiles.size(), md.dGroups, Zsrc, md.dG, dblk, max_h, max_S, st);
+    for (const auto& gb : gblocks) {
+        if (e != hipSuccess) break;
+        const HostGroup& hg = c->groups[gb.first];
+        std::vector<int64_t> dst;
+        for (int k : hg.filters) dst.push_back(map_off[k]);
+        dfree(doff);
+        doff = nullptr;
+        e = hipStreamSynchronize(st);
+        if (e == hipSuccess) e = upload(&doff, dst);
+        const int64_t n_pos = (int64_t)(lv.rows - hg.h + 1) * (lv.cols - hg.w + 1);
+        if (e == hipSuccess) e = launch_block_to_maps(dblk + gb.second, n_pos, (int)hg.filters.size(), doff, out_dev, st);
+    }
+    cleanup();
+    if (e != hipSuccess) return hip_fail(c, e, "level responses");
+    return DPMT_OK;
+}
+
+dpmt_status dpmt_distance_transform(const float* resp_dev, int32_t rows, int32_t cols, int32_t ld,
+                                    const float* deform_host, float* d_dev, int32_t* arg_y_dev,
+                                    int32_t* arg_x_dev, void* hip_stream) {
+    if (!resp_dev || !deform_host || !d_dev) return fail(nullptr, DPMT_E_INVALID, "resp_dev, deform_host and d_dev are required");
+    if (rows < 1 || cols < 1 || ld < cols) return fail(nullptr, DPMT_E_INVALID, "need rows >= 1, cols >= 1, ld >= cols");
+    if ((arg_y_dev == nullptr) != (arg_x_dev == nullptr)) return fail(nullptr, DPMT_E_INVALID, "arg_y_dev and arg_x_dev must both be given or both NULL");
+    for (int t = 0; t < 4; ++t)
+        if (!std::isfinite(deform_host[t])) return fail(nullptr, DPMT_E_INVALID, "non-finite deformation coefficient");
+    if (!(deform_host[1] > 0.f) || !(deform_host[3] > 0.f)) return fail(nullptr, DPMT_E_INVALID, "quadratic deformation coefficients must be > 0");
+    if ((int64_t)rows * cols > (int64_t)1 << 30) return fail(nullptr, DPMT_E_UNSUPPORTED, "map larger than 2^30 cells");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const int64_t n = (int64_t)rows * cols;
+    float* rowmax = nullptr;
+    float* r1v = nullptr;
+    int32_t* r1a = nullptr;
+    hipError_t e = hipMallocAsync((void**)&rowmax, (size_t)std::max(rows, cols) * 4, st);
+    if (e == hipSuccess) e = hipMallocAsync((void**)&r1v, (size_t)n * 4, st);
+    if (e == hipSuccess) e = hipMallocAsync((void**)&r1a, (size_t)n * 4, st);
+    if (e == hipSuccess) e = launch_dt_single(resp_dev, rows, cols, ld, deform_host, rowmax, r1v, r1a, d_dev, arg_y_dev, arg_x_dev, st);
+    if (rowmax) (void)hipFreeAsync(rowmax, st);
+    if (r1v) (void)hipFreeAsync(r1v, st);
+    if (r1a) (void)hipFreeAsync(r1a, st);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "distance transform");
+    return DPMT_OK;
+}
+
+}  // extern "C"

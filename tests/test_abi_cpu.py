@@ -1,0 +1,194 @@
+"""CPU-only checks of the C ABI: the library loads, exports every declared
+symbol, enforces its state machine and argument validation, and its host-side
+FP64 decomposition and planning agree with the oracle.  No GPU calls."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from paper_1707_03268_amd import Context, DpmtError, _abi
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(__file__)), "include", "dpmt.h")
+
+
+def _declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dpmt_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _abi.load()
+    names = _declared_symbols()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_abi.SIGNATURES), "binding and header disagree"
+
+
+def test_status_strings():
+    lib = _abi.load()
+    for s in range(-6, 1):
+        assert lib.dpmt_status_string(s)
+    assert lib.dpmt_status_string(0) == b"ok"
+
+
+def _tiny_bank():
+    wl = workloads.config1()
+    return wl, wl.bank.filters, wl.bank.components
+
+
+def test_state_machine_host_only():
+    wl, fs, comps = _tiny_bank()
+    ctx = Context(device=-1)
+    with pytest.raises(DpmtError) as e:
+        ctx.decompose(4)
+    assert e.value.status == _abi.DPMT_E_STATE
+    with pytest.raises(DpmtError) as e:
+        ctx.plan(wl.pyramids)
+    assert e.value.status == _abi.DPMT_E_STATE
+    ctx.load_filters(fs, comps)
+    lay = ctx.plan(wl.pyramids)
+    assert lay.n_maps == 1
+    # a host-only context plans but never scores
+    lib = _abi.load()
+    st = lib.dpmt_score_pyramid(ctx._h, 0, ctypes.c_void_p(16), ctypes.c_void_p(16), None, None)
+    assert st == _abi.DPMT_E_STATE
+    # tensor mode before decompose
+    ctx2 = Context(device=-1)
+    ctx2.load_filters(fs, comps)
+    ctx2.plan(wl.pyramids)
+    st = lib.dpmt_score_pyramid(ctx2._h, _abi.TENSOR_BF16, ctypes.c_void_p(16), ctypes.c_void_p(16), None, None)
+    assert st == _abi.DPMT_E_STATE
+    assert b"decompose" in lib.dpmt_last_error(ctx2._h)
+
+
+@pytest.mark.parametrize("rank", [0, 33, -1])
+def test_bad_rank(rank):
+    _, fs, comps = _tiny_bank()
+    ctx = Context(device=-1)
+    ctx.load_filters(fs, comps)
+    with pytest.raises(DpmtError) as e:
+        ctx.decompose(rank)
+    assert e.value.status == _abi.DPMT_E_RANK
+
+
+def _comp(root, parts, anchors, deform):
+    class C:
+        pass
+    c = C()
+    c.root, c.parts, c.anchors, c.deform = root, parts, np.array(anchors), np.array(deform, np.float32)
+    return c
+
+
+def test_validation_errors():
+    rng = np.random.default_rng(0)
+    fs = [rng.standard_normal((6, 11, 32)).astype(np.float32), rng.standard_normal((6, 6, 32)).astype(np.float32)]
+    good = _comp(0, [1], [[0, 0]], [[0.1, 0.1, 0.1, 0.1]])
+    ctx = Context(device=-1)
+    ctx.load_filters(fs, [good])
+    bad_cases = [
+        ([_comp(0, [1], [[0, 0]], [[0.1, 0.0, 0.1, 0.1]])], "quadratic"),       # d_xx = 0
+        ([_comp(0, [1], [[0, 0]], [[0.1, 0.1, 0.1, -0.2]])], "quadratic"),      # d_yy < 0
+        ([_comp(0, [1], [[7, 0]], [[0.1, 0.1, 0.1, 0.1]])], "anchor"),          # v_y > 2*6-6
+        ([_comp(0, [1], [[0, 17]], [[0.1, 0.1, 0.1, 0.1]])], "anchor"),         # v_x > 2*11-6
+        ([_comp(0, [1], [[-1, 0]], [[0.1, 0.1, 0.1, 0.1]])], "anchor"),
+        ([_comp(2, [1], [[0, 0]], [[0.1, 0.1, 0.1, 0.1]])], "root"),
+        ([_comp(0, [5], [[0, 0]], [[0.1, 0.1, 0.1, 0.1]])], "part"),
+        ([_comp(0, [1], [[0, 0]], [[np.nan, 0.1, 0.1, 0.1]])], "non-finite"),
+    ]
+    for comps, word in bad_cases:
+        with pytest.raises(DpmtError) as e:
+            ctx.load_filters(fs, comps)
+        assert e.value.status == _abi.DPMT_E_INVALID
+        assert word in str(e.value)
+    nan_fs = [fs[0].copy(), fs[1]]
+    nan_fs[0][1, 2, 3] = np.inf
+    with pytest.raises(DpmtError) as e:
+        ctx.load_filters(nan_fs, [good])
+    assert e.value.status == _abi.DPMT_E_INVALID
+    big = [rng.standard_normal((17, 6, 32)).astype(np.float32), fs[1]]
+    with pytest.raises(DpmtError) as e:
+        ctx.load_filters(big, [good])
+    assert e.value.status == _abi.DPMT_E_UNSUPPORTED
+    # the failed loads left the accepted bank in place
+    ctx.decompose(8)
+
+
+def test_plan_validation():
+    _, fs, comps = _tiny_bank()
+    ctx = Context(device=-1)
+    ctx.load_filters(fs, comps)
+
+    class P:
+        pass
+    p = P()
+    p.levels = [workloads.Level(0, 0, 5)]
+    p.octave = 1
+    with pytest.raises(DpmtError) as e:
+        ctx.plan([p])
+    assert e.value.status == _abi.DPMT_E_INVALID
+    p.levels = [workloads.Level(0, 10, 10)]
+    p.octave = 0
+    with pytest.raises(DpmtError):
+        ctx.plan([p])
+
+
+def test_null_pointer_rejected():
+    lib = _abi.load()
+    assert lib.dpmt_create(None, 0, None) == _abi.DPMT_E_INVALID
+    assert lib.dpmt_load_filters(None, 1, None, None, 1, None) == _abi.DPMT_E_INVALID
+    ctx = Context(device=-1)
+    assert lib.dpmt_load_filters(ctx._h, 1, None, None, 1, None) == _abi.DPMT_E_INVALID
+    d = (ctypes.c_float * 4)(0.1, 0.1, 0.1, 0.1)
+    assert lib.dpmt_distance_transform(None, 4, 4, 4, d, None, None, None, None) == _abi.DPMT_E_INVALID
+    bad = (ctypes.c_float * 4)(0.1, 0.0, 0.1, 0.1)
+    assert lib.dpmt_distance_transform(ctypes.c_void_p(16), 4, 4, 4, bad, ctypes.c_void_p(16), None, None, None) == _abi.DPMT_E_INVALID
+    assert lib.dpmt_distance_transform(ctypes.c_void_p(16), 4, 4, 3, d, ctypes.c_void_p(16), None, None, None) == _abi.DPMT_E_INVALID
+
+
+# ------------------------------------------------------------ host-side parity
+@pytest.mark.parametrize("cfg", [1, 2])
+def test_decompose_matches_oracle(cfg):
+    wl = workloads.PRESETS[cfg]()
+    ctx = Context(device=-1)
+    ctx.load_filters(wl.bank.filters, wl.bank.components)
+    for R in (1, 4, 8, 16, 32):
+        sigma, U = ctx.decompose(R)
+        dec = oracle.decompose(wl.bank.filters, R)
+        np.testing.assert_allclose(sigma, dec.sigma, rtol=1e-10, atol=1e-12 * dec.sigma[0])
+        if dec.gap > 1e-9:      # the subspace is unique only with a gap at R
+            np.testing.assert_allclose(U @ U.T, dec.U @ dec.U.T, atol=1e-10)
+        np.testing.assert_allclose(U.T @ U, np.eye(R), atol=1e-12)
+        # sign convention: largest-magnitude entry of every column positive
+        idx = np.argmax(np.abs(U), axis=0)
+        assert np.all(U[idx, np.arange(R)] > 0)
+
+
+def test_plan_layout_matches_definition():
+    wl = workloads.config2()
+    ctx = Context(device=-1)
+    ctx.load_filters(wl.bank.filters, wl.bank.components)
+    lay = ctx.plan(wl.pyramids)
+    cnt = workloads.count_responses(wl)
+    assert lay.n_resp == cnt["total"] and lay.n_resp_root == cnt["root"] and lay.n_resp_part == cnt["part"]
+    pyr = wl.pyramids[0]
+    L = len(pyr.levels)
+    assert lay.n_maps == (L - pyr.octave) * len(wl.bank.components)
+    off = 0
+    offs = 0
+    for k in range(lay.n_maps):
+        lv = pyr.levels[lay.map_level[k]]
+        comp = wl.bank.components[lay.map_comp[k]]
+        h0, w0 = wl.bank.filters[comp.root].shape[:2]
+        assert lay.map_rows[k] == max(lv.rows - h0 + 1, 0)
+        assert lay.map_cols[k] == max(lv.cols - w0 + 1, 0)
+        assert lay.map_score_off[k] == off and lay.map_offs_off[k] == offs
+        off += lay.map_rows[k] * lay.map_cols[k]
+        offs += lay.map_rows[k] * lay.map_cols[k] * len(comp.parts) * 2
+    assert lay.n_score == off and lay.n_offsets == offs
+    assert lay.n_cells == wl.total_cells
