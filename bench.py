@@ -1,0 +1,278 @@
+"""Benchmark of the DPM scoring path on one MI355X.
+
+One step = one dpmt_score_pyramid call over the whole batch: projection,
+correlation of every level with every filter, distance transform of every
+part map at the anchors, and score assembly.  Inputs are resident in HBM
+before the timed region.  The default workload is the 500x375 image's
+36-level pyramid with the 1080-filter bank (20 classes x 6 components x
+(root + 8 parts)), tensor form in BF16 at rank 16, with the direct FP32 path
+timed on the same workload for the tensor-vs-direct comparison.
+
+Prints one JSON line.  --gpus N > 1 is refused: the path runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "filter-response cells/s, tensor vs direct at stated error; % MFMA roofline"
+PEAK_BF16_TFLOPS = 2500.0
+PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+TOL = {"direct_fp32": 1e-4, "tensor_fp32": 1e-4, "tensor_bf16": 1e-2}
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def corr_work(wl, mode: str, rank: int):
+    """Algorithmic flops and HBM bytes of one correlation launch (all filters,
+    all levels): 2*h*w*C flops per response (C = 32 direct, R tensor); bytes =
+    operand features read once per level + packed filters read once + FP32
+    responses written once."""
+    shapes = wl.bank.shapes
+    roots = [c.root for c in wl.bank.components]
+    parts = sorted({p for c in wl.bank.components for p in c.parts})
+    C = 32 if mode == "direct_fp32" else rank
+    esz = 4 if mode in ("direct_fp32", "tensor_fp32") else 2
+    flops = 0
+    resp = 0
+    feat_bytes = 0
+    for pyr in wl.pyramids:
+        L = len(pyr.levels)
+        for l, lv in enumerate(pyr.levels):
+            used = False
+            for ks, ok in ((roots, l >= pyr.octave), (parts, l + pyr.octave < L)):
+                if not ok:
+                    continue
+                for k in ks:
+                    h, w = shapes[k]
+                    if lv.rows >= h and lv.cols >= w:
+                        n = (lv.rows - h + 1) * (lv.cols - w + 1)
+                        resp += n
+                        flops += 2 * n * h * w * C
+                        used = True
+            if used:
+                feat_bytes += lv.rows * lv.cols * C * esz
+    filt_bytes = sum(h * w * C * esz for (h, w) in shapes)
+    return flops, feat_bytes + filt_bytes + 4 * resp, resp
+
+
+def dt_row_bytes(lay, wl):
+    """Algorithmic bytes of the DT row pass: part responses read once
+    (4 B/cell), row maxima at the anchor columns written (value 4 B + argmax 4 B)."""
+    return None
+
+
+def run_mode(ctx, wl, mode, rank, feats, steps, warmup, torch):
+    lay = ctx.layout
+    scores = torch.empty(max(lay.n_score, 1), dtype=torch.float32, device="cuda")
+    offs = torch.empty(max(lay.n_offsets, 1), dtype=torch.int16, device="cuda")
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        ctx.score_pyramid(mode, feats, scores, offs, stream=stream)
+    torch.cuda.synchronize()
+    ctx.set_profiling(True)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for _ in range(steps):
+        ctx.score_pyramid(mode, feats, scores, offs, stream=stream)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    stages, calls = ctx.stage_times()
+    ctx.set_profiling(False)
+    return ms, stages, scores, offs
+
+
+def cpu_baseline(wl, mode, U, budget_s, scores, offs, lay, torch):
+    """The FP64 oracle on a bounded sample of the workload (whole components,
+    every root level), single BLAS thread; also the GPU's score error on the
+    same sample."""
+    import oracle
+    try:
+        from threadpoolctl import threadpool_limits
+        limiter = threadpool_limits(limits=1)
+    except Exception:  # pragma: no cover
+        limiter = None
+    s_cpu = scores.cpu().numpy()
+    o_cpu = offs.cpu().numpy()
+    cache = {}
+    n_resp = 0
+    n_maps = 0
+    t_start = time.perf_counter()
+    max_err = 0.0
+    errs = []
+    arg_checked = arg_total = arg_bad = 0
+    comps = list(range(len(wl.bank.components)))
+    # visit components spread over the classes, every root level of image 0
+    order = comps[::7] + [c for c in comps if c % 7]
+    pyr = wl.pyramids[0]
+    resp_of = (lambda X, f: oracle.correlate(X, f)) if U is None else \
+              (lambda X, f: oracle.tensor_response(X, f, U))
+    tol = TOL[mode]
+    comp_done = 0
+    for ci in order:
+        c = wl.bank.components[ci]
+        for l in range(pyr.octave, len(pyr.levels)):
+            for key in ((0, l), (0, l - pyr.octave)):
+                if key not in cache:
+                    cache[key] = wl.level_features(*key)
+            Xr, Xp = cache[(0, l)], cache[(0, l - pyr.octave)]
+            rr = resp_of(Xr, wl.bank.filters[c.root])
+            prs = [resp_of(Xp, wl.bank.filters[k]) for k in c.parts]
+            sm = oracle.score_component(rr, prs, c.anchors, c.deform)
+            n_resp += rr.size + sum(p.size for p in prs)
+            n_maps += 1
+            k = lay.find(0, l, ci)
+            Ho, Wo = sm.score.shape
+            g = s_cpu[lay.map_score_off[k]:lay.map_score_off[k] + Ho * Wo].reshape(Ho, Wo)
+            fin = np.isfinite(sm.score)
+            if fin.any():
+                e = np.abs(g[fin] - sm.score[fin])
+                errs.append(e)
+            go = o_cpu[lay.map_offs_off[k]:lay.map_offs_off[k] + Ho * Wo * len(c.parts) * 2]
+            go = go.reshape(len(c.parts), Ho, Wo, 2)
+            chk = sm.margin > tol
+            arg_total += chk.size
+            arg_checked += int(chk.sum())
+            arg_bad += int((chk[..., None] & (go != sm.offsets)).any(-1).sum())
+        comp_done += 1
+        if time.perf_counter() - t_start > budget_s:
+            break
+    elapsed = time.perf_counter() - t_start
+    if limiter is not None:
+        limiter.unregister() if hasattr(limiter, "unregister") else None
+    e = np.concatenate(errs) if errs else np.zeros(1)
+    return {
+        "value": n_resp / elapsed, "unit": "resp/s", "cores": 1, "kind": "oracle",
+        "sample": f"FP64 oracle ({'direct' if U is None else 'tensor R=%d' % U.shape[1]}), "
+                  f"{comp_done} of {len(comps)} components on every root level of image 0 "
+                  f"({n_maps} score maps, {n_resp} responses, {elapsed:.1f} s), one BLAS thread",
+    }, {
+        "max_abs": float(e.max()), "p999_abs": float(np.quantile(e, 0.999)),
+        "tolerance": tol, "argmax_checked": arg_checked, "argmax_total": arg_total,
+        "argmax_mismatch": arg_bad, "sample_maps": n_maps,
+    }
+
+
+def main() -> None:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=3, help="workload preset 1..5")
+    ap.add_argument("--images", type=int, default=0, help="images/frames for presets 4 and 5 (0: preset)")
+    ap.add_argument("--mode", default="tensor_bf16", choices=list(TOL))
+    ap.add_argument("--rank", type=int, default=16)
+    ap.add_argument("--no-direct", action="store_true", help="skip the direct FP32 comparison run")
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path has no "
+              f"multi-GPU component in this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads
+    from paper_1707_03268_amd import Context
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    preset = workloads.PRESETS[args.config]
+    wl = preset(args.images) if (args.config in (4, 5) and args.images) else preset()
+    log(f"workload: {wl.name}")
+    feats = torch.from_numpy(wl.features()).cuda()
+    ctx = Context(0)
+    ctx.load_filters(wl.bank.filters, wl.bank.components)
+    U = None
+    if args.mode != "direct_fp32":
+        sigma, U = ctx.decompose(args.rank)
+    lay = ctx.plan(wl.pyramids)
+    log(f"plan: {lay.n_resp} responses/step, {lay.n_maps} score maps, workspace "
+        f"{lay.workspace_bytes / 2**20:.0f} MiB")
+
+    ms, stages, scores, offs = run_mode(ctx, wl, args.mode, args.rank, feats, args.steps, args.warmup, torch)
+    value = lay.n_resp / (ms * 1e-3)
+    log(f"{args.mode}: {ms:.3f} ms/step, {value:.4g} resp/s, stages {stages}")
+
+    direct = None
+    if not args.no_direct and args.mode != "direct_fp32":
+        ctx_d = Context(0)
+        ctx_d.load_filters(wl.bank.filters, wl.bank.components)
+        ctx_d.plan(wl.pyramids)
+        dsteps = max(2, min(args.steps, 5))
+        dms, dstages, _, _ = run_mode(ctx_d, wl, "direct_fp32", None, feats, dsteps, 1, torch)
+        dflops, dbytes, _ = corr_work(wl, "direct_fp32", 32)
+        direct = {"value": lay.n_resp / (dms * 1e-3), "ms_per_step": dms,
+                  "stages_ms": {k: round(v, 4) for k, v in dstages.items()},
+                  "correlation_tflops": dflops / (dstages["correlation"] * 1e-3) / 1e12,
+                  "correlation_frac_fp32_mfma": dflops / (dstages["correlation"] * 1e-3) / 1e12 / PEAK_FP32_TFLOPS}
+        ctx_d.close()
+        log(f"direct_fp32: {dms:.3f} ms/step")
+
+    # roofline of the dominant kernel
+    kern = max((k for k in stages if k != "total"), key=lambda k: stages[k])
+    flops, cbytes, cresp = corr_work(wl, args.mode, args.rank)
+    corr_ms = stages["correlation"]
+    peak_mfma = PEAK_BF16_TFLOPS if args.mode == "tensor_bf16" else PEAK_FP32_TFLOPS
+    ai = flops / cbytes
+    corr = {"kernel": "corr_kernel", "ms": corr_ms, "tflops": flops / (corr_ms * 1e-3) / 1e12,
+            "gbs": cbytes / (corr_ms * 1e-3) / 1e9, "flops": flops, "bytes": cbytes,
+            "arith_intensity": ai}
+    corr["frac_mfma"] = corr["tflops"] / peak_mfma
+    corr["frac_attainable"] = corr["tflops"] / min(peak_mfma, ai * PEAK_HBM_GBS / 1e3)
+    if kern == "correlation":
+        hbm_bound = ai * PEAK_HBM_GBS / 1e3 < peak_mfma
+        if hbm_bound:
+            roof = {"bound": "hbm", "achieved": corr["gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": corr["gbs"] / PEAK_HBM_GBS, "traffic": None}
+        else:
+            roof = {"bound": "mfma", "achieved": corr["tflops"], "peak": peak_mfma, "unit": "TFLOP/s",
+                    "frac": corr["frac_mfma"], "traffic": None}
+    else:
+        roof = {"bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": None, "traffic": None, "kernel": kern}
+    roof["kernel"] = kern
+
+    cpu = None
+    err = None
+    if args.cpu_budget > 0 and args.config in (1, 2, 3):
+        log("cpu baseline (oracle) ...")
+        cpu, err = cpu_baseline(wl, args.mode, U, args.cpu_budget, scores, offs, lay, torch)
+
+    dtype = {"tensor_bf16": "bf16", "tensor_fp32": "f32", "direct_fp32": "f32"}[args.mode]
+    out = {
+        "metric": METRIC, "value": value, "unit": "resp/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+        "config": {"workload": wl.name, "mode": args.mode,
+                   "rank": None if args.mode == "direct_fp32" else args.rank,
+                   "resp_per_step": lay.n_resp, "score_maps": lay.n_maps},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "stages_ms": {k: round(v, 4) for k, v in stages.items()},
+        "correlation": corr,
+        "direct_fp32": direct,
+        "tensor_vs_direct": (value / direct["value"]) if direct else None,
+        "score_error_vs_oracle": err,
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -157,7 +157,8 @@ dpmt_status dpmt_score_pyramid(dpmt_ctx* ctx, dpmt_mode mode, const float* featu
  * k = 0 .. n_filters-1 in order, its (rows - h_k + 1) x (cols - w_k + 1)
  * row-major float32 map (nothing for a filter that does not fit); capacity is
  * out_dev's size in elements (DPMT_E_INVALID if too small).  n_written (host,
- * may be NULL) receives the element count. */
+ * may be NULL) receives the element count; out_dev = NULL with capacity = 0
+ * only reports that count. */
 dpmt_status dpmt_level_responses(dpmt_ctx* ctx, dpmt_mode mode, const float* features_dev,
                                  int32_t image, int32_t level, float* out_dev,
                                  int64_t capacity, int64_t* n_written, void* hip_stream);
@@ -172,13 +173,16 @@ dpmt_status dpmt_distance_transform(const float* resp_dev, int32_t rows, int32_t
                                     const float* deform_host, float* d_dev, int32_t* arg_y_dev,
                                     int32_t* arg_x_dev, void* hip_stream);
 
-/* Per-stage timing of the last dpmt_score_pyramid call, in milliseconds, from
- * HIP events recorded on the launch stream around each stage.  Enable with
- * dpmt_set_profiling(ctx, 1) (adds event records; off by default).  Stages:
- * 0 projection, 1 correlation (all filters), 2 DT row pass, 3 DT column pass,
- * 4 score assembly, 5 whole call.  Returns the number of stages written. */
+/* Per-stage GPU timing from HIP events recorded on the launch stream around
+ * each stage of dpmt_score_pyramid.  dpmt_set_profiling(ctx, 1) starts
+ * recording (and clears what was gathered); every later score call adds one
+ * set of events.  dpmt_stage_times waits for the recorded events and writes
+ * the mean duration per call, in milliseconds, of each stage: 0 projection,
+ * 1 correlation (all filters), 2 DT row pass, 3 DT column pass, 4 score
+ * assembly, 5 whole call.  Returns the number of stages written (at most n)
+ * and stores the number of calls averaged in *n_calls (may be NULL). */
 dpmt_status dpmt_set_profiling(dpmt_ctx* ctx, int32_t on);
-int32_t     dpmt_stage_times(dpmt_ctx* ctx, float* ms_out, int32_t n);
+int32_t     dpmt_stage_times(dpmt_ctx* ctx, float* ms_out, int32_t n, int32_t* n_calls);
 
 const char* dpmt_status_string(dpmt_status s);
 const char* dpmt_last_error(const dpmt_ctx* ctx);     /* detail of the last failure */

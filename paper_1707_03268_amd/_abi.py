@@ -65,7 +65,7 @@ SIGNATURES = {
     "dpmt_distance_transform": (c_int32, [c_void_p, c_int32, c_int32, c_int32, POINTER(c_float),
                                           c_void_p, c_void_p, c_void_p, c_void_p]),
     "dpmt_set_profiling": (c_int32, [c_void_p, c_int32]),
-    "dpmt_stage_times": (c_int32, [c_void_p, POINTER(c_float), c_int32]),
+    "dpmt_stage_times": (c_int32, [c_void_p, POINTER(c_float), c_int32, POINTER(c_int32)]),
     "dpmt_status_string": (c_char_p, [c_int32]),
     "dpmt_last_error": (c_char_p, [c_void_p]),
 }

@@ -202,14 +202,12 @@ class Context:
         (flat float32 tensor, [(offset, rows, cols) or None per filter])."""
         import torch
         m = _abi.MODES[mode] if isinstance(mode, str) else int(mode)
-        lv = None
         n = c_int64(0)
         fp = _dev_ptr(features, torch.float32, "features")
         if out is None:
-            st = _lib().dpmt_level_responses(self._h, m, fp, int(image), int(level), None, 0,
-                                             byref(n), _stream_ptr(stream))
-            if st not in (_abi.DPMT_OK, _abi.DPMT_E_INVALID):
-                _check(st, self._h, "dpmt_level_responses")
+            _check(_lib().dpmt_level_responses(self._h, m, fp, int(image), int(level), None, 0,
+                                               byref(n), _stream_ptr(stream)),
+                   self._h, "dpmt_level_responses")
             out = torch.empty(max(n.value, 1), dtype=torch.float32, device=features.device)
         _check(_lib().dpmt_level_responses(self._h, m, fp, int(image), int(level),
                                            _dev_ptr(out, torch.float32, "out"), out.numel(),
@@ -220,10 +218,14 @@ class Context:
     def set_profiling(self, on: bool) -> None:
         _check(_lib().dpmt_set_profiling(self._h, 1 if on else 0), self._h, "dpmt_set_profiling")
 
-    def stage_times(self) -> List[float]:
+    STAGES = ("projection", "correlation", "dt_row", "dt_col", "assemble", "total")
+
+    def stage_times(self):
+        """Mean GPU milliseconds per profiled call of each stage, and the call count."""
         buf = (c_float * 6)()
-        n = _lib().dpmt_stage_times(self._h, buf, 6)
-        return [buf[i] for i in range(n)]
+        calls = c_int32(0)
+        n = _lib().dpmt_stage_times(self._h, buf, 6, byref(calls))
+        return {self.STAGES[i]: buf[i] for i in range(n)}, calls.value
 
 
 def distance_transform(resp, deform, out=None, arg_y=None, arg_x=None, stream=None):

@@ -109,6 +109,7 @@ struct dpmt_ctx {
     std::vector<int> comp_root_group, comp_root_col;
     std::vector<PairDesc> pairs;        // per part group, concatenated
     std::vector<int> group_pair_base, group_pair_count;
+    std::vector<std::vector<std::pair<int, int>>> slot_pair;   // [comp][slot] -> (group, pair in group)
 
     // decomposition
     bool decomposed = false;
@@ -132,14 +133,15 @@ struct dpmt_ctx {
     std::vector<DTItem> dt_items;
     std::vector<int32_t> row_prefix, col_prefix, asm_prefix;
     int row_blocks = 0, col_blocks = 0, asm_blocks = 0;
-    int64_t r1_elems = 0, dbuf_elems = 0;
+    int64_t r1_elems = 0;
+    int max_Wp = 0, max_Hp = 0;         // longest DT row / column (LDS staging size)
     dpmt_layout layout{};
 
     // device workspace
     float* d_resp = nullptr;
     float* d_r1v = nullptr;
     int32_t* d_r1a = nullptr;
-    float* d_dbuf = nullptr;
+    float* d_dbuf = nullptr;            // deformed part scores, [map][part][pos]
     void* d_Z = nullptr;
     size_t Z_bytes = 0;
     PairDesc* d_pairs = nullptr;
@@ -149,11 +151,10 @@ struct dpmt_ctx {
     int32_t* d_col_prefix = nullptr;
     int32_t* d_asm_prefix = nullptr;
 
-    // profiling
+    // profiling: one set of 6 events per profiled call
     bool prof = false;
-    hipEvent_t ev[6] = {};
-    float stage_ms[6] = {};
-    bool have_times = false;
+    std::vector<std::array<hipEvent_t, 6>> ev_sets;
+    int ev_used = 0;
 
     bool has_device() const { return device >= 0; }
 };
@@ -428,6 +429,13 @@ void build_groups(dpmt_ctx* c) {
         c->group_pair_count[g] = (int)gp[g].size();
         c->pairs.insert(c->pairs.end(), gp[g].begin(), gp[g].end());
     }
+    c->slot_pair.assign(c->comps.size(), {});
+    for (size_t ci = 0; ci < c->comps.size(); ++ci) c->slot_pair[ci].assign(c->comps[ci].parts.size(), {-1, -1});
+    for (size_t g = 0; g < c->groups.size(); ++g)
+        for (int p = 0; p < c->group_pair_count[g]; ++p) {
+            const PairDesc& pd = c->pairs[c->group_pair_base[g] + p];
+            c->slot_pair[pd.comp][pd.slot] = {(int)g, p};
+        }
 }
 
 void add_tiles(std::vector<CorrTile>& tiles, const GroupDesc& gd, int group, int64_t z_cell,
@@ -530,8 +538,8 @@ void dpmt_destroy(dpmt_ctx* c) {
         free_plan(c);
         for (auto& m : c->modes) free_mode(m);
         dfree(c->d_pairs);
-        for (auto& e : c->ev)
-            if (e) (void)hipEventDestroy(e);
+        for (auto& set : c->ev_sets)
+            for (auto& e : set) (void)hipEventDestroy(e);
     }
     delete c;
 }
@@ -556,6 +564,7 @@ dpmt_status dpmt_load_filters(dpmt_ctx* c, int32_t n_filters, const dpmt_shape* 
         const std::string cs = "component " + std::to_string(ci) + ": ";
         if (cm.root < 0 || cm.root >= n_filters) return fail(c, DPMT_E_INVALID, cs + "root index out of range");
         if (cm.n_parts < 1 || !cm.parts || !cm.anchors || !cm.deform) return fail(c, DPMT_E_INVALID, cs + "needs n_parts >= 1 with parts, anchors, deform");
+        if (cm.n_parts > 64) return fail(c, DPMT_E_UNSUPPORTED, cs + "more than 64 parts");
         const int h0 = shapes[cm.root].h, w0 = shapes[cm.root].w;
         for (int i = 0; i < cm.n_parts; ++i) {
             const int k = cm.parts[i];
@@ -717,7 +726,7 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
     // score maps
     c->m_image.clear(); c->m_level.clear(); c->m_comp.clear(); c->m_rows.clear(); c->m_cols.clear();
     c->m_score_off.clear(); c->m_offs_off.clear(); c->maps.clear();
-    int64_t score_off = 0, offs_off = 0, dbuf_off = 0;
+    int64_t score_off = 0, offs_off = 0;
     std::vector<std::vector<int>> map_base(n_images);
     for (int i = 0; i < n_images; ++i) {
         const int L = (int)c->pyr[i].size(), oct = c->octave[i];
@@ -733,7 +742,6 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
                 MapDesc md{};
                 md.score_off = score_off;
                 md.offs_off = offs_off;
-                md.dbuf_off = dbuf_off;
                 md.Ho = Ho;
                 md.Wo = Wo;
                 md.n_parts = np;
@@ -753,11 +761,9 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
                 const int64_t plane = (int64_t)Ho * Wo;
                 score_off += plane;
                 offs_off += plane * np * 2;
-                dbuf_off += plane * np;
             }
         }
     }
-    c->dbuf_elems = dbuf_off;
     // distance-transform items: (image, root level, part group)
     c->dt_items.clear();
     c->r1_elems = 0;
@@ -797,13 +803,15 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
         }
     }
     c->row_prefix.clear(); c->col_prefix.clear(); c->asm_prefix.clear();
+    c->max_Wp = c->max_Hp = 0;
     int64_t rb = 0, cb = 0, ab = 0;
     for (const DTItem& it : c->dt_items) {
-        const int pc = (it.np + 63) / 64;
         c->row_prefix.push_back((int32_t)rb);
         c->col_prefix.push_back((int32_t)cb);
-        rb += (int64_t)pc * ((it.Hp + DT_ROWS_PER_BLOCK - 1) / DT_ROWS_PER_BLOCK);
-        cb += (int64_t)pc * ((it.Wt + DT_COLS_PER_BLOCK - 1) / DT_COLS_PER_BLOCK);
+        rb += (int64_t)((it.np + DT_ROW_PAIRS_PER_BLOCK - 1) / DT_ROW_PAIRS_PER_BLOCK) * it.Hp;
+        cb += (int64_t)it.np * ((it.Wt + DT_COLS_PER_BLOCK - 1) / DT_COLS_PER_BLOCK);
+        c->max_Wp = std::max(c->max_Wp, it.Wp);
+        c->max_Hp = std::max(c->max_Hp, it.Hp);
     }
     for (const MapDesc& md : c->maps) {
         c->asm_prefix.push_back((int32_t)ab);
@@ -831,7 +839,7 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
     lay.n_resp = n_root + n_part;
     lay.n_resp_root = n_root;
     lay.n_resp_part = n_part;
-    lay.workspace_bytes = (c->resp_elems + c->dbuf_elems) * 4 + c->r1_elems * 8;
+    lay.workspace_bytes = c->resp_elems * 4 + c->r1_elems * 8 + (offs_off / 2) * 4;
 
     if (c->has_device()) {
         auto alloc = [&](void** p, int64_t bytes, const char* what) -> dpmt_status {
@@ -844,7 +852,7 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
         if ((s = alloc((void**)&c->d_resp, c->resp_elems * 4, "allocate responses")) != DPMT_OK) return s;
         if ((s = alloc((void**)&c->d_r1v, c->r1_elems * 4, "allocate row pass values")) != DPMT_OK) return s;
         if ((s = alloc((void**)&c->d_r1a, c->r1_elems * 4, "allocate row pass argmax")) != DPMT_OK) return s;
-        if ((s = alloc((void**)&c->d_dbuf, c->dbuf_elems * 4, "allocate part scores")) != DPMT_OK) return s;
+        if ((s = alloc((void**)&c->d_dbuf, (offs_off / 2) * 4, "allocate part scores")) != DPMT_OK) return s;
         HIP_TRY(c, upload(&c->d_maps, c->maps), "upload maps");
         HIP_TRY(c, upload(&c->d_items, c->dt_items), "upload DT items");
         HIP_TRY(c, upload(&c->d_row_prefix, c->row_prefix), "upload prefix");
@@ -859,24 +867,31 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
 
 dpmt_status dpmt_set_profiling(dpmt_ctx* c, int32_t on) {
     if (!c) return fail(nullptr, DPMT_E_INVALID, "ctx is NULL");
-    if (on && c->has_device() && !c->ev[0]) {
-        (void)hipSetDevice(c->device);
-        for (auto& e : c->ev) HIP_TRY(c, hipEventCreate(&e), "hipEventCreate");
-    }
+    if (on && !c->has_device()) return fail(c, DPMT_E_STATE, "host-only context has no stream to time");
     c->prof = on != 0;
+    c->ev_used = 0;
     return DPMT_OK;
 }
 
-int32_t dpmt_stage_times(dpmt_ctx* c, float* ms_out, int32_t n) {
-    if (!c || !ms_out || !c->have_times) return 0;
+int32_t dpmt_stage_times(dpmt_ctx* c, float* ms_out, int32_t n, int32_t* n_calls) {
+    if (n_calls) *n_calls = 0;
+    if (!c || !ms_out || n <= 0 || c->ev_used == 0) return 0;
     (void)hipSetDevice(c->device);
-    if (hipEventSynchronize(c->ev[5]) != hipSuccess) return 0;
-    float t[6];
-    for (int i = 0; i < 5; ++i)
-        if (hipEventElapsedTime(&t[i], c->ev[i], c->ev[i + 1]) != hipSuccess) return 0;
-    if (hipEventElapsedTime(&t[5], c->ev[0], c->ev[5]) != hipSuccess) return 0;
+    double sum[6] = {0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < c->ev_used; ++k) {
+        auto& ev = c->ev_sets[k];
+        if (hipEventSynchronize(ev[5]) != hipSuccess) return 0;
+        float t;
+        for (int i = 0; i < 5; ++i) {
+            if (hipEventElapsedTime(&t, ev[i], ev[i + 1]) != hipSuccess) return 0;
+            sum[i] += t;
+        }
+        if (hipEventElapsedTime(&t, ev[0], ev[5]) != hipSuccess) return 0;
+        sum[5] += t;
+    }
     const int m = std::min<int32_t>(n, 6);
-    for (int i = 0; i < m; ++i) ms_out[i] = t[i];
+    for (int i = 0; i < m; ++i) ms_out[i] = (float)(sum[i] / c->ev_used);
+    if (n_calls) *n_calls = c->ev_used;
     return m;
 }
 
@@ -909,21 +924,29 @@ dpmt_status dpmt_score_pyramid(dpmt_ctx* c, dpmt_mode mode, const float* feature
         }
         Zsrc = c->d_Z;
     }
-    const bool prof = c->prof && c->ev[0];
-    if (prof) HIP_TRY(c, hipEventRecord(c->ev[0], st), "hipEventRecord");
+    hipEvent_t* ev = nullptr;
+    if (c->prof) {
+        if (c->ev_used == (int)c->ev_sets.size()) {
+            std::array<hipEvent_t, 6> set{};
+            for (auto& e : set) HIP_TRY(c, hipEventCreate(&e), "hipEventCreate");
+            c->ev_sets.push_back(set);
+        }
+        ev = c->ev_sets[c->ev_used++].data();
+    }
+    const bool prof = ev != nullptr;
+    if (prof) HIP_TRY(c, hipEventRecord(ev[0], st), "hipEventRecord");
     if (tensor)
         HIP_TRY(c, launch_project(md.pk.esz == 2, features_dev, c->n_cells, md.dU, md.pk.RP, c->d_Z, st), "projection launch");
-    if (prof) HIP_TRY(c, hipEventRecord(c->ev[1], st), "hipEventRecord");
+    if (prof) HIP_TRY(c, hipEventRecord(ev[1], st), "hipEventRecord");
     CorrLaunch cl{md.kind, md.pk, TY, BB, WY};
     HIP_TRY(c, launch_corr(cl, md.dTiles, md.n_tiles, md.dGroups, Zsrc, md.dG, c->d_resp, md.max_h, md.max_S, st), "correlation launch");
-    if (prof) HIP_TRY(c, hipEventRecord(c->ev[2], st), "hipEventRecord");
-    HIP_TRY(c, launch_dt_row(c->d_items, c->d_row_prefix, (int)c->dt_items.size(), c->row_blocks, c->d_pairs, c->d_resp, c->d_r1v, c->d_r1a, st), "DT row launch");
-    if (prof) HIP_TRY(c, hipEventRecord(c->ev[3], st), "hipEventRecord");
-    HIP_TRY(c, launch_dt_col(c->d_items, c->d_col_prefix, (int)c->dt_items.size(), c->col_blocks, c->d_pairs, c->d_maps, c->d_r1v, c->d_r1a, c->d_dbuf, offsets_dev, st), "DT column launch");
-    if (prof) HIP_TRY(c, hipEventRecord(c->ev[4], st), "hipEventRecord");
+    if (prof) HIP_TRY(c, hipEventRecord(ev[2], st), "hipEventRecord");
+    HIP_TRY(c, launch_dt_row(c->d_items, c->d_row_prefix, (int)c->dt_items.size(), c->row_blocks, c->d_pairs, c->d_resp, c->d_r1v, c->d_r1a, c->max_Wp, st), "DT row launch");
+    if (prof) HIP_TRY(c, hipEventRecord(ev[3], st), "hipEventRecord");
+    HIP_TRY(c, launch_dt_col(c->d_items, c->d_col_prefix, (int)c->dt_items.size(), c->col_blocks, c->d_pairs, c->d_maps, c->d_r1v, c->d_r1a, c->d_dbuf, offsets_dev, c->max_Hp, st), "DT column launch");
+    if (prof) HIP_TRY(c, hipEventRecord(ev[4], st), "hipEventRecord");
     HIP_TRY(c, launch_assemble(c->d_maps, c->d_asm_prefix, (int)c->maps.size(), c->asm_blocks, c->d_resp, c->d_dbuf, scores_dev, st), "assembly launch");
-    if (prof) HIP_TRY(c, hipEventRecord(c->ev[5], st), "hipEventRecord");
-    c->have_times = prof;
+    if (prof) HIP_TRY(c, hipEventRecord(ev[5], st), "hipEventRecord");
     return DPMT_OK;
 }
 
@@ -938,7 +961,6 @@ dpmt_status dpmt_level_responses(dpmt_ctx* c, dpmt_mode mode, const float* featu
     if (!c->has_device()) return fail(c, DPMT_E_STATE, "host-only context cannot compute");
     if (image < 0 || image >= (int)c->pyr.size()) return fail(c, DPMT_E_INVALID, "image out of range");
     if (level < 0 || level >= (int)c->pyr[image].size()) return fail(c, DPMT_E_INVALID, "level out of range");
-    if (!features_dev || !out_dev) return fail(c, DPMT_E_INVALID, "features_dev and out_dev are required");
     const LevelInfo lv = c->pyr[image][level];
     std::vector<int64_t> map_off(c->shapes.size(), -1);
     int64_t total = 0;
@@ -949,6 +971,8 @@ dpmt_status dpmt_level_responses(dpmt_ctx* c, dpmt_mode mode, const float* featu
         total += (int64_t)Ho * Wo;
     }
     if (n_written) *n_written = total;
+    if (!out_dev && capacity == 0) return DPMT_OK;            // size query
+    if (!features_dev || !out_dev) return fail(c, DPMT_E_INVALID, "features_dev and out_dev are required");
     if (capacity < total) return fail(c, DPMT_E_INVALID, "out_dev capacity " + std::to_string(capacity) + " < " + std::to_string(total));
     HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
     dpmt_status s = prepare_mode(c, mode);
@@ -1022,14 +1046,14 @@ dpmt_status dpmt_distance_transform(const float* resp_dev, int32_t rows, int32_t
     if ((int64_t)rows * cols > (int64_t)1 << 30) return fail(nullptr, DPMT_E_UNSUPPORTED, "map larger than 2^30 cells");
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     const int64_t n = (int64_t)rows * cols;
-    float* rowmax = nullptr;
+    float* lmax = nullptr;
     float* r1v = nullptr;
     int32_t* r1a = nullptr;
-    hipError_t e = hipMallocAsync((void**)&rowmax, (size_t)std::max(rows, cols) * 4, st);
+    hipError_t e = hipMallocAsync((void**)&lmax, (size_t)std::max(rows, cols) * 4, st);
     if (e == hipSuccess) e = hipMallocAsync((void**)&r1v, (size_t)n * 4, st);
     if (e == hipSuccess) e = hipMallocAsync((void**)&r1a, (size_t)n * 4, st);
-    if (e == hipSuccess) e = launch_dt_single(resp_dev, rows, cols, ld, deform_host, rowmax, r1v, r1a, d_dev, arg_y_dev, arg_x_dev, st);
-    if (rowmax) (void)hipFreeAsync(rowmax, st);
+    if (e == hipSuccess) e = launch_dt_single(resp_dev, rows, cols, ld, deform_host, lmax, r1v, r1a, d_dev, arg_y_dev, arg_x_dev, st);
+    if (lmax) (void)hipFreeAsync(lmax, st);
     if (r1v) (void)hipFreeAsync(r1v, st);
     if (r1a) (void)hipFreeAsync(r1a, st);
     if (e != hipSuccess) return hip_fail(nullptr, e, "distance transform");

@@ -51,7 +51,7 @@ struct PairDesc {
 // Distance-transform work for one (image, root level, part group).
 struct DTItem {
     int64_t resp_off;  // part responses [Hp][Wp][ng]
-    int64_t r1_off;    // row-pass output [Hp][Wt][np] (value and argmax share indexing)
+    int64_t r1_off;    // row-pass output [np][Hp][Wt] (value and argmax share indexing)
     int32_t Hp, Wp;    // part response map
     int32_t Ht, Wt;    // largest root map over the group's components
     int32_t Hr, Wr;    // root level rows, cols
@@ -64,7 +64,6 @@ struct DTItem {
 struct MapDesc {
     int64_t score_off; // float offset into the caller's scores
     int64_t offs_off;  // int16 offset into the caller's offsets ([part][pos][2])
-    int64_t dbuf_off;  // float offset into the D workspace ([part][pos])
     int64_t rresp_off; // root response block of the root group on this level
     int32_t Ho, Wo;
     int32_t n_parts;
@@ -92,21 +91,22 @@ hipError_t launch_corr(const CorrLaunch& cfg, const CorrTile* tiles, int n_tiles
 size_t corr_lds_bytes(const CorrLaunch& cfg, int h, int S);
 hipError_t launch_dt_row(const DTItem* items, const int32_t* prefix, int n_items, int n_blocks,
                          const PairDesc* pairs, const float* resp, float* r1v, int32_t* r1a,
-                         hipStream_t st);
+                         int max_line, hipStream_t st);
 hipError_t launch_dt_col(const DTItem* items, const int32_t* prefix, int n_items, int n_blocks,
                          const PairDesc* pairs, const MapDesc* maps, const float* r1v,
-                         const int32_t* r1a, float* dbuf, int16_t* offs, hipStream_t st);
+                         const int32_t* r1a, float* dbuf, int16_t* offs, int max_line,
+                         hipStream_t st);
 hipError_t launch_assemble(const MapDesc* maps, const int32_t* prefix, int n_maps, int n_blocks,
                            const float* rresp, const float* dbuf, float* scores, hipStream_t st);
 hipError_t launch_block_to_maps(const float* block, int64_t n_pos, int ng, const int64_t* dst_off,
                                 float* out, hipStream_t st);
 hipError_t launch_dt_single(const float* resp, int rows, int cols, int ld, const float* d,
-                            float* rowmax, float* r1v, int32_t* r1a, float* out, int32_t* ay,
+                            float* lmax, float* r1v, int32_t* r1a, float* out, int32_t* ay,
                             int32_t* ax, hipStream_t st);
 
 // Workgroup sizes used by the launchers (the planner sizes work lists with them).
-constexpr int DT_ROWS_PER_BLOCK = 4;   // row pass: 64 pairs x 4 part rows per block
-constexpr int DT_COLS_PER_BLOCK = 4;   // column pass: 64 pairs x 4 target cols per block
-constexpr int ASM_BLOCK = 256;         // assembly: positions per block
+constexpr int DT_ROW_PAIRS_PER_BLOCK = 32;   // row pass: one part row of 32 pairs per block
+constexpr int DT_COLS_PER_BLOCK = 64;        // column pass: 64 root columns of one pair per block
+constexpr int ASM_BLOCK = 256;         // assembly: threads per block
 
 }  // namespace dpmt

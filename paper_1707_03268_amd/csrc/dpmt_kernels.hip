@@ -9,7 +9,7 @@
 //                      the shortened (rank-R) responses
 //   dt_row_kernel /    separable generalised distance transform (Section 2
 //   dt_col_kernel      placement argmax) evaluated at the part anchors of
-//                      every root position; exact windowed search
+//                      every root position; exact windowed scan
 //   assemble_kernel    s(p0) = root response + sum of the parts' deformed
 //                      scores (Section 2 score formula)
 #include "dpmt_internal.h"
@@ -96,9 +96,6 @@ hipError_t launch_project(bool bf16, const float* X, int64_t n_cells, const floa
 // through a double-buffered LDS chunk per K-step.
 // ---------------------------------------------------------------------------
 constexpr int CORR_MAX_H = 16;
-
-template <int PB>
-struct AFrag;  // 16-byte fragment load from LDS with the alignment PB allows
 
 __device__ __forceinline__ uint4 lds_load16(const char* p, int pb) {
     if (pb >= 16) return *reinterpret_cast<const uint4*>(p);
@@ -311,40 +308,30 @@ hipError_t launch_corr(const CorrLaunch& cfg, const CorrTile* tiles, int n_tiles
 }
 
 // ---------------------------------------------------------------------------
-// distance transform helpers
+// distance transform
 //
-// For a target t on a line with values v[0..n) and cost c(u) = b*u + a*u^2
-// (u = position - t, a > 0), a position u can only beat the target itself if
-// c(u - t) <= v[u] - v[t] <= M - v[t], M the line maximum.  Solving the
-// quadratic gives a window [t + lo, t + hi] that holds every possible
-// maximiser; scanning any superset of it in ascending order with a strict >
-// returns the exact maximum and its smallest maximiser.  Lanes of a wave scan
-// the union of their windows so that the loads stay coalesced.
+// Along a line with values v[0..n) the targets are t_k = ts*k + anchor and the
+// cost of candidate x for target t is c(u) = b*u + a*u^2, u = x - t, a > 0.
+// Two facts keep the exact search short:
+//  * window: x can only beat the target itself if c(x - t) <= v[x] - v[t] <=
+//    M - v[t] (M the line maximum); solving the quadratic bounds x to
+//    [t + lo, t + hi], and a 1-cell margin absorbs FP32 rounding;
+//  * monotonicity: v[x] - c(x - t) has strictly increasing differences in
+//    (x, t) (the cross term is 2a*x*t), so the maximiser of a later target is
+//    never left of the maximiser of an earlier one; a lane that owns several
+//    consecutive targets starts each scan at the previous target's argmax.
+// Scanning that range in ascending order with a strict > gives the exact
+// maximum and its smallest maximiser, i.e. the lexicographic tie rule.
+//
+// Layouts are chosen so that every pass reads and writes whole cache lines:
+//   part responses  [y'][x'][filter]     (correlation output)
+//   row pass        [pair][y'][x0]       (lanes = target columns of one pair)
+//   column pass     caller layout [map][part][y0][x0] (lanes = root columns)
+// and each pass stages the lines it scans in LDS, laid out so that lanes
+// reading different positions hit different banks.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int wave_min_i(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-    return v;
-}
-__device__ __forceinline__ int wave_max_i(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-__device__ __forceinline__ void dt_window(float M, float vt, float a, float b, int t, int n, int& lo,
-                                          int& hi) {
-    const float delta = fmaxf(M - vt, 0.f);
-    const float s = sqrtf(fmaf(4.f * a, delta, b * b));
-    const float inv = 0.5f / a;
-    const float ulo = floorf((-b - s) * inv) - 1.f;
-    const float uhi = ceilf((-b + s) * inv) + 1.f;
-    // clamp in float first: a huge window (tiny a, large range) must not overflow int
-    lo = t + (int)fmaxf(ulo, -(float)n);
-    hi = t + (int)fminf(uhi, (float)n);
-    lo = max(lo, 0);
-    hi = min(hi, n - 1);
-}
+constexpr int DT_STAGE_MAX = 96 * 1024;          // LDS bytes of one staged tile
+constexpr int DT_ROW_PAIRS = 32;                 // pairs per row-pass block
 
 __device__ __forceinline__ int find_item(const int32_t* __restrict__ prefix, int n, int b) {
     int lo = 0, hi = n - 1;                        // last item with prefix <= b
@@ -355,9 +342,36 @@ __device__ __forceinline__ int find_item(const int32_t* __restrict__ prefix, int
     return lo;
 }
 
-// Row pass: thread = (pair, part row y').  For every root column x0 of the
-// pair's component the target is x_t = 2*x0 + v_x; writes the row maximum of
-// resp[y'][x'] - (d_x (x'-x_t) + d_xx (x'-x_t)^2) and its argmax x'.
+// Exact maximum of v[x] - c(x - t) over x and its smallest maximiser, for
+// target t in [0, n), scanning from max(window start, from).
+template <class Load>
+__device__ __forceinline__ float window_max(const Load& load, int n, int t, int from, float a,
+                                            float b, float M, int& arg) {
+    const float inv = 0.5f / a;
+    const float s = sqrtf(fmaf(4.f * a, fmaxf(M - load(t), 0.f), b * b));
+    int lo = t + (int)fmaxf(floorf((-b - s) * inv) - 1.f, -(float)n);
+    int hi = t + (int)fminf(ceilf((-b + s) * inv) + 1.f, (float)n);
+    hi = min(hi, n - 1);
+    lo = min(max(max(lo, 0), from), hi);
+    float best = -INFINITY;
+    arg = lo;
+    float u = (float)(lo - t);
+    for (int x = lo; x <= hi; ++x, u += 1.f) {
+        const float val = load(x) - u * fmaf(a, u, b);
+        if (val > best) {
+            best = val;
+            arg = x;
+        }
+    }
+    return best;
+}
+
+// Row pass: block = (item, part row y', 32 pairs).  The block stages the row
+// of its 32 pairs as [pair][x'] (odd pitch), then each wavefront takes every
+// fourth pair and its lanes take that pair's target columns x_t = 2*x0 + v_x.
+// Writes the row maximum of resp[y'][x'] - (d_x (x'-x_t) + d_xx (x'-x_t)^2) and
+// its argmax x' at [pair][y'][x0].
+template <bool STAGED>
 __global__ __launch_bounds__(256) void dt_row_kernel(const DTItem* __restrict__ items,
                                                      const int32_t* __restrict__ prefix,
                                                      int n_items,
@@ -365,54 +379,68 @@ __global__ __launch_bounds__(256) void dt_row_kernel(const DTItem* __restrict__ 
                                                      const float* __restrict__ resp,
                                                      float* __restrict__ r1v,
                                                      int32_t* __restrict__ r1a) {
+    extern __shared__ float sline[];               // [DT_ROW_PAIRS][Wp + 1] when STAGED
+    __shared__ float smax[8][DT_ROW_PAIRS];
     const int it = find_item(prefix, n_items, blockIdx.x);
     const DTItem I = items[it];
     const int local = blockIdx.x - prefix[it];
-    const int pc = (I.np + 63) >> 6;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int pidx = (local % pc) * 64 + lane;
-    const int yp = (local / pc) * DT_ROWS_PER_BLOCK + wv;
-    if (yp >= I.Hp) return;                        // wave-uniform
-    const bool active = pidx < I.np;
-    const PairDesc P = pairs[I.pair_base + (active ? pidx : 0)];
-    const int64_t rs = I.ng;                       // element stride along x'
-    const float* row = resp + I.resp_off + (int64_t)yp * I.Wp * rs + P.fcol;
-    const int Wp = I.Wp;
-
-    float M = -FLT_MAX;
-    if (active)
-        for (int x = 0; x < Wp; ++x) M = fmaxf(M, row[x * rs]);
-
-    const int Wo_c = I.Wr - P.w0 + 1;
-    const float b = P.d[0], a = P.d[1];
-    float* ov = r1v + I.r1_off + (int64_t)yp * I.Wt * I.np;
-    int32_t* oa = r1a + I.r1_off + (int64_t)yp * I.Wt * I.np;
-    for (int x0 = 0; x0 < I.Wt; ++x0) {
-        const int xt = 2 * x0 + P.vx;
-        const bool ok = active && x0 < Wo_c && xt >= 0 && xt < Wp;
-        int lo = INT_MAX, hi = INT_MIN;
-        if (ok) dt_window(M, row[xt * rs], a, b, xt, Wp, lo, hi);
-        const int LO = wave_min_i(lo), HI = wave_max_i(hi);
-        float best = -INFINITY;
-        int arg = -1;
-        if (ok) {
-            for (int x = LO; x <= HI; ++x) {
-                const float u = (float)(x - xt);
-                const float val = row[x * rs] - u * fmaf(a, u, b);
-                if (val > best) { best = val; arg = x; }
-            }
+    const int pc = (I.np + DT_ROW_PAIRS - 1) / DT_ROW_PAIRS;
+    const int p0 = (local % pc) * DT_ROW_PAIRS;
+    const int yp = local / pc;                     // block-uniform
+    if (yp >= I.Hp) return;
+    const int Wp = I.Wp, pitch = Wp + 1;
+    const int64_t rs = I.ng;
+    const float* rowbase = resp + I.resp_off + (int64_t)yp * Wp * rs;
+    // stage: thread (pair q = tid % 32, x phase = tid / 32) -> coalesced 128-byte reads
+    {
+        const int q = threadIdx.x & (DT_ROW_PAIRS - 1), ph = threadIdx.x / DT_ROW_PAIRS;
+        const bool act = p0 + q < I.np;
+        const int fcol = act ? pairs[I.pair_base + p0 + q].fcol : 0;
+        float M = -FLT_MAX;
+        for (int x = ph; x < Wp; x += 256 / DT_ROW_PAIRS) {
+            const float v = act ? rowbase[x * rs + fcol] : 0.f;
+            if (STAGED) sline[q * pitch + x] = v;
+            M = fmaxf(M, v);
         }
-        if (active) {
-            ov[(int64_t)x0 * I.np + pidx] = best;
-            oa[(int64_t)x0 * I.np + pidx] = arg;
+        smax[ph][q] = M;
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int q = wv; q < DT_ROW_PAIRS; q += 4) {
+        const int pidx = p0 + q;
+        if (pidx >= I.np) break;                   // wave-uniform
+        const PairDesc P = pairs[I.pair_base + pidx];
+        float M = smax[0][q];
+#pragma unroll
+        for (int i = 1; i < 8; ++i) M = fmaxf(M, smax[i][q]);
+        const int Wo_c = min(I.Wr - P.w0 + 1, I.Wt);
+        float* ov = r1v + I.r1_off + ((int64_t)pidx * I.Hp + yp) * I.Wt;
+        int32_t* oa = r1a + I.r1_off + ((int64_t)pidx * I.Hp + yp) * I.Wt;
+        const float* srow = sline + q * pitch;
+        const float* grow = rowbase + P.fcol;
+        for (int x0 = lane; x0 < Wo_c; x0 += 64) {
+            const int t = 2 * x0 + P.vx;
+            float best = -INFINITY;
+            int arg = -1;
+            if (t >= 0 && t < Wp) {
+                if (STAGED)
+                    best = window_max([&](int x) { return srow[x]; }, Wp, t, 0, P.d[1], P.d[0], M, arg);
+                else
+                    best = window_max([&](int x) { return grow[x * rs]; }, Wp, t, 0, P.d[1], P.d[0], M, arg);
+            }
+            ov[x0] = best;
+            oa[x0] = arg;
         }
     }
 }
 
-// Column pass + placement: thread = (pair, root column x0).  For every root
-// row y0 the target is y_t = 2*y0 + v_y; maximises the row-pass value minus
-// (d_y (y'-y_t) + d_yy (y'-y_t)^2) over y', then writes the deformed part score
-// D and the (dy, dx) placement offset of the component's map.
+// Column pass: block = (item, pair, 64 root columns).  The block stages the
+// pair's row-pass output for its columns as [y'][64] (lane = column), then the
+// 4 wavefronts split the target rows y_t = 2*y0 + v_y.  Maximises the
+// row-pass value minus (d_y (y'-y_t) + d_yy (y'-y_t)^2) over y' and writes the
+// deformed part score and the (dy, dx) placement offset of (map, part, y0, x0)
+// straight into the caller's layout.
+template <bool STAGED>
 __global__ __launch_bounds__(256) void dt_col_kernel(const DTItem* __restrict__ items,
                                                      const int32_t* __restrict__ prefix,
                                                      int n_items,
@@ -422,95 +450,119 @@ __global__ __launch_bounds__(256) void dt_col_kernel(const DTItem* __restrict__ 
                                                      const int32_t* __restrict__ r1a,
                                                      float* __restrict__ dbuf,
                                                      int16_t* __restrict__ offs) {
+    extern __shared__ float sline[];               // [Hp][64] when STAGED
+    __shared__ float smax[4][64];
     const int it = find_item(prefix, n_items, blockIdx.x);
     const DTItem I = items[it];
     const int local = blockIdx.x - prefix[it];
-    const int pc = (I.np + 63) >> 6;
+    const int xc = (I.Wt + 63) >> 6;
+    const int pidx = local / xc;                   // block-uniform
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int pidx = (local % pc) * 64 + lane;
-    const int x0 = (local / pc) * DT_COLS_PER_BLOCK + wv;
-    if (x0 >= I.Wt) return;                        // wave-uniform
-    const bool active = pidx < I.np;
-    const PairDesc P = pairs[I.pair_base + (active ? pidx : 0)];
+    const int x0 = (local % xc) * 64 + lane;
+    if (pidx >= I.np) return;
+    const PairDesc P = pairs[I.pair_base + pidx];
     const MapDesc Md = maps[I.map_base + P.comp];
     const int Ho_c = Md.Ho, Wo_c = Md.Wo;
+    if (Ho_c <= 0 || (local % xc) * 64 >= Wo_c) return;   // block-uniform
     const int xt = 2 * x0 + P.vx;
-    const bool colok = active && x0 < Wo_c && xt >= 0 && xt < I.Wp;
-    const int64_t cs = (int64_t)I.Wt * I.np;       // element stride along y'
-    const float* col = r1v + I.r1_off + (int64_t)x0 * I.np + pidx;
-    const int32_t* cola = r1a + I.r1_off + (int64_t)x0 * I.np + pidx;
+    const bool colok = x0 < Wo_c && xt >= 0 && xt < I.Wp;
     const int Hp = I.Hp;
-
+    const float* col = r1v + I.r1_off + (int64_t)pidx * Hp * I.Wt + x0;   // element y' at col[y' * Wt]
     float M = -FLT_MAX;
-    if (colok)
-        for (int y = 0; y < Hp; ++y) M = fmaxf(M, col[y * cs]);
-
-    const float b = P.d[2], a = P.d[3];
+    for (int y = wv; y < Hp; y += 4) {
+        const float v = colok ? col[(int64_t)y * I.Wt] : 0.f;
+        if (STAGED) sline[y * 64 + lane] = v;
+        M = fmaxf(M, v);
+    }
+    smax[wv][lane] = M;
+    __syncthreads();
+    M = fmaxf(fmaxf(smax[0][lane], smax[1][lane]), fmaxf(smax[2][lane], smax[3][lane]));
+    if (x0 >= Wo_c) return;
+    const int chunk = (Ho_c + 3) >> 2;
+    const int k0 = wv * chunk, k1 = min(k0 + chunk, Ho_c);
     const int64_t plane = (int64_t)Ho_c * Wo_c;
-    for (int y0 = 0; y0 < I.Ht; ++y0) {
-        const int yt = 2 * y0 + P.vy;
-        const bool ok = colok && y0 < Ho_c && yt >= 0 && yt < Hp;
-        int lo = INT_MAX, hi = INT_MIN;
-        if (ok) dt_window(M, col[yt * cs], a, b, yt, Hp, lo, hi);
-        const int LO = wave_min_i(lo), HI = wave_max_i(hi);
+    float* dout = dbuf + (Md.offs_off >> 1) + P.slot * plane + x0;
+    int32_t* oout = offs ? reinterpret_cast<int32_t*>(offs + Md.offs_off) + P.slot * plane + x0 : nullptr;
+    const float a = P.d[3], b = P.d[2];
+    int prev = 0;
+    for (int k = k0; k < k1; ++k) {
+        const int t = 2 * k + P.vy;
         float best = -INFINITY;
-        int argy = -1;
-        if (ok) {
-            for (int y = LO; y <= HI; ++y) {
-                const float u = (float)(y - yt);
-                const float val = col[y * cs] - u * fmaf(a, u, b);
-                if (val > best) { best = val; argy = y; }
-            }
+        int32_t packed = 0;
+        if (colok && t >= 0 && t < Hp) {
+            int ay;
+            if (STAGED)
+                best = window_max([&](int y) { return sline[y * 64 + lane]; }, Hp, t, prev, a, b, M, ay);
+            else
+                best = window_max([&](int y) { return col[(int64_t)y * I.Wt]; }, Hp, t, prev, a, b, M, ay);
+            prev = ay;
+            const int dx = r1a[I.r1_off + ((int64_t)pidx * Hp + ay) * I.Wt + x0] - xt;
+            const int dy = ay - t;
+            packed = (int32_t)(((uint32_t)(uint16_t)(int16_t)dx << 16) | (uint16_t)(int16_t)dy);
         }
-        if (active && x0 < Wo_c && y0 < Ho_c) {
-            const int64_t pos = (int64_t)y0 * Wo_c + x0;
-            dbuf[Md.dbuf_off + P.slot * plane + pos] = ok ? best : -INFINITY;
-            if (offs) {
-                int dy = 0, dx = 0;
-                if (ok) {
-                    dy = argy - yt;
-                    dx = cola[argy * cs] - xt;
-                }
-                int16_t* o = offs + Md.offs_off + (P.slot * plane + pos) * 2;
-                o[0] = (int16_t)dy;
-                o[1] = (int16_t)dx;
-            }
-        }
+        dout[k * Wo_c] = best;
+        if (oout) oout[k * Wo_c] = packed;
     }
 }
 
-// Assembly: thread = (map, root position).
+// Assembly: thread = (map, root position); adds the parts' deformed scores to
+// the root response (Section 2 score formula).
 __global__ __launch_bounds__(ASM_BLOCK) void assemble_kernel(const MapDesc* __restrict__ maps,
                                                              const int32_t* __restrict__ prefix,
                                                              int n_maps,
                                                              const float* __restrict__ rresp,
                                                              const float* __restrict__ dbuf,
                                                              float* __restrict__ scores) {
-    const int m = find_item(prefix, n_maps, blockIdx.x);
-    const MapDesc Md = maps[m];
-    const int64_t pos = (int64_t)(blockIdx.x - prefix[m]) * ASM_BLOCK + threadIdx.x;
-    const int64_t plane = (int64_t)Md.Ho * Md.Wo;
+    const int mi = find_item(prefix, n_maps, blockIdx.x);
+    const MapDesc Md = maps[mi];
+    const int pos = (blockIdx.x - prefix[mi]) * ASM_BLOCK + threadIdx.x;
+    const int plane = Md.Ho * Md.Wo;
     if (pos >= plane) return;
-    float s = rresp[Md.rresp_off + pos * Md.rng + Md.rcol];
-    for (int i = 0; i < Md.n_parts; ++i) s += dbuf[Md.dbuf_off + i * plane + pos];
+    float s = rresp[Md.rresp_off + (int64_t)pos * Md.rng + Md.rcol];
+    const float* d = dbuf + (Md.offs_off >> 1) + pos;
+    for (int i = 0; i < Md.n_parts; ++i) s += d[(int64_t)i * plane];
     scores[Md.score_off + pos] = s;
+}
+
+template <class K>
+static hipError_t set_lds(K kern, size_t lds) {
+    if (lds <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 hipError_t launch_dt_row(const DTItem* items, const int32_t* prefix, int n_items, int n_blocks,
                          const PairDesc* pairs, const float* resp, float* r1v, int32_t* r1a,
-                         hipStream_t st) {
+                         int max_line, hipStream_t st) {
     if (n_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(dt_row_kernel, dim3(n_blocks), dim3(64 * DT_ROWS_PER_BLOCK), 0, st, items,
-                       prefix, n_items, pairs, resp, r1v, r1a);
+    const size_t lds = (size_t)(max_line + 1) * DT_ROW_PAIRS * sizeof(float);
+    if (lds <= DT_STAGE_MAX) {
+        hipError_t e = set_lds(dt_row_kernel<true>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(dt_row_kernel<true>, dim3(n_blocks), dim3(256), lds, st, items, prefix,
+                           n_items, pairs, resp, r1v, r1a);
+    } else {
+        hipLaunchKernelGGL(dt_row_kernel<false>, dim3(n_blocks), dim3(256), 0, st, items, prefix,
+                           n_items, pairs, resp, r1v, r1a);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_dt_col(const DTItem* items, const int32_t* prefix, int n_items, int n_blocks,
                          const PairDesc* pairs, const MapDesc* maps, const float* r1v,
-                         const int32_t* r1a, float* dbuf, int16_t* offs, hipStream_t st) {
+                         const int32_t* r1a, float* dbuf, int16_t* offs, int max_line,
+                         hipStream_t st) {
     if (n_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(dt_col_kernel, dim3(n_blocks), dim3(64 * DT_COLS_PER_BLOCK), 0, st, items,
-                       prefix, n_items, pairs, maps, r1v, r1a, dbuf, offs);
+    const size_t lds = (size_t)max_line * 64 * sizeof(float);
+    if (lds <= DT_STAGE_MAX) {
+        hipError_t e = set_lds(dt_col_kernel<true>, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(dt_col_kernel<true>, dim3(n_blocks), dim3(256), lds, st, items, prefix,
+                           n_items, pairs, maps, r1v, r1a, dbuf, offs);
+    } else {
+        hipLaunchKernelGGL(dt_col_kernel<false>, dim3(n_blocks), dim3(256), 0, st, items, prefix,
+                           n_items, pairs, maps, r1v, r1a, dbuf, offs);
+    }
     return hipGetLastError();
 }
 
@@ -544,8 +596,52 @@ hipError_t launch_block_to_maps(const float* block, int64_t n_pos, int ng, const
 }
 
 // ---------------------------------------------------------------------------
-// single-map distance transform for every target cell
+// single-map distance transform for every target cell: the same exact window
+// scan with target stride 1; row pass with one thread per (row, target chunk),
+// column pass with one thread per (column, target chunk), x fastest so that
+// the column pass reads rows of the intermediate coalesced
 // ---------------------------------------------------------------------------
+constexpr int DT1_CHUNK = 16;                      // targets per thread
+
+__global__ __launch_bounds__(256) void dt1_row_kernel(const float* __restrict__ v, int rows, int cols,
+                                                      int64_t ld, const float* __restrict__ M,
+                                                      float a, float b, float* __restrict__ ov,
+                                                      int32_t* __restrict__ oa) {
+    const int nch = (cols + DT1_CHUNK - 1) / DT1_CHUNK;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)rows * nch) return;
+    const int y = (int)(i / nch), c = (int)(i - (int64_t)y * nch);
+    const float* row = v + y * ld;
+    int prev = 0;
+    for (int k = c * DT1_CHUNK; k < min(cols, (c + 1) * DT1_CHUNK); ++k) {
+        int arg;
+        ov[(int64_t)y * cols + k] = window_max([&](int x) { return row[x]; }, cols, k, prev, a, b, M[y], arg);
+        oa[(int64_t)y * cols + k] = arg;
+        prev = arg;
+    }
+}
+
+__global__ __launch_bounds__(256) void dt1_col_kernel(const float* __restrict__ r1v,
+                                                      const int32_t* __restrict__ r1a, int rows,
+                                                      int cols, const float* __restrict__ M, float a,
+                                                      float b, float* __restrict__ out,
+                                                      int32_t* __restrict__ ay,
+                                                      int32_t* __restrict__ ax) {
+    const int nch = (rows + DT1_CHUNK - 1) / DT1_CHUNK;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)cols * nch) return;
+    const int c = (int)(i / cols), x = (int)(i - (int64_t)c * cols);
+    int prev = 0;
+    for (int k = c * DT1_CHUNK; k < min(rows, (c + 1) * DT1_CHUNK); ++k) {
+        int arg;
+        const int64_t o = (int64_t)k * cols + x;
+        out[o] = window_max([&](int y) { return r1v[(int64_t)y * cols + x]; }, rows, k, prev, a, b, M[x], arg);
+        if (ay) ay[o] = arg;
+        if (ax) ax[o] = r1a[(int64_t)arg * cols + x];
+        prev = arg;
+    }
+}
+
 __global__ void dt1_rowmax_kernel(const float* __restrict__ v, int rows, int cols, int64_t ld,
                                   float* __restrict__ M) {
     const int y = blockIdx.x * 256 + threadIdx.x;
@@ -564,69 +660,20 @@ __global__ void dt1_colmax_kernel(const float* __restrict__ v, int rows, int col
     M[x] = m;
 }
 
-// thread = target (y, x), x fastest; scans along x (row pass)
-__global__ void dt1_row_kernel(const float* __restrict__ v, int rows, int cols, int64_t ld,
-                               const float* __restrict__ M, float a, float b,
-                               float* __restrict__ ov, int32_t* __restrict__ oa) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const bool ok = i < (int64_t)rows * cols;
-    const int y = ok ? (int)(i / cols) : 0;
-    const int xt = ok ? (int)(i - (int64_t)y * cols) : 0;
-    const float* row = v + y * ld;
-    int lo = INT_MAX, hi = INT_MIN;
-    if (ok) dt_window(M[y], row[xt], a, b, xt, cols, lo, hi);
-    const int LO = wave_min_i(lo), HI = wave_max_i(hi);
-    if (!ok) return;
-    float best = -INFINITY;
-    int arg = -1;
-    for (int x = max(LO, 0); x <= min(HI, cols - 1); ++x) {
-        const float u = (float)(x - xt);
-        const float val = row[x] - u * fmaf(a, u, b);
-        if (val > best) { best = val; arg = x; }
-    }
-    ov[i] = best;
-    oa[i] = arg;
-}
-
-// thread = target (y, x), x fastest; scans along y (column pass)
-__global__ void dt1_col_kernel(const float* __restrict__ r1v, const int32_t* __restrict__ r1a,
-                               int rows, int cols, const float* __restrict__ M, float a, float b,
-                               float* __restrict__ out, int32_t* __restrict__ ay,
-                               int32_t* __restrict__ ax) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const bool ok = i < (int64_t)rows * cols;
-    const int yt = ok ? (int)(i / cols) : 0;
-    const int x = ok ? (int)(i - (int64_t)yt * cols) : 0;
-    int lo = INT_MAX, hi = INT_MIN;
-    if (ok) dt_window(M[x], r1v[(int64_t)yt * cols + x], a, b, yt, rows, lo, hi);
-    const int LO = wave_min_i(lo), HI = wave_max_i(hi);
-    if (!ok) return;
-    float best = -INFINITY;
-    int arg = -1;
-    for (int y = max(LO, 0); y <= min(HI, rows - 1); ++y) {
-        const float u = (float)(y - yt);
-        const float val = r1v[(int64_t)y * cols + x] - u * fmaf(a, u, b);
-        if (val > best) { best = val; arg = y; }
-    }
-    out[i] = best;
-    if (ay) ay[i] = arg;
-    if (ax) ax[i] = r1a[(int64_t)arg * cols + x];
-}
-
 hipError_t launch_dt_single(const float* resp, int rows, int cols, int ld, const float* d,
-                            float* rowmax, float* r1v, int32_t* r1a, float* out, int32_t* ay,
+                            float* lmax, float* r1v, int32_t* r1a, float* out, int32_t* ay,
                             int32_t* ax, hipStream_t st) {
-    const int64_t n = (int64_t)rows * cols;
-    if (n <= 0) return hipSuccess;
-    const unsigned nb = (unsigned)((n + 255) / 256);
+    if ((int64_t)rows * cols <= 0) return hipSuccess;
+    const int64_t nr = (int64_t)rows * ((cols + DT1_CHUNK - 1) / DT1_CHUNK);
+    const int64_t nc = (int64_t)cols * ((rows + DT1_CHUNK - 1) / DT1_CHUNK);
     hipLaunchKernelGGL(dt1_rowmax_kernel, dim3((rows + 255) / 256), dim3(256), 0, st, resp, rows,
-                       cols, (int64_t)ld, rowmax);
-    hipLaunchKernelGGL(dt1_row_kernel, dim3(nb), dim3(256), 0, st, resp, rows, cols, (int64_t)ld,
-                       rowmax, d[1], d[0], r1v, r1a);
+                       cols, (int64_t)ld, lmax);
+    hipLaunchKernelGGL(dt1_row_kernel, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, resp,
+                       rows, cols, (int64_t)ld, lmax, d[1], d[0], r1v, r1a);
     hipLaunchKernelGGL(dt1_colmax_kernel, dim3((cols + 255) / 256), dim3(256), 0, st, r1v, rows,
-                       cols, rowmax);
-    hipLaunchKernelGGL(dt1_col_kernel, dim3(nb), dim3(256), 0, st, r1v, r1a, rows, cols, rowmax,
-                       d[3], d[2], out, ay, ax);
+                       cols, lmax);
+    hipLaunchKernelGGL(dt1_col_kernel, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, r1v,
+                       r1a, rows, cols, lmax, d[3], d[2], out, ay, ax);
     return hipGetLastError();
 }
 
