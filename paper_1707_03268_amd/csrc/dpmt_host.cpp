@@ -134,7 +134,8 @@ struct dpmt_ctx {
     std::vector<int32_t> row_prefix, col_prefix, asm_prefix;
     int row_blocks = 0, col_blocks = 0, asm_blocks = 0;
     int64_t r1_elems = 0;
-    int max_Wp = 0, max_Hp = 0;         // longest DT row / column (LDS staging size)
+    int max_Wp = 0;                     // longest DT row (row-pass LDS staging)
+    int64_t max_Hp = 0;                 // largest column-pass tile Hp * cw (elements)
     dpmt_layout layout{};
 
     // device workspace
@@ -797,6 +798,9 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
                 it.np = c->group_pair_count[g];
                 it.pair_base = c->group_pair_base[g];
                 it.map_base = map_base[i][l];
+                // column-pass block width: every column of the map when the staged
+                // [Hp][cw] tile fits, at most 256, at least 1
+                it.cw = std::max(1, std::min({Wt, 256, it.Hp > 0 ? (int)(DT_COL_LDS / 4 / it.Hp) : 256}));
                 c->r1_elems += (int64_t)it.Hp * it.Wt * it.np;
                 c->dt_items.push_back(it);
             }
@@ -809,9 +813,9 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
         c->row_prefix.push_back((int32_t)rb);
         c->col_prefix.push_back((int32_t)cb);
         rb += (int64_t)((it.np + DT_ROW_PAIRS_PER_BLOCK - 1) / DT_ROW_PAIRS_PER_BLOCK) * it.Hp;
-        cb += (int64_t)it.np * ((it.Wt + DT_COLS_PER_BLOCK - 1) / DT_COLS_PER_BLOCK);
+        cb += (int64_t)it.np * ((it.Wt + it.cw - 1) / it.cw);
         c->max_Wp = std::max(c->max_Wp, it.Wp);
-        c->max_Hp = std::max(c->max_Hp, it.Hp);
+        c->max_Hp = std::max<int64_t>(c->max_Hp, (int64_t)it.Hp * it.cw);
     }
     for (const MapDesc& md : c->maps) {
         c->asm_prefix.push_back((int32_t)ab);
@@ -943,7 +947,7 @@ dpmt_status dpmt_score_pyramid(dpmt_ctx* c, dpmt_mode mode, const float* feature
     if (prof) HIP_TRY(c, hipEventRecord(ev[2], st), "hipEventRecord");
     HIP_TRY(c, launch_dt_row(c->d_items, c->d_row_prefix, (int)c->dt_items.size(), c->row_blocks, c->d_pairs, c->d_resp, c->d_r1v, c->d_r1a, c->max_Wp, st), "DT row launch");
     if (prof) HIP_TRY(c, hipEventRecord(ev[3], st), "hipEventRecord");
-    HIP_TRY(c, launch_dt_col(c->d_items, c->d_col_prefix, (int)c->dt_items.size(), c->col_blocks, c->d_pairs, c->d_maps, c->d_r1v, c->d_r1a, c->d_dbuf, offsets_dev, c->max_Hp, st), "DT column launch");
+    HIP_TRY(c, launch_dt_col(c->d_items, c->d_col_prefix, (int)c->dt_items.size(), c->col_blocks, c->d_pairs, c->d_maps, c->d_r1v, c->d_r1a, c->d_dbuf, offsets_dev, (int)std::min<int64_t>(c->max_Hp, INT32_MAX), st), "DT column launch");
     if (prof) HIP_TRY(c, hipEventRecord(ev[4], st), "hipEventRecord");
     HIP_TRY(c, launch_assemble(c->d_maps, c->d_asm_prefix, (int)c->maps.size(), c->asm_blocks, c->d_resp, c->d_dbuf, scores_dev, st), "assembly launch");
     if (prof) HIP_TRY(c, hipEventRecord(ev[5], st), "hipEventRecord");

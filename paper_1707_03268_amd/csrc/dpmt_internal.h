@@ -58,6 +58,8 @@ struct DTItem {
     int32_t ng, np;    // filters in the group, pairs in the group
     int32_t pair_base; // first pair of the group in the pair table
     int32_t map_base;  // map index of component 0 at this (image, root level)
+    int32_t cw;        // root columns per column-pass block
+    int32_t pad;
 };
 
 // One score map (image, root level, component).
@@ -106,7 +108,7 @@ hipError_t launch_dt_single(const float* resp, int rows, int cols, int ld, const
 
 // Workgroup sizes used by the launchers (the planner sizes work lists with them).
 constexpr int DT_ROW_PAIRS_PER_BLOCK = 32;   // row pass: one part row of 32 pairs per block
-constexpr int DT_COLS_PER_BLOCK = 64;        // column pass: 64 root columns of one pair per block
+constexpr int DT_COL_LDS = 96 * 1024;        // column pass: LDS bytes of one staged [Hp][cw] tile
 constexpr int ASM_BLOCK = 256;         // assembly: threads per block
 
 }  // namespace dpmt

@@ -97,15 +97,18 @@ hipError_t launch_project(bool bf16, const float* X, int64_t n_cells, const floa
 // ---------------------------------------------------------------------------
 constexpr int CORR_MAX_H = 16;
 
-__device__ __forceinline__ uint4 lds_load16(const char* p, int pb) {
-    if (pb >= 16) return *reinterpret_cast<const uint4*>(p);
-    const uint2 a = *reinterpret_cast<const uint2*>(p);
-    const uint2 b = *reinterpret_cast<const uint2*>(p + 8);
-    return make_uint4(a.x, a.y, b.x, b.y);
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ u32x4 lds_load16(const char* p, int pb) {
+    if (pb >= 16) return *reinterpret_cast<const u32x4*>(p);
+    const u32x2 a = *reinterpret_cast<const u32x2*>(p);
+    const u32x2 b = *reinterpret_cast<const u32x2*>(p + 8);
+    return u32x4{a.x, a.y, b.x, b.y};
 }
 
 template <CorrKind KIND>
-__device__ __forceinline__ v16f mfma_step(const uint4& a, const uint4& b, v16f c) {
+__device__ __forceinline__ v16f mfma_step(const u32x4& a, const u32x4& b, v16f c) {
     if constexpr (KIND == CORR_F32) {
         c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.x), __uint_as_float(b.x), c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.y), __uint_as_float(b.y), c, 0, 0, 0);
@@ -120,8 +123,8 @@ __device__ __forceinline__ v16f mfma_step(const uint4& a, const uint4& b, v16f c
     }
 }
 
-template <CorrKind KIND, int PB, int TY, int BB, int WY>
-__global__ __launch_bounds__(64 * WY) void corr_kernel(const CorrTile* __restrict__ tiles,
+template <CorrKind KIND, int PB, int TY, int BB, int WY, int HMAX>
+__global__ __launch_bounds__(64 * WY) __attribute__((amdgpu_waves_per_eu(HMAX <= 8 ? 2 : 1))) void corr_kernel(const CorrTile* __restrict__ tiles,
                                                        const GroupDesc* __restrict__ groups,
                                                        const char* __restrict__ Z,
                                                        const char* __restrict__ G,
@@ -131,7 +134,8 @@ __global__ __launch_bounds__(64 * WY) void corr_kernel(const CorrTile* __restric
     constexpr int NT = 64 * WY;
     constexpr int TYWG = TY * WY;
     constexpr int CH = PB >= 16 ? 16 : 8;          // window copy granule
-    constexpr int PFMAX = (BB * CORR_MAX_H + WY - 1) / WY;   // prefetch uint4 per thread
+    constexpr int PFMAX = (BB * HMAX * 64 + NT - 1) / NT;   // chunk u32x4 per thread, h <= HMAX
+    constexpr int WBATCH = 4;                      // window loads in flight per thread
 
     const CorrTile t = tiles[blockIdx.x];
     const GroupDesc g = groups[t.group];
@@ -140,8 +144,8 @@ __global__ __launch_bounds__(64 * WY) void corr_kernel(const CorrTile* __restric
     const int pitch = WC * PB;
     const int nrows = TYWG + h - 1;
     char* win = smem;
-    uint4* gbuf0 = reinterpret_cast<uint4*>(smem + win_bytes);
-    uint4* gbuf1 = gbuf0 + BB * h * 64;
+    u32x4* gbuf0 = reinterpret_cast<u32x4*>(smem + win_bytes);
+    u32x4* gbuf1 = gbuf0 + BB * h * 64;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
@@ -155,20 +159,30 @@ __global__ __launch_bounds__(64 * WY) void corr_kernel(const CorrTile* __restric
 #pragma unroll
             for (int k = 0; k < 16; ++k) acc[i][b][k] = 0.f;
 
-    const int n_chunk = BB * h * 64;               // uint4 per G chunk
+    const int n_chunk = BB * h * 64;               // u32x4 per G chunk
     const int total = Q * S;
-    auto chunk_src = [&](int step, int i) -> const uint4* {
+    // element i of chunk `step`: [b][n][lane] of the packed operand.  Indices
+    // past the chunk are clamped to its last element, for the load and for the
+    // LDS store alike, so surplus threads store that element's own value again.
+    auto chunk_src = [&](int step, int i) -> const u32x4* {
+        i = min(i, n_chunk - 1);
         const int q = step / S, s = step - q * S;
         const int l = i & 63;
         const int n = (i >> 6) % h;
         const int b = i / (64 * h);
         const int64_t blk = t.fb0 + b;
-        return reinterpret_cast<const uint4*>(
+        return reinterpret_cast<const u32x4*>(
                    G + g.g_off + ((((blk * Q + q) * S + s) * (int64_t)h + n) << 10)) + l;
     };
 
     // prologue: chunk 0 straight into buffer 0
-    for (int i = tid; i < n_chunk; i += NT) gbuf0[i] = *chunk_src(0, i);
+    {
+        u32x4 pf[PFMAX];
+#pragma unroll
+        for (int k = 0; k < PFMAX; ++k) pf[k] = *chunk_src(0, tid + k * NT);
+#pragma unroll
+        for (int k = 0; k < PFMAX; ++k) gbuf0[min(tid + k * NT, n_chunk - 1)] = pf[k];
+    }
 
     for (int step = 0; step < total; ++step) {
         const int q = step / S, s = step - q * S;
@@ -176,62 +190,81 @@ __global__ __launch_bounds__(64 * WY) void corr_kernel(const CorrTile* __restric
             __syncthreads();                       // previous plane fully consumed
             const int cpc = PB / CH;
             const int nch = nrows * WC * cpc;
-            for (int i = tid; i < nch; i += NT) {
-                const int k = i % cpc;
-                const int cc = (i / cpc) % WC;
-                const int r = i / (cpc * WC);
-                const int y = t.y0 + r, x = t.x0 + cc;
-                char* dst = win + r * pitch + cc * PB + k * CH;
-                const bool in = (y < t.H) && (x < t.W);
-                const char* src = Z + ((t.z_cell + (int64_t)y * t.W + x) * cell_bytes + q * PB + k * CH);
-                if constexpr (CH == 16) {
-                    *reinterpret_cast<uint4*>(dst) = in ? *reinterpret_cast<const uint4*>(src)
-                                                        : make_uint4(0, 0, 0, 0);
-                } else {
-                    *reinterpret_cast<uint2*>(dst) = in ? *reinterpret_cast<const uint2*>(src)
-                                                        : make_uint2(0, 0);
+            for (int i0 = tid; i0 < nch; i0 += WBATCH * NT) {
+                u32x4 r[WBATCH];
+#pragma unroll
+                for (int u = 0; u < WBATCH; ++u) {
+                    const int i = min(i0 + u * NT, nch - 1);
+                    const int k = i % cpc;
+                    const int cc = (i / cpc) % WC;
+                    const int rr = i / (cpc * WC);
+                    const int y = t.y0 + rr, x = t.x0 + cc;
+                    const bool in = (y < t.H) && (x < t.W);
+                    const int64_t cell = t.z_cell + (in ? (int64_t)y * t.W + x : 0);
+                    const char* src = Z + (cell * cell_bytes + q * PB + k * CH);
+                    if constexpr (CH == 16) {
+                        r[u] = *reinterpret_cast<const u32x4*>(src);
+                    } else {
+                        const u32x2 v = *reinterpret_cast<const u32x2*>(src);
+                        r[u] = u32x4{v.x, v.y, 0u, 0u};
+                    }
+                    if (!in) r[u] = u32x4{0u, 0u, 0u, 0u};
+                }
+#pragma unroll
+                for (int u = 0; u < WBATCH; ++u) {
+                    const int i = min(i0 + u * NT, nch - 1);   // surplus: same value again
+                    const int k = i % cpc;
+                    const int cc = (i / cpc) % WC;
+                    const int rr = i / (cpc * WC);
+                    char* dst = win + rr * pitch + cc * PB + k * CH;
+                    if constexpr (CH == 16) *reinterpret_cast<u32x4*>(dst) = r[u];
+                    else *reinterpret_cast<u32x2*>(dst) = u32x2{r[u].x, r[u].y};
                 }
             }
         }
         __syncthreads();                           // window and chunk `step` visible
 
-        uint4 pf[PFMAX];
+        // issue the loads of the next chunk before this step's MFMAs (the last
+        // step reloads its own chunk and does not store it)
+        u32x4 pf[PFMAX];
         const bool more = step + 1 < total;
-        if (more) {
+        const int nstep = more ? step + 1 : step;
 #pragma unroll
-            for (int k = 0; k < PFMAX; ++k) {
-                const int i = tid + k * NT;
-                if (i < n_chunk) pf[k] = *chunk_src(step + 1, i);
-            }
-        }
+        for (int k = 0; k < PFMAX; ++k) pf[k] = *chunk_src(nstep, tid + k * NT);
 
-        const uint4* gb = (step & 1) ? gbuf1 : gbuf0;
+        const u32x4* gb = (step & 1) ? gbuf1 : gbuf0;
         const char* abase = win + (wv * TY) * pitch + p * PB + 32 * s + 16 * j;
-        uint4 A[TY];
+        u32x4 A[TY];
 #pragma unroll
         for (int i = 0; i < TY; ++i) A[i] = lds_load16(abase + i * pitch, PB);
-        for (int n = 0; n < h; ++n) {
-            uint4 B[BB];
+        u32x4 B[BB];
 #pragma unroll
-            for (int b = 0; b < BB; ++b) B[b] = gb[(b * h + n) * 64 + lane];
+        for (int b = 0; b < BB; ++b) B[b] = gb[(b * h) * 64 + lane];
+        for (int n = 0; n < h; ++n) {
+            u32x4 Bn[BB], An;
+            const bool nx = n + 1 < h;
+            if (nx) {
+#pragma unroll
+                for (int b = 0; b < BB; ++b) Bn[b] = gb[(b * h + n + 1) * 64 + lane];
+                An = lds_load16(abase + (n + TY) * pitch, PB);
+            }
 #pragma unroll
             for (int i = 0; i < TY; ++i)
 #pragma unroll
                 for (int b = 0; b < BB; ++b) acc[i][b] = mfma_step<KIND>(A[i], B[b], acc[i][b]);
-            if (n + 1 < h) {
+            if (nx) {
 #pragma unroll
                 for (int i = 0; i + 1 < TY; ++i) A[i] = A[i + 1];
-                A[TY - 1] = lds_load16(abase + (n + TY) * pitch, PB);
+                A[TY - 1] = An;
+#pragma unroll
+                for (int b = 0; b < BB; ++b) B[b] = Bn[b];
             }
         }
 
         if (more) {
-            uint4* nb = (step & 1) ? gbuf0 : gbuf1;
+            u32x4* nb = (step & 1) ? gbuf0 : gbuf1;
 #pragma unroll
-            for (int k = 0; k < PFMAX; ++k) {
-                const int i = tid + k * NT;
-                if (i < n_chunk) nb[i] = pf[k];
-            }
+            for (int k = 0; k < PFMAX; ++k) nb[min(tid + k * NT, n_chunk - 1)] = pf[k];
         }
     }
 
@@ -261,8 +294,8 @@ size_t corr_lds_bytes(const CorrLaunch& cfg, int h, int S) {
     return winal + 2 * (size_t)cfg.bb * h * 1024;
 }
 
-template <CorrKind KIND, int PB, int TY, int BB, int WY>
-static hipError_t launch_corr_t(const CorrTile* tiles, int n_tiles, const GroupDesc* groups,
+template <CorrKind KIND, int PB, int TY, int BB, int WY, int HMAX>
+static hipError_t launch_corr_h(const CorrTile* tiles, int n_tiles, const GroupDesc* groups,
                                 const void* Z, const void* G, float* out, int cell_bytes, int Q,
                                 int max_h, int max_S, hipStream_t st) {
     CorrLaunch cfg{KIND, Packing{0, 0, PB, Q}, TY, BB, WY};
@@ -270,7 +303,7 @@ static hipError_t launch_corr_t(const CorrTile* tiles, int n_tiles, const GroupD
     const int WC = 31 + (32 * max_S) / PB;
     const size_t win = (size_t)(TY * WY + max_h - 1) * WC * PB;
     const int win_bytes = (int)((win + 15) & ~size_t(15));
-    auto kern = corr_kernel<KIND, PB, TY, BB, WY>;
+    auto kern = corr_kernel<KIND, PB, TY, BB, WY, HMAX>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -280,6 +313,19 @@ static hipError_t launch_corr_t(const CorrTile* tiles, int n_tiles, const GroupD
                        static_cast<const char*>(Z), static_cast<const char*>(G), out, cell_bytes,
                        Q, win_bytes);
     return hipGetLastError();
+}
+
+// Filters of at most 8 rows (every DPM root and part shape) get a kernel whose
+// chunk prefetch needs half the registers.
+template <CorrKind KIND, int PB, int TY, int BB, int WY>
+static hipError_t launch_corr_t(const CorrTile* tiles, int n_tiles, const GroupDesc* groups,
+                                const void* Z, const void* G, float* out, int cell_bytes, int Q,
+                                int max_h, int max_S, hipStream_t st) {
+    if (max_h <= 8)
+        return launch_corr_h<KIND, PB, TY, BB, WY, 8>(tiles, n_tiles, groups, Z, G, out,
+                                                      cell_bytes, Q, max_h, max_S, st);
+    return launch_corr_h<KIND, PB, TY, BB, WY, CORR_MAX_H>(tiles, n_tiles, groups, Z, G, out,
+                                                           cell_bytes, Q, max_h, max_S, st);
 }
 
 hipError_t launch_corr(const CorrLaunch& cfg, const CorrTile* tiles, int n_tiles,
@@ -342,35 +388,73 @@ __device__ __forceinline__ int find_item(const int32_t* __restrict__ prefix, int
     return lo;
 }
 
-// Exact maximum of v[x] - c(x - t) over x and its smallest maximiser, for
-// target t in [0, n), scanning from max(window start, from).
-template <class Load>
-__device__ __forceinline__ float window_max(const Load& load, int n, int t, int from, float a,
-                                            float b, float M, int& arg) {
-    const float inv = 0.5f / a;
-    const float s = sqrtf(fmaf(4.f * a, fmaxf(M - load(t), 0.f), b * b));
-    int lo = t + (int)fmaxf(floorf((-b - s) * inv) - 1.f, -(float)n);
-    int hi = t + (int)fminf(ceilf((-b + s) * inv) + 1.f, (float)n);
+// Per-line constants of one pair's cost c(u) = b*u + a*u^2 and the line maximum.
+struct LineConst {
+    float a, b, inv2a, bb4a;   // inv2a = 1/(2a); bb4a unused slot kept for alignment
+    float M;                   // line maximum
+};
+
+// Window [t + lo, t + hi] (clamped to [from, n-1]) holding every possible
+// maximiser of target t: x can only beat t itself if c(x - t) <= M - v[t].
+// The hardware square root and reciprocal are within a few ulp; the 1-cell
+// margin on each side covers that and the FP32 rounding of the bound.
+__device__ __forceinline__ void dt_bounds(float vt, const LineConst& c, int t, int from, int n,
+                                          int& lo, int& hi) {
+    const float delta = fmaxf(c.M - vt, 0.f);
+    const float s = __builtin_amdgcn_sqrtf(fmaf(4.f * c.a, delta, c.b * c.b));
+    const float ulo = floorf((-c.b - s) * c.inv2a) - 1.f;
+    const float uhi = ceilf((-c.b + s) * c.inv2a) + 1.f;
+    lo = t + (int)fmaxf(ulo, -(float)n);
+    hi = t + (int)fminf(uhi, (float)n);
     hi = min(hi, n - 1);
     lo = min(max(max(lo, 0), from), hi);
+}
+
+// Exact maximum of v[x] - c(x - t) for x in [lo, hi] and its smallest
+// maximiser, four candidates per iteration so that their loads overlap.
+template <class Load>
+__device__ __forceinline__ float scan_range(const Load& load, int lo, int hi, int t, float a,
+                                            float b, int& arg) {
     float best = -INFINITY;
     arg = lo;
-    float u = (float)(lo - t);
-    for (int x = lo; x <= hi; ++x, u += 1.f) {
-        const float val = load(x) - u * fmaf(a, u, b);
-        if (val > best) {
-            best = val;
-            arg = x;
-        }
+    int x = lo;
+    for (; x + 3 <= hi; x += 4) {
+        const float v0 = load(x), v1 = load(x + 1), v2 = load(x + 2), v3 = load(x + 3);
+        const float u = (float)(x - t);
+        const float e0 = v0 - u * fmaf(a, u, b);
+        const float e1 = v1 - (u + 1.f) * fmaf(a, u + 1.f, b);
+        const float e2 = v2 - (u + 2.f) * fmaf(a, u + 2.f, b);
+        const float e3 = v3 - (u + 3.f) * fmaf(a, u + 3.f, b);
+        if (e0 > best) { best = e0; arg = x; }
+        if (e1 > best) { best = e1; arg = x + 1; }
+        if (e2 > best) { best = e2; arg = x + 2; }
+        if (e3 > best) { best = e3; arg = x + 3; }
+    }
+    for (; x <= hi; ++x) {
+        const float u = (float)(x - t);
+        const float e = load(x) - u * fmaf(a, u, b);
+        if (e > best) { best = e; arg = x; }
     }
     return best;
 }
 
+// Generic form used by the single-map transform.
+template <class Load>
+__device__ __forceinline__ float window_max(const Load& load, int n, int t, int from, float a,
+                                            float b, float M, int& arg) {
+    LineConst c{a, b, 0.5f / a, 0.f, M};
+    int lo, hi;
+    dt_bounds(load(t), c, t, from, n, lo, hi);
+    return scan_range(load, lo, hi, t, a, b, arg);
+}
+
 // Row pass: block = (item, part row y', 32 pairs).  The block stages the row
-// of its 32 pairs as [pair][x'] (odd pitch), then each wavefront takes every
-// fourth pair and its lanes take that pair's target columns x_t = 2*x0 + v_x.
-// Writes the row maximum of resp[y'][x'] - (d_x (x'-x_t) + d_xx (x'-x_t)^2) and
-// its argmax x' at [pair][y'][x0].
+// of its 32 pairs in LDS split by parity, [pair][x' & 1][x' >> 1], so that
+// lanes holding consecutive target columns (targets 2 apart) read
+// consecutive words; then thread (column x0 = tid % Wt, pair slot tid / Wt)
+// walks the block's pairs.  Writes the row maximum of
+// resp[y'][x'] - (d_x (x'-x_t) + d_xx (x'-x_t)^2), x_t = 2*x0 + v_x, and its
+// argmax x' at [pair][y'][x0].
 template <bool STAGED>
 __global__ __launch_bounds__(256) void dt_row_kernel(const DTItem* __restrict__ items,
                                                      const int32_t* __restrict__ prefix,
@@ -379,8 +463,10 @@ __global__ __launch_bounds__(256) void dt_row_kernel(const DTItem* __restrict__ 
                                                      const float* __restrict__ resp,
                                                      float* __restrict__ r1v,
                                                      int32_t* __restrict__ r1a) {
-    extern __shared__ float sline[];               // [DT_ROW_PAIRS][Wp + 1] when STAGED
+    extern __shared__ float sline[];               // [DT_ROW_PAIRS][2][half] when STAGED
     __shared__ float smax[8][DT_ROW_PAIRS];
+    __shared__ LineConst sc[DT_ROW_PAIRS];
+    __shared__ int2 sv[DT_ROW_PAIRS];              // (v_x, root columns Wo_c)
     const int it = find_item(prefix, n_items, blockIdx.x);
     const DTItem I = items[it];
     const int local = blockIdx.x - prefix[it];
@@ -388,58 +474,100 @@ __global__ __launch_bounds__(256) void dt_row_kernel(const DTItem* __restrict__ 
     const int p0 = (local % pc) * DT_ROW_PAIRS;
     const int yp = local / pc;                     // block-uniform
     if (yp >= I.Hp) return;
-    const int Wp = I.Wp, pitch = Wp + 1;
+    const int npb = min(DT_ROW_PAIRS, I.np - p0);  // pairs of this block
+    const int Wp = I.Wp;
+    const int half = (Wp + 2) >> 1;                // words per parity plane (odd pitch below)
+    const int hp = half | 1;
     const int64_t rs = I.ng;
     const float* rowbase = resp + I.resp_off + (int64_t)yp * Wp * rs;
-    // stage: thread (pair q = tid % 32, x phase = tid / 32) -> coalesced 128-byte reads
-    {
+    {   // stage: thread (pair q, x phase) -> coalesced 128-byte reads, 8 in flight
+        constexpr int XS = 256 / DT_ROW_PAIRS;
         const int q = threadIdx.x & (DT_ROW_PAIRS - 1), ph = threadIdx.x / DT_ROW_PAIRS;
-        const bool act = p0 + q < I.np;
+        const bool act = q < npb;
         const int fcol = act ? pairs[I.pair_base + p0 + q].fcol : 0;
         float M = -FLT_MAX;
-        for (int x = ph; x < Wp; x += 256 / DT_ROW_PAIRS) {
-            const float v = act ? rowbase[x * rs + fcol] : 0.f;
-            if (STAGED) sline[q * pitch + x] = v;
-            M = fmaxf(M, v);
+        for (int xb = ph; xb < Wp; xb += 8 * XS) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = rowbase[min(xb + u * XS, Wp - 1) * rs + fcol];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int x = xb + u * XS;
+                if (x < Wp) {
+                    const float vv = act ? v[u] : 0.f;
+                    if (STAGED) sline[(q * 2 + (x & 1)) * hp + (x >> 1)] = vv;
+                    M = fmaxf(M, vv);
+                }
+            }
         }
         smax[ph][q] = M;
     }
     __syncthreads();
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int q = wv; q < DT_ROW_PAIRS; q += 4) {
-        const int pidx = p0 + q;
-        if (pidx >= I.np) break;                   // wave-uniform
-        const PairDesc P = pairs[I.pair_base + pidx];
+    if (threadIdx.x < npb) {
+        const int q = threadIdx.x;
+        const PairDesc P = pairs[I.pair_base + p0 + q];
         float M = smax[0][q];
 #pragma unroll
         for (int i = 1; i < 8; ++i) M = fmaxf(M, smax[i][q]);
-        const int Wo_c = min(I.Wr - P.w0 + 1, I.Wt);
-        float* ov = r1v + I.r1_off + ((int64_t)pidx * I.Hp + yp) * I.Wt;
-        int32_t* oa = r1a + I.r1_off + ((int64_t)pidx * I.Hp + yp) * I.Wt;
-        const float* srow = sline + q * pitch;
-        const float* grow = rowbase + P.fcol;
-        for (int x0 = lane; x0 < Wo_c; x0 += 64) {
-            const int t = 2 * x0 + P.vx;
+        sc[q] = LineConst{P.d[1], P.d[0], 0.5f / P.d[1], 0.f, M};
+        sv[q] = make_int2(P.vx, min(I.Wr - P.w0 + 1, I.Wt));
+    }
+    __syncthreads();
+    const int Wt = I.Wt;
+    const int cols = min(Wt, 256);
+    const int qstep = 256 / cols;
+    const int x0s = threadIdx.x % cols, qs = threadIdx.x / cols;
+    if (qs >= qstep) return;
+    const int64_t obase = I.r1_off + ((int64_t)p0 * I.Hp + yp) * Wt;
+    const int64_t opair = (int64_t)I.Hp * Wt;
+    for (int q = qs; q < npb; q += qstep) {
+        const LineConst c = sc[q];
+        const int2 vw = sv[q];
+        const float* sp = sline + q * 2 * hp;
+        for (int x0 = x0s; x0 < vw.y; x0 += cols) {
+            const int t = 2 * x0 + vw.x;
             float best = -INFINITY;
             int arg = -1;
             if (t >= 0 && t < Wp) {
-                if (STAGED)
-                    best = window_max([&](int x) { return srow[x]; }, Wp, t, 0, P.d[1], P.d[0], M, arg);
-                else
-                    best = window_max([&](int x) { return grow[x * rs]; }, Wp, t, 0, P.d[1], P.d[0], M, arg);
+                int lo, hi;
+                if (STAGED) {
+                    auto ld = [&](int x) { return sp[(x & 1) * hp + (x >> 1)]; };
+                    dt_bounds(ld(t), c, t, 0, Wp, lo, hi);
+                    best = scan_range(ld, lo, hi, t, c.a, c.b, arg);
+                } else {
+                    const float* grow = rowbase + pairs[I.pair_base + p0 + q].fcol;
+                    auto ld = [&](int x) { return grow[x * rs]; };
+                    dt_bounds(ld(t), c, t, 0, Wp, lo, hi);
+                    best = scan_range(ld, lo, hi, t, c.a, c.b, arg);
+                }
             }
-            ov[x0] = best;
-            oa[x0] = arg;
+            r1v[obase + q * opair + x0] = best;
+            r1a[obase + q * opair + x0] = arg;
         }
     }
 }
 
-// Column pass: block = (item, pair, 64 root columns).  The block stages the
-// pair's row-pass output for its columns as [y'][64] (lane = column), then the
-// 4 wavefronts split the target rows y_t = 2*y0 + v_y.  Maximises the
-// row-pass value minus (d_y (y'-y_t) + d_yy (y'-y_t)^2) over y' and writes the
-// deformed part score and the (dy, dx) placement offset of (map, part, y0, x0)
-// straight into the caller's layout.
+// Column pass: block = (item, pair, chunk of cw root columns).  The block
+// stages the pair's row-pass output for its columns as [y'][cw] and the
+// column maxima, then thread (column j, segment s) takes the target rows
+// y_t = 2*y0 + v_y of one segment of y0, chaining the argmax from one target
+// to the next.  All lanes of a wavefront scan the union of their windows, so
+// every LDS read of the scan is one row of the tile (no bank conflicts) and
+// the loop is uniform.  Maximises the row-pass value minus
+// (d_y (y'-y_t) + d_yy (y'-y_t)^2) over y' and writes the deformed part score
+// and the (dy, dx) placement offset of (map, part, y0, x0) straight into the
+// caller's layout.
+__device__ __forceinline__ int wave_min_i(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
 template <bool STAGED>
 __global__ __launch_bounds__(256) void dt_col_kernel(const DTItem* __restrict__ items,
                                                      const int32_t* __restrict__ prefix,
@@ -450,58 +578,93 @@ __global__ __launch_bounds__(256) void dt_col_kernel(const DTItem* __restrict__ 
                                                      const int32_t* __restrict__ r1a,
                                                      float* __restrict__ dbuf,
                                                      int16_t* __restrict__ offs) {
-    extern __shared__ float sline[];               // [Hp][64] when STAGED
-    __shared__ float smax[4][64];
+    extern __shared__ float sline[];               // [Hp][cw] when STAGED
+    __shared__ float smax[256];
     const int it = find_item(prefix, n_items, blockIdx.x);
     const DTItem I = items[it];
     const int local = blockIdx.x - prefix[it];
-    const int xc = (I.Wt + 63) >> 6;
+    const int cw = I.cw;                           // columns per block
+    const int xc = (I.Wt + cw - 1) / cw;
     const int pidx = local / xc;                   // block-uniform
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int x0 = (local % xc) * 64 + lane;
-    if (pidx >= I.np) return;
+    const int xb = (local - pidx * xc) * cw;       // first column of the block
     const PairDesc P = pairs[I.pair_base + pidx];
     const MapDesc Md = maps[I.map_base + P.comp];
     const int Ho_c = Md.Ho, Wo_c = Md.Wo;
-    if (Ho_c <= 0 || (local % xc) * 64 >= Wo_c) return;   // block-uniform
+    if (Ho_c <= 0 || xb >= Wo_c) return;           // block-uniform
+    const int nseg = 256 / cw;                     // >= 1
+    const int j = threadIdx.x % cw, sg = threadIdx.x / cw;
+    const int x0 = xb + j;
     const int xt = 2 * x0 + P.vx;
     const bool colok = x0 < Wo_c && xt >= 0 && xt < I.Wp;
     const int Hp = I.Hp;
-    const float* col = r1v + I.r1_off + (int64_t)pidx * Hp * I.Wt + x0;   // element y' at col[y' * Wt]
+    const int64_t lbase = I.r1_off + (int64_t)pidx * Hp * I.Wt;   // this pair's [y'][Wt] plane
     float M = -FLT_MAX;
-    for (int y = wv; y < Hp; y += 4) {
-        const float v = colok ? col[(int64_t)y * I.Wt] : 0.f;
-        if (STAGED) sline[y * 64 + lane] = v;
-        M = fmaxf(M, v);
+    if (sg < nseg) {                               // 8 loads in flight per thread
+        const int64_t cbase = lbase + (colok ? x0 : 0);
+        for (int yb = sg; yb < Hp; yb += 8 * nseg) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = r1v[cbase + (int64_t)min(yb + u * nseg, Hp - 1) * I.Wt];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int y = yb + u * nseg;
+                if (y < Hp) {
+                    const float vv = colok ? v[u] : 0.f;
+                    if (STAGED) sline[y * cw + j] = vv;
+                    M = fmaxf(M, vv);
+                }
+            }
+        }
     }
-    smax[wv][lane] = M;
+    smax[threadIdx.x] = M;
     __syncthreads();
-    M = fmaxf(fmaxf(smax[0][lane], smax[1][lane]), fmaxf(smax[2][lane], smax[3][lane]));
-    if (x0 >= Wo_c) return;
-    const int chunk = (Ho_c + 3) >> 2;
-    const int k0 = wv * chunk, k1 = min(k0 + chunk, Ho_c);
+    const bool act = sg < nseg && x0 < Wo_c;
+    if (act)
+        for (int i = 0; i < nseg; ++i) M = fmaxf(M, smax[i * cw + j]);
+    const int chunk = (Ho_c + nseg - 1) / nseg;
+    const int k0 = sg * chunk, k1 = act ? min(k0 + chunk, Ho_c) : k0;
     const int64_t plane = (int64_t)Ho_c * Wo_c;
     float* dout = dbuf + (Md.offs_off >> 1) + P.slot * plane + x0;
     int32_t* oout = offs ? reinterpret_cast<int32_t*>(offs + Md.offs_off) + P.slot * plane + x0 : nullptr;
-    const float a = P.d[3], b = P.d[2];
+    const LineConst c{P.d[3], P.d[2], 0.5f / P.d[3], 0.f, M};
+    // a wavefront whose lanes all lie in one segment (same targets) scans the
+    // union of its lanes' windows; otherwise every lane scans its own window
+    const int wfirst = threadIdx.x & ~63;
+    const bool one_seg = wfirst / cw == (wfirst + 63) / cw;
+    const int kmax = wave_max_i(k1 - k0);
     int prev = 0;
-    for (int k = k0; k < k1; ++k) {
+    for (int kk = 0; kk < kmax; ++kk) {
+        const int k = k0 + kk;
+        const bool live = k < k1;
         const int t = 2 * k + P.vy;
-        float best = -INFINITY;
-        int32_t packed = 0;
-        if (colok && t >= 0 && t < Hp) {
-            int ay;
-            if (STAGED)
-                best = window_max([&](int y) { return sline[y * 64 + lane]; }, Hp, t, prev, a, b, M, ay);
-            else
-                best = window_max([&](int y) { return col[(int64_t)y * I.Wt]; }, Hp, t, prev, a, b, M, ay);
-            prev = ay;
-            const int dx = r1a[I.r1_off + ((int64_t)pidx * Hp + ay) * I.Wt + x0] - xt;
-            const int dy = ay - t;
-            packed = (int32_t)(((uint32_t)(uint16_t)(int16_t)dx << 16) | (uint16_t)(int16_t)dy);
+        const bool ok = live && colok && t >= 0 && t < Hp;
+        int lo = INT_MAX, hi = INT_MIN;
+        if (ok) {
+            if (STAGED) dt_bounds(sline[t * cw + j], c, t, prev, Hp, lo, hi);
+            else dt_bounds(r1v[lbase + (int64_t)t * I.Wt + x0], c, t, prev, Hp, lo, hi);
         }
-        dout[k * Wo_c] = best;
-        if (oout) oout[k * Wo_c] = packed;
+        const int LO = wave_min_i(lo), HI = wave_max_i(hi);
+        float best = -INFINITY;
+        int ay = -1;
+        if (ok) {
+            const int from = (STAGED && one_seg) ? LO : lo;
+            const int to = (STAGED && one_seg) ? HI : hi;
+            if (STAGED)
+                best = scan_range([&](int y) { return sline[y * cw + j]; }, from, to, t, c.a, c.b, ay);
+            else
+                best = scan_range([&](int y) { return r1v[lbase + (int64_t)y * I.Wt + x0]; }, from, to, t, c.a, c.b, ay);
+            prev = ay;
+        }
+        if (live) {
+            int32_t packed = 0;
+            if (ok) {
+                const int dx = r1a[lbase + (int64_t)ay * I.Wt + x0] - xt;
+                const int dy = ay - t;
+                packed = (int32_t)(((uint32_t)(uint16_t)(int16_t)dx << 16) | (uint16_t)(int16_t)dy);
+            }
+            dout[k * Wo_c] = best;
+            if (oout) oout[k * Wo_c] = packed;
+        }
     }
 }
 
@@ -535,7 +698,7 @@ hipError_t launch_dt_row(const DTItem* items, const int32_t* prefix, int n_items
                          const PairDesc* pairs, const float* resp, float* r1v, int32_t* r1a,
                          int max_line, hipStream_t st) {
     if (n_blocks <= 0) return hipSuccess;
-    const size_t lds = (size_t)(max_line + 1) * DT_ROW_PAIRS * sizeof(float);
+    const size_t lds = (size_t)((((max_line + 2) >> 1) | 1) * 2) * DT_ROW_PAIRS * sizeof(float);
     if (lds <= DT_STAGE_MAX) {
         hipError_t e = set_lds(dt_row_kernel<true>, lds);
         if (e != hipSuccess) return e;
@@ -553,7 +716,7 @@ hipError_t launch_dt_col(const DTItem* items, const int32_t* prefix, int n_items
                          const int32_t* r1a, float* dbuf, int16_t* offs, int max_line,
                          hipStream_t st) {
     if (n_blocks <= 0) return hipSuccess;
-    const size_t lds = (size_t)max_line * 64 * sizeof(float);
+    const size_t lds = (size_t)max_line * sizeof(float);    // largest Hp * cw
     if (lds <= DT_STAGE_MAX) {
         hipError_t e = set_lds(dt_col_kernel<true>, lds);
         if (e != hipSuccess) return e;
