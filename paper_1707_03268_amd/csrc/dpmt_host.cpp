@@ -40,6 +40,11 @@ struct ModeData {
     GroupDesc* dGroups = nullptr;
     std::vector<GroupDesc> groups;
     float* dU = nullptr;        // 32 x RP projection basis (tensor modes)
+    float* dMaster = nullptr;   // FP8: FP32 factors in operand order
+    RequantBlock* dRequant = nullptr;
+    int n_requant = 0;
+    float* dTk = nullptr;       // FP8: per-filter scales
+    float* dScales = nullptr;   // FP8: RP channel scales + channel-max scratch
     int max_h = 0, max_S = 0;   // over the groups used by score_pyramid
     // planned correlation tiles of this mode (valid for plan_id)
     int plan_id = -1;
@@ -131,7 +136,7 @@ struct dpmt_ctx {
     std::vector<int64_t> m_score_off, m_offs_off;
     std::vector<MapDesc> maps;
     std::vector<DTItem> dt_items;
-    std::vector<int32_t> row_prefix, col_prefix, asm_prefix;
+    std::vector<int2> row_blk, col_blk, asm_blk;   // per launched block: (work item, block within it)
     int row_blocks = 0, col_blocks = 0, asm_blocks = 0;
     int64_t r1_elems = 0;
     int max_Wp = 0;                     // longest DT row (row-pass LDS staging)
@@ -148,9 +153,9 @@ struct dpmt_ctx {
     PairDesc* d_pairs = nullptr;
     MapDesc* d_maps = nullptr;
     DTItem* d_items = nullptr;
-    int32_t* d_row_prefix = nullptr;
-    int32_t* d_col_prefix = nullptr;
-    int32_t* d_asm_prefix = nullptr;
+    int2* d_row_blk = nullptr;
+    int2* d_col_blk = nullptr;
+    int2* d_asm_blk = nullptr;
 
     // profiling: one set of 6 events per profiled call
     bool prof = false;
@@ -180,6 +185,10 @@ dpmt_status hip_fail(dpmt_ctx* c, hipError_t e, const char* what) {
     } while (0)
 
 void free_mode(ModeData& m) {
+    dfree(m.dMaster);
+    dfree(m.dRequant);
+    dfree(m.dTk);
+    dfree(m.dScales);
     dfree(m.dG);
     dfree(m.dGroups);
     dfree(m.dU);
@@ -195,9 +204,9 @@ void free_plan(dpmt_ctx* c) {
     dfree(c->d_Z); c->d_Z = nullptr; c->Z_bytes = 0;
     dfree(c->d_maps); c->d_maps = nullptr;
     dfree(c->d_items); c->d_items = nullptr;
-    dfree(c->d_row_prefix); c->d_row_prefix = nullptr;
-    dfree(c->d_col_prefix); c->d_col_prefix = nullptr;
-    dfree(c->d_asm_prefix); c->d_asm_prefix = nullptr;
+    dfree(c->d_row_blk); c->d_row_blk = nullptr;
+    dfree(c->d_col_blk); c->d_col_blk = nullptr;
+    dfree(c->d_asm_blk); c->d_asm_blk = nullptr;
     for (auto& m : c->modes) {
         dfree(m.dTiles);
         m.dTiles = nullptr;
@@ -210,6 +219,7 @@ void free_plan(dpmt_ctx* c) {
 // Channels padded to what the operand packing supports.
 int padded_rank(dpmt_mode mode, int R) {
     if (mode == DPMT_DIRECT_FP32) return 32;
+    if (mode == DPMT_TENSOR_FP8) return R <= 16 ? 16 : 32;
     if (R <= 4) return 4;
     if (R <= 8) return 8;
     if (R <= 16) return 16;
@@ -220,7 +230,7 @@ int padded_rank(dpmt_mode mode, int R) {
 Packing packing_for(dpmt_mode mode, int R) {
     Packing p{};
     p.RP = padded_rank(mode, R);
-    p.esz = (mode == DPMT_TENSOR_BF16) ? 2 : 4;
+    p.esz = (mode == DPMT_TENSOR_BF16) ? 2 : (mode == DPMT_TENSOR_FP8 ? 1 : 4);
     p.PB = std::min(p.RP * p.esz, 32);
     p.Q = p.RP * p.esz / p.PB;
     return p;
@@ -290,19 +300,27 @@ std::vector<double> operand_weights(const dpmt_ctx* c, int k, const Packing& pk,
 }
 
 // Pack every group's operand in MFMA B-fragment order:
-// [block][plane q][step s][filter row n][lane 0..63][16 bytes], lane = f + 32*j
-// holding bytes [32 s + 16 j, 32 s + 16 j + 16) of filter (32*block + f)'s
-// flattened plane-q row n (w cells x PB bytes, zero beyond).
+// [block][plane q][step s][filter row n][lane 0..63][FB bytes], lane = f + 32*j
+// holding bytes [2FB s + FB j, 2FB s + FB j + FB) of filter (32*block + f)'s
+// flattened plane-q row n (w cells x PB bytes, zero beyond).  FB is the
+// fragment width: 16 bytes for FP32/BF16, 32 for FP8.  FP8 operands are made
+// on the device at every call (their scales depend on the features), from an
+// FP32 master copy in the same element order.
 dpmt_status prepare_mode(dpmt_ctx* c, dpmt_mode mode) {
     ModeData& md = c->modes[mode];
     if (md.ready) return DPMT_OK;
     const bool tensor = mode != DPMT_DIRECT_FP32;
+    const bool fp8 = mode == DPMT_TENSOR_FP8;
     if (tensor && !c->decomposed) return fail(c, DPMT_E_STATE, "tensor mode needs dpmt_decompose first");
-    if (mode == DPMT_TENSOR_FP8) return fail(c, DPMT_E_UNSUPPORTED, "FP8 tensor mode is not built");
     md.pk = packing_for(mode, c->rank);
-    md.kind = (mode == DPMT_TENSOR_BF16) ? CORR_BF16 : CORR_F32;
+    md.kind = (mode == DPMT_TENSOR_BF16) ? CORR_BF16 : (fp8 ? CORR_FP8 : CORR_F32);
     const Packing pk = md.pk;
-    std::vector<unsigned char> G;
+    const int FB = fp8 ? 32 : 16;
+    const int KS = 2 * FB;
+    std::vector<unsigned char> G;       // FP32 / BF16 operand bytes
+    std::vector<float> master;          // FP8: FP32 values in operand element order
+    std::vector<RequantBlock> rq;
+    int t_slots = 0;
     md.groups.clear();
     md.max_h = md.max_S = 0;
     std::vector<std::vector<double>> opw(c->shapes.size());
@@ -312,40 +330,59 @@ dpmt_status prepare_mode(dpmt_ctx* c, dpmt_mode mode) {
         gd.h = hg.h;
         gd.w = hg.w;
         gd.ng = (int)hg.filters.size();
-        gd.S = (hg.w * pk.PB + 31) / 32;
-        gd.g_off = (int64_t)G.size();
+        gd.S = (hg.w * pk.PB + KS - 1) / KS;
+        const int nblk = (gd.ng + 31) / 32;
+        const int nblk_pad = (nblk + BB - 1) / BB * BB;
+        const size_t chunk = (size_t)64 * FB;      // bytes per (block, plane, step, row)
+        const size_t blk_bytes = (size_t)pk.Q * gd.S * gd.h * chunk;
+        const size_t base_elems = fp8 ? master.size() : G.size();
+        gd.g_off = (int64_t)base_elems;               // byte offset (FP8: one byte per element)
+        gd.t_off = t_slots;
+        t_slots += nblk_pad * 32;
         if (hg.role != ROLE_ALL) {
             md.max_h = std::max(md.max_h, gd.h);
             md.max_S = std::max(md.max_S, gd.S);
         }
-        const int nblk = (gd.ng + 31) / 32;
-        const int nblk_pad = (nblk + BB - 1) / BB * BB;
-        const size_t bytes = (size_t)nblk_pad * pk.Q * gd.S * gd.h * 1024;
-        G.resize(G.size() + bytes, 0);
-        unsigned char* base = G.data() + gd.g_off;
+        if (fp8) master.resize(master.size() + nblk_pad * blk_bytes, 0.f);
+        else G.resize(G.size() + nblk_pad * blk_bytes, 0);
+        for (int b = 0; b < nblk_pad && fp8; ++b) {
+            RequantBlock r{};
+            r.m_off = (int64_t)(base_elems + b * blk_bytes);
+            r.g_off = (int64_t)(base_elems + b * blk_bytes);
+            r.chunks = pk.Q * gd.S * gd.h;
+            r.h = gd.h;
+            r.S = gd.S;
+            r.ng = gd.ng;
+            r.f0 = b * 32;
+            r.t_off = gd.t_off + b * 32;
+            rq.push_back(r);
+        }
         for (int fi = 0; fi < gd.ng; ++fi) {
             const int k = hg.filters[fi];
             if (opw[k].empty()) opw[k] = operand_weights(c, k, pk, tensor);
             const std::vector<double>& wv = opw[k];
             const int blk = fi / 32, f = fi % 32;
             for (int q = 0; q < pk.Q; ++q)
-                for (int s = 0; s < gd.S; ++s)
+                for (int sx = 0; sx < gd.S; ++sx)
                     for (int n = 0; n < gd.h; ++n)
                         for (int j = 0; j < 2; ++j) {
-                            unsigned char* dst = base + ((((size_t)blk * pk.Q + q) * gd.S + s) * gd.h + n) * 1024 +
-                                                 (size_t)(f + 32 * j) * 16;
-                            for (int e = 0; e < 16 / pk.esz; ++e) {
-                                const int o = 32 * s + 16 * j + e * pk.esz;   // flattened byte
+                            const size_t unit = base_elems + blk * blk_bytes +
+                                                (((size_t)q * gd.S + sx) * gd.h + n) * chunk +
+                                                (size_t)(f + 32 * j) * FB;
+                            for (int e = 0; e < FB / pk.esz; ++e) {
+                                const int o = KS * sx + FB * j + e * pk.esz;   // flattened byte
                                 const int m = o / pk.PB;
                                 const int ch = q * (pk.PB / pk.esz) + (o % pk.PB) / pk.esz;
                                 if (m >= gd.w) continue;
                                 const double v = wv[((size_t)n * gd.w + m) * pk.RP + ch];
-                                if (pk.esz == 4) {
+                                if (fp8) {
+                                    master[unit + e] = (float)v;
+                                } else if (pk.esz == 4) {
                                     const float fv = (float)v;
-                                    std::memcpy(dst + e * 4, &fv, 4);
+                                    std::memcpy(G.data() + unit + e * 4, &fv, 4);
                                 } else {
                                     const uint16_t bv = f32_to_bf16((float)v);
-                                    std::memcpy(dst + e * 2, &bv, 2);
+                                    std::memcpy(G.data() + unit + e * 2, &bv, 2);
                                 }
                             }
                         }
@@ -354,9 +391,17 @@ dpmt_status prepare_mode(dpmt_ctx* c, dpmt_mode mode) {
     }
     if (c->has_device()) {
         HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
-        std::vector<unsigned char> Gv(G);
-        HIP_TRY(c, upload(reinterpret_cast<unsigned char**>(&md.dG), Gv), "upload packed filters");
         HIP_TRY(c, upload(&md.dGroups, md.groups), "upload group table");
+        if (fp8) {
+            HIP_TRY(c, upload(&md.dMaster, master), "upload FP8 master factors");
+            HIP_TRY(c, upload(&md.dRequant, rq), "upload requant table");
+            md.n_requant = (int)rq.size();
+            HIP_TRY(c, hipMalloc(&md.dG, std::max<size_t>(master.size(), 16)), "allocate FP8 operand");
+            HIP_TRY(c, hipMalloc((void**)&md.dTk, (size_t)std::max(t_slots, 1) * 4), "allocate FP8 filter scales");
+            HIP_TRY(c, hipMalloc((void**)&md.dScales, (size_t)(pk.RP + FP8_PARTIALS) * 4), "allocate FP8 channel scales");
+        } else {
+            HIP_TRY(c, upload(reinterpret_cast<unsigned char**>(&md.dG), G), "upload packed filters");
+        }
         if (tensor) {
             std::vector<float> U((size_t)32 * pk.RP, 0.f);
             for (int l = 0; l < 32; ++l)
@@ -366,6 +411,19 @@ dpmt_status prepare_mode(dpmt_ctx* c, dpmt_mode mode) {
     }
     md.ready = true;
     return DPMT_OK;
+}
+
+// FP8 mode: channel maxima of the given cells, channel scales, requantised
+// factors, then the scaled projection of the same cells into Z.
+hipError_t fp8_operands(dpmt_ctx* c, ModeData& md, const float* X, int64_t n_cells, void* Z,
+                        hipStream_t st) {
+    float* scales = md.dScales;
+    float* partial = md.dScales + md.pk.RP;
+    hipError_t e = launch_fp8_prepare(X, n_cells, md.dU, md.pk.RP, partial, scales, md.dRequant,
+                                      md.n_requant, md.dMaster, static_cast<uint8_t*>(md.dG),
+                                      md.dTk, st);
+    if (e != hipSuccess) return e;
+    return launch_project_fp8(X, n_cells, md.dU, md.pk.RP, scales, Z, st);
 }
 
 void build_groups(dpmt_ctx* c) {
@@ -806,20 +864,27 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
             }
         }
     }
-    c->row_prefix.clear(); c->col_prefix.clear(); c->asm_prefix.clear();
+    c->row_blk.clear(); c->col_blk.clear(); c->asm_blk.clear();
     c->max_Wp = c->max_Hp = 0;
     int64_t rb = 0, cb = 0, ab = 0;
-    for (const DTItem& it : c->dt_items) {
-        c->row_prefix.push_back((int32_t)rb);
-        c->col_prefix.push_back((int32_t)cb);
-        rb += (int64_t)((it.np + DT_ROW_PAIRS_PER_BLOCK - 1) / DT_ROW_PAIRS_PER_BLOCK) * it.Hp;
-        cb += (int64_t)it.np * ((it.Wt + it.cw - 1) / it.cw);
+    for (size_t k = 0; k < c->dt_items.size(); ++k) {
+        const DTItem& it = c->dt_items[k];
+        const int64_t nr = (int64_t)((it.np + DT_ROW_PAIRS_PER_BLOCK - 1) / DT_ROW_PAIRS_PER_BLOCK) * it.Hp;
+        const int64_t nc = (int64_t)it.np * ((it.Wt + it.cw - 1) / it.cw);
+        rb += nr;
+        cb += nc;
+        if (rb > INT32_MAX || cb > INT32_MAX) break;
+        for (int64_t b = 0; b < nr; ++b) c->row_blk.push_back(make_int2((int)k, (int)b));
+        for (int64_t b = 0; b < nc; ++b) c->col_blk.push_back(make_int2((int)k, (int)b));
         c->max_Wp = std::max(c->max_Wp, it.Wp);
         c->max_Hp = std::max<int64_t>(c->max_Hp, (int64_t)it.Hp * it.cw);
     }
-    for (const MapDesc& md : c->maps) {
-        c->asm_prefix.push_back((int32_t)ab);
-        ab += ((int64_t)md.Ho * md.Wo + ASM_BLOCK - 1) / ASM_BLOCK;
+    for (size_t k = 0; k < c->maps.size() && ab <= INT32_MAX; ++k) {
+        const MapDesc& md = c->maps[k];
+        const int64_t na = ((int64_t)md.Ho * md.Wo + ASM_BLOCK - 1) / ASM_BLOCK;
+        ab += na;
+        if (ab > INT32_MAX) break;
+        for (int64_t b = 0; b < na; ++b) c->asm_blk.push_back(make_int2((int)k, (int)b));
     }
     if (rb > INT32_MAX || cb > INT32_MAX || ab > INT32_MAX)
         return fail(c, DPMT_E_UNSUPPORTED, "batch too large for one launch");
@@ -859,9 +924,9 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
         if ((s = alloc((void**)&c->d_dbuf, (offs_off / 2) * 4, "allocate part scores")) != DPMT_OK) return s;
         HIP_TRY(c, upload(&c->d_maps, c->maps), "upload maps");
         HIP_TRY(c, upload(&c->d_items, c->dt_items), "upload DT items");
-        HIP_TRY(c, upload(&c->d_row_prefix, c->row_prefix), "upload prefix");
-        HIP_TRY(c, upload(&c->d_col_prefix, c->col_prefix), "upload prefix");
-        HIP_TRY(c, upload(&c->d_asm_prefix, c->asm_prefix), "upload prefix");
+        HIP_TRY(c, upload(&c->d_row_blk, c->row_blk), "upload block map");
+        HIP_TRY(c, upload(&c->d_col_blk, c->col_blk), "upload block map");
+        HIP_TRY(c, upload(&c->d_asm_blk, c->asm_blk), "upload block map");
     }
     c->planned = true;
     *out = &c->layout;
@@ -939,17 +1004,19 @@ dpmt_status dpmt_score_pyramid(dpmt_ctx* c, dpmt_mode mode, const float* feature
     }
     const bool prof = ev != nullptr;
     if (prof) HIP_TRY(c, hipEventRecord(ev[0], st), "hipEventRecord");
-    if (tensor)
+    if (mode == DPMT_TENSOR_FP8)
+        HIP_TRY(c, fp8_operands(c, md, features_dev, c->n_cells, c->d_Z, st), "FP8 operand launch");
+    else if (tensor)
         HIP_TRY(c, launch_project(md.pk.esz == 2, features_dev, c->n_cells, md.dU, md.pk.RP, c->d_Z, st), "projection launch");
     if (prof) HIP_TRY(c, hipEventRecord(ev[1], st), "hipEventRecord");
     CorrLaunch cl{md.kind, md.pk, TY, BB, WY};
-    HIP_TRY(c, launch_corr(cl, md.dTiles, md.n_tiles, md.dGroups, Zsrc, md.dG, c->d_resp, md.max_h, md.max_S, st), "correlation launch");
+    HIP_TRY(c, launch_corr(cl, md.dTiles, md.n_tiles, md.dGroups, Zsrc, md.dG, md.dTk, c->d_resp, md.max_h, md.max_S, st), "correlation launch");
     if (prof) HIP_TRY(c, hipEventRecord(ev[2], st), "hipEventRecord");
-    HIP_TRY(c, launch_dt_row(c->d_items, c->d_row_prefix, (int)c->dt_items.size(), c->row_blocks, c->d_pairs, c->d_resp, c->d_r1v, c->d_r1a, c->max_Wp, st), "DT row launch");
+    HIP_TRY(c, launch_dt_row(c->d_items, c->d_row_blk, c->row_blocks, c->d_pairs, c->d_resp, c->d_r1v, c->d_r1a, c->max_Wp, st), "DT row launch");
     if (prof) HIP_TRY(c, hipEventRecord(ev[3], st), "hipEventRecord");
-    HIP_TRY(c, launch_dt_col(c->d_items, c->d_col_prefix, (int)c->dt_items.size(), c->col_blocks, c->d_pairs, c->d_maps, c->d_r1v, c->d_r1a, c->d_dbuf, offsets_dev, (int)std::min<int64_t>(c->max_Hp, INT32_MAX), st), "DT column launch");
+    HIP_TRY(c, launch_dt_col(c->d_items, c->d_col_blk, c->col_blocks, c->d_pairs, c->d_maps, c->d_r1v, c->d_r1a, c->d_dbuf, offsets_dev, (int)std::min<int64_t>(c->max_Hp, INT32_MAX), st), "DT column launch");
     if (prof) HIP_TRY(c, hipEventRecord(ev[4], st), "hipEventRecord");
-    HIP_TRY(c, launch_assemble(c->d_maps, c->d_asm_prefix, (int)c->maps.size(), c->asm_blocks, c->d_resp, c->d_dbuf, scores_dev, st), "assembly launch");
+    HIP_TRY(c, launch_assemble(c->d_maps, c->d_asm_blk, c->asm_blocks, c->d_resp, c->d_dbuf, scores_dev, st), "assembly launch");
     if (prof) HIP_TRY(c, hipEventRecord(ev[5], st), "hipEventRecord");
     return DPMT_OK;
 }
@@ -1014,13 +1081,16 @@ dpmt_status dpmt_level_responses(dpmt_ctx* c, dpmt_mode mode, const float* featu
     const void* Zsrc = features_dev + lv.cell_offset * 32;
     if (tensor) {
         e = hipMalloc(&dZ, (size_t)cells * md.pk.RP * md.pk.esz);
-        if (e == hipSuccess) e = launch_project(md.pk.esz == 2, features_dev + lv.cell_offset * 32, cells, md.dU, md.pk.RP, dZ, st);
+        if (e == hipSuccess) {
+            if (mode == DPMT_TENSOR_FP8) e = fp8_operands(c, md, features_dev + lv.cell_offset * 32, cells, dZ, st);
+            else e = launch_project(md.pk.esz == 2, features_dev + lv.cell_offset * 32, cells, md.dU, md.pk.RP, dZ, st);
+        }
         Zsrc = dZ;
     }
     if (e == hipSuccess) e = hipMalloc((void**)&dblk, (size_t)blk_total * 4);
     if (e == hipSuccess) e = upload(&dtiles, tiles);
     CorrLaunch cl{md.kind, md.pk, TY, BB, WY};
-    if (e == hipSuccess) e = launch_corr(cl, dtiles, (int)tiles.size(), md.dGroups, Zsrc, md.dG, dblk, max_h, max_S, st);
+    if (e == hipSuccess) e = launch_corr(cl, dtiles, (int)tiles.size(), md.dGroups, Zsrc, md.dG, md.dTk, dblk, max_h, max_S, st);
     for (const auto& gb : gblocks) {
         if (e != hipSuccess) break;
         const HostGroup& hg = c->groups[gb.first];

@@ -22,8 +22,21 @@ struct Packing {
 struct GroupDesc {
     int32_t h, w;      // filter rows, cols
     int32_t ng;        // filters in the group
-    int32_t S;         // 32-byte K-steps per filter row per plane
+    int32_t S;         // K-steps per filter row per plane (32 bytes; 64 for FP8)
     int64_t g_off;     // byte offset of the group's packed operand in the G buffer
+    int32_t t_off;     // first per-filter scale of the group (FP8)
+    int32_t pad;
+};
+
+// One 32-filter block of a group, for the per-call FP8 requantisation.
+struct RequantBlock {
+    int64_t m_off;     // float offset of the block's FP32 master factors
+    int64_t g_off;     // byte offset of the block's FP8 operand
+    int32_t chunks;    // Q * S * h chunks of 64 lanes x 32 elements
+    int32_t h, S;
+    int32_t ng;        // filters in the group
+    int32_t f0;        // first filter column of the block
+    int32_t t_off;     // scale slot of the block's first filter
 };
 
 // One workgroup tile of the correlation: TYWG output rows x 32 output cols x
@@ -88,17 +101,24 @@ struct CorrLaunch {
 hipError_t launch_project(bool bf16, const float* X, int64_t n_cells, const float* U,
                           int RP, void* Z, hipStream_t st);
 hipError_t launch_corr(const CorrLaunch& cfg, const CorrTile* tiles, int n_tiles,
-                       const GroupDesc* groups, const void* Z, const void* G, float* out,
-                       int max_h, int max_S, hipStream_t st);
+                       const GroupDesc* groups, const void* Z, const void* G, const float* tk,
+                       float* out, int max_h, int max_S, hipStream_t st);
+hipError_t launch_fp8_prepare(const float* X, int64_t n_cells, const float* U, int RP,
+                              float* partial, float* scales, const RequantBlock* blocks,
+                              int n_blocks, const float* master, uint8_t* G, float* tk,
+                              hipStream_t st);
+hipError_t launch_project_fp8(const float* X, int64_t n_cells, const float* U, int RP,
+                              const float* scales, void* Z, hipStream_t st);
+constexpr int FP8_PARTIALS = 512 * 32;   // floats of the channel-max scratch
 size_t corr_lds_bytes(const CorrLaunch& cfg, int h, int S);
-hipError_t launch_dt_row(const DTItem* items, const int32_t* prefix, int n_items, int n_blocks,
+hipError_t launch_dt_row(const DTItem* items, const int2* blkmap, int n_blocks,
                          const PairDesc* pairs, const float* resp, float* r1v, int32_t* r1a,
                          int max_line, hipStream_t st);
-hipError_t launch_dt_col(const DTItem* items, const int32_t* prefix, int n_items, int n_blocks,
+hipError_t launch_dt_col(const DTItem* items, const int2* blkmap, int n_blocks,
                          const PairDesc* pairs, const MapDesc* maps, const float* r1v,
                          const int32_t* r1a, float* dbuf, int16_t* offs, int max_line,
                          hipStream_t st);
-hipError_t launch_assemble(const MapDesc* maps, const int32_t* prefix, int n_maps, int n_blocks,
+hipError_t launch_assemble(const MapDesc* maps, const int2* blkmap, int n_blocks,
                            const float* rresp, const float* dbuf, float* scores, hipStream_t st);
 hipError_t launch_block_to_maps(const float* block, int64_t n_pos, int ng, const int64_t* dst_off,
                                 float* out, hipStream_t st);

@@ -99,6 +99,13 @@ constexpr int CORR_MAX_H = 16;
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x8 __attribute__((ext_vector_type(8)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+
+// Per-lane operand fragment: 16 bytes (FP32: 4 x K=1 steps of 32x32x2; BF16:
+// 8 values of 32x32x16) or 32 bytes (FP8: 32 values of 32x32x64).
+template <CorrKind KIND> struct FragT { typedef u32x4 type; static constexpr int bytes = 16; };
+template <> struct FragT<CORR_FP8> { typedef u32x8 type; static constexpr int bytes = 32; };
 
 __device__ __forceinline__ u32x4 lds_load16(const char* p, int pb) {
     if (pb >= 16) return *reinterpret_cast<const u32x4*>(p);
@@ -108,44 +115,67 @@ __device__ __forceinline__ u32x4 lds_load16(const char* p, int pb) {
 }
 
 template <CorrKind KIND>
-__device__ __forceinline__ v16f mfma_step(const u32x4& a, const u32x4& b, v16f c) {
+__device__ __forceinline__ v16f mfma_step(const typename FragT<KIND>::type& a,
+                                          const typename FragT<KIND>::type& b, v16f c) {
     if constexpr (KIND == CORR_F32) {
         c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.x), __uint_as_float(b.x), c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.y), __uint_as_float(b.y), c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.z), __uint_as_float(b.z), c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_32x32x2f32(__uint_as_float(a.w), __uint_as_float(b.w), c, 0, 0, 0);
         return c;
-    } else {
+    } else if constexpr (KIND == CORR_BF16) {
         v8bf av, bv;
         __builtin_memcpy(&av, &a, 16);
         __builtin_memcpy(&bv, &b, 16);
         return __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, c, 0, 0, 0);
+    } else {
+        // OCP e4m3 operands (format 0 for A and B), unit block scales (E8M0 127)
+        i32x8 av, bv;
+        __builtin_memcpy(&av, &a, 32);
+        __builtin_memcpy(&bv, &b, 32);
+        return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(av, bv, c, 0, 0, 0, 127, 0, 127);
+    }
+}
+
+// Fragment load from LDS at the alignment the plane width allows.
+template <CorrKind KIND>
+__device__ __forceinline__ typename FragT<KIND>::type lds_frag(const char* p, int pb) {
+    if constexpr (FragT<KIND>::bytes == 16) {
+        return lds_load16(p, pb);
+    } else {
+        const u32x4 lo = lds_load16(p, pb), hi = lds_load16(p + 16, pb);
+        return u32x8{lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
     }
 }
 
 template <CorrKind KIND, int PB, int TY, int BB, int WY, int HMAX>
-__global__ __launch_bounds__(64 * WY) __attribute__((amdgpu_waves_per_eu(HMAX <= 8 ? 2 : 1))) void corr_kernel(const CorrTile* __restrict__ tiles,
+__global__ __launch_bounds__(64 * WY) __attribute__((amdgpu_waves_per_eu((HMAX <= 8 && KIND != CORR_FP8) ? 2 : 1))) void corr_kernel(const CorrTile* __restrict__ tiles,
                                                        const GroupDesc* __restrict__ groups,
                                                        const char* __restrict__ Z,
                                                        const char* __restrict__ G,
+                                                       const float* __restrict__ tk,
                                                        float* __restrict__ out, int cell_bytes,
                                                        int Q, int win_bytes) {
     extern __shared__ __align__(16) char smem[];
     constexpr int NT = 64 * WY;
     constexpr int TYWG = TY * WY;
     constexpr int CH = PB >= 16 ? 16 : 8;          // window copy granule
-    constexpr int PFMAX = (BB * HMAX * 64 + NT - 1) / NT;   // chunk u32x4 per thread, h <= HMAX
+    constexpr int FB = FragT<KIND>::bytes;         // fragment bytes per lane
+    constexpr int KS = 2 * FB;                     // flattened row bytes per K-step
+    constexpr int CU = 4 * FB;                     // u32x4 per (block, plane, step, row) chunk
+    typedef typename FragT<KIND>::type Frag;
+    constexpr int PFMAX = (BB * HMAX * CU + NT - 1) / NT;   // chunk u32x4 per thread, h <= HMAX
     constexpr int WBATCH = 4;                      // window loads in flight per thread
 
     const CorrTile t = tiles[blockIdx.x];
     const GroupDesc g = groups[t.group];
     const int h = g.h, S = g.S;
-    const int WC = 31 + (32 * S) / PB;             // window cells per row
+    const int WC = 31 + (KS * S) / PB;             // window cells per row
     const int pitch = WC * PB;
     const int nrows = TYWG + h - 1;
     char* win = smem;
     u32x4* gbuf0 = reinterpret_cast<u32x4*>(smem + win_bytes);
-    u32x4* gbuf1 = gbuf0 + BB * h * 64;
+    u32x4* gbuf1 = gbuf0 + BB * h * CU;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
@@ -159,7 +189,7 @@ __global__ __launch_bounds__(64 * WY) __attribute__((amdgpu_waves_per_eu(HMAX <=
 #pragma unroll
             for (int k = 0; k < 16; ++k) acc[i][b][k] = 0.f;
 
-    const int n_chunk = BB * h * 64;               // u32x4 per G chunk
+    const int n_chunk = BB * h * CU;               // u32x4 per G chunk
     const int total = Q * S;
     // element i of chunk `step`: [b][n][lane] of the packed operand.  Indices
     // past the chunk are clamped to its last element, for the load and for the
@@ -167,12 +197,12 @@ __global__ __launch_bounds__(64 * WY) __attribute__((amdgpu_waves_per_eu(HMAX <=
     auto chunk_src = [&](int step, int i) -> const u32x4* {
         i = min(i, n_chunk - 1);
         const int q = step / S, s = step - q * S;
-        const int l = i & 63;
-        const int n = (i >> 6) % h;
-        const int b = i / (64 * h);
+        const int l = i % CU;
+        const int n = (i / CU) % h;
+        const int b = i / (CU * h);
         const int64_t blk = t.fb0 + b;
         return reinterpret_cast<const u32x4*>(
-                   G + g.g_off + ((((blk * Q + q) * S + s) * (int64_t)h + n) << 10)) + l;
+                   G + g.g_off + (((blk * Q + q) * S + s) * (int64_t)h + n) * (64 * FB)) + l;
     };
 
     // prologue: chunk 0 straight into buffer 0
@@ -233,20 +263,22 @@ __global__ __launch_bounds__(64 * WY) __attribute__((amdgpu_waves_per_eu(HMAX <=
         for (int k = 0; k < PFMAX; ++k) pf[k] = *chunk_src(nstep, tid + k * NT);
 
         const u32x4* gb = (step & 1) ? gbuf1 : gbuf0;
-        const char* abase = win + (wv * TY) * pitch + p * PB + 32 * s + 16 * j;
-        u32x4 A[TY];
+        const char* abase = win + (wv * TY) * pitch + p * PB + KS * s + FB * j;
+        const char* gbb = reinterpret_cast<const char*>(gb) + lane * FB;
+        Frag A[TY];
 #pragma unroll
-        for (int i = 0; i < TY; ++i) A[i] = lds_load16(abase + i * pitch, PB);
-        u32x4 B[BB];
+        for (int i = 0; i < TY; ++i) A[i] = lds_frag<KIND>(abase + i * pitch, PB);
+        Frag B[BB];
 #pragma unroll
-        for (int b = 0; b < BB; ++b) B[b] = gb[(b * h) * 64 + lane];
+        for (int b = 0; b < BB; ++b) B[b] = *reinterpret_cast<const Frag*>(gbb + (b * h) * (64 * FB));
         for (int n = 0; n < h; ++n) {
-            u32x4 Bn[BB], An;
+            Frag Bn[BB], An;
             const bool nx = n + 1 < h;
             if (nx) {
 #pragma unroll
-                for (int b = 0; b < BB; ++b) Bn[b] = gb[(b * h + n + 1) * 64 + lane];
-                An = lds_load16(abase + (n + TY) * pitch, PB);
+                for (int b = 0; b < BB; ++b)
+                    Bn[b] = *reinterpret_cast<const Frag*>(gbb + (b * h + n + 1) * (64 * FB));
+                An = lds_frag<KIND>(abase + (n + TY) * pitch, PB);
             }
 #pragma unroll
             for (int i = 0; i < TY; ++i)
@@ -278,31 +310,37 @@ __global__ __launch_bounds__(64 * WY) __attribute__((amdgpu_waves_per_eu(HMAX <=
             const int f = (t.fb0 + b) * 32 + p;
             if (f >= g.ng) continue;
             float* orow = out + t.out_off + (int64_t)y * t.Wo * g.ng + f;
+            const float sc = (KIND == CORR_FP8) ? tk[g.t_off + f] : 1.f;
 #pragma unroll
             for (int k = 0; k < 16; ++k) {
                 const int x = t.x0 + 8 * (k >> 2) + 4 * j + (k & 3);
-                if (x < t.Wo) orow[(int64_t)x * g.ng] = acc[i][b][k];
+                if (x < t.Wo) orow[(int64_t)x * g.ng] = (KIND == CORR_FP8) ? acc[i][b][k] * sc : acc[i][b][k];
             }
         }
     }
 }
 
+static int frag_bytes(CorrKind k) { return k == CORR_FP8 ? 32 : 16; }
+
 size_t corr_lds_bytes(const CorrLaunch& cfg, int h, int S) {
-    const int WC = 31 + (32 * S) / cfg.pk.PB;
+    const int FB = frag_bytes(cfg.kind);
+    const int WC = 31 + (2 * FB * S) / cfg.pk.PB;
     const size_t win = (size_t)(cfg.ty * cfg.wy + h - 1) * WC * cfg.pk.PB;
     const size_t winal = (win + 15) & ~size_t(15);
-    return winal + 2 * (size_t)cfg.bb * h * 1024;
+    return winal + 2 * (size_t)cfg.bb * h * 64 * FB;
 }
 
 template <CorrKind KIND, int PB, int TY, int BB, int WY, int HMAX>
 static hipError_t launch_corr_h(const CorrTile* tiles, int n_tiles, const GroupDesc* groups,
-                                const void* Z, const void* G, float* out, int cell_bytes, int Q,
-                                int max_h, int max_S, hipStream_t st) {
+                                const void* Z, const void* G, const float* tk, float* out,
+                                int cell_bytes, int Q, int max_h, int max_S, hipStream_t st) {
     CorrLaunch cfg{KIND, Packing{0, 0, PB, Q}, TY, BB, WY};
     const size_t lds = corr_lds_bytes(cfg, max_h, max_S);
-    const int WC = 31 + (32 * max_S) / PB;
+    const int FB = FragT<KIND>::bytes;
+    const int WC = 31 + (2 * FB * max_S) / PB;
     const size_t win = (size_t)(TY * WY + max_h - 1) * WC * PB;
     const int win_bytes = (int)((win + 15) & ~size_t(15));
+    if (lds > 160 * 1024) return hipErrorInvalidValue;
     auto kern = corr_kernel<KIND, PB, TY, BB, WY, HMAX>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -310,8 +348,8 @@ static hipError_t launch_corr_h(const CorrTile* tiles, int n_tiles, const GroupD
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(kern, dim3(n_tiles), dim3(64 * WY), lds, st, tiles, groups,
-                       static_cast<const char*>(Z), static_cast<const char*>(G), out, cell_bytes,
-                       Q, win_bytes);
+                       static_cast<const char*>(Z), static_cast<const char*>(G), tk, out,
+                       cell_bytes, Q, win_bytes);
     return hipGetLastError();
 }
 
@@ -319,38 +357,211 @@ static hipError_t launch_corr_h(const CorrTile* tiles, int n_tiles, const GroupD
 // chunk prefetch needs half the registers.
 template <CorrKind KIND, int PB, int TY, int BB, int WY>
 static hipError_t launch_corr_t(const CorrTile* tiles, int n_tiles, const GroupDesc* groups,
-                                const void* Z, const void* G, float* out, int cell_bytes, int Q,
-                                int max_h, int max_S, hipStream_t st) {
+                                const void* Z, const void* G, const float* tk, float* out,
+                                int cell_bytes, int Q, int max_h, int max_S, hipStream_t st) {
     if (max_h <= 8)
-        return launch_corr_h<KIND, PB, TY, BB, WY, 8>(tiles, n_tiles, groups, Z, G, out,
+        return launch_corr_h<KIND, PB, TY, BB, WY, 8>(tiles, n_tiles, groups, Z, G, tk, out,
                                                       cell_bytes, Q, max_h, max_S, st);
-    return launch_corr_h<KIND, PB, TY, BB, WY, CORR_MAX_H>(tiles, n_tiles, groups, Z, G, out,
+    return launch_corr_h<KIND, PB, TY, BB, WY, CORR_MAX_H>(tiles, n_tiles, groups, Z, G, tk, out,
                                                            cell_bytes, Q, max_h, max_S, st);
 }
 
 hipError_t launch_corr(const CorrLaunch& cfg, const CorrTile* tiles, int n_tiles,
-                       const GroupDesc* groups, const void* Z, const void* G, float* out,
-                       int max_h, int max_S, hipStream_t st) {
+                       const GroupDesc* groups, const void* Z, const void* G, const float* tk,
+                       float* out, int max_h, int max_S, hipStream_t st) {
     if (n_tiles <= 0) return hipSuccess;
     if (max_h > CORR_MAX_H) return hipErrorInvalidValue;
     if (cfg.ty != 4 || cfg.bb != 2 || cfg.wy != 4) return hipErrorInvalidValue;
     const int cb = cfg.pk.RP * cfg.pk.esz;
     const int Q = cfg.pk.Q;
+#define DPMT_CORR(K, P) \
+    case P: return launch_corr_t<K, P, 4, 2, 4>(tiles, n_tiles, groups, Z, G, tk, out, cb, Q, max_h, max_S, st);
     if (cfg.kind == CORR_F32) {
-        switch (cfg.pk.PB) {
-            case 16: return launch_corr_t<CORR_F32, 16, 4, 2, 4>(tiles, n_tiles, groups, Z, G, out, cb, Q, max_h, max_S, st);
-            case 32: return launch_corr_t<CORR_F32, 32, 4, 2, 4>(tiles, n_tiles, groups, Z, G, out, cb, Q, max_h, max_S, st);
-            default: return hipErrorInvalidValue;
-        }
+        switch (cfg.pk.PB) { DPMT_CORR(CORR_F32, 16) DPMT_CORR(CORR_F32, 32) default: break; }
     } else if (cfg.kind == CORR_BF16) {
-        switch (cfg.pk.PB) {
-            case 8: return launch_corr_t<CORR_BF16, 8, 4, 2, 4>(tiles, n_tiles, groups, Z, G, out, cb, Q, max_h, max_S, st);
-            case 16: return launch_corr_t<CORR_BF16, 16, 4, 2, 4>(tiles, n_tiles, groups, Z, G, out, cb, Q, max_h, max_S, st);
-            case 32: return launch_corr_t<CORR_BF16, 32, 4, 2, 4>(tiles, n_tiles, groups, Z, G, out, cb, Q, max_h, max_S, st);
-            default: return hipErrorInvalidValue;
+        switch (cfg.pk.PB) { DPMT_CORR(CORR_BF16, 8) DPMT_CORR(CORR_BF16, 16) DPMT_CORR(CORR_BF16, 32) default: break; }
+    } else if (cfg.kind == CORR_FP8) {
+        switch (cfg.pk.PB) { DPMT_CORR(CORR_FP8, 16) DPMT_CORR(CORR_FP8, 32) default: break; }
+    }
+#undef DPMT_CORR
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// FP8 (OCP e4m3) operands with per-channel scales
+//
+// The contraction runs over projected channels r, so a scale per channel
+// cannot be applied after the sum; it is folded into the filter factors
+// instead.  Per call:
+//   xmax_l = max over cells |X[c][l]|                       (fp8_chanmax_*)
+//   s_r    = sum_l |U[l][r]| * xmax_l / 448 >= max_c |Z[c][r]| / 448, so
+//            Zq = e4m3(Z / s_r) never overflows             (fp8_scales)
+//   t_k    = max |G_k * s| / 448 per filter k,
+//   Gq_k   = e4m3(G_k * s / t_k)                            (fp8_requant)
+//   resp_k = t_k * sum Gq_k Zq                               (corr epilogue)
+// Conversions round to nearest even after an explicit clamp to +-448 (the
+// hardware conversion does not saturate).
+// ---------------------------------------------------------------------------
+constexpr float FP8_MAX = 448.f;
+constexpr int CHANMAX_BLOCKS = 512;
+
+__device__ __forceinline__ uint32_t fp8x4(float a, float b, float c, float d) {
+    a = fminf(fmaxf(a, -FP8_MAX), FP8_MAX);
+    b = fminf(fmaxf(b, -FP8_MAX), FP8_MAX);
+    c = fminf(fmaxf(c, -FP8_MAX), FP8_MAX);
+    d = fminf(fmaxf(d, -FP8_MAX), FP8_MAX);
+    int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+    w = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
+    return (uint32_t)w;
+}
+
+// partial[b][l] = max |X[c][l]| over the cells of block b's stride
+__global__ __launch_bounds__(256) void fp8_chanmax_kernel(const float* __restrict__ X, int64_t n_cells,
+                                                          float* __restrict__ partial) {
+    __shared__ float sm[8][32];
+    const int l = threadIdx.x & 31, r = threadIdx.x >> 5;
+    float m = 0.f;
+    for (int64_t c = (int64_t)blockIdx.x * 8 + r; c < n_cells; c += (int64_t)gridDim.x * 8)
+        m = fmaxf(m, fabsf(X[c * 32 + l]));
+    sm[r][l] = m;
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        float v = sm[0][l];
+        for (int i = 1; i < 8; ++i) v = fmaxf(v, sm[i][l]);
+        partial[blockIdx.x * 32 + l] = v;
+    }
+}
+
+// s[r] = sum_l |U[l][r]| xmax_l / 448 (1 for an all-zero channel), one block
+__global__ __launch_bounds__(256) void fp8_scales_kernel(const float* __restrict__ partial, int nb,
+                                                         const float* __restrict__ U, int RP,
+                                                         float* __restrict__ s) {
+    __shared__ float xm[32];
+    __shared__ float red[8][32];
+    const int l = threadIdx.x & 31, r = threadIdx.x >> 5;
+    float m = 0.f;
+    for (int b = r; b < nb; b += 8) m = fmaxf(m, partial[b * 32 + l]);
+    red[r][l] = m;
+    __syncthreads();
+    if (threadIdx.x < 32) {
+        float v = red[0][l];
+        for (int i = 1; i < 8; ++i) v = fmaxf(v, red[i][l]);
+        xm[l] = v;
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < RP; c += 256) {
+        float acc = 0.f;
+        for (int k = 0; k < 32; ++k) acc = fmaf(fabsf(U[k * RP + c]), xm[k], acc);
+        s[c] = acc > 0.f ? acc / FP8_MAX : 1.f;
+    }
+}
+
+// Zq[c][r] = e4m3(Z[c][r] / s_r)
+template <int RP>
+__global__ __launch_bounds__(256) void project_fp8_kernel(const float* __restrict__ X, int64_t n_cells,
+                                                          const float* __restrict__ U,
+                                                          const float* __restrict__ s,
+                                                          uint32_t* __restrict__ Zq) {
+    __shared__ float sU[32 * RP];
+    __shared__ float sinv[RP];
+    for (int i = threadIdx.x; i < 32 * RP; i += 256) sU[i] = U[i];
+    for (int i = threadIdx.x; i < RP; i += 256) sinv[i] = 1.f / s[i];
+    __syncthreads();
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (c >= n_cells) return;
+    const float4* x4 = reinterpret_cast<const float4*>(X + c * 32);
+    float acc[RP];
+#pragma unroll
+    for (int r = 0; r < RP; ++r) acc[r] = 0.f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const float4 v = x4[k];
+#pragma unroll
+        for (int r = 0; r < RP; ++r) {
+            acc[r] = fmaf(v.x, sU[(4 * k + 0) * RP + r], acc[r]);
+            acc[r] = fmaf(v.y, sU[(4 * k + 1) * RP + r], acc[r]);
+            acc[r] = fmaf(v.z, sU[(4 * k + 2) * RP + r], acc[r]);
+            acc[r] = fmaf(v.w, sU[(4 * k + 3) * RP + r], acc[r]);
         }
     }
-    return hipErrorInvalidValue;
+    uint32_t* z = Zq + c * (RP / 4);
+#pragma unroll
+    for (int r = 0; r < RP; r += 4)
+        z[r / 4] = fp8x4(acc[r] * sinv[r], acc[r + 1] * sinv[r + 1], acc[r + 2] * sinv[r + 2],
+                         acc[r + 3] * sinv[r + 3]);
+}
+
+// One block per 32-filter block of a group: the FP32 master factors are laid
+// out exactly like the FP8 operand (fragment order, 4 bytes per element).
+// Pass 1: per-filter max |G * s|; pass 2: quantise with t_k folded in.
+__global__ __launch_bounds__(256) void fp8_requant_kernel(const RequantBlock* __restrict__ blocks,
+                                                          const float* __restrict__ master,
+                                                          const float* __restrict__ s, int PB,
+                                                          uint8_t* __restrict__ G,
+                                                          float* __restrict__ tk) {
+    __shared__ unsigned int tmax[32];
+    const RequantBlock B = blocks[blockIdx.x];
+    if (threadIdx.x < 32) tmax[threadIdx.x] = 0u;
+    __syncthreads();
+    // unit = (chunk, lane): 32 consecutive elements of one filter's flattened row
+    const int units = B.chunks * 64;
+    for (int u = threadIdx.x; u < units; u += 256) {
+        const int lane = u & 63, ch = u >> 6;
+        const int sidx = (ch / B.h) % B.S;         // K-step of this chunk
+        const int q = (ch / B.h) / B.S;            // plane
+        const float* src = master + B.m_off + (int64_t)u * 32;
+        float m = 0.f;
+        for (int e = 0; e < 32; ++e) {
+            const int o = 64 * sidx + 32 * (lane >> 5) + e;   // flattened plane byte
+            m = fmaxf(m, fabsf(src[e] * s[q * PB + o % PB]));
+        }
+        atomicMax(&tmax[lane & 31], __float_as_uint(m));
+    }
+    __syncthreads();
+    for (int u = threadIdx.x; u < units; u += 256) {
+        const int lane = u & 63, ch = u >> 6;
+        const int sidx = (ch / B.h) % B.S;
+        const int q = (ch / B.h) / B.S;
+        const float t = __uint_as_float(tmax[lane & 31]);
+        const float inv = t > 0.f ? FP8_MAX / t : 0.f;
+        const float* src = master + B.m_off + (int64_t)u * 32;
+        uint32_t* dst = reinterpret_cast<uint32_t*>(G + B.g_off + (int64_t)u * 32);
+        for (int e = 0; e < 32; e += 4) {
+            float v[4];
+            for (int i = 0; i < 4; ++i) {
+                const int o = 64 * sidx + 32 * (lane >> 5) + e + i;
+                v[i] = src[e + i] * s[q * PB + o % PB] * inv;
+            }
+            dst[e / 4] = fp8x4(v[0], v[1], v[2], v[3]);
+        }
+    }
+    if (threadIdx.x < 32 && B.f0 + (int)threadIdx.x < B.ng) {
+        const float t = __uint_as_float(tmax[threadIdx.x]);
+        tk[B.t_off + threadIdx.x] = t > 0.f ? t / FP8_MAX : 1.f;
+    }
+}
+
+hipError_t launch_fp8_prepare(const float* X, int64_t n_cells, const float* U, int RP,
+                              float* partial, float* scales, const RequantBlock* blocks,
+                              int n_blocks, const float* master, uint8_t* G, float* tk,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(fp8_chanmax_kernel, dim3(CHANMAX_BLOCKS), dim3(256), 0, st, X, n_cells, partial);
+    hipLaunchKernelGGL(fp8_scales_kernel, dim3(1), dim3(256), 0, st, partial, CHANMAX_BLOCKS, U, RP, scales);
+    if (n_blocks > 0)
+        hipLaunchKernelGGL(fp8_requant_kernel, dim3(n_blocks), dim3(256), 0, st, blocks, master,
+                           scales, RP, G, tk);
+    return hipGetLastError();
+}
+
+hipError_t launch_project_fp8(const float* X, int64_t n_cells, const float* U, int RP,
+                              const float* scales, void* Z, hipStream_t st) {
+    if (n_cells <= 0) return hipSuccess;
+    const unsigned nb = (unsigned)((n_cells + 255) / 256);
+    uint32_t* Zq = static_cast<uint32_t*>(Z);
+    if (RP == 16) hipLaunchKernelGGL(project_fp8_kernel<16>, dim3(nb), dim3(256), 0, st, X, n_cells, U, scales, Zq);
+    else if (RP == 32) hipLaunchKernelGGL(project_fp8_kernel<32>, dim3(nb), dim3(256), 0, st, X, n_cells, U, scales, Zq);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -378,15 +589,6 @@ hipError_t launch_corr(const CorrLaunch& cfg, const CorrTile* tiles, int n_tiles
 // ---------------------------------------------------------------------------
 constexpr int DT_STAGE_MAX = 96 * 1024;          // LDS bytes of one staged tile
 constexpr int DT_ROW_PAIRS = 32;                 // pairs per row-pass block
-
-__device__ __forceinline__ int find_item(const int32_t* __restrict__ prefix, int n, int b) {
-    int lo = 0, hi = n - 1;                        // last item with prefix <= b
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (prefix[mid] <= b) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
 
 // Per-line constants of one pair's cost c(u) = b*u + a*u^2 and the line maximum.
 struct LineConst {
@@ -448,36 +650,83 @@ __device__ __forceinline__ float window_max(const Load& load, int n, int t, int 
     return scan_range(load, lo, hi, t, a, b, arg);
 }
 
+// Fixed window of a line: with D its value range (max - min), any candidate
+// farther than [lo, hi] from its target costs more than D and so cannot beat
+// the target itself; lo = floor((-b - s)/2a) - 1, hi = ceil((-b + s)/2a) + 1,
+// s = sqrt(b^2 + 4aD).  The 1-cell margins cover FP32 rounding of the bound.
+__device__ __forceinline__ void line_window(float a, float b, float range, int n, int& ulo,
+                                           int& uhi) {
+    const float s = sqrtf(fmaf(4.f * a, fmaxf(range, 0.f), b * b));
+    const float inv = 0.5f / a;
+    ulo = (int)fmaxf(floorf((-b - s) * inv) - 1.f, -(float)n);
+    uhi = (int)fminf(ceilf((-b + s) * inv) + 1.f, (float)n);
+}
+
+// Exact maximum of v[x] - (b*u + a*u^2), u = x - t, over x in [lo, hi] and its
+// smallest maximiser; the cost is advanced by finite differences.
+template <class Load>
+__device__ __forceinline__ float scan_fd(const Load& load, int lo, int hi, int t, float a, float b,
+                                         int& arg) {
+    float best = -INFINITY;
+    arg = lo;
+    const float u0 = (float)(lo - t);
+    float c = u0 * fmaf(a, u0, b);                 // cost at lo
+    float dc = fmaf(a, fmaf(2.f, u0, 1.f), b);     // cost(u0 + 1) - cost(u0)
+    const float a2 = 2.f * a;
+    int x = lo;
+    for (; x + 3 <= hi; x += 4) {
+        const float v0 = load(x), v1 = load(x + 1), v2 = load(x + 2), v3 = load(x + 3);
+        const float e0 = v0 - c;
+        c += dc; dc += a2;
+        const float e1 = v1 - c;
+        c += dc; dc += a2;
+        const float e2 = v2 - c;
+        c += dc; dc += a2;
+        const float e3 = v3 - c;
+        c += dc; dc += a2;
+        if (e0 > best) { best = e0; arg = x; }
+        if (e1 > best) { best = e1; arg = x + 1; }
+        if (e2 > best) { best = e2; arg = x + 2; }
+        if (e3 > best) { best = e3; arg = x + 3; }
+    }
+    for (; x <= hi; ++x) {
+        const float e = load(x) - c;
+        c += dc; dc += a2;
+        if (e > best) { best = e; arg = x; }
+    }
+    return best;
+}
+
 // Row pass: block = (item, part row y', 32 pairs).  The block stages the row
-// of its 32 pairs in LDS split by parity, [pair][x' & 1][x' >> 1], so that
-// lanes holding consecutive target columns (targets 2 apart) read
-// consecutive words; then thread (column x0 = tid % Wt, pair slot tid / Wt)
-// walks the block's pairs.  Writes the row maximum of
-// resp[y'][x'] - (d_x (x'-x_t) + d_xx (x'-x_t)^2), x_t = 2*x0 + v_x, and its
-// argmax x' at [pair][y'][x0].
+// of its 32 pairs as [pair][x'] (odd pitch) with each pair's fixed window,
+// then thread (column x0 = tid % Wt, pair slot tid / Wt) walks the block's
+// pairs.  Writes the row maximum of resp[y'][x'] - (d_x (x'-x_t) +
+// d_xx (x'-x_t)^2), x_t = 2*x0 + v_x, and its argmax x' at [pair][y'][x0].
+struct RowPair {
+    float a, b;
+    int ulo, uhi;
+    int vx, wo;
+};
+
 template <bool STAGED>
 __global__ __launch_bounds__(256) void dt_row_kernel(const DTItem* __restrict__ items,
-                                                     const int32_t* __restrict__ prefix,
-                                                     int n_items,
+                                                     const int2* __restrict__ blkmap,
                                                      const PairDesc* __restrict__ pairs,
                                                      const float* __restrict__ resp,
                                                      float* __restrict__ r1v,
                                                      int32_t* __restrict__ r1a) {
-    extern __shared__ float sline[];               // [DT_ROW_PAIRS][2][half] when STAGED
-    __shared__ float smax[8][DT_ROW_PAIRS];
-    __shared__ LineConst sc[DT_ROW_PAIRS];
-    __shared__ int2 sv[DT_ROW_PAIRS];              // (v_x, root columns Wo_c)
-    const int it = find_item(prefix, n_items, blockIdx.x);
-    const DTItem I = items[it];
-    const int local = blockIdx.x - prefix[it];
+    extern __shared__ float sline[];               // [DT_ROW_PAIRS][pitch] when STAGED
+    __shared__ float smax[8][DT_ROW_PAIRS], smin[8][DT_ROW_PAIRS];
+    __shared__ RowPair sp[DT_ROW_PAIRS];
+    const int2 bm = blkmap[blockIdx.x];            // (item, block within the item)
+    const DTItem I = items[bm.x];
+    const int local = bm.y;
     const int pc = (I.np + DT_ROW_PAIRS - 1) / DT_ROW_PAIRS;
     const int p0 = (local % pc) * DT_ROW_PAIRS;
     const int yp = local / pc;                     // block-uniform
     if (yp >= I.Hp) return;
     const int npb = min(DT_ROW_PAIRS, I.np - p0);  // pairs of this block
-    const int Wp = I.Wp;
-    const int half = (Wp + 2) >> 1;                // words per parity plane (odd pitch below)
-    const int hp = half | 1;
+    const int Wp = I.Wp, pitch = Wp | 1;
     const int64_t rs = I.ng;
     const float* rowbase = resp + I.resp_off + (int64_t)yp * Wp * rs;
     {   // stage: thread (pair q, x phase) -> coalesced 128-byte reads, 8 in flight
@@ -485,7 +734,7 @@ __global__ __launch_bounds__(256) void dt_row_kernel(const DTItem* __restrict__ 
         const int q = threadIdx.x & (DT_ROW_PAIRS - 1), ph = threadIdx.x / DT_ROW_PAIRS;
         const bool act = q < npb;
         const int fcol = act ? pairs[I.pair_base + p0 + q].fcol : 0;
-        float M = -FLT_MAX;
+        float M = -FLT_MAX, m = FLT_MAX;
         for (int xb = ph; xb < Wp; xb += 8 * XS) {
             float v[8];
 #pragma unroll
@@ -495,22 +744,32 @@ __global__ __launch_bounds__(256) void dt_row_kernel(const DTItem* __restrict__ 
                 const int x = xb + u * XS;
                 if (x < Wp) {
                     const float vv = act ? v[u] : 0.f;
-                    if (STAGED) sline[(q * 2 + (x & 1)) * hp + (x >> 1)] = vv;
+                    if (STAGED) sline[q * pitch + x] = vv;
                     M = fmaxf(M, vv);
+                    m = fminf(m, vv);
                 }
             }
         }
         smax[ph][q] = M;
+        smin[ph][q] = m;
     }
     __syncthreads();
     if (threadIdx.x < npb) {
         const int q = threadIdx.x;
         const PairDesc P = pairs[I.pair_base + p0 + q];
-        float M = smax[0][q];
+        float M = smax[0][q], m = smin[0][q];
 #pragma unroll
-        for (int i = 1; i < 8; ++i) M = fmaxf(M, smax[i][q]);
-        sc[q] = LineConst{P.d[1], P.d[0], 0.5f / P.d[1], 0.f, M};
-        sv[q] = make_int2(P.vx, min(I.Wr - P.w0 + 1, I.Wt));
+        for (int i = 1; i < 8; ++i) {
+            M = fmaxf(M, smax[i][q]);
+            m = fminf(m, smin[i][q]);
+        }
+        RowPair r;
+        r.a = P.d[1];
+        r.b = P.d[0];
+        line_window(r.a, r.b, M - m, Wp, r.ulo, r.uhi);
+        r.vx = P.vx;
+        r.wo = min(I.Wr - P.w0 + 1, I.Wt);
+        sp[q] = r;
     }
     __syncthreads();
     const int Wt = I.Wt;
@@ -521,25 +780,17 @@ __global__ __launch_bounds__(256) void dt_row_kernel(const DTItem* __restrict__ 
     const int64_t obase = I.r1_off + ((int64_t)p0 * I.Hp + yp) * Wt;
     const int64_t opair = (int64_t)I.Hp * Wt;
     for (int q = qs; q < npb; q += qstep) {
-        const LineConst c = sc[q];
-        const int2 vw = sv[q];
-        const float* sp = sline + q * 2 * hp;
-        for (int x0 = x0s; x0 < vw.y; x0 += cols) {
-            const int t = 2 * x0 + vw.x;
+        const RowPair r = sp[q];
+        const float* srow = sline + q * pitch;
+        const float* grow = rowbase + (STAGED ? 0 : pairs[I.pair_base + p0 + q].fcol);
+        for (int x0 = x0s; x0 < r.wo; x0 += cols) {
+            const int t = 2 * x0 + r.vx;
             float best = -INFINITY;
             int arg = -1;
             if (t >= 0 && t < Wp) {
-                int lo, hi;
-                if (STAGED) {
-                    auto ld = [&](int x) { return sp[(x & 1) * hp + (x >> 1)]; };
-                    dt_bounds(ld(t), c, t, 0, Wp, lo, hi);
-                    best = scan_range(ld, lo, hi, t, c.a, c.b, arg);
-                } else {
-                    const float* grow = rowbase + pairs[I.pair_base + p0 + q].fcol;
-                    auto ld = [&](int x) { return grow[x * rs]; };
-                    dt_bounds(ld(t), c, t, 0, Wp, lo, hi);
-                    best = scan_range(ld, lo, hi, t, c.a, c.b, arg);
-                }
+                const int lo = max(t + r.ulo, 0), hi = min(t + r.uhi, Wp - 1);
+                if (STAGED) best = scan_fd([&](int x) { return srow[x]; }, lo, hi, t, r.a, r.b, arg);
+                else best = scan_fd([&](int x) { return grow[x * rs]; }, lo, hi, t, r.a, r.b, arg);
             }
             r1v[obase + q * opair + x0] = best;
             r1a[obase + q * opair + x0] = arg;
@@ -548,15 +799,14 @@ __global__ __launch_bounds__(256) void dt_row_kernel(const DTItem* __restrict__ 
 }
 
 // Column pass: block = (item, pair, chunk of cw root columns).  The block
-// stages the pair's row-pass output for its columns as [y'][cw] and the
-// column maxima, then thread (column j, segment s) takes the target rows
+// stages the pair's row-pass output for its columns as [y'][cw] with each
+// column's range, then thread (column j, segment s) takes the target rows
 // y_t = 2*y0 + v_y of one segment of y0, chaining the argmax from one target
-// to the next.  All lanes of a wavefront scan the union of their windows, so
-// every LDS read of the scan is one row of the tile (no bank conflicts) and
-// the loop is uniform.  Maximises the row-pass value minus
-// (d_y (y'-y_t) + d_yy (y'-y_t)^2) over y' and writes the deformed part score
-// and the (dy, dx) placement offset of (map, part, y0, x0) straight into the
-// caller's layout.
+// to the next.  A wavefront whose lanes share their targets scans the union
+// of their windows, so every LDS read is one row of the tile and the loop is
+// uniform.  Maximises the row-pass value minus (d_y (y'-y_t) + d_yy (y'-y_t)^2)
+// over y' and writes the deformed part score and the (dy, dx) placement
+// offset of (map, part, y0, x0) straight into the caller's layout.
 __device__ __forceinline__ int wave_min_i(int v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
@@ -570,8 +820,7 @@ __device__ __forceinline__ int wave_max_i(int v) {
 
 template <bool STAGED>
 __global__ __launch_bounds__(256) void dt_col_kernel(const DTItem* __restrict__ items,
-                                                     const int32_t* __restrict__ prefix,
-                                                     int n_items,
+                                                     const int2* __restrict__ blkmap,
                                                      const PairDesc* __restrict__ pairs,
                                                      const MapDesc* __restrict__ maps,
                                                      const float* __restrict__ r1v,
@@ -579,10 +828,10 @@ __global__ __launch_bounds__(256) void dt_col_kernel(const DTItem* __restrict__ 
                                                      float* __restrict__ dbuf,
                                                      int16_t* __restrict__ offs) {
     extern __shared__ float sline[];               // [Hp][cw] when STAGED
-    __shared__ float smax[256];
-    const int it = find_item(prefix, n_items, blockIdx.x);
-    const DTItem I = items[it];
-    const int local = blockIdx.x - prefix[it];
+    __shared__ float smax[256], smin[256];
+    const int2 bm = blkmap[blockIdx.x];            // (item, block within the item)
+    const DTItem I = items[bm.x];
+    const int local = bm.y;
     const int cw = I.cw;                           // columns per block
     const int xc = (I.Wt + cw - 1) / cw;
     const int pidx = local / xc;                   // block-uniform
@@ -598,7 +847,7 @@ __global__ __launch_bounds__(256) void dt_col_kernel(const DTItem* __restrict__ 
     const bool colok = x0 < Wo_c && xt >= 0 && xt < I.Wp;
     const int Hp = I.Hp;
     const int64_t lbase = I.r1_off + (int64_t)pidx * Hp * I.Wt;   // this pair's [y'][Wt] plane
-    float M = -FLT_MAX;
+    float M = -FLT_MAX, m = FLT_MAX;
     if (sg < nseg) {                               // 8 loads in flight per thread
         const int64_t cbase = lbase + (colok ? x0 : 0);
         for (int yb = sg; yb < Hp; yb += 8 * nseg) {
@@ -612,23 +861,28 @@ __global__ __launch_bounds__(256) void dt_col_kernel(const DTItem* __restrict__ 
                     const float vv = colok ? v[u] : 0.f;
                     if (STAGED) sline[y * cw + j] = vv;
                     M = fmaxf(M, vv);
+                    m = fminf(m, vv);
                 }
             }
         }
     }
     smax[threadIdx.x] = M;
+    smin[threadIdx.x] = m;
     __syncthreads();
     const bool act = sg < nseg && x0 < Wo_c;
     if (act)
-        for (int i = 0; i < nseg; ++i) M = fmaxf(M, smax[i * cw + j]);
+        for (int i = 0; i < nseg; ++i) {
+            M = fmaxf(M, smax[i * cw + j]);
+            m = fminf(m, smin[i * cw + j]);
+        }
+    const float a = P.d[3], b = P.d[2];
+    int ulo = 0, uhi = 0;
+    if (act) line_window(a, b, M - m, Hp, ulo, uhi);
     const int chunk = (Ho_c + nseg - 1) / nseg;
     const int k0 = sg * chunk, k1 = act ? min(k0 + chunk, Ho_c) : k0;
     const int64_t plane = (int64_t)Ho_c * Wo_c;
     float* dout = dbuf + (Md.offs_off >> 1) + P.slot * plane + x0;
     int32_t* oout = offs ? reinterpret_cast<int32_t*>(offs + Md.offs_off) + P.slot * plane + x0 : nullptr;
-    const LineConst c{P.d[3], P.d[2], 0.5f / P.d[3], 0.f, M};
-    // a wavefront whose lanes all lie in one segment (same targets) scans the
-    // union of its lanes' windows; otherwise every lane scans its own window
     const int wfirst = threadIdx.x & ~63;
     const bool one_seg = wfirst / cw == (wfirst + 63) / cw;
     const int kmax = wave_max_i(k1 - k0);
@@ -640,8 +894,8 @@ __global__ __launch_bounds__(256) void dt_col_kernel(const DTItem* __restrict__ 
         const bool ok = live && colok && t >= 0 && t < Hp;
         int lo = INT_MAX, hi = INT_MIN;
         if (ok) {
-            if (STAGED) dt_bounds(sline[t * cw + j], c, t, prev, Hp, lo, hi);
-            else dt_bounds(r1v[lbase + (int64_t)t * I.Wt + x0], c, t, prev, Hp, lo, hi);
+            hi = min(t + uhi, Hp - 1);
+            lo = min(max(max(t + ulo, 0), prev), hi);
         }
         const int LO = wave_min_i(lo), HI = wave_max_i(hi);
         float best = -INFINITY;
@@ -650,9 +904,9 @@ __global__ __launch_bounds__(256) void dt_col_kernel(const DTItem* __restrict__ 
             const int from = (STAGED && one_seg) ? LO : lo;
             const int to = (STAGED && one_seg) ? HI : hi;
             if (STAGED)
-                best = scan_range([&](int y) { return sline[y * cw + j]; }, from, to, t, c.a, c.b, ay);
+                best = scan_fd([&](int y) { return sline[y * cw + j]; }, from, to, t, a, b, ay);
             else
-                best = scan_range([&](int y) { return r1v[lbase + (int64_t)y * I.Wt + x0]; }, from, to, t, c.a, c.b, ay);
+                best = scan_fd([&](int y) { return r1v[lbase + (int64_t)y * I.Wt + x0]; }, from, to, t, a, b, ay);
             prev = ay;
         }
         if (live) {
@@ -671,14 +925,13 @@ __global__ __launch_bounds__(256) void dt_col_kernel(const DTItem* __restrict__ 
 // Assembly: thread = (map, root position); adds the parts' deformed scores to
 // the root response (Section 2 score formula).
 __global__ __launch_bounds__(ASM_BLOCK) void assemble_kernel(const MapDesc* __restrict__ maps,
-                                                             const int32_t* __restrict__ prefix,
-                                                             int n_maps,
+                                                             const int2* __restrict__ blkmap,
                                                              const float* __restrict__ rresp,
                                                              const float* __restrict__ dbuf,
                                                              float* __restrict__ scores) {
-    const int mi = find_item(prefix, n_maps, blockIdx.x);
-    const MapDesc Md = maps[mi];
-    const int pos = (blockIdx.x - prefix[mi]) * ASM_BLOCK + threadIdx.x;
+    const int2 bm = blkmap[blockIdx.x];            // (map, block within the map)
+    const MapDesc Md = maps[bm.x];
+    const int pos = bm.y * ASM_BLOCK + threadIdx.x;
     const int plane = Md.Ho * Md.Wo;
     if (pos >= plane) return;
     float s = rresp[Md.rresp_off + (int64_t)pos * Md.rng + Md.rcol];
@@ -694,24 +947,24 @@ static hipError_t set_lds(K kern, size_t lds) {
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-hipError_t launch_dt_row(const DTItem* items, const int32_t* prefix, int n_items, int n_blocks,
+hipError_t launch_dt_row(const DTItem* items, const int2* blkmap, int n_blocks,
                          const PairDesc* pairs, const float* resp, float* r1v, int32_t* r1a,
                          int max_line, hipStream_t st) {
     if (n_blocks <= 0) return hipSuccess;
-    const size_t lds = (size_t)((((max_line + 2) >> 1) | 1) * 2) * DT_ROW_PAIRS * sizeof(float);
+    const size_t lds = (size_t)(max_line | 1) * DT_ROW_PAIRS * sizeof(float);
     if (lds <= DT_STAGE_MAX) {
         hipError_t e = set_lds(dt_row_kernel<true>, lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(dt_row_kernel<true>, dim3(n_blocks), dim3(256), lds, st, items, prefix,
-                           n_items, pairs, resp, r1v, r1a);
+        hipLaunchKernelGGL(dt_row_kernel<true>, dim3(n_blocks), dim3(256), lds, st, items, blkmap,
+                           pairs, resp, r1v, r1a);
     } else {
-        hipLaunchKernelGGL(dt_row_kernel<false>, dim3(n_blocks), dim3(256), 0, st, items, prefix,
-                           n_items, pairs, resp, r1v, r1a);
+        hipLaunchKernelGGL(dt_row_kernel<false>, dim3(n_blocks), dim3(256), 0, st, items, blkmap,
+                           pairs, resp, r1v, r1a);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_dt_col(const DTItem* items, const int32_t* prefix, int n_items, int n_blocks,
+hipError_t launch_dt_col(const DTItem* items, const int2* blkmap, int n_blocks,
                          const PairDesc* pairs, const MapDesc* maps, const float* r1v,
                          const int32_t* r1a, float* dbuf, int16_t* offs, int max_line,
                          hipStream_t st) {
@@ -720,20 +973,20 @@ hipError_t launch_dt_col(const DTItem* items, const int32_t* prefix, int n_items
     if (lds <= DT_STAGE_MAX) {
         hipError_t e = set_lds(dt_col_kernel<true>, lds);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(dt_col_kernel<true>, dim3(n_blocks), dim3(256), lds, st, items, prefix,
-                           n_items, pairs, maps, r1v, r1a, dbuf, offs);
+        hipLaunchKernelGGL(dt_col_kernel<true>, dim3(n_blocks), dim3(256), lds, st, items, blkmap,
+                           pairs, maps, r1v, r1a, dbuf, offs);
     } else {
-        hipLaunchKernelGGL(dt_col_kernel<false>, dim3(n_blocks), dim3(256), 0, st, items, prefix,
-                           n_items, pairs, maps, r1v, r1a, dbuf, offs);
+        hipLaunchKernelGGL(dt_col_kernel<false>, dim3(n_blocks), dim3(256), 0, st, items, blkmap,
+                           pairs, maps, r1v, r1a, dbuf, offs);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_assemble(const MapDesc* maps, const int32_t* prefix, int n_maps, int n_blocks,
+hipError_t launch_assemble(const MapDesc* maps, const int2* blkmap, int n_blocks,
                            const float* rresp, const float* dbuf, float* scores, hipStream_t st) {
     if (n_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(assemble_kernel, dim3(n_blocks), dim3(ASM_BLOCK), 0, st, maps, prefix,
-                       n_maps, rresp, dbuf, scores);
+    hipLaunchKernelGGL(assemble_kernel, dim3(n_blocks), dim3(ASM_BLOCK), 0, st, maps, blkmap,
+                       rresp, dbuf, scores);
     return hipGetLastError();
 }
 

@@ -108,3 +108,38 @@ def compare_map(run: GpuRun, wl, image, level, comp, sm, tol: float, cmp: Cmp) -
     cmp.n_arg_excluded += int((~check).sum())
     bad = check[..., None] & (go != sm.offsets)
     assert not bad.any(), f"map (img {image}, level {level}, comp {comp}): {int(bad.any(-1).sum())} placements differ above margin {tol}"
+
+
+# --------------------------------------------------------------- FP8 error bound
+FP8_U = 2.0 ** -4        # unit roundoff of OCP e4m3 (3 mantissa bits, round to nearest even)
+FP8_SUB = 2.0 ** -10     # half the e4m3 subnormal spacing (2^-9)
+
+
+def fp8_channel_scales(xmax: np.ndarray, U: np.ndarray, RP: int) -> np.ndarray:
+    """s_r = sum_l |U[l, r]| xmax_l / 448 (1 where zero), as the device computes them."""
+    s = np.ones(RP)
+    R = U.shape[1]
+    v = np.abs(U.astype(np.float32).astype(np.float64)).T @ xmax / 448.0
+    s[:R] = np.where(v > 0, v, 1.0)
+    return s
+
+
+def fp8_response_bound(X: np.ndarray, f: np.ndarray, U: np.ndarray, s: np.ndarray) -> np.ndarray:
+    """Per-response bound on |FP8 response - FP64 tensor response|.
+
+    With z' = Z/s_r and g' = G s_r / t_k rounded to e4m3, each rounding error is
+    at most u|v| + sub (u = 2^-4, sub = 2^-10 in scaled units), so one product
+    g z errs by at most |g||z|(2u + u^2) + |g| sub s_r (1+u) + |z| sub (t_k/s_r)(1+u)
+    + sub^2 t_k; summed over the h*w*R terms, plus FP32 accumulation."""
+    R = U.shape[1]
+    Z = oracle.project(X, U)                      # (H, W, R)
+    G = oracle.factor(f, U)                       # (h, w, R)
+    sR = s[:R]
+    tk = np.max(np.abs(G * sR)) / 448.0
+    tk = tk if tk > 0 else 1.0
+    u, sub = FP8_U, FP8_SUB
+    absprod = oracle.correlate(np.abs(Z), np.abs(G))
+    term_g = sub * (1 + u) * np.sum(np.abs(G) * sR)
+    term_z = sub * (1 + u) * tk * oracle.correlate(np.abs(Z) / sR, np.ones(G.shape))
+    nterm = G.size
+    return absprod * (2 * u + u * u + 1e-6) + term_g + term_z + sub * sub * tk * nterm

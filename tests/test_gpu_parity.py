@@ -213,3 +213,77 @@ def test_repeat_calls_bitwise_identical():
     assert np.array_equal(outs[0][0].view(np.int32), outs[1][0].view(np.int32))
     assert np.array_equal(outs[0][1], outs[1][1])
     ctx.close()
+
+
+# ----------------------------------------------------------------- FP8
+@pytest.mark.parametrize("rank", [8, 16, 32])
+def test_level_responses_c2_fp8_within_rounding_bound(rank):
+    """FP8 responses of every filter on a ragged multi-tile level stay within
+    the e4m3 rounding bound of the FP64 tensor response at the same rank."""
+    from _gpu_common import fp8_channel_scales, fp8_response_bound
+    wl = workloads.config2()
+    level = 3
+    note(f"responses c2 level {level} tensor_fp8 R={rank}")
+    flat, U = _responses(wl, "tensor_fp8", rank, 0, level)
+    X = wl.level_features(0, level).astype(np.float64)
+    RP = 16 if rank <= 16 else 32
+    s = fp8_channel_scales(np.abs(X).reshape(-1, 32).max(0), U, RP)
+    off = 0
+    worst = 0.0
+    for k, f in enumerate(wl.bank.filters):
+        ref = oracle.tensor_response(X, f, U)
+        got = flat[off:off + ref.size].reshape(ref.shape)
+        off += ref.size
+        bound = fp8_response_bound(X, f, U, s)
+        ratio = np.max(np.abs(got - ref) / bound)
+        worst = max(worst, ratio)
+        assert ratio <= 1.0, f"filter {k}: error exceeds the e4m3 rounding bound (ratio {ratio:.3g})"
+    note(f"  worst error / bound {worst:.3g}")
+
+
+@pytest.mark.parametrize("cfg,rank", [(1, 16), (2, 16)])
+def test_scores_fp8_within_propagated_bound(cfg, rank):
+    """FP8 scores against the FP64 tensor oracle: the distance transform is
+    1-Lipschitz, so a score errs by at most the root's response bound plus, per
+    part, the largest response bound over its part map; placements must match
+    where the oracle margin exceeds twice that part bound."""
+    from _gpu_common import fp8_channel_scales, fp8_response_bound
+    wl = workloads.PRESETS[cfg]()
+    note(f"c{cfg} tensor_fp8 R={rank} scores")
+    run = run_gpu(wl, "tensor_fp8", rank)
+    U = run.basis
+    RP = 16 if rank <= 16 else 32
+    feats = wl.features().astype(np.float64)
+    s = fp8_channel_scales(np.abs(feats).max(0), U, RP)
+    lay = run.layout
+    cache = {}
+    worst = 0.0
+    checked = total = 0
+    maps = range(lay.n_maps) if cfg == 1 else range(0, lay.n_maps, 7)
+    for k in maps:
+        img, lvl, comp = int(lay.map_image[k]), int(lay.map_level[k]), int(lay.map_comp[k])
+        sm = oracle_map(wl, img, lvl, comp, U, cache)
+        Ho, Wo = sm.score.shape
+        if Ho * Wo == 0:
+            continue
+        c = wl.bank.components[comp]
+        pyr = wl.pyramids[img]
+        Xr, Xp = cache[(img, lvl)], cache[(img, lvl - pyr.octave)]
+        tol = np.max(fp8_response_bound(Xr, wl.bank.filters[c.root], U, s))
+        pb = [np.max(fp8_response_bound(Xp, wl.bank.filters[p], U, s)) for p in c.parts]
+        tol += sum(pb)
+        g = run.scores[lay.map_score_off[k]:lay.map_score_off[k] + Ho * Wo].reshape(Ho, Wo)
+        fin = np.isfinite(sm.score)
+        assert np.array_equal(np.isfinite(g), fin)
+        if fin.any():
+            err = np.max(np.abs(g[fin] - sm.score[fin]))
+            worst = max(worst, err / tol)
+            assert err <= tol, f"map {k}: score error {err:.3g} > propagated bound {tol:.3g}"
+        go = run.offsets[lay.map_offs_off[k]:lay.map_offs_off[k] + Ho * Wo * len(c.parts) * 2]
+        go = go.reshape(len(c.parts), Ho, Wo, 2)
+        for i in range(len(c.parts)):
+            chk = sm.margin[i] > 2 * pb[i]
+            total += chk.size
+            checked += int(chk.sum())
+            assert np.array_equal(go[i][chk], sm.offsets[i][chk]), f"map {k} part {i}: placements differ"
+    note(f"  worst score error / bound {worst:.3g}; placements checked {checked}/{total}")
