@@ -191,64 +191,91 @@ __global__ __launch_bounds__(64 * WY) __attribute__((amdgpu_waves_per_eu((HMAX <
 
     const int n_chunk = BB * h * CU;               // u32x4 per G chunk
     const int total = Q * S;
-    // element i of chunk `step`: [b][n][lane] of the packed operand.  Indices
-    // past the chunk are clamped to its last element, for the load and for the
-    // LDS store alike, so surplus threads store that element's own value again.
-    auto chunk_src = [&](int step, int i) -> const u32x4* {
-        i = min(i, n_chunk - 1);
-        const int q = step / S, s = step - q * S;
+    // Element i of a chunk is [b][n][lane] of the packed operand; thread tid
+    // owns elements tid + k*NT (clamped to the chunk's last element, whose value
+    // surplus threads then store again).  Its source address for step `st` is
+    // pf_base[k] + st * h * chunk bytes: the division by h happens once per tile.
+    const int chunk_bytes = 64 * FB;
+    uint32_t pf_base[PFMAX];                       // byte offsets into G (< 4 GiB)
+    int pf_dst[PFMAX];
+#pragma unroll
+    for (int k = 0; k < PFMAX; ++k) {
+        const int i = min(tid + k * NT, n_chunk - 1);
         const int l = i % CU;
         const int n = (i / CU) % h;
         const int b = i / (CU * h);
-        const int64_t blk = t.fb0 + b;
-        return reinterpret_cast<const u32x4*>(
-                   G + g.g_off + (((blk * Q + q) * S + s) * (int64_t)h + n) * (64 * FB)) + l;
+        pf_base[k] = (uint32_t)(g.g_off + (((int64_t)(t.fb0 + b) * Q * S) * h + n) * chunk_bytes + l * 16);
+        pf_dst[k] = i;
+    }
+    const uint32_t step_bytes = (uint32_t)(h * chunk_bytes);
+    auto chunk_ld = [&](int st, int k) -> u32x4 {
+        return *reinterpret_cast<const u32x4*>(G + (pf_base[k] + (uint32_t)st * step_bytes));
     };
+
+    // window fill: thread -> (row offset r0, 16/8-byte chunk c of a row), one
+    // division per tile; rows advance by rpp
+    const int cpc = PB / CH;
+    const int cpr = WC * cpc;                      // chunks per window row
+    const int rpp = max(NT / cpr, 1);              // rows per pass
+    const int wr0 = tid / cpr, wc = tid - wr0 * cpr;
+    const int wcc = wc / cpc, wk = wc - wcc * cpc; // cell, chunk within the cell
+    const bool wact = wr0 < rpp;
+    const int wx = t.x0 + wcc;
 
     // prologue: chunk 0 straight into buffer 0
     {
         u32x4 pf[PFMAX];
 #pragma unroll
-        for (int k = 0; k < PFMAX; ++k) pf[k] = *chunk_src(0, tid + k * NT);
+        for (int k = 0; k < PFMAX; ++k) pf[k] = chunk_ld(0, k);
 #pragma unroll
-        for (int k = 0; k < PFMAX; ++k) gbuf0[min(tid + k * NT, n_chunk - 1)] = pf[k];
+        for (int k = 0; k < PFMAX; ++k) gbuf0[pf_dst[k]] = pf[k];
     }
 
     for (int step = 0; step < total; ++step) {
         const int q = step / S, s = step - q * S;
         if (s == 0) {
             __syncthreads();                       // previous plane fully consumed
-            const int cpc = PB / CH;
-            const int nch = nrows * WC * cpc;
-            for (int i0 = tid; i0 < nch; i0 += WBATCH * NT) {
-                u32x4 r[WBATCH];
+            if (cpr <= NT) {
+                for (int rb = 0; rb < nrows; rb += WBATCH * rpp) {
+                    u32x4 r[WBATCH];
 #pragma unroll
-                for (int u = 0; u < WBATCH; ++u) {
-                    const int i = min(i0 + u * NT, nch - 1);
-                    const int k = i % cpc;
-                    const int cc = (i / cpc) % WC;
-                    const int rr = i / (cpc * WC);
+                    for (int u = 0; u < WBATCH; ++u) {
+                        const int rr = min(rb + u * rpp + wr0, nrows - 1);
+                        const int y = t.y0 + rr;
+                        const bool in = wact && (y < t.H) && (wx < t.W);
+                        const int64_t cell = t.z_cell + (in ? (int64_t)y * t.W + wx : 0);
+                        const char* src = Z + (cell * cell_bytes + q * PB + wk * CH);
+                        if constexpr (CH == 16) {
+                            r[u] = *reinterpret_cast<const u32x4*>(src);
+                        } else {
+                            const u32x2 v = *reinterpret_cast<const u32x2*>(src);
+                            r[u] = u32x4{v.x, v.y, 0u, 0u};
+                        }
+                        if (!in) r[u] = u32x4{0u, 0u, 0u, 0u};
+                    }
+#pragma unroll
+                    for (int u = 0; u < WBATCH; ++u) {
+                        const int rr = rb + u * rpp + wr0;
+                        if (wact && rr < nrows) {
+                            char* dst = win + rr * pitch + wcc * PB + wk * CH;
+                            if constexpr (CH == 16) *reinterpret_cast<u32x4*>(dst) = r[u];
+                            else *reinterpret_cast<u32x2*>(dst) = u32x2{r[u].x, r[u].y};
+                        }
+                    }
+                }
+            } else {                               // very wide rows: generic mapping
+                const int nch = nrows * cpr;
+                for (int i = tid; i < nch; i += NT) {
+                    const int k = i % cpc, cc = (i / cpc) % WC, rr = i / cpr;
                     const int y = t.y0 + rr, x = t.x0 + cc;
                     const bool in = (y < t.H) && (x < t.W);
                     const int64_t cell = t.z_cell + (in ? (int64_t)y * t.W + x : 0);
                     const char* src = Z + (cell * cell_bytes + q * PB + k * CH);
-                    if constexpr (CH == 16) {
-                        r[u] = *reinterpret_cast<const u32x4*>(src);
-                    } else {
-                        const u32x2 v = *reinterpret_cast<const u32x2*>(src);
-                        r[u] = u32x4{v.x, v.y, 0u, 0u};
-                    }
-                    if (!in) r[u] = u32x4{0u, 0u, 0u, 0u};
-                }
-#pragma unroll
-                for (int u = 0; u < WBATCH; ++u) {
-                    const int i = min(i0 + u * NT, nch - 1);   // surplus: same value again
-                    const int k = i % cpc;
-                    const int cc = (i / cpc) % WC;
-                    const int rr = i / (cpc * WC);
                     char* dst = win + rr * pitch + cc * PB + k * CH;
-                    if constexpr (CH == 16) *reinterpret_cast<u32x4*>(dst) = r[u];
-                    else *reinterpret_cast<u32x2*>(dst) = u32x2{r[u].x, r[u].y};
+                    if constexpr (CH == 16)
+                        *reinterpret_cast<u32x4*>(dst) = in ? *reinterpret_cast<const u32x4*>(src) : u32x4{0u, 0u, 0u, 0u};
+                    else
+                        *reinterpret_cast<u32x2*>(dst) = in ? *reinterpret_cast<const u32x2*>(src) : u32x2{0u, 0u};
                 }
             }
         }
@@ -260,43 +287,45 @@ __global__ __launch_bounds__(64 * WY) __attribute__((amdgpu_waves_per_eu((HMAX <
         const bool more = step + 1 < total;
         const int nstep = more ? step + 1 : step;
 #pragma unroll
-        for (int k = 0; k < PFMAX; ++k) pf[k] = *chunk_src(nstep, tid + k * NT);
+        for (int k = 0; k < PFMAX; ++k) pf[k] = chunk_ld(nstep, k);
 
         const u32x4* gb = (step & 1) ? gbuf1 : gbuf0;
         const char* abase = win + (wv * TY) * pitch + p * PB + KS * s + FB * j;
         const char* gbb = reinterpret_cast<const char*>(gb) + lane * FB;
-        Frag A[TY];
+        {
+            Frag A[TY];
 #pragma unroll
-        for (int i = 0; i < TY; ++i) A[i] = lds_frag<KIND>(abase + i * pitch, PB);
-        Frag B[BB];
+            for (int i = 0; i < TY; ++i) A[i] = lds_frag<KIND>(abase + i * pitch, PB);
+            Frag B[BB];
 #pragma unroll
-        for (int b = 0; b < BB; ++b) B[b] = *reinterpret_cast<const Frag*>(gbb + (b * h) * (64 * FB));
-        for (int n = 0; n < h; ++n) {
-            Frag Bn[BB], An;
-            const bool nx = n + 1 < h;
-            if (nx) {
+            for (int b = 0; b < BB; ++b) B[b] = *reinterpret_cast<const Frag*>(gbb + (b * h) * chunk_bytes);
+            for (int n = 0; n < h; ++n) {
+                Frag Bn[BB], An;
+                const bool nx = n + 1 < h;
+                if (nx) {
 #pragma unroll
-                for (int b = 0; b < BB; ++b)
-                    Bn[b] = *reinterpret_cast<const Frag*>(gbb + (b * h + n + 1) * (64 * FB));
-                An = lds_frag<KIND>(abase + (n + TY) * pitch, PB);
-            }
+                    for (int b = 0; b < BB; ++b)
+                        Bn[b] = *reinterpret_cast<const Frag*>(gbb + (b * h + n + 1) * chunk_bytes);
+                    An = lds_frag<KIND>(abase + (n + TY) * pitch, PB);
+                }
 #pragma unroll
-            for (int i = 0; i < TY; ++i)
+                for (int i = 0; i < TY; ++i)
 #pragma unroll
-                for (int b = 0; b < BB; ++b) acc[i][b] = mfma_step<KIND>(A[i], B[b], acc[i][b]);
-            if (nx) {
+                    for (int b = 0; b < BB; ++b) acc[i][b] = mfma_step<KIND>(A[i], B[b], acc[i][b]);
+                if (nx) {
 #pragma unroll
-                for (int i = 0; i + 1 < TY; ++i) A[i] = A[i + 1];
-                A[TY - 1] = An;
+                    for (int i = 0; i + 1 < TY; ++i) A[i] = A[i + 1];
+                    A[TY - 1] = An;
 #pragma unroll
-                for (int b = 0; b < BB; ++b) B[b] = Bn[b];
+                    for (int b = 0; b < BB; ++b) B[b] = Bn[b];
+                }
             }
         }
 
         if (more) {
             u32x4* nb = (step & 1) ? gbuf0 : gbuf1;
 #pragma unroll
-            for (int k = 0; k < PFMAX; ++k) nb[min(tid + k * NT, n_chunk - 1)] = pf[k];
+            for (int k = 0; k < PFMAX; ++k) nb[pf_dst[k]] = pf[k];
         }
     }
 
