@@ -141,7 +141,11 @@ dpmt_status dpmt_load_filters(dpmt_ctx* ctx, int32_t n_filters, const dpmt_shape
 dpmt_status dpmt_decompose(dpmt_ctx* ctx, int32_t rank, double* sigma_out, double* basis_out);
 
 /* Plan a batch of n_images pyramids (host descriptors, copied): output layout,
- * work lists and device workspace.  *out points at the context-owned layout. */
+ * work lists and device workspace.  *out points at the context-owned layout.
+ * Limits (DPMT_E_UNSUPPORTED beyond them): level sides up to 16384 cells,
+ * part response maps up to 2940 columns, and score maps whose placement
+ * working set (map height and part map height) fits one workgroup's 160 KB
+ * of LDS, which holds part maps up to about 550 rows. */
 dpmt_status dpmt_plan(dpmt_ctx* ctx, int32_t n_images, const dpmt_pyramid* pyrs,
                       const dpmt_layout** out);
 
@@ -177,9 +181,10 @@ dpmt_status dpmt_distance_transform(const float* resp_dev, int32_t rows, int32_t
  * each stage of dpmt_score_pyramid.  dpmt_set_profiling(ctx, 1) starts
  * recording (and clears what was gathered); every later score call adds one
  * set of events.  dpmt_stage_times waits for the recorded events and writes
- * the mean duration per call, in milliseconds, of each stage: 0 projection,
- * 1 correlation (all filters), 2 DT row pass, 3 DT column pass, 4 score
- * assembly, 5 whole call.  Returns the number of stages written (at most n)
+ * the mean duration per call, in milliseconds, of each stage: 0 projection
+ * (with the reset of the per-plane value ranges), 1 correlation (all filters
+ * of all levels), 2 placement (distance transform at the anchors and score
+ * assembly), 3 whole call.  Returns the number of stages written (at most n)
  * and stores the number of calls averaged in *n_calls (may be NULL). */
 dpmt_status dpmt_set_profiling(dpmt_ctx* ctx, int32_t on);
 int32_t     dpmt_stage_times(dpmt_ctx* ctx, float* ms_out, int32_t n, int32_t* n_calls);

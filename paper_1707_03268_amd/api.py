@@ -218,13 +218,13 @@ class Context:
     def set_profiling(self, on: bool) -> None:
         _check(_lib().dpmt_set_profiling(self._h, 1 if on else 0), self._h, "dpmt_set_profiling")
 
-    STAGES = ("projection", "correlation", "dt_row", "dt_col", "assemble", "total")
+    STAGES = ("projection", "correlation", "placement", "total")
 
     def stage_times(self):
         """Mean GPU milliseconds per profiled call of each stage, and the call count."""
-        buf = (c_float * 6)()
+        buf = (c_float * len(self.STAGES))()
         calls = c_int32(0)
-        n = _lib().dpmt_stage_times(self._h, buf, 6, byref(calls))
+        n = _lib().dpmt_stage_times(self._h, buf, len(self.STAGES), byref(calls))
         return {self.STAGES[i]: buf[i] for i in range(n)}, calls.value
 
 

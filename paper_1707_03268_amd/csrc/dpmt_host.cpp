@@ -65,9 +65,13 @@ struct BlockKey {
 };
 
 struct BlockInfo {
-    int64_t off;      // element offset in the response workspace
+    int64_t off;      // element offset of the group's first plane in the response workspace
     int Ho, Wo;
+    int ld;           // plane row pitch (Wo rounded up to a multiple of 4)
+    int64_t rng;      // range slot of the group's first plane
 };
+
+int pitch_of(int Wo) { return (Wo + 3) & ~3; }
 
 template <typename T>
 hipError_t upload(T** dptr, const std::vector<T>& v) {
@@ -93,6 +97,9 @@ uint16_t f32_to_bf16(float f) {
 
 }  // namespace
 
+constexpr int N_STAGES = 3;             // projection, correlation, placement
+constexpr int N_EVENTS = N_STAGES + 1;
+
 struct dpmt_ctx {
     int device = -1;
     hipStream_t stream = nullptr;
@@ -112,9 +119,7 @@ struct dpmt_ctx {
     std::vector<Comp> comps;
     std::vector<HostGroup> groups;      // root groups, part groups, all groups
     std::vector<int> comp_root_group, comp_root_col;
-    std::vector<PairDesc> pairs;        // per part group, concatenated
-    std::vector<int> group_pair_base, group_pair_count;
-    std::vector<std::vector<std::pair<int, int>>> slot_pair;   // [comp][slot] -> (group, pair in group)
+    std::vector<std::vector<std::pair<int, int>>> comp_part_gc;   // [comp][slot] -> (part group, column)
 
     // decomposition
     bool decomposed = false;
@@ -131,35 +136,28 @@ struct dpmt_ctx {
     std::vector<int> octave;
     std::map<BlockKey, BlockInfo> blocks;
     int64_t resp_elems = 0;
+    int64_t n_slots = 0;                // response planes (one value range each)
     int64_t n_cells = 0;
     std::vector<int32_t> m_image, m_level, m_comp, m_rows, m_cols;
     std::vector<int64_t> m_score_off, m_offs_off;
     std::vector<MapDesc> maps;
-    std::vector<DTItem> dt_items;
-    std::vector<int2> row_blk, col_blk, asm_blk;   // per launched block: (work item, block within it)
-    int row_blocks = 0, col_blocks = 0, asm_blocks = 0;
-    int64_t r1_elems = 0;
-    int max_Wp = 0;                     // longest DT row (row-pass LDS staging)
-    int64_t max_Hp = 0;                 // largest column-pass tile Hp * cw (elements)
+    std::vector<MapPart> map_parts;
+    std::vector<int2> place_blk;        // per placement block: (map, strip)
+    PlaceLds place_lds{};
     dpmt_layout layout{};
 
     // device workspace
-    float* d_resp = nullptr;
-    float* d_r1v = nullptr;
-    int32_t* d_r1a = nullptr;
-    float* d_dbuf = nullptr;            // deformed part scores, [map][part][pos]
+    float* d_resp = nullptr;            // filter response planes
+    int* d_rkeys = nullptr;             // 2 * n_slots value-range keys
     void* d_Z = nullptr;
     size_t Z_bytes = 0;
-    PairDesc* d_pairs = nullptr;
     MapDesc* d_maps = nullptr;
-    DTItem* d_items = nullptr;
-    int2* d_row_blk = nullptr;
-    int2* d_col_blk = nullptr;
-    int2* d_asm_blk = nullptr;
+    MapPart* d_parts = nullptr;
+    int2* d_place_blk = nullptr;
 
-    // profiling: one set of 6 events per profiled call
+    // profiling: one set of events per profiled call
     bool prof = false;
-    std::vector<std::array<hipEvent_t, 6>> ev_sets;
+    std::vector<std::array<hipEvent_t, N_EVENTS>> ev_sets;
     int ev_used = 0;
 
     bool has_device() const { return device >= 0; }
@@ -198,15 +196,11 @@ void free_mode(ModeData& m) {
 
 void free_plan(dpmt_ctx* c) {
     dfree(c->d_resp); c->d_resp = nullptr;
-    dfree(c->d_r1v); c->d_r1v = nullptr;
-    dfree(c->d_r1a); c->d_r1a = nullptr;
-    dfree(c->d_dbuf); c->d_dbuf = nullptr;
+    dfree(c->d_rkeys); c->d_rkeys = nullptr;
     dfree(c->d_Z); c->d_Z = nullptr; c->Z_bytes = 0;
     dfree(c->d_maps); c->d_maps = nullptr;
-    dfree(c->d_items); c->d_items = nullptr;
-    dfree(c->d_row_blk); c->d_row_blk = nullptr;
-    dfree(c->d_col_blk); c->d_col_blk = nullptr;
-    dfree(c->d_asm_blk); c->d_asm_blk = nullptr;
+    dfree(c->d_parts); c->d_parts = nullptr;
+    dfree(c->d_place_blk); c->d_place_blk = nullptr;
     for (auto& m : c->modes) {
         dfree(m.dTiles);
         m.dTiles = nullptr;
@@ -451,54 +445,20 @@ void build_groups(dpmt_ctx* c) {
         c->comp_root_group[ci] = g;
         c->comp_root_col[ci] = col_of(g, c->comps[ci].root);
     }
-    std::vector<std::vector<PairDesc>> gp;
-    for (size_t ci = 0; ci < c->comps.size(); ++ci) {
-        const auto& cm = c->comps[ci];
-        for (size_t s = 0; s < cm.parts.size(); ++s) {
-            const int k = cm.parts[s];
+    c->comp_part_gc.assign(c->comps.size(), {});
+    for (size_t ci = 0; ci < c->comps.size(); ++ci)
+        for (int k : c->comps[ci].parts) {
             const int g = group_for(part_g, ROLE_PART, k);
-            const int col = col_of(g, k);
-            if ((int)gp.size() <= g) gp.resize(g + 1);
-            PairDesc pd{};
-            pd.fcol = col;
-            pd.comp = (int)ci;
-            pd.slot = (int)s;
-            pd.vy = cm.anchors[s][0];
-            pd.vx = cm.anchors[s][1];
-            pd.h0 = c->shapes[cm.root].h;
-            pd.w0 = c->shapes[cm.root].w;
-            for (int t = 0; t < 4; ++t) pd.d[t] = cm.deform[s][t];
-            gp[g].push_back(pd);
+            c->comp_part_gc[ci].push_back({g, col_of(g, k)});
         }
-    }
     for (size_t k = 0; k < c->shapes.size(); ++k) {
         const int g = group_for(all_g, ROLE_ALL, (int)k);
         col_of(g, (int)k);
     }
-    gp.resize(c->groups.size());
-    c->pairs.clear();
-    c->group_pair_base.assign(c->groups.size(), 0);
-    c->group_pair_count.assign(c->groups.size(), 0);
-    for (size_t g = 0; g < c->groups.size(); ++g) {
-        // pairs ordered by the column of their filter, so that lanes of a
-        // wavefront read neighbouring columns of the response block
-        std::stable_sort(gp[g].begin(), gp[g].end(),
-                         [](const PairDesc& a, const PairDesc& b) { return a.fcol < b.fcol; });
-        c->group_pair_base[g] = (int)c->pairs.size();
-        c->group_pair_count[g] = (int)gp[g].size();
-        c->pairs.insert(c->pairs.end(), gp[g].begin(), gp[g].end());
-    }
-    c->slot_pair.assign(c->comps.size(), {});
-    for (size_t ci = 0; ci < c->comps.size(); ++ci) c->slot_pair[ci].assign(c->comps[ci].parts.size(), {-1, -1});
-    for (size_t g = 0; g < c->groups.size(); ++g)
-        for (int p = 0; p < c->group_pair_count[g]; ++p) {
-            const PairDesc& pd = c->pairs[c->group_pair_base[g] + p];
-            c->slot_pair[pd.comp][pd.slot] = {(int)g, p};
-        }
 }
 
 void add_tiles(std::vector<CorrTile>& tiles, const GroupDesc& gd, int group, int64_t z_cell,
-               int64_t out_off, int H, int W) {
+               int64_t out_off, int rng, int H, int W) {
     const int Ho = H - gd.h + 1, Wo = W - gd.w + 1;
     if (Ho <= 0 || Wo <= 0) return;
     const int nblk = (gd.ng + 31) / 32;
@@ -512,6 +472,8 @@ void add_tiles(std::vector<CorrTile>& tiles, const GroupDesc& gd, int group, int
                 t.W = W;
                 t.Ho = Ho;
                 t.Wo = Wo;
+                t.ld = pitch_of(Wo);
+                t.rng = rng;
                 t.y0 = y0;
                 t.x0 = x0;
                 t.fb0 = fb;
@@ -527,7 +489,8 @@ dpmt_status prepare_tiles(dpmt_ctx* c, dpmt_mode mode) {
     for (const auto& kv : c->blocks) {
         const BlockKey& k = kv.first;
         const LevelInfo& lv = c->pyr[k.img][k.level];
-        add_tiles(tiles, md.groups[k.group], k.group, lv.cell_offset, kv.second.off, lv.rows, lv.cols);
+        add_tiles(tiles, md.groups[k.group], k.group, lv.cell_offset, kv.second.off,
+                  (int)kv.second.rng, lv.rows, lv.cols);
     }
     // most expensive groups first so that the tail of the launch is short tiles
     std::stable_sort(tiles.begin(), tiles.end(), [&](const CorrTile& a, const CorrTile& b) {
@@ -596,7 +559,6 @@ void dpmt_destroy(dpmt_ctx* c) {
         (void)hipDeviceSynchronize();
         free_plan(c);
         for (auto& m : c->modes) free_mode(m);
-        dfree(c->d_pairs);
         for (auto& set : c->ev_sets)
             for (auto& e : set) (void)hipEventDestroy(e);
     }
@@ -667,7 +629,6 @@ dpmt_status dpmt_load_filters(dpmt_ctx* c, int32_t n_filters, const dpmt_shape* 
         c->comps.push_back(cp);
     }
     build_groups(c);
-    if (c->has_device()) HIP_TRY(c, upload(&c->d_pairs, c->pairs), "upload pair table");
     c->loaded = true;
     c->err.clear();
     return DPMT_OK;
@@ -741,6 +702,8 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
                 return fail(c, DPMT_E_INVALID, "image " + std::to_string(i) + " level " + std::to_string(l) + ": bad size or offset");
             if ((int64_t)lv.rows * lv.cols > (int64_t)1 << 30)
                 return fail(c, DPMT_E_UNSUPPORTED, "level larger than 2^30 cells");
+            if (lv.rows > 16384 || lv.cols > 16384)
+                return fail(c, DPMT_E_UNSUPPORTED, "level side longer than 16384 cells");
         }
     }
     if (c->has_device()) {
@@ -760,9 +723,11 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
             c->n_cells = std::max(c->n_cells, lv.cell_offset + (int64_t)lv.rows * lv.cols);
         }
     }
-    // response blocks: root groups on levels >= octave, part groups one octave below
+    // response blocks: root groups on levels >= octave, part groups one octave
+    // below; one plane per filter with a pitch of whole 16-byte runs
     c->blocks.clear();
     c->resp_elems = 0;
+    c->n_slots = 0;
     int64_t n_root = 0, n_part = 0;
     for (int i = 0; i < n_images; ++i) {
         const int L = (int)c->pyr[i].size(), oct = c->octave[i];
@@ -775,23 +740,24 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
                 const LevelInfo& lv = c->pyr[i][l];
                 const int Ho = lv.rows - hg.h + 1, Wo = lv.cols - hg.w + 1;
                 if (Ho <= 0 || Wo <= 0) continue;
-                c->blocks[BlockKey{i, l, (int)g}] = BlockInfo{c->resp_elems, Ho, Wo};
-                const int64_t n = (int64_t)Ho * Wo * hg.filters.size();
-                c->resp_elems += n;
-                (hg.role == ROLE_ROOT ? n_root : n_part) += n;
+                const int ld = pitch_of(Wo);
+                c->blocks[BlockKey{i, l, (int)g}] = BlockInfo{c->resp_elems, Ho, Wo, ld, c->n_slots};
+                const int64_t ng = (int64_t)hg.filters.size();
+                c->resp_elems += ng * Ho * ld;
+                c->n_slots += ng;
+                (hg.role == ROLE_ROOT ? n_root : n_part) += ng * Ho * Wo;
             }
         }
     }
-    // score maps
+    if (c->n_slots >= INT32_MAX) return fail(c, DPMT_E_UNSUPPORTED, "batch has too many response planes");
+    // score maps and their parts
     c->m_image.clear(); c->m_level.clear(); c->m_comp.clear(); c->m_rows.clear(); c->m_cols.clear();
-    c->m_score_off.clear(); c->m_offs_off.clear(); c->maps.clear();
+    c->m_score_off.clear(); c->m_offs_off.clear(); c->maps.clear(); c->map_parts.clear();
     int64_t score_off = 0, offs_off = 0;
-    std::vector<std::vector<int>> map_base(n_images);
+    int max_Ho = 0, max_Hp = 0, max_Wp = 0;
     for (int i = 0; i < n_images; ++i) {
         const int L = (int)c->pyr[i].size(), oct = c->octave[i];
-        map_base[i].assign(L, -1);
         for (int l = oct; l < L; ++l) {
-            map_base[i][l] = (int)c->maps.size();
             const LevelInfo& lv = c->pyr[i][l];
             for (size_t ci = 0; ci < c->comps.size(); ++ci) {
                 const auto& cm = c->comps[ci];
@@ -804,11 +770,34 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
                 md.Ho = Ho;
                 md.Wo = Wo;
                 md.n_parts = np;
-                const int rg = c->comp_root_group[ci];
-                md.rng = (int)c->groups[rg].filters.size();
-                md.rcol = c->comp_root_col[ci];
-                auto bit = c->blocks.find(BlockKey{i, l, rg});
-                md.rresp_off = bit == c->blocks.end() ? 0 : bit->second.off;
+                md.part_base = (int)c->map_parts.size();
+                auto rb = c->blocks.find(BlockKey{i, l, c->comp_root_group[ci]});
+                if (rb != c->blocks.end()) {
+                    md.root_plane = rb->second.off + (int64_t)c->comp_root_col[ci] * rb->second.Ho * rb->second.ld;
+                    md.ldr = rb->second.ld;
+                }
+                for (int sl = 0; sl < np; ++sl) {
+                    MapPart mp{};
+                    const auto gc = c->comp_part_gc[ci][sl];
+                    auto pb = c->blocks.find(BlockKey{i, l - oct, gc.first});
+                    if (pb != c->blocks.end()) {
+                        const BlockInfo& bi = pb->second;
+                        mp.plane = bi.off + (int64_t)gc.second * bi.Ho * bi.ld;
+                        mp.ld = bi.ld;
+                        mp.Hp = bi.Ho;
+                        mp.Wp = bi.Wo;
+                        mp.rng = (int32_t)(bi.rng + gc.second);
+                    }
+                    mp.vy = cm.anchors[sl][0];
+                    mp.vx = cm.anchors[sl][1];
+                    for (int t = 0; t < 4; ++t) mp.d[t] = cm.deform[sl][t];
+                    if (Ho > 0 && Wo > 0) {
+                        max_Hp = std::max(max_Hp, mp.Hp);
+                        max_Wp = std::max(max_Wp, mp.Wp);
+                    }
+                    c->map_parts.push_back(mp);
+                }
+                if (Ho > 0 && Wo > 0) max_Ho = std::max(max_Ho, Ho);
                 c->maps.push_back(md);
                 c->m_image.push_back(i);
                 c->m_level.push_back(l);
@@ -823,74 +812,40 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
             }
         }
     }
-    // distance-transform items: (image, root level, part group)
-    c->dt_items.clear();
-    c->r1_elems = 0;
-    for (int i = 0; i < n_images; ++i) {
-        const int L = (int)c->pyr[i].size(), oct = c->octave[i];
-        for (int l = oct; l < L; ++l) {
-            const LevelInfo& rl = c->pyr[i][l];
-            const LevelInfo& pl = c->pyr[i][l - oct];
-            for (size_t g = 0; g < c->groups.size(); ++g) {
-                const HostGroup& hg = c->groups[g];
-                if (hg.role != ROLE_PART || c->group_pair_count[g] == 0) continue;
-                int Ht = 0, Wt = 0;
-                for (int p = 0; p < c->group_pair_count[g]; ++p) {
-                    const PairDesc& pd = c->pairs[c->group_pair_base[g] + p];
-                    Ht = std::max(Ht, rl.rows - pd.h0 + 1);
-                    Wt = std::max(Wt, rl.cols - pd.w0 + 1);
-                }
-                if (Ht <= 0 || Wt <= 0) continue;
-                DTItem it{};
-                it.Hp = std::max(pl.rows - hg.h + 1, 0);
-                it.Wp = std::max(pl.cols - hg.w + 1, 0);
-                if (it.Hp == 0 || it.Wp == 0) it.Hp = it.Wp = 0;
-                auto bit = c->blocks.find(BlockKey{i, l - oct, (int)g});
-                it.resp_off = bit == c->blocks.end() ? 0 : bit->second.off;
-                it.r1_off = c->r1_elems;
-                it.Ht = Ht;
-                it.Wt = Wt;
-                it.Hr = rl.rows;
-                it.Wr = rl.cols;
-                it.ng = (int)hg.filters.size();
-                it.np = c->group_pair_count[g];
-                it.pair_base = c->group_pair_base[g];
-                it.map_base = map_base[i][l];
-                // column-pass block width: every column of the map when the staged
-                // [Hp][cw] tile fits, at most 256, at least 1
-                it.cw = std::max(1, std::min({Wt, 256, it.Hp > 0 ? (int)(DT_COL_LDS / 4 / it.Hp) : 256}));
-                c->r1_elems += (int64_t)it.Hp * it.Wt * it.np;
-                c->dt_items.push_back(it);
-            }
+    if (c->map_parts.size() >= (size_t)INT32_MAX) return fail(c, DPMT_E_UNSUPPORTED, "batch has too many score maps");
+    // placement blocks: (map, strip of PLACE_CW root columns), largest work first
+    // so that the launch ends on short blocks
+    {
+        std::vector<std::pair<int64_t, int>> order;
+        for (size_t k = 0; k < c->maps.size(); ++k) {
+            const MapDesc& md = c->maps[k];
+            if (md.Ho <= 0 || md.Wo <= 0) continue;
+            int64_t work = 0;
+            for (int sl = 0; sl < md.n_parts; ++sl) work += c->map_parts[md.part_base + sl].Hp + md.Ho;
+            order.push_back({-work, (int)k});
         }
+        std::stable_sort(order.begin(), order.end());
+        c->place_blk.clear();
+        int64_t nb = 0;
+        for (const auto& o : order) nb += (c->maps[o.second].Wo + PLACE_CW - 1) / PLACE_CW;
+        if (nb > INT32_MAX) return fail(c, DPMT_E_UNSUPPORTED, "batch too large for one launch");
+        for (const auto& o : order) {
+            const int strips = (c->maps[o.second].Wo + PLACE_CW - 1) / PLACE_CW;
+            for (int st = 0; st < strips; ++st) c->place_blk.push_back(make_int2(o.second, st));
+        }
+        const int span = place_span_max(max_Wp);
+        if (span > PLACE_STAGE)
+            return fail(c, DPMT_E_UNSUPPORTED, "part level wider than the placement staging supports");
+        PlaceLds& pl = c->place_lds;
+        pl.acc_rows = std::max(max_Ho, 1);
+        pl.r1_rows = max_Hp + 2 * PLACE_PAD;
+        pl.stage_words = PLACE_STAGE;
+        // row table: window of at most Wp + 2 (CW - 1) + 3 (alignment) + 1 offsets,
+        // rounded up to 4; column table: at most 2 (Hp + 1) + 1 offsets plus 4
+        pl.ctab_words = (std::max(max_Wp + 2 * (PLACE_CW - 1) + 8, 2 * (max_Hp + 1) + 1 + 4) + 3) & ~3;
+        if (place_lds_bytes(pl) > 160 * 1024)
+            return fail(c, DPMT_E_UNSUPPORTED, "score maps too tall for one placement block");
     }
-    c->row_blk.clear(); c->col_blk.clear(); c->asm_blk.clear();
-    c->max_Wp = c->max_Hp = 0;
-    int64_t rb = 0, cb = 0, ab = 0;
-    for (size_t k = 0; k < c->dt_items.size(); ++k) {
-        const DTItem& it = c->dt_items[k];
-        const int64_t nr = (int64_t)((it.np + DT_ROW_PAIRS_PER_BLOCK - 1) / DT_ROW_PAIRS_PER_BLOCK) * it.Hp;
-        const int64_t nc = (int64_t)it.np * ((it.Wt + it.cw - 1) / it.cw);
-        rb += nr;
-        cb += nc;
-        if (rb > INT32_MAX || cb > INT32_MAX) break;
-        for (int64_t b = 0; b < nr; ++b) c->row_blk.push_back(make_int2((int)k, (int)b));
-        for (int64_t b = 0; b < nc; ++b) c->col_blk.push_back(make_int2((int)k, (int)b));
-        c->max_Wp = std::max(c->max_Wp, it.Wp);
-        c->max_Hp = std::max<int64_t>(c->max_Hp, (int64_t)it.Hp * it.cw);
-    }
-    for (size_t k = 0; k < c->maps.size() && ab <= INT32_MAX; ++k) {
-        const MapDesc& md = c->maps[k];
-        const int64_t na = ((int64_t)md.Ho * md.Wo + ASM_BLOCK - 1) / ASM_BLOCK;
-        ab += na;
-        if (ab > INT32_MAX) break;
-        for (int64_t b = 0; b < na; ++b) c->asm_blk.push_back(make_int2((int)k, (int)b));
-    }
-    if (rb > INT32_MAX || cb > INT32_MAX || ab > INT32_MAX)
-        return fail(c, DPMT_E_UNSUPPORTED, "batch too large for one launch");
-    c->row_blocks = (int)rb;
-    c->col_blocks = (int)cb;
-    c->asm_blocks = (int)ab;
 
     dpmt_layout& lay = c->layout;
     lay = dpmt_layout{};
@@ -908,7 +863,7 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
     lay.n_resp = n_root + n_part;
     lay.n_resp_root = n_root;
     lay.n_resp_part = n_part;
-    lay.workspace_bytes = c->resp_elems * 4 + c->r1_elems * 8 + (offs_off / 2) * 4;
+    lay.workspace_bytes = c->resp_elems * 4 + c->n_slots * 8;
 
     if (c->has_device()) {
         auto alloc = [&](void** p, int64_t bytes, const char* what) -> dpmt_status {
@@ -919,14 +874,10 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
         };
         dpmt_status s;
         if ((s = alloc((void**)&c->d_resp, c->resp_elems * 4, "allocate responses")) != DPMT_OK) return s;
-        if ((s = alloc((void**)&c->d_r1v, c->r1_elems * 4, "allocate row pass values")) != DPMT_OK) return s;
-        if ((s = alloc((void**)&c->d_r1a, c->r1_elems * 4, "allocate row pass argmax")) != DPMT_OK) return s;
-        if ((s = alloc((void**)&c->d_dbuf, (offs_off / 2) * 4, "allocate part scores")) != DPMT_OK) return s;
+        if ((s = alloc((void**)&c->d_rkeys, std::max<int64_t>(c->n_slots, 1) * 8, "allocate value ranges")) != DPMT_OK) return s;
         HIP_TRY(c, upload(&c->d_maps, c->maps), "upload maps");
-        HIP_TRY(c, upload(&c->d_items, c->dt_items), "upload DT items");
-        HIP_TRY(c, upload(&c->d_row_blk, c->row_blk), "upload block map");
-        HIP_TRY(c, upload(&c->d_col_blk, c->col_blk), "upload block map");
-        HIP_TRY(c, upload(&c->d_asm_blk, c->asm_blk), "upload block map");
+        HIP_TRY(c, upload(&c->d_parts, c->map_parts), "upload map parts");
+        HIP_TRY(c, upload(&c->d_place_blk, c->place_blk), "upload block map");
     }
     c->planned = true;
     *out = &c->layout;
@@ -946,19 +897,19 @@ int32_t dpmt_stage_times(dpmt_ctx* c, float* ms_out, int32_t n, int32_t* n_calls
     if (n_calls) *n_calls = 0;
     if (!c || !ms_out || n <= 0 || c->ev_used == 0) return 0;
     (void)hipSetDevice(c->device);
-    double sum[6] = {0, 0, 0, 0, 0, 0};
+    double sum[N_STAGES + 1] = {};
     for (int k = 0; k < c->ev_used; ++k) {
         auto& ev = c->ev_sets[k];
-        if (hipEventSynchronize(ev[5]) != hipSuccess) return 0;
+        if (hipEventSynchronize(ev[N_STAGES]) != hipSuccess) return 0;
         float t;
-        for (int i = 0; i < 5; ++i) {
+        for (int i = 0; i < N_STAGES; ++i) {
             if (hipEventElapsedTime(&t, ev[i], ev[i + 1]) != hipSuccess) return 0;
             sum[i] += t;
         }
-        if (hipEventElapsedTime(&t, ev[0], ev[5]) != hipSuccess) return 0;
-        sum[5] += t;
+        if (hipEventElapsedTime(&t, ev[0], ev[N_STAGES]) != hipSuccess) return 0;
+        sum[N_STAGES] += t;
     }
-    const int m = std::min<int32_t>(n, 6);
+    const int m = std::min<int32_t>(n, N_STAGES + 1);
     for (int i = 0; i < m; ++i) ms_out[i] = (float)(sum[i] / c->ev_used);
     if (n_calls) *n_calls = c->ev_used;
     return m;
@@ -996,28 +947,28 @@ dpmt_status dpmt_score_pyramid(dpmt_ctx* c, dpmt_mode mode, const float* feature
     hipEvent_t* ev = nullptr;
     if (c->prof) {
         if (c->ev_used == (int)c->ev_sets.size()) {
-            std::array<hipEvent_t, 6> set{};
+            std::array<hipEvent_t, N_EVENTS> set{};
             for (auto& e : set) HIP_TRY(c, hipEventCreate(&e), "hipEventCreate");
             c->ev_sets.push_back(set);
         }
         ev = c->ev_sets[c->ev_used++].data();
     }
-    const bool prof = ev != nullptr;
-    if (prof) HIP_TRY(c, hipEventRecord(ev[0], st), "hipEventRecord");
+    auto mark = [&](int k) -> hipError_t { return ev ? hipEventRecord(ev[k], st) : hipSuccess; };
+    HIP_TRY(c, mark(0), "hipEventRecord");
+    HIP_TRY(c, launch_range_init(c->d_rkeys, c->n_slots, st), "range init launch");
     if (mode == DPMT_TENSOR_FP8)
         HIP_TRY(c, fp8_operands(c, md, features_dev, c->n_cells, c->d_Z, st), "FP8 operand launch");
     else if (tensor)
         HIP_TRY(c, launch_project(md.pk.esz == 2, features_dev, c->n_cells, md.dU, md.pk.RP, c->d_Z, st), "projection launch");
-    if (prof) HIP_TRY(c, hipEventRecord(ev[1], st), "hipEventRecord");
+    HIP_TRY(c, mark(1), "hipEventRecord");
     CorrLaunch cl{md.kind, md.pk, TY, BB, WY};
-    HIP_TRY(c, launch_corr(cl, md.dTiles, md.n_tiles, md.dGroups, Zsrc, md.dG, md.dTk, c->d_resp, md.max_h, md.max_S, st), "correlation launch");
-    if (prof) HIP_TRY(c, hipEventRecord(ev[2], st), "hipEventRecord");
-    HIP_TRY(c, launch_dt_row(c->d_items, c->d_row_blk, c->row_blocks, c->d_pairs, c->d_resp, c->d_r1v, c->d_r1a, c->max_Wp, st), "DT row launch");
-    if (prof) HIP_TRY(c, hipEventRecord(ev[3], st), "hipEventRecord");
-    HIP_TRY(c, launch_dt_col(c->d_items, c->d_col_blk, c->col_blocks, c->d_pairs, c->d_maps, c->d_r1v, c->d_r1a, c->d_dbuf, offsets_dev, (int)std::min<int64_t>(c->max_Hp, INT32_MAX), st), "DT column launch");
-    if (prof) HIP_TRY(c, hipEventRecord(ev[4], st), "hipEventRecord");
-    HIP_TRY(c, launch_assemble(c->d_maps, c->d_asm_blk, c->asm_blocks, c->d_resp, c->d_dbuf, scores_dev, st), "assembly launch");
-    if (prof) HIP_TRY(c, hipEventRecord(ev[5], st), "hipEventRecord");
+    HIP_TRY(c, launch_corr(cl, md.dTiles, md.n_tiles, md.dGroups, Zsrc, md.dG, md.dTk, c->d_resp,
+                           c->d_rkeys, c->n_slots, md.max_h, md.max_S, st), "correlation launch");
+    HIP_TRY(c, mark(2), "hipEventRecord");
+    HIP_TRY(c, launch_place(c->d_maps, c->d_parts, c->d_place_blk, (int)c->place_blk.size(), c->d_resp,
+                            c->d_rkeys, c->n_slots, scores_dev, offsets_dev, c->place_lds, st),
+            "placement launch");
+    HIP_TRY(c, mark(3), "hipEventRecord");
     return DPMT_OK;
 }
 
@@ -1051,9 +1002,10 @@ dpmt_status dpmt_level_responses(dpmt_ctx* c, dpmt_mode mode, const float* featu
     ModeData& md = c->modes[mode];
     hipStream_t st = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
     const bool tensor = mode != DPMT_DIRECT_FP32;
-    // per-group blocks in a temporary buffer, then scattered to per-filter maps
+    // per-group planes in a temporary buffer, then copied to per-filter maps
     std::vector<CorrTile> tiles;
-    std::vector<std::pair<int, int64_t>> gblocks;   // (group, block offset)
+    struct GB { int g; int64_t off; int Ho, Wo, ld; };
+    std::vector<GB> gblocks;
     int64_t blk_total = 0;
     int max_h = 0, max_S = 0;
     for (size_t g = 0; g < c->groups.size(); ++g) {
@@ -1061,9 +1013,9 @@ dpmt_status dpmt_level_responses(dpmt_ctx* c, dpmt_mode mode, const float* featu
         const GroupDesc& gd = md.groups[g];
         const int Ho = lv.rows - gd.h + 1, Wo = lv.cols - gd.w + 1;
         if (Ho <= 0 || Wo <= 0) continue;
-        add_tiles(tiles, gd, (int)g, 0, blk_total, lv.rows, lv.cols);
-        gblocks.push_back({(int)g, blk_total});
-        blk_total += (int64_t)Ho * Wo * gd.ng;
+        add_tiles(tiles, gd, (int)g, 0, blk_total, -1, lv.rows, lv.cols);
+        gblocks.push_back({(int)g, blk_total, Ho, Wo, pitch_of(Wo)});
+        blk_total += (int64_t)Ho * pitch_of(Wo) * gd.ng;
         max_h = std::max(max_h, gd.h);
         max_S = std::max(max_S, gd.S);
     }
@@ -1090,18 +1042,17 @@ dpmt_status dpmt_level_responses(dpmt_ctx* c, dpmt_mode mode, const float* featu
     if (e == hipSuccess) e = hipMalloc((void**)&dblk, (size_t)blk_total * 4);
     if (e == hipSuccess) e = upload(&dtiles, tiles);
     CorrLaunch cl{md.kind, md.pk, TY, BB, WY};
-    if (e == hipSuccess) e = launch_corr(cl, dtiles, (int)tiles.size(), md.dGroups, Zsrc, md.dG, md.dTk, dblk, max_h, max_S, st);
+    if (e == hipSuccess) e = launch_corr(cl, dtiles, (int)tiles.size(), md.dGroups, Zsrc, md.dG, md.dTk, dblk, nullptr, 0, max_h, max_S, st);
     for (const auto& gb : gblocks) {
         if (e != hipSuccess) break;
-        const HostGroup& hg = c->groups[gb.first];
+        const HostGroup& hg = c->groups[gb.g];
         std::vector<int64_t> dst;
         for (int k : hg.filters) dst.push_back(map_off[k]);
         dfree(doff);
         doff = nullptr;
         e = hipStreamSynchronize(st);
         if (e == hipSuccess) e = upload(&doff, dst);
-        const int64_t n_pos = (int64_t)(lv.rows - hg.h + 1) * (lv.cols - hg.w + 1);
-        if (e == hipSuccess) e = launch_block_to_maps(dblk + gb.second, n_pos, (int)hg.filters.size(), doff, out_dev, st);
+        if (e == hipSuccess) e = launch_planes_to_maps(dblk + gb.off, (int)hg.filters.size(), gb.Ho, gb.Wo, gb.ld, doff, out_dev, st);
     }
     cleanup();
     if (e != hipSuccess) return hip_fail(c, e, "level responses");

@@ -18,7 +18,8 @@ struct Packing {
 };
 
 // One (role, shape) group of filters.  Responses of a group on a level are
-// stored as a [position][ng] float32 block, position = y * Wo + x.
+// stored filter-major: one Ho x ld float32 plane per filter of the group,
+// position (y, x) at y * ld + x, ld = Wo rounded up to a multiple of 4.
 struct GroupDesc {
     int32_t h, w;      // filter rows, cols
     int32_t ng;        // filters in the group
@@ -43,35 +44,25 @@ struct RequantBlock {
 // (BB * 32) filters of one group on one level.
 struct CorrTile {
     int64_t z_cell;    // first cell of the level in the feature / projected buffer
-    int64_t out_off;   // element offset of the group's response block on this level
+    int64_t out_off;   // element offset of the group's first response plane on this level
     int32_t H, W;      // level rows, cols
     int32_t Ho, Wo;    // response rows, cols
+    int32_t ld;        // row pitch of the response planes (multiple of 4)
+    int32_t rng;       // range slot of the group's first plane (-1: no ranges)
     int32_t y0, x0;    // first output row, col
     int32_t fb0;       // first 32-filter block
     int32_t group;
 };
 
-// One (component, part slot) whose part filter belongs to a part group.
-struct PairDesc {
-    int32_t fcol;      // column of the part filter in the group's response block
-    int32_t comp, slot;
+// One part of one score map: where its response plane lives, its anchor and
+// its deformation coefficients.
+struct MapPart {
+    int64_t plane;     // element offset of the part filter's response plane
+    int32_t ld;        // plane row pitch
+    int32_t Hp, Wp;    // part response map (0 x 0 when the filter does not fit)
+    int32_t rng;       // range slot of the plane
     int32_t vy, vx;    // anchor (part-level cells)
-    int32_t h0, w0;    // root filter shape of the component
-    int32_t pad;
     float d[4];        // d_x, d_xx, d_y, d_yy
-};
-
-// Distance-transform work for one (image, root level, part group).
-struct DTItem {
-    int64_t resp_off;  // part responses [Hp][Wp][ng]
-    int64_t r1_off;    // row-pass output [np][Hp][Wt] (value and argmax share indexing)
-    int32_t Hp, Wp;    // part response map
-    int32_t Ht, Wt;    // largest root map over the group's components
-    int32_t Hr, Wr;    // root level rows, cols
-    int32_t ng, np;    // filters in the group, pairs in the group
-    int32_t pair_base; // first pair of the group in the pair table
-    int32_t map_base;  // map index of component 0 at this (image, root level)
-    int32_t cw;        // root columns per column-pass block
     int32_t pad;
 };
 
@@ -79,10 +70,11 @@ struct DTItem {
 struct MapDesc {
     int64_t score_off; // float offset into the caller's scores
     int64_t offs_off;  // int16 offset into the caller's offsets ([part][pos][2])
-    int64_t rresp_off; // root response block of the root group on this level
+    int64_t root_plane;// element offset of the root filter's response plane
     int32_t Ho, Wo;
+    int32_t ldr;       // root plane row pitch
     int32_t n_parts;
-    int32_t rng, rcol; // root group width and the root filter's column
+    int32_t part_base; // first MapPart of the map
     int32_t pad;
 };
 
@@ -97,12 +89,34 @@ struct CorrLaunch {
     int wy;            // waves per workgroup (stacked along rows)
 };
 
+// Placement kernel geometry.  A block owns PLACE_CW consecutive root columns
+// of one score map; its LDS holds the score accumulator, the row-pass tile of
+// the current part with PLACE_PAD -inf rows above and below, a staging area
+// for response rows, and the two cost tables.
+constexpr int PLACE_CW = 32;
+constexpr int PLACE_PAD = 5;
+constexpr int PLACE_STAGE = 3072;         // floats of the staging buffer (32 rows of 96)
+struct PlaceLds {
+    int acc_rows;      // largest map height
+    int r1_rows;       // largest part map height + 2 * PLACE_PAD
+    int stage_words;   // floats of the staging buffer (PLACE_STAGE)
+    int ctab_words;    // floats per cost table (multiple of 4)
+};
+size_t place_lds_bytes(const PlaceLds& l);
+// Row span (floats) a part of response width Wp can need in the staging
+// buffer: 2 * (PLACE_CW - 1) targets apart, plus a window clamped to the line
+// and aligned to whole 16-byte runs.
+inline int place_span_max(int Wp) { return Wp + 4 * (PLACE_CW - 1) + 12; }
+
 // --- kernel launchers (dpmt_kernels.hip) -----------------------------------
 hipError_t launch_project(bool bf16, const float* X, int64_t n_cells, const float* U,
                           int RP, void* Z, hipStream_t st);
+// rkeys (may be NULL): 2 * n_slots range keys, maxima then minima, updated
+// with the value range of every response plane whose tile names a slot.
 hipError_t launch_corr(const CorrLaunch& cfg, const CorrTile* tiles, int n_tiles,
                        const GroupDesc* groups, const void* Z, const void* G, const float* tk,
-                       float* out, int max_h, int max_S, hipStream_t st);
+                       float* out, int* rkeys, int64_t n_slots, int max_h, int max_S,
+                       hipStream_t st);
 hipError_t launch_fp8_prepare(const float* X, int64_t n_cells, const float* U, int RP,
                               float* partial, float* scales, const RequantBlock* blocks,
                               int n_blocks, const float* master, uint8_t* G, float* tk,
@@ -111,24 +125,14 @@ hipError_t launch_project_fp8(const float* X, int64_t n_cells, const float* U, i
                               const float* scales, void* Z, hipStream_t st);
 constexpr int FP8_PARTIALS = 512 * 32;   // floats of the channel-max scratch
 size_t corr_lds_bytes(const CorrLaunch& cfg, int h, int S);
-hipError_t launch_dt_row(const DTItem* items, const int2* blkmap, int n_blocks,
-                         const PairDesc* pairs, const float* resp, float* r1v, int32_t* r1a,
-                         int max_line, hipStream_t st);
-hipError_t launch_dt_col(const DTItem* items, const int2* blkmap, int n_blocks,
-                         const PairDesc* pairs, const MapDesc* maps, const float* r1v,
-                         const int32_t* r1a, float* dbuf, int16_t* offs, int max_line,
-                         hipStream_t st);
-hipError_t launch_assemble(const MapDesc* maps, const int2* blkmap, int n_blocks,
-                           const float* rresp, const float* dbuf, float* scores, hipStream_t st);
-hipError_t launch_block_to_maps(const float* block, int64_t n_pos, int ng, const int64_t* dst_off,
-                                float* out, hipStream_t st);
+hipError_t launch_range_init(int* rkeys, int64_t n_slots, hipStream_t st);
+hipError_t launch_place(const MapDesc* maps, const MapPart* parts, const int2* blkmap,
+                        int n_blocks, const float* resp, const int* rkeys, int64_t n_slots,
+                        float* scores, int16_t* offs, const PlaceLds& lds, hipStream_t st);
+hipError_t launch_planes_to_maps(const float* planes, int ng, int Ho, int Wo, int ld,
+                                 const int64_t* dst_off, float* out, hipStream_t st);
 hipError_t launch_dt_single(const float* resp, int rows, int cols, int ld, const float* d,
                             float* lmax, float* r1v, int32_t* r1a, float* out, int32_t* ay,
                             int32_t* ax, hipStream_t st);
-
-// Workgroup sizes used by the launchers (the planner sizes work lists with them).
-constexpr int DT_ROW_PAIRS_PER_BLOCK = 32;   // row pass: one part row of 32 pairs per block
-constexpr int DT_COL_LDS = 96 * 1024;        // column pass: LDS bytes of one staged [Hp][cw] tile
-constexpr int ASM_BLOCK = 256;         // assembly: threads per block
 
 }  // namespace dpmt

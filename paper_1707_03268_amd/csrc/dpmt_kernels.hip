@@ -7,11 +7,12 @@
 //                      (positions x filters x (taps * channels)), FP32 or BF16
 //                      operands, FP32 accumulation; used for the direct and
 //                      the shortened (rank-R) responses
-//   dt_row_kernel /    separable generalised distance transform (Section 2
-//   dt_col_kernel      placement argmax) evaluated at the part anchors of
-//                      every root position; exact windowed scan
-//   assemble_kernel    s(p0) = root response + sum of the parts' deformed
+//   place_kernel       separable generalised distance transform (Section 2
+//                      placement argmax) evaluated at the part anchors of
+//                      every root position, exact windowed scans, fused with
+//                      s(p0) = root response + sum of the parts' deformed
 //                      scores (Section 2 score formula)
+//   dt1_*_kernel       the same transform for every cell of one map
 #include "dpmt_internal.h"
 
 #include <cfloat>
@@ -21,6 +22,16 @@ namespace dpmt {
 
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+// Order-preserving map between float32 and int32, so that integer atomic
+// max / min keep float value ranges.
+__device__ __forceinline__ int range_key(float f) {
+    const int i = __float_as_int(f);
+    return i >= 0 ? i : i ^ 0x7fffffff;
+}
+__device__ __forceinline__ float range_value(int k) {
+    return __int_as_float(k >= 0 ? k : k ^ 0x7fffffff);
+}
 
 // ---------------------------------------------------------------------------
 // projection: Z[c][r] = sum_l X[c][l] * U[l][r]   (U: 32 x RP fp32, row major)
@@ -154,7 +165,9 @@ __global__ __launch_bounds__(64 * WY) __attribute__((amdgpu_waves_per_eu((HMAX <
                                                        const char* __restrict__ Z,
                                                        const char* __restrict__ G,
                                                        const float* __restrict__ tk,
-                                                       float* __restrict__ out, int cell_bytes,
+                                                       float* __restrict__ out,
+                                                       int* __restrict__ rmax,
+                                                       int* __restrict__ rmin, int cell_bytes,
                                                        int Q, int win_bytes) {
     extern __shared__ __align__(16) char smem[];
     constexpr int NT = 64 * WY;
@@ -329,7 +342,17 @@ __global__ __launch_bounds__(64 * WY) __attribute__((amdgpu_waves_per_eu((HMAX <
         }
     }
 
-    // epilogue: lane holds filter column p, positions 8*(k/4) + 4*j + k%4
+    // epilogue: lane holds filter column p, positions x0 + 8*(k/4) + 4*j + k%4,
+    // i.e. four runs of 4 consecutive positions stored as 16-byte vectors into
+    // the filter's plane (the pitch is a multiple of 4, so a run that starts
+    // inside the map ends inside the pitch).  The value range of every plane
+    // over its valid positions goes to the range slots.
+    float vmax[BB], vmin[BB];
+#pragma unroll
+    for (int b = 0; b < BB; ++b) {
+        vmax[b] = -INFINITY;
+        vmin[b] = INFINITY;
+    }
 #pragma unroll
     for (int i = 0; i < TY; ++i) {
         const int y = t.y0 + wv * TY + i;
@@ -338,12 +361,35 @@ __global__ __launch_bounds__(64 * WY) __attribute__((amdgpu_waves_per_eu((HMAX <
         for (int b = 0; b < BB; ++b) {
             const int f = (t.fb0 + b) * 32 + p;
             if (f >= g.ng) continue;
-            float* orow = out + t.out_off + (int64_t)y * t.Wo * g.ng + f;
+            float* orow = out + t.out_off + ((int64_t)f * t.Ho + y) * t.ld + t.x0 + 4 * j;
             const float sc = (KIND == CORR_FP8) ? tk[g.t_off + f] : 1.f;
 #pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                const int x = t.x0 + 8 * (k >> 2) + 4 * j + (k & 3);
-                if (x < t.Wo) orow[(int64_t)x * g.ng] = (KIND == CORR_FP8) ? acc[i][b][k] * sc : acc[i][b][k];
+            for (int m = 0; m < 4; ++m) {
+                const int x = t.x0 + 8 * m + 4 * j;
+                if (x >= t.Wo) continue;
+                float4 v;
+                v.x = acc[i][b][4 * m + 0] * sc;
+                v.y = acc[i][b][4 * m + 1] * sc;
+                v.z = acc[i][b][4 * m + 2] * sc;
+                v.w = acc[i][b][4 * m + 3] * sc;
+                *reinterpret_cast<float4*>(orow + 8 * m) = v;
+                vmax[b] = fmaxf(vmax[b], v.x);
+                vmin[b] = fminf(vmin[b], v.x);
+                if (x + 1 < t.Wo) { vmax[b] = fmaxf(vmax[b], v.y); vmin[b] = fminf(vmin[b], v.y); }
+                if (x + 2 < t.Wo) { vmax[b] = fmaxf(vmax[b], v.z); vmin[b] = fminf(vmin[b], v.z); }
+                if (x + 3 < t.Wo) { vmax[b] = fmaxf(vmax[b], v.w); vmin[b] = fminf(vmin[b], v.w); }
+            }
+        }
+    }
+    if (rmax != nullptr && t.rng >= 0) {
+#pragma unroll
+        for (int b = 0; b < BB; ++b) {
+            const float hi = fmaxf(vmax[b], __shfl_xor(vmax[b], 32, 64));
+            const float lo = fminf(vmin[b], __shfl_xor(vmin[b], 32, 64));
+            const int f = (t.fb0 + b) * 32 + p;
+            if (j == 0 && f < g.ng && hi >= lo) {
+                atomicMax(rmax + t.rng + f, range_key(hi));
+                atomicMin(rmin + t.rng + f, range_key(lo));
             }
         }
     }
@@ -362,7 +408,8 @@ size_t corr_lds_bytes(const CorrLaunch& cfg, int h, int S) {
 template <CorrKind KIND, int PB, int TY, int BB, int WY, int HMAX>
 static hipError_t launch_corr_h(const CorrTile* tiles, int n_tiles, const GroupDesc* groups,
                                 const void* Z, const void* G, const float* tk, float* out,
-                                int cell_bytes, int Q, int max_h, int max_S, hipStream_t st) {
+                                int* rkeys, int64_t n_slots, int cell_bytes, int Q, int max_h,
+                                int max_S, hipStream_t st) {
     CorrLaunch cfg{KIND, Packing{0, 0, PB, Q}, TY, BB, WY};
     const size_t lds = corr_lds_bytes(cfg, max_h, max_S);
     const int FB = FragT<KIND>::bytes;
@@ -378,7 +425,7 @@ static hipError_t launch_corr_h(const CorrTile* tiles, int n_tiles, const GroupD
     }
     hipLaunchKernelGGL(kern, dim3(n_tiles), dim3(64 * WY), lds, st, tiles, groups,
                        static_cast<const char*>(Z), static_cast<const char*>(G), tk, out,
-                       cell_bytes, Q, win_bytes);
+                       rkeys, rkeys ? rkeys + n_slots : nullptr, cell_bytes, Q, win_bytes);
     return hipGetLastError();
 }
 
@@ -387,24 +434,27 @@ static hipError_t launch_corr_h(const CorrTile* tiles, int n_tiles, const GroupD
 template <CorrKind KIND, int PB, int TY, int BB, int WY>
 static hipError_t launch_corr_t(const CorrTile* tiles, int n_tiles, const GroupDesc* groups,
                                 const void* Z, const void* G, const float* tk, float* out,
-                                int cell_bytes, int Q, int max_h, int max_S, hipStream_t st) {
+                                int* rkeys, int64_t n_slots, int cell_bytes, int Q, int max_h,
+                                int max_S, hipStream_t st) {
     if (max_h <= 8)
-        return launch_corr_h<KIND, PB, TY, BB, WY, 8>(tiles, n_tiles, groups, Z, G, tk, out,
-                                                      cell_bytes, Q, max_h, max_S, st);
+        return launch_corr_h<KIND, PB, TY, BB, WY, 8>(tiles, n_tiles, groups, Z, G, tk, out, rkeys,
+                                                      n_slots, cell_bytes, Q, max_h, max_S, st);
     return launch_corr_h<KIND, PB, TY, BB, WY, CORR_MAX_H>(tiles, n_tiles, groups, Z, G, tk, out,
-                                                           cell_bytes, Q, max_h, max_S, st);
+                                                           rkeys, n_slots, cell_bytes, Q, max_h,
+                                                           max_S, st);
 }
 
 hipError_t launch_corr(const CorrLaunch& cfg, const CorrTile* tiles, int n_tiles,
                        const GroupDesc* groups, const void* Z, const void* G, const float* tk,
-                       float* out, int max_h, int max_S, hipStream_t st) {
+                       float* out, int* rkeys, int64_t n_slots, int max_h, int max_S,
+                       hipStream_t st) {
     if (n_tiles <= 0) return hipSuccess;
     if (max_h > CORR_MAX_H) return hipErrorInvalidValue;
     if (cfg.ty != 4 || cfg.bb != 2 || cfg.wy != 4) return hipErrorInvalidValue;
     const int cb = cfg.pk.RP * cfg.pk.esz;
     const int Q = cfg.pk.Q;
 #define DPMT_CORR(K, P) \
-    case P: return launch_corr_t<K, P, 4, 2, 4>(tiles, n_tiles, groups, Z, G, tk, out, cb, Q, max_h, max_S, st);
+    case P: return launch_corr_t<K, P, 4, 2, 4>(tiles, n_tiles, groups, Z, G, tk, out, rkeys, n_slots, cb, Q, max_h, max_S, st);
     if (cfg.kind == CORR_F32) {
         switch (cfg.pk.PB) { DPMT_CORR(CORR_F32, 16) DPMT_CORR(CORR_F32, 32) default: break; }
     } else if (cfg.kind == CORR_BF16) {
@@ -609,16 +659,7 @@ hipError_t launch_project_fp8(const float* X, int64_t n_cells, const float* U, i
 // Scanning that range in ascending order with a strict > gives the exact
 // maximum and its smallest maximiser, i.e. the lexicographic tie rule.
 //
-// Layouts are chosen so that every pass reads and writes whole cache lines:
-//   part responses  [y'][x'][filter]     (correlation output)
-//   row pass        [pair][y'][x0]       (lanes = target columns of one pair)
-//   column pass     caller layout [map][part][y0][x0] (lanes = root columns)
-// and each pass stages the lines it scans in LDS, laid out so that lanes
-// reading different positions hit different banks.
 // ---------------------------------------------------------------------------
-constexpr int DT_STAGE_MAX = 96 * 1024;          // LDS bytes of one staged tile
-constexpr int DT_ROW_PAIRS = 32;                 // pairs per row-pass block
-
 // Per-line constants of one pair's cost c(u) = b*u + a*u^2 and the line maximum.
 struct LineConst {
     float a, b, inv2a, bb4a;   // inv2a = 1/(2a); bb4a unused slot kept for alignment
@@ -691,352 +732,356 @@ __device__ __forceinline__ void line_window(float a, float b, float range, int n
     uhi = (int)fminf(ceilf((-b + s) * inv) + 1.f, (float)n);
 }
 
-// Exact maximum of v[x] - (b*u + a*u^2), u = x - t, over x in [lo, hi] and its
-// smallest maximiser; the cost is advanced by finite differences.
-template <class Load>
-__device__ __forceinline__ float scan_fd(const Load& load, int lo, int hi, int t, float a, float b,
-                                         int& arg) {
-    float best = -INFINITY;
-    arg = lo;
-    const float u0 = (float)(lo - t);
-    float c = u0 * fmaf(a, u0, b);                 // cost at lo
-    float dc = fmaf(a, fmaf(2.f, u0, 1.f), b);     // cost(u0 + 1) - cost(u0)
-    const float a2 = 2.f * a;
-    int x = lo;
-    for (; x + 3 <= hi; x += 4) {
-        const float v0 = load(x), v1 = load(x + 1), v2 = load(x + 2), v3 = load(x + 3);
-        const float e0 = v0 - c;
-        c += dc; dc += a2;
-        const float e1 = v1 - c;
-        c += dc; dc += a2;
-        const float e2 = v2 - c;
-        c += dc; dc += a2;
-        const float e3 = v3 - c;
-        c += dc; dc += a2;
-        if (e0 > best) { best = e0; arg = x; }
-        if (e1 > best) { best = e1; arg = x + 1; }
-        if (e2 > best) { best = e2; arg = x + 2; }
-        if (e3 > best) { best = e3; arg = x + 3; }
-    }
-    for (; x <= hi; ++x) {
-        const float e = load(x) - c;
-        c += dc; dc += a2;
-        if (e > best) { best = e; arg = x; }
-    }
-    return best;
+// ---------------------------------------------------------------------------
+// Placement: the distance transform evaluated at the part anchors of every
+// root position, and the score assembly, in one kernel.
+//
+// Block = (score map, PLACE_CW consecutive root columns x0).  For each part i
+// of the map's component (anchor v, cost d) the block
+//   1. row pass: for every part-map row y' it needs and every column of the
+//      strip, R1[y'][x0] = max over x' of resp_i[y'][x'] - c_x(x' - t_x) with
+//      t_x = 2 x0 + v_x, and the smallest maximiser; R1 stays in LDS;
+//   2. column pass: for every root row y0, D = max over y' of R1[y'][x0] -
+//      c_y(y' - t_y) with t_y = 2 y0 + v_y, the smallest maximiser, and the
+//      (dy, dx) placement offset, written straight to the caller's layout;
+//   3. adds D to the block's score accumulator.
+// Finally score = root response + accumulator.
+//
+// Both passes use the window fact above with the value range of the part's
+// whole response plane (the correlation records it per plane): with D_r the
+// range, only |u| inside the roots of a u^2 + b u = D_r can beat the target
+// itself.  Row-pass values exceed the plane maximum by at most b_x^2 / 4a_x,
+// which widens the column window's range accordingly.  The window is thus
+// uniform over the strip, so in every pass the wavefront walks the window
+// offsets u in lockstep: the cost c(u) is one LDS broadcast shared by all
+// lanes, and a lane's candidate is one conflict-free LDS read.  The staged
+// response rows are split by parity of x' so that lanes whose targets are two
+// apart read consecutive words.  Out-of-map candidates read -inf.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float quad_cost(float a, float b, int u) {
+    const float fu = (float)u;
+    return fu * fmaf(a, fu, b);
 }
 
-// Row pass: block = (item, part row y', 32 pairs).  The block stages the row
-// of its 32 pairs as [pair][x'] (odd pitch) with each pair's fixed window,
-// then thread (column x0 = tid % Wt, pair slot tid / Wt) walks the block's
-// pairs.  Writes the row maximum of resp[y'][x'] - (d_x (x'-x_t) +
-// d_xx (x'-x_t)^2), x_t = 2*x0 + v_x, and its argmax x' at [pair][y'][x0].
-struct RowPair {
-    float a, b;
-    int ulo, uhi;
-    int vx, wo;
+size_t place_lds_bytes(const PlaceLds& l) {
+    return (size_t)4 * ((size_t)l.acc_rows * PLACE_CW + (size_t)l.r1_rows * PLACE_CW +
+                        (size_t)l.stage_words + 2 * (size_t)l.ctab_words) +
+           (size_t)2 * l.r1_rows * PLACE_CW;
+}
+
+constexpr int PLACE_LOADS = PLACE_STAGE / 1024;        // staged float4 per thread and round
+constexpr int PLACE_RB = 32;                           // most response rows per round
+
+// Geometry of one part inside a placement block; every thread computes the
+// same values.
+struct PlaceGeo {
+    int64_t plane;
+    int ld, Hp, Wp, vy;
+    float ax, bx, ay, by;
+    int tx0;            // target column of lane 0
+    int ulo, Wr, Wq;    // row window (clamped to the strip, start aligned), length, rounded to 4
+    int vlo, vhi, Wc;   // column window (clamped to the map +- 1 row) and its length
+    int CH, SH, RB;     // staged float4 per row, floats per parity half-row, rows per round
+    int ry0, ry1, rounds;
+    int X0;             // first staged column (multiple of 4)
+    int nq;             // float4 loads per thread and round
+    int lrow, lcol;     // this thread's first staged (row, float4) of a round
+    int drow, dcol;     // step of the flat index by 256 threads
+    int live;
 };
 
-template <bool STAGED>
-__global__ __launch_bounds__(256) void dt_row_kernel(const DTItem* __restrict__ items,
-                                                     const int2* __restrict__ blkmap,
-                                                     const PairDesc* __restrict__ pairs,
-                                                     const float* __restrict__ resp,
-                                                     float* __restrict__ r1v,
-                                                     int32_t* __restrict__ r1a) {
-    extern __shared__ float sline[];               // [DT_ROW_PAIRS][pitch] when STAGED
-    __shared__ float smax[8][DT_ROW_PAIRS], smin[8][DT_ROW_PAIRS];
-    __shared__ RowPair sp[DT_ROW_PAIRS];
-    const int2 bm = blkmap[blockIdx.x];            // (item, block within the item)
-    const DTItem I = items[bm.x];
-    const int local = bm.y;
-    const int pc = (I.np + DT_ROW_PAIRS - 1) / DT_ROW_PAIRS;
-    const int p0 = (local % pc) * DT_ROW_PAIRS;
-    const int yp = local / pc;                     // block-uniform
-    if (yp >= I.Hp) return;
-    const int npb = min(DT_ROW_PAIRS, I.np - p0);  // pairs of this block
-    const int Wp = I.Wp, pitch = Wp | 1;
-    const int64_t rs = I.ng;
-    const float* rowbase = resp + I.resp_off + (int64_t)yp * Wp * rs;
-    {   // stage: thread (pair q, x phase) -> coalesced 128-byte reads, 8 in flight
-        constexpr int XS = 256 / DT_ROW_PAIRS;
-        const int q = threadIdx.x & (DT_ROW_PAIRS - 1), ph = threadIdx.x / DT_ROW_PAIRS;
-        const bool act = q < npb;
-        const int fcol = act ? pairs[I.pair_base + p0 + q].fcol : 0;
-        float M = -FLT_MAX, m = FLT_MAX;
-        for (int xb = ph; xb < Wp; xb += 8 * XS) {
-            float v[8];
+__device__ __forceinline__ PlaceGeo place_geo(const MapPart& P, const MapDesc& M, int xs,
+                                              const int* __restrict__ rmax,
+                                              const int* __restrict__ rmin, int stage_words) {
+    constexpr int CW = PLACE_CW;
+    PlaceGeo G;
+    G.plane = P.plane;
+    G.ld = P.ld;
+    G.Hp = P.Hp;
+    G.Wp = P.Wp;
+    G.vy = P.vy;
+    G.ax = P.d[1];
+    G.bx = P.d[0];
+    G.ay = P.d[3];
+    G.by = P.d[2];
+    const float hi = range_value(rmax[P.rng]), lo = range_value(rmin[P.rng]);
+    const float range = hi >= lo ? hi - lo : 0.f;
+    G.tx0 = 2 * xs + P.vx;
+    int ulo, uhi;
+    line_window(G.ax, G.bx, range, P.Wp, ulo, uhi);
+    ulo = max(ulo, -(G.tx0 + 2 * (CW - 1)));              // beyond: left of every map column
+    uhi = min(uhi, P.Wp - 1 - G.tx0);                     // beyond: right of every map column
+    ulo -= (G.tx0 + ulo) & 3;                             // staged rows start 16-byte aligned
+    G.ulo = ulo;
+    G.Wr = uhi - ulo + 1;
+    G.Wq = (G.Wr + 3) & ~3;
+    line_window(G.ay, G.by, range + G.bx * G.bx / (4.f * G.ax), P.Hp, G.vlo, G.vhi);
+    G.vlo = max(G.vlo, -(P.Hp + 1));
+    G.vhi = min(G.vhi, P.Hp + 1);
+    G.Wc = G.vhi - G.vlo + 1;
+    G.live = P.Hp > 0 && P.Wp > 0 && G.Wr > 0;
+    G.CH = (2 * (CW - 1) + G.Wq + 3) >> 2;
+    G.SH = 2 * G.CH;
+    int RB = PLACE_RB;
+    while (RB > 1 && RB * 2 * G.SH > stage_words) RB >>= 1;
+    G.RB = RB;
+    G.ry0 = max(0, P.vy + G.vlo);
+    G.ry1 = min(P.Hp - 1, 2 * (M.Ho - 1) + P.vy + G.vhi);
+    G.rounds = (G.live && G.ry1 >= G.ry0) ? (G.ry1 - G.ry0 + RB) / RB : 0;
+    G.X0 = G.tx0 + ulo;
+    G.nq = (RB * G.CH + 255) / 256;
+    G.lrow = threadIdx.x / G.CH;
+    G.lcol = threadIdx.x - G.lrow * G.CH;
+    G.drow = 256 / G.CH;
+    G.dcol = 256 - G.drow * G.CH;
+    return G;
+}
+
+// Loads of one round of staged response rows into registers: flat index
+// i = tid + 256 q over [rows of the round][CH float4 runs].  Every load is
+// issued at a clamped, aligned address with nothing depending on it until the
+// store, so that all of them are in flight together; out-of-map columns are
+// masked at the store (a clamped run lies wholly outside the map).
+__device__ __forceinline__ void place_load(const PlaceGeo& G, const float* __restrict__ resp,
+                                           int round, float4 (&pf)[PLACE_LOADS]) {
+    const int y0 = G.ry0 + round * G.RB;
+    const int last = min(G.RB, G.ry1 - y0 + 1) - 1;       // last row of the round
+    const float* base = resp + G.plane + (int64_t)y0 * G.ld;
+    int row = G.lrow, col = G.lcol;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = rowbase[min(xb + u * XS, Wp - 1) * rs + fcol];
+    for (int q = 0; q < PLACE_LOADS; ++q) {
+        const int x = G.X0 + 4 * col;
+        const int xc = min(max(x, 0), G.ld - 4);
+        pf[q] = *reinterpret_cast<const float4*>(base + min(row, last) * G.ld + xc);
+        col += G.dcol;
+        row += G.drow;
+        if (col >= G.CH) {
+            col -= G.CH;
+            ++row;
+        }
+    }
+}
+
+// Store of a loaded round into the staging buffer, [row][parity][SH]: the
+// run x, x+1, x+2, x+3 (x even) goes to even[x/2 .. x/2+1], odd[x/2 .. x/2+1].
+__device__ __forceinline__ void place_store(const PlaceGeo& G, float* stage,
+                                            const float4 (&pf)[PLACE_LOADS]) {
+    int row = G.lrow, col = G.lcol;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int x = xb + u * XS;
-                if (x < Wp) {
-                    const float vv = act ? v[u] : 0.f;
-                    if (STAGED) sline[q * pitch + x] = vv;
-                    M = fmaxf(M, vv);
-                    m = fminf(m, vv);
+    for (int q = 0; q < PLACE_LOADS; ++q) {
+        if (q < G.nq && row < G.RB) {
+            const int x = G.X0 + 4 * col;
+            const float4 v = pf[q];
+            const float v0 = (unsigned)x < (unsigned)G.Wp ? v.x : -INFINITY;
+            const float v1 = (unsigned)(x + 1) < (unsigned)G.Wp ? v.y : -INFINITY;
+            const float v2 = (unsigned)(x + 2) < (unsigned)G.Wp ? v.z : -INFINITY;
+            const float v3 = (unsigned)(x + 3) < (unsigned)G.Wp ? v.w : -INFINITY;
+            float* even = stage + row * 2 * G.SH + 2 * col;
+            *reinterpret_cast<float2*>(even) = make_float2(v0, v2);
+            *reinterpret_cast<float2*>(even + G.SH) = make_float2(v1, v3);
+        }
+        col += G.dcol;
+        row += G.drow;
+        if (col >= G.CH) {
+            col -= G.CH;
+            ++row;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ maps,
+                                                    const MapPart* __restrict__ parts,
+                                                    const int2* __restrict__ blkmap,
+                                                    const float* __restrict__ resp,
+                                                    const int* __restrict__ rmax,
+                                                    const int* __restrict__ rmin,
+                                                    float* __restrict__ scores,
+                                                    int16_t* __restrict__ offs, PlaceLds L) {
+    constexpr int CW = PLACE_CW, PAD = PLACE_PAD;
+    extern __shared__ __align__(16) float psm[];
+    float* acc = psm;                                      // [acc_rows][CW]
+    float* r1v = acc + L.acc_rows * CW;                    // [r1_rows][CW], row y' at y' + PAD
+    float* stage = r1v + L.r1_rows * CW;                   // [stage_words]
+    float* crow = stage + L.stage_words;                   // row-pass cost table
+    float* ccol = crow + L.ctab_words;                     // column-pass cost table
+    int16_t* r1a = reinterpret_cast<int16_t*>(ccol + L.ctab_words);   // [r1_rows][CW]
+
+    const int2 bm = blkmap[blockIdx.x];                    // (map, strip)
+    const MapDesc M = maps[bm.x];
+    const int xs = bm.y * CW;
+    const int ncol = min(CW, M.Wo - xs);
+    const int tid = threadIdx.x;
+    const int w = tid >> 6, j = tid & 31, hr = (tid >> 5) & 1, rr = tid >> 5;
+
+    float4 pf[PLACE_LOADS];
+    PlaceGeo G = place_geo(parts[M.part_base], M, xs, rmax, rmin, L.stage_words);
+    if (G.rounds > 0) place_load(G, resp, 0, pf);
+
+    for (int s = 0; s < M.n_parts; ++s) {
+        // pf holds round 0 of part s (when it has rows)
+        if (G.live) {
+            for (int e = tid; e < G.Wq; e += 256) crow[e] = e < G.Wr ? quad_cost(G.ax, G.bx, G.ulo + e) : INFINITY;
+            for (int e = tid; e < G.Wc + 4; e += 256) ccol[e] = e < G.Wc ? quad_cost(G.ay, G.by, G.vlo + e) : INFINITY;
+            for (int i = tid; i < 2 * PAD * CW; i += 256) {
+                const int r = i / CW;
+                r1v[(r < PAD ? r : G.Hp + r) * CW + (i - r * CW)] = -INFINITY;
+            }
+            if (G.rounds > 0) place_store(G, stage, pf);
+        }
+        __syncthreads();                                   // tables, pads, round 0 staged
+        const bool has_next = s + 1 < M.n_parts;
+        PlaceGeo Gn = G;
+        if (has_next) Gn = place_geo(parts[M.part_base + s + 1], M, xs, rmax, rmin, L.stage_words);
+        if (G.live) {
+            // row pass
+            for (int r = 0; r < G.rounds; ++r) {
+                const bool more = r + 1 < G.rounds;
+                if (more) place_load(G, resp, r + 1, pf);
+                else if (has_next && Gn.rounds > 0) place_load(Gn, resp, 0, pf);
+                const int yr = G.ry0 + r * G.RB;
+                for (int q = rr; q < G.RB; q += 8) {
+                    const int y = yr + q;
+                    if (y > G.ry1) break;
+                    const float* SE = stage + q * 2 * G.SH + j;
+                    const float* SO = SE + G.SH;
+                    float best = -INFINITY;
+                    int arg = 0;
+                    for (int e = 0; e < G.Wq; e += 4) {
+                        const int k = e >> 1;
+                        const float4 c = *reinterpret_cast<const float4*>(crow + e);
+                        const float v0 = SE[k] - c.x, v1 = SO[k] - c.y;
+                        const float v2 = SE[k + 1] - c.z, v3 = SO[k + 1] - c.w;
+                        if (v0 > best) { best = v0; arg = e; }
+                        if (v1 > best) { best = v1; arg = e + 1; }
+                        if (v2 > best) { best = v2; arg = e + 2; }
+                        if (v3 > best) { best = v3; arg = e + 3; }
+                    }
+                    const bool ok = G.tx0 + 2 * j < G.Wp;
+                    r1v[(y + PAD) * CW + j] = ok ? best : -INFINITY;
+                    r1a[(y + PAD) * CW + j] = (int16_t)(G.X0 + 2 * j + arg);
+                }
+                __syncthreads();                           // stage consumed, R1 rows visible
+                if (more) {
+                    place_store(G, stage, pf);
+                    __syncthreads();
+                }
+            }
+            if (G.rounds == 0 && has_next && Gn.rounds > 0) place_load(Gn, resp, 0, pf);
+            // column pass: wave w takes root rows 8k + 2w and 8k + 2w + 1
+            for (int y0a = 2 * w; y0a < M.Ho; y0a += 8) {
+                const int tya = 2 * y0a + G.vy;
+                const int ulw = max(G.vlo, -2 - tya), uhw = min(G.vhi, G.Hp - 1 - tya);
+                float best = -INFINITY;
+                int arg = 0;
+                if (ulw <= uhw) {
+                    const int e0 = (ulw - G.vlo) & ~3, e1 = uhw - G.vlo;
+                    const float* col = r1v + (tya + 2 * hr + G.vlo + PAD) * CW + j;
+                    for (int e = e0; e <= e1; e += 4) {
+                        const float4 c = *reinterpret_cast<const float4*>(ccol + e);
+                        const float* q = col + e * CW;
+                        const float v0 = q[0] - c.x, v1 = q[CW] - c.y;
+                        const float v2 = q[2 * CW] - c.z, v3 = q[3 * CW] - c.w;
+                        if (v0 > best) { best = v0; arg = e; }
+                        if (v1 > best) { best = v1; arg = e + 1; }
+                        if (v2 > best) { best = v2; arg = e + 2; }
+                        if (v3 > best) { best = v3; arg = e + 3; }
+                    }
+                }
+                const int y0 = y0a + hr;
+                if (y0 < M.Ho && j < ncol) {
+                    const int ty = tya + 2 * hr, tx = G.tx0 + 2 * j;
+                    float D = -INFINITY;
+                    uint32_t packed = 0;
+                    if (ty < G.Hp && tx < G.Wp) {
+                        const int yb = ty + G.vlo + arg;
+                        const int dx = r1a[(yb + PAD) * CW + j] - tx, dy = yb - ty;
+                        D = best;
+                        packed = (uint32_t)(uint16_t)(int16_t)dy | ((uint32_t)(uint16_t)(int16_t)dx << 16);
+                    }
+                    float* a = acc + y0 * CW + j;
+                    *a = s == 0 ? D : *a + D;
+                    if (offs)
+                        reinterpret_cast<uint32_t*>(offs + M.offs_off)[((int64_t)s * M.Ho + y0) * M.Wo + xs + j] = packed;
+                }
+            }
+        } else {
+            // no target of this strip lies inside the part map
+            if (has_next && Gn.rounds > 0) place_load(Gn, resp, 0, pf);
+            for (int y0a = 2 * w; y0a < M.Ho; y0a += 8) {
+                const int y0 = y0a + hr;
+                if (y0 < M.Ho && j < ncol) {
+                    acc[y0 * CW + j] = -INFINITY;
+                    if (offs)
+                        reinterpret_cast<uint32_t*>(offs + M.offs_off)[((int64_t)s * M.Ho + y0) * M.Wo + xs + j] = 0u;
                 }
             }
         }
-        smax[ph][q] = M;
-        smin[ph][q] = m;
+        __syncthreads();                                   // R1, tables and stage reused by the next part
+        G = Gn;
     }
-    __syncthreads();
-    if (threadIdx.x < npb) {
-        const int q = threadIdx.x;
-        const PairDesc P = pairs[I.pair_base + p0 + q];
-        float M = smax[0][q], m = smin[0][q];
-#pragma unroll
-        for (int i = 1; i < 8; ++i) {
-            M = fmaxf(M, smax[i][q]);
-            m = fminf(m, smin[i][q]);
-        }
-        RowPair r;
-        r.a = P.d[1];
-        r.b = P.d[0];
-        line_window(r.a, r.b, M - m, Wp, r.ulo, r.uhi);
-        r.vx = P.vx;
-        r.wo = min(I.Wr - P.w0 + 1, I.Wt);
-        sp[q] = r;
-    }
-    __syncthreads();
-    const int Wt = I.Wt;
-    const int cols = min(Wt, 256);
-    const int qstep = 256 / cols;
-    const int x0s = threadIdx.x % cols, qs = threadIdx.x / cols;
-    if (qs >= qstep) return;
-    const int64_t obase = I.r1_off + ((int64_t)p0 * I.Hp + yp) * Wt;
-    const int64_t opair = (int64_t)I.Hp * Wt;
-    for (int q = qs; q < npb; q += qstep) {
-        const RowPair r = sp[q];
-        const float* srow = sline + q * pitch;
-        const float* grow = rowbase + (STAGED ? 0 : pairs[I.pair_base + p0 + q].fcol);
-        for (int x0 = x0s; x0 < r.wo; x0 += cols) {
-            const int t = 2 * x0 + r.vx;
-            float best = -INFINITY;
-            int arg = -1;
-            if (t >= 0 && t < Wp) {
-                const int lo = max(t + r.ulo, 0), hi = min(t + r.uhi, Wp - 1);
-                if (STAGED) best = scan_fd([&](int x) { return srow[x]; }, lo, hi, t, r.a, r.b, arg);
-                else best = scan_fd([&](int x) { return grow[x * rs]; }, lo, hi, t, r.a, r.b, arg);
-            }
-            r1v[obase + q * opair + x0] = best;
-            r1a[obase + q * opair + x0] = arg;
-        }
+    for (int y0a = 2 * w; y0a < M.Ho; y0a += 8) {
+        const int y0 = y0a + hr;
+        if (y0 < M.Ho && j < ncol)
+            scores[M.score_off + (int64_t)y0 * M.Wo + xs + j] =
+                resp[M.root_plane + (int64_t)y0 * M.ldr + xs + j] + acc[y0 * CW + j];
     }
 }
 
-// Column pass: block = (item, pair, chunk of cw root columns).  The block
-// stages the pair's row-pass output for its columns as [y'][cw] with each
-// column's range, then thread (column j, segment s) takes the target rows
-// y_t = 2*y0 + v_y of one segment of y0, chaining the argmax from one target
-// to the next.  A wavefront whose lanes share their targets scans the union
-// of their windows, so every LDS read is one row of the tile and the loop is
-// uniform.  Maximises the row-pass value minus (d_y (y'-y_t) + d_yy (y'-y_t)^2)
-// over y' and writes the deformed part score and the (dy, dx) placement
-// offset of (map, part, y0, x0) straight into the caller's layout.
-__device__ __forceinline__ int wave_min_i(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-    return v;
-}
-__device__ __forceinline__ int wave_max_i(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
-template <bool STAGED>
-__global__ __launch_bounds__(256) void dt_col_kernel(const DTItem* __restrict__ items,
-                                                     const int2* __restrict__ blkmap,
-                                                     const PairDesc* __restrict__ pairs,
-                                                     const MapDesc* __restrict__ maps,
-                                                     const float* __restrict__ r1v,
-                                                     const int32_t* __restrict__ r1a,
-                                                     float* __restrict__ dbuf,
-                                                     int16_t* __restrict__ offs) {
-    extern __shared__ float sline[];               // [Hp][cw] when STAGED
-    __shared__ float smax[256], smin[256];
-    const int2 bm = blkmap[blockIdx.x];            // (item, block within the item)
-    const DTItem I = items[bm.x];
-    const int local = bm.y;
-    const int cw = I.cw;                           // columns per block
-    const int xc = (I.Wt + cw - 1) / cw;
-    const int pidx = local / xc;                   // block-uniform
-    const int xb = (local - pidx * xc) * cw;       // first column of the block
-    const PairDesc P = pairs[I.pair_base + pidx];
-    const MapDesc Md = maps[I.map_base + P.comp];
-    const int Ho_c = Md.Ho, Wo_c = Md.Wo;
-    if (Ho_c <= 0 || xb >= Wo_c) return;           // block-uniform
-    const int nseg = 256 / cw;                     // >= 1
-    const int j = threadIdx.x % cw, sg = threadIdx.x / cw;
-    const int x0 = xb + j;
-    const int xt = 2 * x0 + P.vx;
-    const bool colok = x0 < Wo_c && xt >= 0 && xt < I.Wp;
-    const int Hp = I.Hp;
-    const int64_t lbase = I.r1_off + (int64_t)pidx * Hp * I.Wt;   // this pair's [y'][Wt] plane
-    float M = -FLT_MAX, m = FLT_MAX;
-    if (sg < nseg) {                               // 8 loads in flight per thread
-        const int64_t cbase = lbase + (colok ? x0 : 0);
-        for (int yb = sg; yb < Hp; yb += 8 * nseg) {
-            float v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = r1v[cbase + (int64_t)min(yb + u * nseg, Hp - 1) * I.Wt];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int y = yb + u * nseg;
-                if (y < Hp) {
-                    const float vv = colok ? v[u] : 0.f;
-                    if (STAGED) sline[y * cw + j] = vv;
-                    M = fmaxf(M, vv);
-                    m = fminf(m, vv);
-                }
-            }
-        }
-    }
-    smax[threadIdx.x] = M;
-    smin[threadIdx.x] = m;
-    __syncthreads();
-    const bool act = sg < nseg && x0 < Wo_c;
-    if (act)
-        for (int i = 0; i < nseg; ++i) {
-            M = fmaxf(M, smax[i * cw + j]);
-            m = fminf(m, smin[i * cw + j]);
-        }
-    const float a = P.d[3], b = P.d[2];
-    int ulo = 0, uhi = 0;
-    if (act) line_window(a, b, M - m, Hp, ulo, uhi);
-    const int chunk = (Ho_c + nseg - 1) / nseg;
-    const int k0 = sg * chunk, k1 = act ? min(k0 + chunk, Ho_c) : k0;
-    const int64_t plane = (int64_t)Ho_c * Wo_c;
-    float* dout = dbuf + (Md.offs_off >> 1) + P.slot * plane + x0;
-    int32_t* oout = offs ? reinterpret_cast<int32_t*>(offs + Md.offs_off) + P.slot * plane + x0 : nullptr;
-    const int wfirst = threadIdx.x & ~63;
-    const bool one_seg = wfirst / cw == (wfirst + 63) / cw;
-    const int kmax = wave_max_i(k1 - k0);
-    int prev = 0;
-    for (int kk = 0; kk < kmax; ++kk) {
-        const int k = k0 + kk;
-        const bool live = k < k1;
-        const int t = 2 * k + P.vy;
-        const bool ok = live && colok && t >= 0 && t < Hp;
-        int lo = INT_MAX, hi = INT_MIN;
-        if (ok) {
-            hi = min(t + uhi, Hp - 1);
-            lo = min(max(max(t + ulo, 0), prev), hi);
-        }
-        const int LO = wave_min_i(lo), HI = wave_max_i(hi);
-        float best = -INFINITY;
-        int ay = -1;
-        if (ok) {
-            const int from = (STAGED && one_seg) ? LO : lo;
-            const int to = (STAGED && one_seg) ? HI : hi;
-            if (STAGED)
-                best = scan_fd([&](int y) { return sline[y * cw + j]; }, from, to, t, a, b, ay);
-            else
-                best = scan_fd([&](int y) { return r1v[lbase + (int64_t)y * I.Wt + x0]; }, from, to, t, a, b, ay);
-            prev = ay;
-        }
-        if (live) {
-            int32_t packed = 0;
-            if (ok) {
-                const int dx = r1a[lbase + (int64_t)ay * I.Wt + x0] - xt;
-                const int dy = ay - t;
-                packed = (int32_t)(((uint32_t)(uint16_t)(int16_t)dx << 16) | (uint16_t)(int16_t)dy);
-            }
-            dout[k * Wo_c] = best;
-            if (oout) oout[k * Wo_c] = packed;
-        }
-    }
-}
-
-// Assembly: thread = (map, root position); adds the parts' deformed scores to
-// the root response (Section 2 score formula).
-__global__ __launch_bounds__(ASM_BLOCK) void assemble_kernel(const MapDesc* __restrict__ maps,
-                                                             const int2* __restrict__ blkmap,
-                                                             const float* __restrict__ rresp,
-                                                             const float* __restrict__ dbuf,
-                                                             float* __restrict__ scores) {
-    const int2 bm = blkmap[blockIdx.x];            // (map, block within the map)
-    const MapDesc Md = maps[bm.x];
-    const int pos = bm.y * ASM_BLOCK + threadIdx.x;
-    const int plane = Md.Ho * Md.Wo;
-    if (pos >= plane) return;
-    float s = rresp[Md.rresp_off + (int64_t)pos * Md.rng + Md.rcol];
-    const float* d = dbuf + (Md.offs_off >> 1) + pos;
-    for (int i = 0; i < Md.n_parts; ++i) s += d[(int64_t)i * plane];
-    scores[Md.score_off + pos] = s;
-}
-
-template <class K>
-static hipError_t set_lds(K kern, size_t lds) {
-    if (lds <= 65536) return hipSuccess;
-    return hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-}
-
-hipError_t launch_dt_row(const DTItem* items, const int2* blkmap, int n_blocks,
-                         const PairDesc* pairs, const float* resp, float* r1v, int32_t* r1a,
-                         int max_line, hipStream_t st) {
-    if (n_blocks <= 0) return hipSuccess;
-    const size_t lds = (size_t)(max_line | 1) * DT_ROW_PAIRS * sizeof(float);
-    if (lds <= DT_STAGE_MAX) {
-        hipError_t e = set_lds(dt_row_kernel<true>, lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(dt_row_kernel<true>, dim3(n_blocks), dim3(256), lds, st, items, blkmap,
-                           pairs, resp, r1v, r1a);
-    } else {
-        hipLaunchKernelGGL(dt_row_kernel<false>, dim3(n_blocks), dim3(256), 0, st, items, blkmap,
-                           pairs, resp, r1v, r1a);
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_dt_col(const DTItem* items, const int2* blkmap, int n_blocks,
-                         const PairDesc* pairs, const MapDesc* maps, const float* r1v,
-                         const int32_t* r1a, float* dbuf, int16_t* offs, int max_line,
-                         hipStream_t st) {
-    if (n_blocks <= 0) return hipSuccess;
-    const size_t lds = (size_t)max_line * sizeof(float);    // largest Hp * cw
-    if (lds <= DT_STAGE_MAX) {
-        hipError_t e = set_lds(dt_col_kernel<true>, lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(dt_col_kernel<true>, dim3(n_blocks), dim3(256), lds, st, items, blkmap,
-                           pairs, maps, r1v, r1a, dbuf, offs);
-    } else {
-        hipLaunchKernelGGL(dt_col_kernel<false>, dim3(n_blocks), dim3(256), 0, st, items, blkmap,
-                           pairs, maps, r1v, r1a, dbuf, offs);
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_assemble(const MapDesc* maps, const int2* blkmap, int n_blocks,
-                           const float* rresp, const float* dbuf, float* scores, hipStream_t st) {
-    if (n_blocks <= 0) return hipSuccess;
-    hipLaunchKernelGGL(assemble_kernel, dim3(n_blocks), dim3(ASM_BLOCK), 0, st, maps, blkmap,
-                       rresp, dbuf, scores);
-    return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// [pos][ng] response block -> one row-major map per filter
-// ---------------------------------------------------------------------------
-__global__ void block_to_maps_kernel(const float* __restrict__ block, int64_t n_pos, int ng,
-                                     const int64_t* __restrict__ dst_off, float* __restrict__ out) {
+__global__ void range_init_kernel(int* __restrict__ rkeys, int64_t n_slots) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n_pos * ng) return;
-    const int64_t pos = i / ng;
-    const int f = (int)(i - pos * ng);
-    out[dst_off[f] + pos] = block[i];
+    if (i < n_slots) {
+        rkeys[i] = INT_MIN;             // maxima
+        rkeys[n_slots + i] = INT_MAX;   // minima
+    }
 }
 
-hipError_t launch_block_to_maps(const float* block, int64_t n_pos, int ng, const int64_t* dst_off,
-                                float* out, hipStream_t st) {
-    const int64_t n = n_pos * ng;
+hipError_t launch_range_init(int* rkeys, int64_t n_slots, hipStream_t st) {
+    if (n_slots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(range_init_kernel, dim3((unsigned)((n_slots + 255) / 256)), dim3(256), 0, st,
+                       rkeys, n_slots);
+    return hipGetLastError();
+}
+
+hipError_t launch_place(const MapDesc* maps, const MapPart* parts, const int2* blkmap,
+                        int n_blocks, const float* resp, const int* rkeys, int64_t n_slots,
+                        float* scores, int16_t* offs, const PlaceLds& lds, hipStream_t st) {
+    if (n_blocks <= 0) return hipSuccess;
+    if (lds.stage_words != PLACE_STAGE || lds.ctab_words % 4)
+        return hipErrorInvalidValue;
+    const size_t bytes = place_lds_bytes(lds);
+    if (bytes > 160 * 1024) return hipErrorInvalidValue;
+    if (bytes > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(place_kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(place_kernel, dim3(n_blocks), dim3(256), bytes, st, maps, parts, blkmap, resp,
+                       rkeys, rkeys + n_slots, scores, offs, lds);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// filter planes of one group (pitch ld) -> one row-major map per filter
+// ---------------------------------------------------------------------------
+__global__ void planes_to_maps_kernel(const float* __restrict__ planes, int ng, int Ho, int Wo,
+                                      int ld, const int64_t* __restrict__ dst_off,
+                                      float* __restrict__ out) {
+    const int64_t n = (int64_t)ng * Ho * Wo;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int64_t row = i / Wo;                    // f * Ho + y
+    const int x = (int)(i - row * Wo);
+    const int f = (int)(row / Ho);
+    const int y = (int)(row - (int64_t)f * Ho);
+    out[dst_off[f] + (int64_t)y * Wo + x] = planes[row * ld + x];
+}
+
+hipError_t launch_planes_to_maps(const float* planes, int ng, int Ho, int Wo, int ld,
+                                 const int64_t* dst_off, float* out, hipStream_t st) {
+    const int64_t n = (int64_t)ng * Ho * Wo;
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(block_to_maps_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
-                       block, n_pos, ng, dst_off, out);
+    hipLaunchKernelGGL(planes_to_maps_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st,
+                       planes, ng, Ho, Wo, ld, dst_off, out);
     return hipGetLastError();
 }
 
