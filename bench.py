@@ -71,6 +71,34 @@ def corr_work(wl, mode: str, rank: int):
     return flops, feat_bytes + filt_bytes + 4 * resp, resp
 
 
+def kernel_source_digest() -> str:
+    """SHA-256 of the kernel sources; byte counters recorded for another
+    digest describe other kernels and are not reported."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("dpmt_kernels.hip", "dpmt_internal.h"):
+        with open(os.path.join(ROOT, "paper_1707_03268_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def recorded_traffic(kernel: str, config: int, mode: str, rank) -> "int | None":
+    """HBM bytes per launch of `kernel` measured with rocprofv3 FETCH_SIZE and
+    WRITE_SIZE (scaled by a plain copy's counter reading), from the summary in
+    profiles/, if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    digest = kernel_source_digest()
+    want = [kernel, f"c{config}", mode, str(rank if mode != "direct_fp32" else 0), digest]
+    with open(path) as f:
+        for line in f:
+            t = line.split()
+            if len(t) == 8 and t[0] == "traffic" and t[1:6] == want:
+                return int(float(t[6]) + float(t[7]))
+    return None
+
+
 def place_bytes(lay) -> int:
     """Algorithmic HBM bytes of one placement launch: every part and root
     response read once (FP32), every score (FP32) and placement offset pair
@@ -183,6 +211,9 @@ def main() -> None:
     ap.add_argument("--rank", type=int, default=16)
     ap.add_argument("--no-direct", action="store_true", help="skip the direct FP32 comparison run")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work (0: skip)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 1 GiB device to device three times (a known-size copy kernel "
+                         "for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path has no "
@@ -196,6 +227,14 @@ def main() -> None:
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {src.numel() * 4} bytes")
+        del src, dst
     preset = workloads.PRESETS[args.config]
     wl = preset(args.images) if (args.config in (4, 5) and args.images) else preset()
     log(f"workload: {wl.name}")
@@ -241,13 +280,14 @@ def main() -> None:
     # the correlation is priced against the MFMA peak of its operand type (the
     # target the tensor form is judged on), the placement against HBM
     rf_corr = {"bound": "mfma", "achieved": corr["tflops"], "peak": peak_mfma, "unit": "TFLOP/s",
-               "frac": corr["frac_mfma"], "traffic": None, "kernel": "corr_kernel"}
+               "frac": corr["frac_mfma"], "kernel": "corr_kernel", "bytes": cbytes,
+               "traffic": recorded_traffic("corr_kernel", args.config, args.mode, args.rank)}
     pbytes = place_bytes(lay)
     place_ms = stages["placement"]
     pgbs = pbytes / (place_ms * 1e-3) / 1e9
     rf_place = {"bound": "hbm", "achieved": pgbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": pgbs / PEAK_HBM_GBS, "traffic": None, "kernel": "place_kernel",
-                "bytes": pbytes}
+                "frac": pgbs / PEAK_HBM_GBS, "kernel": "place_kernel", "bytes": pbytes,
+                "traffic": recorded_traffic("place_kernel", args.config, args.mode, args.rank)}
     roof = dict(rf_corr if corr_ms >= place_ms else rf_place)
 
     cpu = None
