@@ -106,27 +106,34 @@ def place_bytes(lay) -> int:
     return 4 * lay.n_resp_part + 4 * lay.n_resp_root + 4 * lay.n_score + 2 * lay.n_offsets
 
 
-def run_mode(ctx, wl, mode, rank, feats, steps, warmup, torch):
+def run_mode(ctx, mode, feats, steps, warmup, torch, launch="batched"):
+    """Warm up, then time exactly `steps` calls on torch's current stream with
+    an event between consecutive calls.  Returns (mean ms, per-stage ms, step
+    percentiles, scores, offsets)."""
     lay = ctx.layout
     scores = torch.empty(max(lay.n_score, 1), dtype=torch.float32, device="cuda")
     offs = torch.empty(max(lay.n_offsets, 1), dtype=torch.int16, device="cuda")
     stream = torch.cuda.current_stream()
+    ctx.set_launch(launch)
     for _ in range(warmup):
         ctx.score_pyramid(mode, feats, scores, offs, stream=stream)
     torch.cuda.synchronize()
     ctx.set_profiling(True)
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
-    t0.record(stream)
-    for _ in range(steps):
+    ev[0].record(stream)
+    for i in range(steps):
         ctx.score_pyramid(mode, feats, scores, offs, stream=stream)
-    t1.record(stream)
+        ev[i + 1].record(stream)
     torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1) / steps
+    ms = ev[0].elapsed_time(ev[steps]) / steps
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+    pct = {"p10": float(np.percentile(per, 10)), "p50": float(np.percentile(per, 50)),
+           "p90": float(np.percentile(per, 90))}
     stages, calls = ctx.stage_times()
     ctx.set_profiling(False)
-    return ms, stages, scores, offs
+    ctx.set_launch("batched")
+    return ms, stages, pct, scores, offs
 
 
 def cpu_baseline(wl, mode, U, budget_s, scores, offs, lay, torch):
@@ -211,6 +218,12 @@ def main() -> None:
     ap.add_argument("--rank", type=int, default=16)
     ap.add_argument("--no-direct", action="store_true", help="skip the direct FP32 comparison run")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work (0: skip)")
+    ap.add_argument("--launch", default="batched", choices=["batched", "per_level", "graph"],
+                    help="launch strategy of the timed steps")
+    ap.add_argument("--compare-launch", action="store_true",
+                    help="also time every launch strategy (batched, per level, graph)")
+    ap.add_argument("--autotune", action="store_true", help="pick the correlation tile configuration by timing")
+    ap.add_argument("--tile-config", type=int, default=None, help="correlation tile configuration index")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device to device three times (a known-size copy kernel "
                          "for scaling hardware byte counters)")
@@ -222,7 +235,7 @@ def main() -> None:
 
     import torch
     import workloads
-    from paper_1707_03268_amd import Context
+    from paper_1707_03268_amd import Context, tile_config_name
 
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
@@ -248,23 +261,44 @@ def main() -> None:
     log(f"plan: {lay.n_resp} responses/step, {lay.n_maps} score maps, workspace "
         f"{lay.workspace_bytes / 2**20:.0f} MiB")
 
-    ms, stages, scores, offs = run_mode(ctx, wl, args.mode, args.rank, feats, args.steps, args.warmup, torch)
+    tuning = None
+    if args.autotune:
+        s_t = torch.empty(max(lay.n_score, 1), dtype=torch.float32, device="cuda")
+        o_t = torch.empty(max(lay.n_offsets, 1), dtype=torch.int16, device="cuda")
+        best, tms = ctx.autotune(args.mode, feats, s_t, o_t, reps=3)
+        del s_t, o_t
+        tuning = {"chosen": best, "name": tile_config_name(best),
+                  "median_ms": {tile_config_name(i): m for i, m in enumerate(tms) if m is not None}}
+        log(f"autotune: {tuning}")
+    elif args.tile_config is not None:
+        ctx.set_tile_config(args.mode, args.tile_config)
+
+    # stage split from the batched strategy (a graph launch has none)
+    ms, stages, pct, scores, offs = run_mode(ctx, args.mode, feats, args.steps, args.warmup, torch)
+    if args.launch != "batched":
+        ms, _, pct, scores, offs = run_mode(ctx, args.mode, feats, args.steps, args.warmup, torch,
+                                            launch=args.launch)
     value = lay.n_resp / (ms * 1e-3)
-    log(f"{args.mode}: {ms:.3f} ms/step, {value:.4g} resp/s, stages {stages}")
+    log(f"{args.mode} ({args.launch}): {ms:.3f} ms/step, {value:.4g} resp/s, stages {stages}")
+
+    launches = None
+    if args.compare_launch:
+        launches = {}
+        for launch in ("batched", "per_level", "graph"):
+            lms, _, lpct, _, _ = run_mode(ctx, args.mode, feats, max(2, min(args.steps, 10)), 1,
+                                          torch, launch=launch)
+            launches[launch] = {"ms_per_step": lms, "resp_per_s": lay.n_resp / (lms * 1e-3), **lpct}
+            log(f"launch {launch}: {lms:.3f} ms/step")
 
     direct = None
     if not args.no_direct and args.mode != "direct_fp32":
-        ctx_d = Context(0)
-        ctx_d.load_filters(wl.bank.filters, wl.bank.components)
-        ctx_d.plan(wl.pyramids)
         dsteps = max(2, min(args.steps, 5))
-        dms, dstages, _, _ = run_mode(ctx_d, wl, "direct_fp32", None, feats, dsteps, 1, torch)
+        dms, dstages, _, _, _ = run_mode(ctx, "direct_fp32", feats, dsteps, 1, torch)
         dflops, dbytes, _ = corr_work(wl, "direct_fp32", 32)
         direct = {"value": lay.n_resp / (dms * 1e-3), "ms_per_step": dms,
                   "stages_ms": {k: round(v, 4) for k, v in dstages.items()},
                   "correlation_tflops": dflops / (dstages["correlation"] * 1e-3) / 1e12,
                   "correlation_frac_fp32_mfma": dflops / (dstages["correlation"] * 1e-3) / 1e12 / PEAK_FP32_TFLOPS}
-        ctx_d.close()
         log(f"direct_fp32: {dms:.3f} ms/step")
 
     # roofline of each kernel; the headline object is the dominant one
@@ -292,7 +326,7 @@ def main() -> None:
 
     cpu = None
     err = None
-    if args.cpu_budget > 0 and args.config in (1, 2, 3):
+    if args.cpu_budget > 0:
         log("cpu baseline (oracle) ...")
         cpu, err = cpu_baseline(wl, args.mode, U, args.cpu_budget, scores, offs, lay, torch)
 
@@ -307,6 +341,11 @@ def main() -> None:
         "roofline": roof,
         "cpu_baseline": cpu,
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
+        "step_ms_percentiles": pct,
+        "launch": args.launch,
+        "launch_strategies": launches,
+        "tile_config": tuning if tuning else {"chosen": ctx.get_tile_config(args.mode),
+                                              "name": tile_config_name(ctx.get_tile_config(args.mode))},
         "correlation": corr,
         "placement_roofline": rf_place,
         "direct_fp32": direct,

@@ -64,6 +64,19 @@ typedef enum {
                                  scales, FP32 accumulation                               */
 } dpmt_mode;
 
+/* How dpmt_score_pyramid issues its work (dpmt_set_launch).  Every strategy
+ * runs the same kernels on the same tiles and produces the same bits. */
+typedef enum {
+    DPMT_LAUNCH_BATCHED = 0,  /* one launch per stage over every level of every image
+                                 (value-range reset, projection, correlation, placement)  */
+    DPMT_LAUNCH_PER_LEVEL = 1,/* projection and correlation launched per (image, level),
+                                 placement per (image, root level): the reference for
+                                 what batching saves                                     */
+    DPMT_LAUNCH_GRAPH = 2     /* the batched launches captured once into a HIP graph and
+                                 replayed; re-captured when the mode, plan, tile
+                                 configuration or a device pointer changes               */
+} dpmt_launch;
+
 typedef struct { int32_t h, w; } dpmt_shape;          /* filter rows, cols; 32 channels */
 
 /* One mixture component (Section 2: a root filter f0, n > 0 part filters f_i
@@ -188,6 +201,35 @@ dpmt_status dpmt_distance_transform(const float* resp_dev, int32_t rows, int32_t
  * and stores the number of calls averaged in *n_calls (may be NULL). */
 dpmt_status dpmt_set_profiling(dpmt_ctx* ctx, int32_t on);
 int32_t     dpmt_stage_times(dpmt_ctx* ctx, float* ms_out, int32_t n, int32_t* n_calls);
+
+/* Launch strategy of later dpmt_score_pyramid calls (a dpmt_launch value;
+ * DPMT_E_INVALID otherwise).  In graph mode the per-stage times of
+ * dpmt_stage_times are NaN (one launch) and only the whole-call time is kept. */
+dpmt_status dpmt_set_launch(dpmt_ctx* ctx, int32_t launch);
+
+/* Correlation tile configurations (output rows x 32 columns x filters per
+ * workgroup, threads, one workgroup per tile or a resident grid striding the
+ * tile list).  All accumulate each response in the same order, so results are
+ * bitwise equal; only speed differs.  dpmt_tile_config_name returns a static
+ * description, NULL outside [0, count). */
+int32_t     dpmt_tile_config_count(void);
+const char* dpmt_tile_config_name(int32_t config);
+/* Select the configuration a mode uses (DPMT_E_UNSUPPORTED if the loaded
+ * filters are too tall for it); dpmt_get_tile_config returns it (-1 on a bad
+ * argument). */
+dpmt_status dpmt_set_tile_config(dpmt_ctx* ctx, dpmt_mode mode, int32_t config);
+int32_t     dpmt_get_tile_config(const dpmt_ctx* ctx, dpmt_mode mode);
+
+/* Autotuner: runs the planned batch once per supported tile configuration as
+ * a warm-up and then `reps` (1..1000) timed times with the batched strategy,
+ * on hip_stream, waiting for each run; keeps the configuration with the
+ * smallest median time for `mode`.  Same arguments and state rules as
+ * dpmt_score_pyramid (its outputs are overwritten).  ms_out (host, may be
+ * NULL) receives dpmt_tile_config_count() medians in milliseconds, -1 for
+ * unsupported configurations; *best_out (may be NULL) the chosen index. */
+dpmt_status dpmt_autotune(dpmt_ctx* ctx, dpmt_mode mode, const float* features_dev,
+                          float* scores_dev, int16_t* offsets_dev, int32_t reps, float* ms_out,
+                          int32_t* best_out, void* hip_stream);
 
 const char* dpmt_status_string(dpmt_status s);
 const char* dpmt_last_error(const dpmt_ctx* ctx);     /* detail of the last failure */

@@ -6,4 +6,5 @@ Importing the package does not load the library; the first call does, and it
 raises ImportError if libdpmt.so has not been built.
 """
 from ._abi import LIB_PATH, MODES, DIRECT_FP32, TENSOR_FP32, TENSOR_BF16, TENSOR_FP8  # noqa: F401
-from .api import Context, DpmtError, Layout, distance_transform  # noqa: F401
+from .api import (Context, DpmtError, Layout, distance_transform, tile_config_count,  # noqa: F401
+                  tile_config_name)

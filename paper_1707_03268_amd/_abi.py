@@ -23,6 +23,11 @@ TENSOR_FP8 = 3
 MODES = {"direct_fp32": DIRECT_FP32, "tensor_fp32": TENSOR_FP32,
          "tensor_bf16": TENSOR_BF16, "tensor_fp8": TENSOR_FP8}
 
+LAUNCH_BATCHED = 0
+LAUNCH_PER_LEVEL = 1
+LAUNCH_GRAPH = 2
+LAUNCHES = {"batched": LAUNCH_BATCHED, "per_level": LAUNCH_PER_LEVEL, "graph": LAUNCH_GRAPH}
+
 
 class Shape(ctypes.Structure):
     _fields_ = [("h", c_int32), ("w", c_int32)]
@@ -66,6 +71,13 @@ SIGNATURES = {
                                           c_void_p, c_void_p, c_void_p, c_void_p]),
     "dpmt_set_profiling": (c_int32, [c_void_p, c_int32]),
     "dpmt_stage_times": (c_int32, [c_void_p, POINTER(c_float), c_int32, POINTER(c_int32)]),
+    "dpmt_set_launch": (c_int32, [c_void_p, c_int32]),
+    "dpmt_tile_config_count": (c_int32, []),
+    "dpmt_tile_config_name": (c_char_p, [c_int32]),
+    "dpmt_set_tile_config": (c_int32, [c_void_p, c_int32, c_int32]),
+    "dpmt_get_tile_config": (c_int32, [c_void_p, c_int32]),
+    "dpmt_autotune": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_int32,
+                                POINTER(c_float), POINTER(c_int32), c_void_p]),
     "dpmt_status_string": (c_char_p, [c_int32]),
     "dpmt_last_error": (c_char_p, [c_void_p]),
 }

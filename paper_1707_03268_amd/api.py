@@ -215,6 +215,35 @@ class Context:
                self._h, "dpmt_level_responses")
         return out, n.value
 
+    # ------------------------------------------------------ launch strategy
+    def set_launch(self, launch) -> None:
+        """'batched' (default), 'per_level' or 'graph' (see dpmt_launch)."""
+        v = _abi.LAUNCHES[launch] if isinstance(launch, str) else int(launch)
+        _check(_lib().dpmt_set_launch(self._h, v), self._h, "dpmt_set_launch")
+
+    def set_tile_config(self, mode, config: int) -> None:
+        m = _abi.MODES[mode] if isinstance(mode, str) else int(mode)
+        _check(_lib().dpmt_set_tile_config(self._h, m, int(config)), self._h, "dpmt_set_tile_config")
+
+    def get_tile_config(self, mode) -> int:
+        m = _abi.MODES[mode] if isinstance(mode, str) else int(mode)
+        return int(_lib().dpmt_get_tile_config(self._h, m))
+
+    def autotune(self, mode, features, scores, offsets=None, reps: int = 5, stream=None):
+        """Time every tile configuration on the planned batch and keep the
+        fastest for ``mode``.  Returns (best index, [median ms or None])."""
+        import torch
+        m = _abi.MODES[mode] if isinstance(mode, str) else int(mode)
+        n = tile_config_count()
+        ms = (c_float * n)()
+        best = c_int32(-1)
+        _check(_lib().dpmt_autotune(
+            self._h, m, _dev_ptr(features, torch.float32, "features"),
+            _dev_ptr(scores, torch.float32, "scores"),
+            _dev_ptr(offsets, torch.int16, "offsets") if offsets is not None else None,
+            int(reps), ms, byref(best), _stream_ptr(stream)), self._h, "dpmt_autotune")
+        return best.value, [ms[i] if ms[i] >= 0 else None for i in range(n)]
+
     def set_profiling(self, on: bool) -> None:
         _check(_lib().dpmt_set_profiling(self._h, 1 if on else 0), self._h, "dpmt_set_profiling")
 
@@ -226,6 +255,15 @@ class Context:
         calls = c_int32(0)
         n = _lib().dpmt_stage_times(self._h, buf, len(self.STAGES), byref(calls))
         return {self.STAGES[i]: buf[i] for i in range(n)}, calls.value
+
+
+def tile_config_count() -> int:
+    return int(_lib().dpmt_tile_config_count())
+
+
+def tile_config_name(config: int) -> Optional[str]:
+    r = _lib().dpmt_tile_config_name(int(config))
+    return r.decode() if r is not None else None
 
 
 def distance_transform(resp, deform, out=None, arg_y=None, arg_x=None, stream=None):

@@ -19,8 +19,22 @@ namespace {
 
 thread_local std::string g_free_error;   // errors of calls without a context
 
-constexpr int TY = 4, BB = 2, WY = 4;     // correlation tile: 16 rows x 32 cols x 64 filters
-constexpr int TYWG = TY * WY;
+// Correlation tile configurations the autotuner chooses from: output rows per
+// wave, 32-filter blocks per wave, waves per workgroup, resident grid.  All of
+// them accumulate every response in the same order, so they give equal bits.
+struct TileCfg {
+    int ty, bb, wy, persistent;
+    const char* name;
+};
+constexpr TileCfg TILE_CFGS[] = {
+    {4, 2, 4, 0, "16 rows x 32 cols x 64 filters, 256 threads, one workgroup per tile"},
+    {4, 2, 4, 1, "16 rows x 32 cols x 64 filters, 256 threads, resident grid"},
+    {2, 2, 4, 0, "8 rows x 32 cols x 64 filters, 256 threads, one workgroup per tile"},
+    {4, 1, 4, 0, "16 rows x 32 cols x 32 filters, 256 threads, one workgroup per tile"},
+    {2, 2, 4, 1, "8 rows x 32 cols x 64 filters, 256 threads, resident grid"},
+};
+constexpr int N_TILE_CFGS = (int)(sizeof(TILE_CFGS) / sizeof(TILE_CFGS[0]));
+constexpr int MAX_BB = 2;                 // most filter blocks per tile over TILE_CFGS
 constexpr int MAX_FILTER_H = 16;
 constexpr int MAX_FILTER_W = 32;
 
@@ -46,11 +60,21 @@ struct ModeData {
     float* dTk = nullptr;       // FP8: per-filter scales
     float* dScales = nullptr;   // FP8: RP channel scales + channel-max scratch
     int max_h = 0, max_S = 0;   // over the groups used by score_pyramid
-    // planned correlation tiles of this mode (valid for plan_id)
-    int plan_id = -1;
-    CorrTile* dTiles = nullptr;
-    int n_tiles = 0;
+    int tile_cfg = 0;           // TILE_CFGS entry used by score_pyramid
+    // planned correlation tiles per tile shape (rows per tile, filter blocks),
+    // valid for plan_id: cost order for batched launches, (image, level) order
+    // with ranges for per-level launches
+    struct TileSet {
+        int plan_id = -1;
+        CorrTile* dTiles = nullptr;
+        CorrTile* dTilesLvl = nullptr;
+        int n_tiles = 0;
+        std::vector<std::array<int, 4>> lvl;   // (image, level, begin, end)
+    };
+    std::map<std::pair<int, int>, TileSet> tilesets;
 };
+
+void free_tilesets(ModeData& m);
 
 struct LevelInfo {
     int64_t cell_offset;
@@ -142,7 +166,9 @@ struct dpmt_ctx {
     std::vector<int64_t> m_score_off, m_offs_off;
     std::vector<MapDesc> maps;
     std::vector<MapPart> map_parts;
-    std::vector<int2> place_blk;        // per placement block: (map, strip)
+    std::vector<int2> place_blk;        // per placement block: (map, strip), work order
+    std::vector<int2> place_blk_lvl;    // the same blocks in (image, level) order
+    std::vector<std::array<int, 4>> place_lvl;   // (image, level, begin, end) into place_blk_lvl
     PlaceLds place_lds{};
     dpmt_layout layout{};
 
@@ -154,10 +180,27 @@ struct dpmt_ctx {
     MapDesc* d_maps = nullptr;
     MapPart* d_parts = nullptr;
     int2* d_place_blk = nullptr;
+    int2* d_place_blk_lvl = nullptr;
+
+    // launch strategy and the captured graph of the batched launches
+    int launch = DPMT_LAUNCH_BATCHED;
+    hipStream_t cap_stream = nullptr;
+    struct GraphKey {
+        int mode = -1, plan_id = -1, cfg = -1;
+        const void* f = nullptr;
+        const void* s = nullptr;
+        const void* o = nullptr;
+        bool operator==(const GraphKey& k) const {
+            return mode == k.mode && plan_id == k.plan_id && cfg == k.cfg && f == k.f && s == k.s && o == k.o;
+        }
+    };
+    GraphKey graph_key;
+    hipGraphExec_t graph_exec = nullptr;
 
     // profiling: one set of events per profiled call
     bool prof = false;
     std::vector<std::array<hipEvent_t, N_EVENTS>> ev_sets;
+    std::vector<char> ev_whole_only;    // per set: stages not separable (graph launch)
     int ev_used = 0;
 
     bool has_device() const { return device >= 0; }
@@ -182,6 +225,14 @@ dpmt_status hip_fail(dpmt_ctx* c, hipError_t e, const char* what) {
         if (e_ != hipSuccess) return hip_fail(ctx, e_, what); \
     } while (0)
 
+void free_tilesets(ModeData& m) {
+    for (auto& kv : m.tilesets) {
+        dfree(kv.second.dTiles);
+        dfree(kv.second.dTilesLvl);
+    }
+    m.tilesets.clear();
+}
+
 void free_mode(ModeData& m) {
     dfree(m.dMaster);
     dfree(m.dRequant);
@@ -190,8 +241,16 @@ void free_mode(ModeData& m) {
     dfree(m.dG);
     dfree(m.dGroups);
     dfree(m.dU);
-    dfree(m.dTiles);
+    free_tilesets(m);
+    const int cfg = m.tile_cfg;
     m = ModeData{};
+    m.tile_cfg = cfg;
+}
+
+void drop_graph(dpmt_ctx* c) {
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    c->graph_exec = nullptr;
+    c->graph_key = dpmt_ctx::GraphKey{};
 }
 
 void free_plan(dpmt_ctx* c) {
@@ -201,12 +260,9 @@ void free_plan(dpmt_ctx* c) {
     dfree(c->d_maps); c->d_maps = nullptr;
     dfree(c->d_parts); c->d_parts = nullptr;
     dfree(c->d_place_blk); c->d_place_blk = nullptr;
-    for (auto& m : c->modes) {
-        dfree(m.dTiles);
-        m.dTiles = nullptr;
-        m.n_tiles = 0;
-        m.plan_id = -1;
-    }
+    dfree(c->d_place_blk_lvl); c->d_place_blk_lvl = nullptr;
+    for (auto& m : c->modes) free_tilesets(m);
+    drop_graph(c);
     c->planned = false;
 }
 
@@ -326,7 +382,7 @@ dpmt_status prepare_mode(dpmt_ctx* c, dpmt_mode mode) {
         gd.ng = (int)hg.filters.size();
         gd.S = (hg.w * pk.PB + KS - 1) / KS;
         const int nblk = (gd.ng + 31) / 32;
-        const int nblk_pad = (nblk + BB - 1) / BB * BB;
+        const int nblk_pad = (nblk + MAX_BB - 1) / MAX_BB * MAX_BB;   // a tile may read MAX_BB blocks
         const size_t chunk = (size_t)64 * FB;      // bytes per (block, plane, step, row)
         const size_t blk_bytes = (size_t)pk.Q * gd.S * gd.h * chunk;
         const size_t base_elems = fp8 ? master.size() : G.size();
@@ -407,17 +463,19 @@ dpmt_status prepare_mode(dpmt_ctx* c, dpmt_mode mode) {
     return DPMT_OK;
 }
 
-// FP8 mode: channel maxima of the given cells, channel scales, requantised
-// factors, then the scaled projection of the same cells into Z.
-hipError_t fp8_operands(dpmt_ctx* c, ModeData& md, const float* X, int64_t n_cells, void* Z,
+// FP8 mode: channel maxima of the given cells, channel scales and the
+// requantised factors; then the scaled projection of cells into Z.
+hipError_t fp8_prepare(ModeData& md, const float* X, int64_t n_cells, hipStream_t st) {
+    return launch_fp8_prepare(X, n_cells, md.dU, md.pk.RP, md.dScales + md.pk.RP, md.dScales,
+                              md.dRequant, md.n_requant, md.dMaster, static_cast<uint8_t*>(md.dG),
+                              md.dTk, st);
+}
+
+hipError_t fp8_operands(dpmt_ctx*, ModeData& md, const float* X, int64_t n_cells, void* Z,
                         hipStream_t st) {
-    float* scales = md.dScales;
-    float* partial = md.dScales + md.pk.RP;
-    hipError_t e = launch_fp8_prepare(X, n_cells, md.dU, md.pk.RP, partial, scales, md.dRequant,
-                                      md.n_requant, md.dMaster, static_cast<uint8_t*>(md.dG),
-                                      md.dTk, st);
+    hipError_t e = fp8_prepare(md, X, n_cells, st);
     if (e != hipSuccess) return e;
-    return launch_project_fp8(X, n_cells, md.dU, md.pk.RP, scales, Z, st);
+    return launch_project_fp8(X, n_cells, md.dU, md.pk.RP, md.dScales, Z, st);
 }
 
 void build_groups(dpmt_ctx* c) {
@@ -458,13 +516,13 @@ void build_groups(dpmt_ctx* c) {
 }
 
 void add_tiles(std::vector<CorrTile>& tiles, const GroupDesc& gd, int group, int64_t z_cell,
-               int64_t out_off, int rng, int H, int W) {
+               int64_t out_off, int rng, int H, int W, int rows, int bb) {
     const int Ho = H - gd.h + 1, Wo = W - gd.w + 1;
     if (Ho <= 0 || Wo <= 0) return;
     const int nblk = (gd.ng + 31) / 32;
-    for (int y0 = 0; y0 < Ho; y0 += TYWG)
+    for (int y0 = 0; y0 < Ho; y0 += rows)
         for (int x0 = 0; x0 < Wo; x0 += 32)
-            for (int fb = 0; fb < nblk; fb += BB) {
+            for (int fb = 0; fb < nblk; fb += bb) {
                 CorrTile t{};
                 t.z_cell = z_cell;
                 t.out_off = out_off;
@@ -482,26 +540,154 @@ void add_tiles(std::vector<CorrTile>& tiles, const GroupDesc& gd, int group, int
             }
 }
 
-dpmt_status prepare_tiles(dpmt_ctx* c, dpmt_mode mode) {
+// Correlation tiles of the mode's tile configuration for the current plan.
+dpmt_status prepare_tiles(dpmt_ctx* c, dpmt_mode mode, ModeData::TileSet** out) {
     ModeData& md = c->modes[mode];
-    if (md.plan_id == c->plan_id && md.dTiles) return DPMT_OK;
-    std::vector<CorrTile> tiles;
+    const TileCfg& tc = TILE_CFGS[md.tile_cfg];
+    const std::pair<int, int> key{tc.ty * tc.wy, tc.bb};
+    ModeData::TileSet& ts = md.tilesets[key];
+    *out = &ts;
+    if (ts.plan_id == c->plan_id && (ts.dTiles || ts.n_tiles == 0)) return DPMT_OK;
+    dfree(ts.dTiles);
+    dfree(ts.dTilesLvl);
+    ts = ModeData::TileSet{};
+    std::vector<CorrTile> tiles;                   // blocks are ordered by (image, level, group)
     for (const auto& kv : c->blocks) {
         const BlockKey& k = kv.first;
         const LevelInfo& lv = c->pyr[k.img][k.level];
+        const size_t b0 = tiles.size();
         add_tiles(tiles, md.groups[k.group], k.group, lv.cell_offset, kv.second.off,
-                  (int)kv.second.rng, lv.rows, lv.cols);
+                  (int)kv.second.rng, lv.rows, lv.cols, key.first, key.second);
+        if (tiles.size() == b0) continue;
+        if (!ts.lvl.empty() && ts.lvl.back()[0] == k.img && ts.lvl.back()[1] == k.level)
+            ts.lvl.back()[3] = (int)tiles.size();
+        else
+            ts.lvl.push_back({k.img, k.level, (int)b0, (int)tiles.size()});
     }
-    // most expensive groups first so that the tail of the launch is short tiles
+    if (tiles.size() > (size_t)INT32_MAX) return fail(c, DPMT_E_UNSUPPORTED, "batch too large for one launch");
+    HIP_TRY(c, upload(&ts.dTilesLvl, tiles), "upload tiles");
+    // most expensive groups first so that the tail of the batched launch is short tiles
     std::stable_sort(tiles.begin(), tiles.end(), [&](const CorrTile& a, const CorrTile& b) {
         const GroupDesc& ga = md.groups[a.group];
         const GroupDesc& gb = md.groups[b.group];
         return (int64_t)ga.h * ga.S > (int64_t)gb.h * gb.S;
     });
-    HIP_TRY(c, upload(&md.dTiles, tiles), "upload tiles");
-    md.n_tiles = (int)tiles.size();
-    md.plan_id = c->plan_id;
+    HIP_TRY(c, upload(&ts.dTiles, tiles), "upload tiles");
+    ts.n_tiles = (int)tiles.size();
+    ts.plan_id = c->plan_id;
     return DPMT_OK;
+}
+
+dpmt_status score_checks(dpmt_ctx* c, dpmt_mode mode, const float* features_dev,
+                         const float* scores_dev) {
+    if (!c) return fail(nullptr, DPMT_E_INVALID, "ctx is NULL");
+    if (mode < DPMT_DIRECT_FP32 || mode > DPMT_TENSOR_FP8) return fail(c, DPMT_E_INVALID, "unknown mode");
+    if (!c->loaded) return fail(c, DPMT_E_STATE, "score call before dpmt_load_filters");
+    if (mode != DPMT_DIRECT_FP32 && !c->decomposed) return fail(c, DPMT_E_STATE, "tensor mode needs dpmt_decompose first");
+    if (!c->planned) return fail(c, DPMT_E_STATE, "score call before dpmt_plan");
+    if (!c->has_device()) return fail(c, DPMT_E_STATE, "host-only context cannot score");
+    if (!features_dev || (!scores_dev && c->layout.n_score > 0)) return fail(c, DPMT_E_INVALID, "features_dev and scores_dev are required");
+    return DPMT_OK;
+}
+
+// Operands, tiles and the projected-feature buffer of a mode for the plan;
+// allocates, so it never runs while a graph is being captured.
+dpmt_status score_prepare(dpmt_ctx* c, dpmt_mode mode, hipStream_t st) {
+    HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
+    dpmt_status s = prepare_mode(c, mode);
+    if (s != DPMT_OK) return s;
+    ModeData::TileSet* ts = nullptr;
+    if ((s = prepare_tiles(c, mode, &ts)) != DPMT_OK) return s;
+    ModeData& md = c->modes[mode];
+    if (mode != DPMT_DIRECT_FP32) {
+        const size_t need = (size_t)c->n_cells * md.pk.RP * md.pk.esz;
+        if (need > c->Z_bytes) {
+            HIP_TRY(c, hipStreamSynchronize(st), "hipStreamSynchronize");
+            drop_graph(c);
+            dfree(c->d_Z);
+            c->d_Z = nullptr;
+            c->Z_bytes = 0;
+            HIP_TRY(c, hipMalloc(&c->d_Z, need), "allocate projected features");
+            c->Z_bytes = need;
+        }
+    }
+    return DPMT_OK;
+}
+
+ModeData::TileSet& current_tiles(dpmt_ctx* c, dpmt_mode mode) {
+    ModeData& md = c->modes[mode];
+    const TileCfg& tc = TILE_CFGS[md.tile_cfg];
+    return md.tilesets[{tc.ty * tc.wy, tc.bb}];
+}
+
+CorrLaunch corr_launch(const ModeData& md) {
+    const TileCfg& tc = TILE_CFGS[md.tile_cfg];
+    return CorrLaunch{md.kind, md.pk, tc.ty, tc.bb, tc.wy, tc.persistent};
+}
+
+// The whole call as one launch per stage: value-range reset, projection of
+// every level, correlation of every tile, placement of every score map.
+hipError_t enqueue_batched(dpmt_ctx* c, dpmt_mode mode, const float* X, float* scores,
+                           int16_t* offs, hipStream_t st, hipEvent_t* ev) {
+    ModeData& md = c->modes[mode];
+    ModeData::TileSet& ts = current_tiles(c, mode);
+    const bool tensor = mode != DPMT_DIRECT_FP32;
+    const void* Z = tensor ? c->d_Z : static_cast<const void*>(X);
+    hipError_t e = ev ? hipEventRecord(ev[0], st) : hipSuccess;
+    if (e == hipSuccess) e = launch_range_init(c->d_rkeys, c->n_slots, st);
+    if (e == hipSuccess) {
+        if (mode == DPMT_TENSOR_FP8) e = fp8_operands(c, md, X, c->n_cells, c->d_Z, st);
+        else if (tensor) e = launch_project(md.pk.esz == 2, X, c->n_cells, md.dU, md.pk.RP, c->d_Z, st);
+    }
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[1], st);
+    if (e == hipSuccess)
+        e = launch_corr(corr_launch(md), ts.dTiles, ts.n_tiles, md.dGroups, Z, md.dG, md.dTk, c->d_resp,
+                        c->d_rkeys, c->n_slots, md.max_h, md.max_S, st);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[2], st);
+    if (e == hipSuccess)
+        e = launch_place(c->d_maps, c->d_parts, c->d_place_blk, (int)c->place_blk.size(), c->d_resp,
+                         c->d_rkeys, c->n_slots, scores, offs, c->place_lds, st);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[3], st);
+    return e;
+}
+
+// The same work as separate launches per pyramid level: projection and
+// correlation of each (image, level), then placement of each (image, root
+// level).  FP8 scales stay global, so both strategies compute equal bits.
+hipError_t enqueue_per_level(dpmt_ctx* c, dpmt_mode mode, const float* X, float* scores,
+                             int16_t* offs, hipStream_t st, hipEvent_t* ev) {
+    ModeData& md = c->modes[mode];
+    ModeData::TileSet& ts = current_tiles(c, mode);
+    const bool tensor = mode != DPMT_DIRECT_FP32;
+    const void* Z = tensor ? c->d_Z : static_cast<const void*>(X);
+    const size_t zcell = (size_t)md.pk.RP * md.pk.esz;
+    hipError_t e = ev ? hipEventRecord(ev[0], st) : hipSuccess;
+    if (e == hipSuccess) e = launch_range_init(c->d_rkeys, c->n_slots, st);
+    if (e == hipSuccess && mode == DPMT_TENSOR_FP8) e = fp8_prepare(md, X, c->n_cells, st);
+    for (size_t i = 0; i < c->pyr.size() && e == hipSuccess && tensor; ++i)
+        for (const LevelInfo& lv : c->pyr[i]) {
+            if (e != hipSuccess) break;
+            const int64_t n = (int64_t)lv.rows * lv.cols;
+            const float* Xl = X + lv.cell_offset * 32;
+            void* Zl = static_cast<char*>(c->d_Z) + lv.cell_offset * zcell;
+            e = mode == DPMT_TENSOR_FP8 ? launch_project_fp8(Xl, n, md.dU, md.pk.RP, md.dScales, Zl, st)
+                                        : launch_project(md.pk.esz == 2, Xl, n, md.dU, md.pk.RP, Zl, st);
+        }
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[1], st);
+    const CorrLaunch cl = corr_launch(md);
+    for (const auto& r : ts.lvl) {
+        if (e != hipSuccess) break;
+        e = launch_corr(cl, ts.dTilesLvl + r[2], r[3] - r[2], md.dGroups, Z, md.dG, md.dTk, c->d_resp,
+                        c->d_rkeys, c->n_slots, md.max_h, md.max_S, st);
+    }
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[2], st);
+    for (const auto& r : c->place_lvl) {
+        if (e != hipSuccess) break;
+        e = launch_place(c->d_maps, c->d_parts, c->d_place_blk_lvl + r[2], r[3] - r[2], c->d_resp,
+                         c->d_rkeys, c->n_slots, scores, offs, c->place_lds, st);
+    }
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[3], st);
+    return e;
 }
 
 }  // namespace
@@ -559,6 +745,7 @@ void dpmt_destroy(dpmt_ctx* c) {
         (void)hipDeviceSynchronize();
         free_plan(c);
         for (auto& m : c->modes) free_mode(m);
+        if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
         for (auto& set : c->ev_sets)
             for (auto& e : set) (void)hipEventDestroy(e);
     }
@@ -606,6 +793,7 @@ dpmt_status dpmt_load_filters(dpmt_ctx* c, int32_t n_filters, const dpmt_shape* 
         free_plan(c);
         for (auto& m : c->modes) free_mode(m);
     }
+    for (auto& m : c->modes) m.tile_cfg = 0;
     c->planned = false;
     c->decomposed = false;
     c->shapes.assign(shapes, shapes + n_filters);
@@ -666,14 +854,12 @@ dpmt_status dpmt_decompose(dpmt_ctx* c, int32_t rank, double* sigma_out, double*
     }
     c->rank = rank;
     c->decomposed = true;
-    for (int m = 1; m < 4; ++m) {             // tensor operands depend on U_R
-        ModeData& md = c->modes[m];
-        if (c->has_device()) {
-            (void)hipSetDevice(c->device);
-            (void)hipDeviceSynchronize();
-        }
-        free_mode(md);
+    if (c->has_device()) {
+        (void)hipSetDevice(c->device);
+        (void)hipDeviceSynchronize();
     }
+    drop_graph(c);
+    for (int m = 1; m < 4; ++m) free_mode(c->modes[m]);   // tensor operands depend on U_R
     if (sigma_out) std::memcpy(sigma_out, c->sigma.data(), 32 * sizeof(double));
     if (basis_out)
         for (int l = 0; l < 32; ++l)
@@ -833,6 +1019,21 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
             const int strips = (c->maps[o.second].Wo + PLACE_CW - 1) / PLACE_CW;
             for (int st = 0; st < strips; ++st) c->place_blk.push_back(make_int2(o.second, st));
         }
+        // the same blocks grouped by (image, root level) for per-level launches
+        c->place_blk_lvl.clear();
+        c->place_lvl.clear();
+        for (size_t k = 0; k < c->maps.size(); ++k) {
+            const MapDesc& md = c->maps[k];
+            if (md.Ho <= 0 || md.Wo <= 0) continue;
+            const int img = c->m_image[k], lvl = c->m_level[k];
+            const int b0 = (int)c->place_blk_lvl.size();
+            for (int st = 0; st < (md.Wo + PLACE_CW - 1) / PLACE_CW; ++st)
+                c->place_blk_lvl.push_back(make_int2((int)k, st));
+            if (!c->place_lvl.empty() && c->place_lvl.back()[0] == img && c->place_lvl.back()[1] == lvl)
+                c->place_lvl.back()[3] = (int)c->place_blk_lvl.size();
+            else
+                c->place_lvl.push_back({img, lvl, b0, (int)c->place_blk_lvl.size()});
+        }
         const int span = place_span_max(max_Wp);
         if (span > PLACE_STAGE)
             return fail(c, DPMT_E_UNSUPPORTED, "part level wider than the placement staging supports");
@@ -878,6 +1079,7 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
         HIP_TRY(c, upload(&c->d_maps, c->maps), "upload maps");
         HIP_TRY(c, upload(&c->d_parts, c->map_parts), "upload map parts");
         HIP_TRY(c, upload(&c->d_place_blk, c->place_blk), "upload block map");
+        HIP_TRY(c, upload(&c->d_place_blk_lvl, c->place_blk_lvl), "upload block map");
     }
     c->planned = true;
     *out = &c->layout;
@@ -903,6 +1105,10 @@ int32_t dpmt_stage_times(dpmt_ctx* c, float* ms_out, int32_t n, int32_t* n_calls
         if (hipEventSynchronize(ev[N_STAGES]) != hipSuccess) return 0;
         float t;
         for (int i = 0; i < N_STAGES; ++i) {
+            if (c->ev_whole_only[k]) {
+                sum[i] = NAN;                          // one graph launch: no stage split
+                continue;
+            }
             if (hipEventElapsedTime(&t, ev[i], ev[i + 1]) != hipSuccess) return 0;
             sum[i] += t;
         }
@@ -917,58 +1123,147 @@ int32_t dpmt_stage_times(dpmt_ctx* c, float* ms_out, int32_t n, int32_t* n_calls
 
 dpmt_status dpmt_score_pyramid(dpmt_ctx* c, dpmt_mode mode, const float* features_dev,
                                float* scores_dev, int16_t* offsets_dev, void* hip_stream) {
-    if (!c) return fail(nullptr, DPMT_E_INVALID, "ctx is NULL");
-    if (mode < DPMT_DIRECT_FP32 || mode > DPMT_TENSOR_FP8) return fail(c, DPMT_E_INVALID, "unknown mode");
-    if (!c->loaded) return fail(c, DPMT_E_STATE, "dpmt_score_pyramid before dpmt_load_filters");
-    if (mode != DPMT_DIRECT_FP32 && !c->decomposed) return fail(c, DPMT_E_STATE, "tensor mode needs dpmt_decompose first");
-    if (!c->planned) return fail(c, DPMT_E_STATE, "dpmt_score_pyramid before dpmt_plan");
-    if (!c->has_device()) return fail(c, DPMT_E_STATE, "host-only context cannot score");
-    if (!features_dev || (!scores_dev && c->layout.n_score > 0)) return fail(c, DPMT_E_INVALID, "features_dev and scores_dev are required");
-    HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
-    dpmt_status s = prepare_mode(c, mode);
+    dpmt_status s = score_checks(c, mode, features_dev, scores_dev);
     if (s != DPMT_OK) return s;
-    if ((s = prepare_tiles(c, mode)) != DPMT_OK) return s;
-    ModeData& md = c->modes[mode];
     hipStream_t st = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
-    const bool tensor = mode != DPMT_DIRECT_FP32;
-    const void* Zsrc = features_dev;
-    if (tensor) {
-        const size_t need = (size_t)c->n_cells * md.pk.RP * md.pk.esz;
-        if (need > c->Z_bytes) {
-            HIP_TRY(c, hipStreamSynchronize(st), "hipStreamSynchronize");
-            dfree(c->d_Z);
-            c->d_Z = nullptr;
-            c->Z_bytes = 0;
-            HIP_TRY(c, hipMalloc(&c->d_Z, need), "allocate projected features");
-            c->Z_bytes = need;
-        }
-        Zsrc = c->d_Z;
-    }
+    if ((s = score_prepare(c, mode, st)) != DPMT_OK) return s;
     hipEvent_t* ev = nullptr;
     if (c->prof) {
         if (c->ev_used == (int)c->ev_sets.size()) {
             std::array<hipEvent_t, N_EVENTS> set{};
             for (auto& e : set) HIP_TRY(c, hipEventCreate(&e), "hipEventCreate");
             c->ev_sets.push_back(set);
+            c->ev_whole_only.push_back(0);
         }
+        c->ev_whole_only[c->ev_used] = c->launch == DPMT_LAUNCH_GRAPH;
         ev = c->ev_sets[c->ev_used++].data();
     }
-    auto mark = [&](int k) -> hipError_t { return ev ? hipEventRecord(ev[k], st) : hipSuccess; };
-    HIP_TRY(c, mark(0), "hipEventRecord");
-    HIP_TRY(c, launch_range_init(c->d_rkeys, c->n_slots, st), "range init launch");
-    if (mode == DPMT_TENSOR_FP8)
-        HIP_TRY(c, fp8_operands(c, md, features_dev, c->n_cells, c->d_Z, st), "FP8 operand launch");
-    else if (tensor)
-        HIP_TRY(c, launch_project(md.pk.esz == 2, features_dev, c->n_cells, md.dU, md.pk.RP, c->d_Z, st), "projection launch");
-    HIP_TRY(c, mark(1), "hipEventRecord");
-    CorrLaunch cl{md.kind, md.pk, TY, BB, WY};
-    HIP_TRY(c, launch_corr(cl, md.dTiles, md.n_tiles, md.dGroups, Zsrc, md.dG, md.dTk, c->d_resp,
-                           c->d_rkeys, c->n_slots, md.max_h, md.max_S, st), "correlation launch");
-    HIP_TRY(c, mark(2), "hipEventRecord");
-    HIP_TRY(c, launch_place(c->d_maps, c->d_parts, c->d_place_blk, (int)c->place_blk.size(), c->d_resp,
-                            c->d_rkeys, c->n_slots, scores_dev, offsets_dev, c->place_lds, st),
-            "placement launch");
-    HIP_TRY(c, mark(3), "hipEventRecord");
+    if (c->launch == DPMT_LAUNCH_GRAPH) {
+        dpmt_ctx::GraphKey key;
+        key.mode = mode;
+        key.plan_id = c->plan_id;
+        key.cfg = c->modes[mode].tile_cfg;
+        key.f = features_dev;
+        key.s = scores_dev;
+        key.o = offsets_dev;
+        if (!c->graph_exec || !(c->graph_key == key)) {
+            drop_graph(c);
+            if (!c->cap_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking), "hipStreamCreate");
+            HIP_TRY(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed), "hipStreamBeginCapture");
+            hipError_t e = enqueue_batched(c, mode, features_dev, scores_dev, offsets_dev, c->cap_stream, nullptr);
+            hipGraph_t graph = nullptr;
+            hipError_t e2 = hipStreamEndCapture(c->cap_stream, &graph);
+            if (e == hipSuccess) e = e2;
+            if (e == hipSuccess) e = hipGraphInstantiate(&c->graph_exec, graph, nullptr, nullptr, 0);
+            if (graph) (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                c->graph_exec = nullptr;
+                return hip_fail(c, e, "graph capture");
+            }
+            c->graph_key = key;
+        }
+        if (ev) for (int k = 0; k < N_STAGES; ++k) HIP_TRY(c, hipEventRecord(ev[k], st), "hipEventRecord");
+        HIP_TRY(c, hipGraphLaunch(c->graph_exec, st), "hipGraphLaunch");
+        if (ev) HIP_TRY(c, hipEventRecord(ev[N_STAGES], st), "hipEventRecord");
+        return DPMT_OK;
+    }
+    const hipError_t e = c->launch == DPMT_LAUNCH_PER_LEVEL
+                             ? enqueue_per_level(c, mode, features_dev, scores_dev, offsets_dev, st, ev)
+                             : enqueue_batched(c, mode, features_dev, scores_dev, offsets_dev, st, ev);
+    if (e != hipSuccess) return hip_fail(c, e, "score launch");
+    return DPMT_OK;
+}
+
+dpmt_status dpmt_set_launch(dpmt_ctx* c, int32_t launch) {
+    if (!c) return fail(nullptr, DPMT_E_INVALID, "ctx is NULL");
+    if (launch < DPMT_LAUNCH_BATCHED || launch > DPMT_LAUNCH_GRAPH) return fail(c, DPMT_E_INVALID, "unknown launch strategy");
+    if (c->has_device() && c->graph_exec) {
+        (void)hipSetDevice(c->device);
+        (void)hipDeviceSynchronize();
+        drop_graph(c);
+    }
+    c->launch = launch;
+    return DPMT_OK;
+}
+
+int32_t dpmt_tile_config_count(void) { return N_TILE_CFGS; }
+
+const char* dpmt_tile_config_name(int32_t config) {
+    return (config >= 0 && config < N_TILE_CFGS) ? TILE_CFGS[config].name : nullptr;
+}
+
+dpmt_status dpmt_set_tile_config(dpmt_ctx* c, dpmt_mode mode, int32_t config) {
+    if (!c) return fail(nullptr, DPMT_E_INVALID, "ctx is NULL");
+    if (mode < DPMT_DIRECT_FP32 || mode > DPMT_TENSOR_FP8) return fail(c, DPMT_E_INVALID, "unknown mode");
+    if (config < 0 || config >= N_TILE_CFGS) return fail(c, DPMT_E_INVALID, "tile configuration out of range");
+    const TileCfg& tc = TILE_CFGS[config];
+    int max_h = 0;
+    for (const auto& sh : c->shapes) max_h = std::max(max_h, sh.h);
+    if (!corr_shape_supported(tc.ty, tc.bb, tc.wy, max_h))
+        return fail(c, DPMT_E_UNSUPPORTED, "tile configuration does not support filters of " + std::to_string(max_h) + " rows");
+    c->modes[mode].tile_cfg = config;
+    return DPMT_OK;
+}
+
+int32_t dpmt_get_tile_config(const dpmt_ctx* c, dpmt_mode mode) {
+    if (!c || mode < DPMT_DIRECT_FP32 || mode > DPMT_TENSOR_FP8) return -1;
+    return c->modes[mode].tile_cfg;
+}
+
+dpmt_status dpmt_autotune(dpmt_ctx* c, dpmt_mode mode, const float* features_dev, float* scores_dev,
+                          int16_t* offsets_dev, int32_t reps, float* ms_out, int32_t* best_out,
+                          void* hip_stream) {
+    dpmt_status s = score_checks(c, mode, features_dev, scores_dev);
+    if (s != DPMT_OK) return s;
+    if (reps < 1 || reps > 1000) return fail(c, DPMT_E_INVALID, "reps must be in [1, 1000]");
+    hipStream_t st = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
+    ModeData& md = c->modes[mode];
+    const int keep = md.tile_cfg;
+    int max_h = 0;
+    for (const auto& sh : c->shapes) max_h = std::max(max_h, sh.h);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(c, hipEventCreate(&e0), "hipEventCreate");
+    HIP_TRY(c, hipEventCreate(&e1), "hipEventCreate");
+    int best = -1;
+    float best_ms = 0.f;
+    hipError_t err = hipSuccess;
+    for (int k = 0; k < N_TILE_CFGS && err == hipSuccess; ++k) {
+        if (ms_out) ms_out[k] = -1.f;
+        const TileCfg& tc = TILE_CFGS[k];
+        if (!corr_shape_supported(tc.ty, tc.bb, tc.wy, max_h)) continue;
+        md.tile_cfg = k;
+        if ((s = score_prepare(c, mode, st)) != DPMT_OK) break;
+        std::vector<float> t;
+        for (int r = 0; r <= reps && err == hipSuccess; ++r) {        // the first run warms up
+            err = hipEventRecord(e0, st);
+            if (err == hipSuccess) err = enqueue_batched(c, mode, features_dev, scores_dev, offsets_dev, st, nullptr);
+            if (err == hipSuccess) err = hipEventRecord(e1, st);
+            if (err == hipSuccess) err = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+            if (r > 0) t.push_back(ms);
+        }
+        if (err != hipSuccess) break;
+        std::sort(t.begin(), t.end());
+        const float med = t[t.size() / 2];
+        if (ms_out) ms_out[k] = med;
+        if (best < 0 || med < best_ms) {
+            best = k;
+            best_ms = med;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (s != DPMT_OK) {
+        md.tile_cfg = keep;
+        return s;
+    }
+    if (err != hipSuccess) {
+        md.tile_cfg = keep;
+        return hip_fail(c, err, "autotune");
+    }
+    md.tile_cfg = best >= 0 ? best : keep;
+    if (best_out) *best_out = md.tile_cfg;
     return DPMT_OK;
 }
 
@@ -1013,7 +1308,7 @@ dpmt_status dpmt_level_responses(dpmt_ctx* c, dpmt_mode mode, const float* featu
         const GroupDesc& gd = md.groups[g];
         const int Ho = lv.rows - gd.h + 1, Wo = lv.cols - gd.w + 1;
         if (Ho <= 0 || Wo <= 0) continue;
-        add_tiles(tiles, gd, (int)g, 0, blk_total, -1, lv.rows, lv.cols);
+        add_tiles(tiles, gd, (int)g, 0, blk_total, -1, lv.rows, lv.cols, 16, 2);
         gblocks.push_back({(int)g, blk_total, Ho, Wo, pitch_of(Wo)});
         blk_total += (int64_t)Ho * pitch_of(Wo) * gd.ng;
         max_h = std::max(max_h, gd.h);
@@ -1041,7 +1336,7 @@ dpmt_status dpmt_level_responses(dpmt_ctx* c, dpmt_mode mode, const float* featu
     }
     if (e == hipSuccess) e = hipMalloc((void**)&dblk, (size_t)blk_total * 4);
     if (e == hipSuccess) e = upload(&dtiles, tiles);
-    CorrLaunch cl{md.kind, md.pk, TY, BB, WY};
+    CorrLaunch cl{md.kind, md.pk, 4, 2, 4, 0};
     if (e == hipSuccess) e = launch_corr(cl, dtiles, (int)tiles.size(), md.dGroups, Zsrc, md.dG, md.dTk, dblk, nullptr, 0, max_h, max_S, st);
     for (const auto& gb : gblocks) {
         if (e != hipSuccess) break;

@@ -87,7 +87,11 @@ struct CorrLaunch {
     int ty;            // output rows per wave
     int bb;            // 32-filter blocks per wave
     int wy;            // waves per workgroup (stacked along rows)
+    int persistent;    // 0: one workgroup per tile; 1: resident grid striding the tiles
 };
+// Tile shapes the correlation kernel is built for (ty, bb, wy); filters taller
+// than 8 rows only with (4, 2, 4).
+bool corr_shape_supported(int ty, int bb, int wy, int max_h);
 
 // Placement kernel geometry.  A block owns PLACE_CW consecutive root columns
 // of one score map; its LDS holds the score accumulator, the row-pass tile of

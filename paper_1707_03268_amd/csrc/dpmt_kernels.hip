@@ -15,6 +15,7 @@
 //   dt1_*_kernel       the same transform for every cell of one map
 #include "dpmt_internal.h"
 
+#include <algorithm>
 #include <cfloat>
 #include <climits>
 
@@ -160,15 +161,11 @@ __device__ __forceinline__ typename FragT<KIND>::type lds_frag(const char* p, in
 }
 
 template <CorrKind KIND, int PB, int TY, int BB, int WY, int HMAX>
-__global__ __launch_bounds__(64 * WY) __attribute__((amdgpu_waves_per_eu((HMAX <= 8 && KIND != CORR_FP8) ? 2 : 1))) void corr_kernel(const CorrTile* __restrict__ tiles,
-                                                       const GroupDesc* __restrict__ groups,
-                                                       const char* __restrict__ Z,
-                                                       const char* __restrict__ G,
-                                                       const float* __restrict__ tk,
-                                                       float* __restrict__ out,
-                                                       int* __restrict__ rmax,
-                                                       int* __restrict__ rmin, int cell_bytes,
-                                                       int Q, int win_bytes) {
+__device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __restrict__ groups,
+                                          const char* __restrict__ Z, const char* __restrict__ G,
+                                          const float* __restrict__ tk, float* __restrict__ out,
+                                          int* __restrict__ rmax, int* __restrict__ rmin,
+                                          int cell_bytes, int Q, int win_bytes) {
     extern __shared__ __align__(16) char smem[];
     constexpr int NT = 64 * WY;
     constexpr int TYWG = TY * WY;
@@ -180,7 +177,6 @@ __global__ __launch_bounds__(64 * WY) __attribute__((amdgpu_waves_per_eu((HMAX <
     constexpr int PFMAX = (BB * HMAX * CU + NT - 1) / NT;   // chunk u32x4 per thread, h <= HMAX
     constexpr int WBATCH = 4;                      // window loads in flight per thread
 
-    const CorrTile t = tiles[blockIdx.x];
     const GroupDesc g = groups[t.group];
     const int h = g.h, S = g.S;
     const int WC = 31 + (KS * S) / PB;             // window cells per row
@@ -395,6 +391,26 @@ __global__ __launch_bounds__(64 * WY) __attribute__((amdgpu_waves_per_eu((HMAX <
     }
 }
 
+// One workgroup per tile (grid = tiles), or a persistent grid that strides
+// over the cost-sorted tile list; both produce the same bits.
+template <CorrKind KIND, int PB, int TY, int BB, int WY, int HMAX>
+__global__ __launch_bounds__(64 * WY) __attribute__((amdgpu_waves_per_eu((HMAX <= 8 && KIND != CORR_FP8 && TY * BB <= 8) ? 2 : 1))) void corr_kernel(const CorrTile* __restrict__ tiles, int n_tiles,
+                                                       const GroupDesc* __restrict__ groups,
+                                                       const char* __restrict__ Z,
+                                                       const char* __restrict__ G,
+                                                       const float* __restrict__ tk,
+                                                       float* __restrict__ out,
+                                                       int* __restrict__ rmax,
+                                                       int* __restrict__ rmin, int cell_bytes,
+                                                       int Q, int win_bytes) {
+    for (int i = blockIdx.x; i < n_tiles; i += gridDim.x) {
+        const CorrTile t = tiles[i];
+        corr_tile<KIND, PB, TY, BB, WY, HMAX>(t, groups, Z, G, tk, out, rmax, rmin, cell_bytes, Q,
+                                              win_bytes);
+        if (i + (int)gridDim.x < n_tiles) __syncthreads();   // LDS reused by the next tile
+    }
+}
+
 static int frag_bytes(CorrKind k) { return k == CORR_FP8 ? 32 : 16; }
 
 size_t corr_lds_bytes(const CorrLaunch& cfg, int h, int S) {
@@ -406,11 +422,10 @@ size_t corr_lds_bytes(const CorrLaunch& cfg, int h, int S) {
 }
 
 template <CorrKind KIND, int PB, int TY, int BB, int WY, int HMAX>
-static hipError_t launch_corr_h(const CorrTile* tiles, int n_tiles, const GroupDesc* groups,
-                                const void* Z, const void* G, const float* tk, float* out,
-                                int* rkeys, int64_t n_slots, int cell_bytes, int Q, int max_h,
-                                int max_S, hipStream_t st) {
-    CorrLaunch cfg{KIND, Packing{0, 0, PB, Q}, TY, BB, WY};
+static hipError_t launch_corr_h(const CorrLaunch& cfg, const CorrTile* tiles, int n_tiles,
+                                const GroupDesc* groups, const void* Z, const void* G,
+                                const float* tk, float* out, int* rkeys, int64_t n_slots,
+                                int cell_bytes, int max_h, int max_S, hipStream_t st) {
     const size_t lds = corr_lds_bytes(cfg, max_h, max_S);
     const int FB = FragT<KIND>::bytes;
     const int WC = 31 + (2 * FB * max_S) / PB;
@@ -423,25 +438,59 @@ static hipError_t launch_corr_h(const CorrTile* tiles, int n_tiles, const GroupD
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(kern, dim3(n_tiles), dim3(64 * WY), lds, st, tiles, groups,
+    int grid = n_tiles;
+    if (cfg.persistent) {
+        int per_cu = 0, dev = 0, cus = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, 64 * WY, lds);
+        if (e == hipSuccess) e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        grid = std::max(1, std::min(n_tiles, std::max(per_cu, 1) * cus));
+    }
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(64 * WY), lds, st, tiles, n_tiles, groups,
                        static_cast<const char*>(Z), static_cast<const char*>(G), tk, out,
-                       rkeys, rkeys ? rkeys + n_slots : nullptr, cell_bytes, Q, win_bytes);
+                       rkeys, rkeys ? rkeys + n_slots : nullptr, cell_bytes, cfg.pk.Q, win_bytes);
     return hipGetLastError();
 }
 
 // Filters of at most 8 rows (every DPM root and part shape) get a kernel whose
-// chunk prefetch needs half the registers.
+// chunk prefetch needs half the registers; taller filters only the default tile.
 template <CorrKind KIND, int PB, int TY, int BB, int WY>
-static hipError_t launch_corr_t(const CorrTile* tiles, int n_tiles, const GroupDesc* groups,
-                                const void* Z, const void* G, const float* tk, float* out,
-                                int* rkeys, int64_t n_slots, int cell_bytes, int Q, int max_h,
-                                int max_S, hipStream_t st) {
+static hipError_t launch_corr_t(const CorrLaunch& cfg, const CorrTile* tiles, int n_tiles,
+                                const GroupDesc* groups, const void* Z, const void* G,
+                                const float* tk, float* out, int* rkeys, int64_t n_slots,
+                                int cell_bytes, int max_h, int max_S, hipStream_t st) {
     if (max_h <= 8)
-        return launch_corr_h<KIND, PB, TY, BB, WY, 8>(tiles, n_tiles, groups, Z, G, tk, out, rkeys,
-                                                      n_slots, cell_bytes, Q, max_h, max_S, st);
-    return launch_corr_h<KIND, PB, TY, BB, WY, CORR_MAX_H>(tiles, n_tiles, groups, Z, G, tk, out,
-                                                           rkeys, n_slots, cell_bytes, Q, max_h,
-                                                           max_S, st);
+        return launch_corr_h<KIND, PB, TY, BB, WY, 8>(cfg, tiles, n_tiles, groups, Z, G, tk, out,
+                                                      rkeys, n_slots, cell_bytes, max_h, max_S, st);
+    if constexpr (TY == 4 && BB == 2 && WY == 4)
+        return launch_corr_h<KIND, PB, TY, BB, WY, CORR_MAX_H>(cfg, tiles, n_tiles, groups, Z, G, tk,
+                                                               out, rkeys, n_slots, cell_bytes,
+                                                               max_h, max_S, st);
+    return hipErrorInvalidValue;
+}
+
+template <CorrKind KIND, int PB>
+static hipError_t launch_corr_p(const CorrLaunch& cfg, const CorrTile* tiles, int n_tiles,
+                                const GroupDesc* groups, const void* Z, const void* G,
+                                const float* tk, float* out, int* rkeys, int64_t n_slots,
+                                int cell_bytes, int max_h, int max_S, hipStream_t st) {
+#define DPMT_SHAPE(A, B, C)                                                                      \
+    if (cfg.ty == A && cfg.bb == B && cfg.wy == C)                                               \
+        return launch_corr_t<KIND, PB, A, B, C>(cfg, tiles, n_tiles, groups, Z, G, tk, out, rkeys, \
+                                                n_slots, cell_bytes, max_h, max_S, st);
+    DPMT_SHAPE(4, 2, 4)
+    DPMT_SHAPE(2, 2, 4)
+    DPMT_SHAPE(4, 1, 4)
+#undef DPMT_SHAPE
+    return hipErrorInvalidValue;
+}
+
+bool corr_shape_supported(int ty, int bb, int wy, int max_h) {
+    const bool listed = (ty == 4 && bb == 2 && wy == 4) || (ty == 2 && bb == 2 && wy == 4) ||
+                        (ty == 4 && bb == 1 && wy == 4);
+    if (!listed || max_h > CORR_MAX_H) return false;
+    return max_h <= 8 || (ty == 4 && bb == 2 && wy == 4);
 }
 
 hipError_t launch_corr(const CorrLaunch& cfg, const CorrTile* tiles, int n_tiles,
@@ -449,12 +498,10 @@ hipError_t launch_corr(const CorrLaunch& cfg, const CorrTile* tiles, int n_tiles
                        float* out, int* rkeys, int64_t n_slots, int max_h, int max_S,
                        hipStream_t st) {
     if (n_tiles <= 0) return hipSuccess;
-    if (max_h > CORR_MAX_H) return hipErrorInvalidValue;
-    if (cfg.ty != 4 || cfg.bb != 2 || cfg.wy != 4) return hipErrorInvalidValue;
+    if (!corr_shape_supported(cfg.ty, cfg.bb, cfg.wy, max_h)) return hipErrorInvalidValue;
     const int cb = cfg.pk.RP * cfg.pk.esz;
-    const int Q = cfg.pk.Q;
 #define DPMT_CORR(K, P) \
-    case P: return launch_corr_t<K, P, 4, 2, 4>(tiles, n_tiles, groups, Z, G, tk, out, rkeys, n_slots, cb, Q, max_h, max_S, st);
+    case P: return launch_corr_p<K, P>(cfg, tiles, n_tiles, groups, Z, G, tk, out, rkeys, n_slots, cb, max_h, max_S, st);
     if (cfg.kind == CORR_F32) {
         switch (cfg.pk.PB) { DPMT_CORR(CORR_F32, 16) DPMT_CORR(CORR_F32, 32) default: break; }
     } else if (cfg.kind == CORR_BF16) {

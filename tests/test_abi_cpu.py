@@ -192,3 +192,55 @@ def test_plan_layout_matches_definition():
         offs += lay.map_rows[k] * lay.map_cols[k] * len(comp.parts) * 2
     assert lay.n_score == off and lay.n_offsets == offs
     assert lay.n_cells == wl.total_cells
+
+
+def test_launch_strategy_and_tile_config_validation():
+    from paper_1707_03268_amd import tile_config_count, tile_config_name
+    lib = _abi.load()
+    n = tile_config_count()
+    assert n >= 2
+    names = [tile_config_name(i) for i in range(n)]
+    assert all(names) and len(set(names)) == n
+    assert tile_config_name(-1) is None and tile_config_name(n) is None
+    wl, fs, comps = _tiny_bank()
+    ctx = Context(device=-1)
+    ctx.load_filters(fs, comps)
+    for launch in ("batched", "per_level", "graph"):
+        ctx.set_launch(launch)
+    with pytest.raises(DpmtError) as e:
+        ctx.set_launch(3)
+    assert e.value.status == _abi.DPMT_E_INVALID
+    assert ctx.get_tile_config("tensor_bf16") == 0
+    ctx.set_tile_config("tensor_bf16", n - 1)
+    assert ctx.get_tile_config("tensor_bf16") == n - 1
+    for bad in (-1, n):
+        with pytest.raises(DpmtError) as e:
+            ctx.set_tile_config("tensor_bf16", bad)
+        assert e.value.status == _abi.DPMT_E_INVALID
+    assert lib.dpmt_get_tile_config(None, 0) == -1
+    # autotuning needs a device context
+    ctx.plan(wl.pyramids)
+    st = lib.dpmt_autotune(ctx._h, 0, ctypes.c_void_p(16), ctypes.c_void_p(16), None, 3, None, None, None)
+    assert st == _abi.DPMT_E_STATE
+    ctx.close()
+
+
+def test_tall_filters_restrict_tile_configs():
+    """Filters taller than 8 rows are supported by the default tile only."""
+    from paper_1707_03268_amd import tile_config_count
+    rng = np.random.default_rng(0)
+    fs = [rng.standard_normal((12, 5, 32)).astype(np.float32), rng.standard_normal((3, 3, 32)).astype(np.float32)]
+    comps = [workloads.Component(root=0, parts=[1], anchors=np.array([[0, 0]], np.int32),
+                                 deform=np.array([[0.05, 0.05, 0.05, 0.05]], np.float32))]
+    ctx = Context(device=-1)
+    ctx.load_filters(fs, comps)
+    ctx.set_tile_config("direct_fp32", 0)
+    rejected = 0
+    for cfg in range(1, tile_config_count()):
+        try:
+            ctx.set_tile_config("direct_fp32", cfg)
+        except DpmtError as e:
+            assert e.status == _abi.DPMT_E_UNSUPPORTED
+            rejected += 1
+    assert rejected >= 1
+    ctx.close()

@@ -298,6 +298,21 @@ def config5(n_frames: int = 256) -> Workload:
                     5, pyrs, bank, total, feature_seed(5), True, sizes)
 
 
+def uneven_batch(n_images: int = 3, n_classes: int = 2, size_lo=(160, 120),
+                 size_hi=(400, 300)) -> Workload:
+    """A small batch in the shape of the 64-image workload: images of uneven
+    sizes drawn uniformly from size_lo..size_hi (width, height), full padded
+    pyramids, n_classes class models drawn like the 20-class bank."""
+    rng = seed_rng(4, 3)
+    sizes = [(int(rng.integers(size_lo[0], size_hi[0] + 1)), int(rng.integers(size_lo[1], size_hi[1] + 1)))
+             for _ in range(n_images)]
+    pyrs, total = build_pyramids(sizes)
+    bank = build_bank(4, n_classes)
+    return Workload(f"uneven batch: {n_images} images {size_lo[0]}x{size_lo[1]}..{size_hi[0]}x{size_hi[1]}, "
+                    f"{n_classes} classes ({54 * n_classes} filters)", 4, pyrs, bank, total,
+                    feature_seed(4), True, sizes)
+
+
 PRESETS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}
 
 
