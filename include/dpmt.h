@@ -156,7 +156,7 @@ dpmt_status dpmt_decompose(dpmt_ctx* ctx, int32_t rank, double* sigma_out, doubl
 /* Plan a batch of n_images pyramids (host descriptors, copied): output layout,
  * work lists and device workspace.  *out points at the context-owned layout.
  * Limits (DPMT_E_UNSUPPORTED beyond them): level sides up to 16384 cells,
- * part response maps up to 2940 columns, and score maps whose placement
+ * part response maps up to 1976 columns, and score maps whose placement
  * working set (map height and part map height) fits one workgroup's 160 KB
  * of LDS, which holds part maps up to about 550 rows. */
 dpmt_status dpmt_plan(dpmt_ctx* ctx, int32_t n_images, const dpmt_pyramid* pyrs,

@@ -97,9 +97,12 @@ bool corr_shape_supported(int ty, int bb, int wy, int max_h);
 // of one score map; its LDS holds the score accumulator, the row-pass tile of
 // the current part with PLACE_PAD -inf rows above and below, a staging area
 // for response rows, and the two cost tables.
-constexpr int PLACE_CW = 32;
-constexpr int PLACE_PAD = 5;
-constexpr int PLACE_STAGE = 3072;         // floats of the staging buffer (32 rows of 96)
+constexpr int PLACE_CW = 16;
+constexpr int PLACE_RPW = 64 / PLACE_CW;  // rows per wavefront
+// -inf rows above and below the row-pass tile: a wavefront's column-pass
+// window clamp spans its PLACE_RPW target rows, plus 3 for the unroll by 4
+constexpr int PLACE_PAD = 2 * (PLACE_RPW - 1) + 3;
+constexpr int PLACE_STAGE = 2048;         // floats of the staging buffer (32 rows of 64)
 struct PlaceLds {
     int acc_rows;      // largest map height
     int r1_rows;       // largest part map height + 2 * PLACE_PAD

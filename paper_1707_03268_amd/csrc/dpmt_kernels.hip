@@ -944,7 +944,8 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
                                                     const int* __restrict__ rmin,
                                                     float* __restrict__ scores,
                                                     int16_t* __restrict__ offs, PlaceLds L) {
-    constexpr int CW = PLACE_CW, PAD = PLACE_PAD;
+    constexpr int CW = PLACE_CW, PAD = PLACE_PAD, RPW = PLACE_RPW;
+    constexpr int ROWS = 256 / CW;                         // row slots of the workgroup
     extern __shared__ __align__(16) float psm[];
     float* acc = psm;                                      // [acc_rows][CW]
     float* r1v = acc + L.acc_rows * CW;                    // [r1_rows][CW], row y' at y' + PAD
@@ -958,7 +959,7 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
     const int xs = bm.y * CW;
     const int ncol = min(CW, M.Wo - xs);
     const int tid = threadIdx.x;
-    const int w = tid >> 6, j = tid & 31, hr = (tid >> 5) & 1, rr = tid >> 5;
+    const int w = tid >> 6, j = tid % CW, rr = tid / CW, hr = rr % RPW;
 
     float4 pf[PLACE_LOADS];
     PlaceGeo G = place_geo(parts[M.part_base], M, xs, rmax, rmin, L.stage_words);
@@ -986,7 +987,7 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
                 if (more) place_load(G, resp, r + 1, pf);
                 else if (has_next && Gn.rounds > 0) place_load(Gn, resp, 0, pf);
                 const int yr = G.ry0 + r * G.RB;
-                for (int q = rr; q < G.RB; q += 8) {
+                for (int q = rr; q < G.RB; q += ROWS) {
                     const int y = yr + q;
                     if (y > G.ry1) break;
                     const float* SE = stage + q * 2 * G.SH + j;
@@ -1014,10 +1015,12 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
                 }
             }
             if (G.rounds == 0 && has_next && Gn.rounds > 0) place_load(Gn, resp, 0, pf);
-            // column pass: wave w takes root rows 8k + 2w and 8k + 2w + 1
-            for (int y0a = 2 * w; y0a < M.Ho; y0a += 8) {
+            // column pass: wave w takes RPW consecutive root rows of every ROWS;
+            // window offsets clamped so that every skipped candidate lies
+            // outside the map for all of them and every read stays in the pads
+            for (int y0a = RPW * w; y0a < M.Ho; y0a += ROWS) {
                 const int tya = 2 * y0a + G.vy;
-                const int ulw = max(G.vlo, -2 - tya), uhw = min(G.vhi, G.Hp - 1 - tya);
+                const int ulw = max(G.vlo, -2 * (RPW - 1) - tya), uhw = min(G.vhi, G.Hp - 1 - tya);
                 float best = -INFINITY;
                 int arg = 0;
                 if (ulw <= uhw) {
@@ -1054,7 +1057,7 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
         } else {
             // no target of this strip lies inside the part map
             if (has_next && Gn.rounds > 0) place_load(Gn, resp, 0, pf);
-            for (int y0a = 2 * w; y0a < M.Ho; y0a += 8) {
+            for (int y0a = RPW * w; y0a < M.Ho; y0a += ROWS) {
                 const int y0 = y0a + hr;
                 if (y0 < M.Ho && j < ncol) {
                     acc[y0 * CW + j] = -INFINITY;
@@ -1066,7 +1069,7 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
         __syncthreads();                                   // R1, tables and stage reused by the next part
         G = Gn;
     }
-    for (int y0a = 2 * w; y0a < M.Ho; y0a += 8) {
+    for (int y0a = RPW * w; y0a < M.Ho; y0a += ROWS) {
         const int y0 = y0a + hr;
         if (y0 < M.Ho && j < ncol)
             scores[M.score_off + (int64_t)y0 * M.Wo + xs + j] =
