@@ -977,6 +977,9 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
                     mp.vy = cm.anchors[sl][0];
                     mp.vx = cm.anchors[sl][1];
                     for (int t = 0; t < 4; ++t) mp.d[t] = cm.deform[sl][t];
+                    mp.inv2ax = (float)(0.5 / (double)mp.d[1]);
+                    mp.inv2ay = (float)(0.5 / (double)mp.d[3]);
+                    mp.bb4a = (float)((double)mp.d[0] * mp.d[0] / (4.0 * mp.d[1]));
                     if (Ho > 0 && Wo > 0) {
                         max_Hp = std::max(max_Hp, mp.Hp);
                         max_Wp = std::max(max_Wp, mp.Wp);

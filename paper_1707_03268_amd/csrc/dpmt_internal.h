@@ -63,6 +63,9 @@ struct MapPart {
     int32_t rng;       // range slot of the plane
     int32_t vy, vx;    // anchor (part-level cells)
     float d[4];        // d_x, d_xx, d_y, d_yy
+    float inv2ax;      // 1 / (2 d_xx)
+    float inv2ay;      // 1 / (2 d_yy)
+    float bb4a;        // d_x^2 / (4 d_xx): how far a row-pass value can exceed the response maximum
     int32_t pad;
 };
 

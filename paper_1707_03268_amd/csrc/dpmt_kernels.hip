@@ -817,10 +817,19 @@ size_t place_lds_bytes(const PlaceLds& l) {
 }
 
 constexpr int PLACE_LOADS = PLACE_STAGE / 1024;        // staged float4 per thread and round
-constexpr int PLACE_RB = 32;                           // most response rows per round
+
+// Window of a line from its value range with the reciprocal 1/(2a) given;
+// the hardware square root is within a few ulp, which the 1-cell margins of
+// the bound absorb (as in line_window).
+__device__ __forceinline__ void line_window_r(float a, float b, float inv2a, float range, int n,
+                                              int& ulo, int& uhi) {
+    const float s = __builtin_amdgcn_sqrtf(fmaf(4.f * a, fmaxf(range, 0.f), b * b));
+    ulo = (int)fmaxf(floorf((-b - s) * inv2a) - 1.f, -(float)n);
+    uhi = (int)fminf(ceilf((-b + s) * inv2a) + 1.f, (float)n);
+}
 
 // Geometry of one part inside a placement block; every thread computes the
-// same values.
+// same values, without divisions.
 struct PlaceGeo {
     int64_t plane;
     int ld, Hp, Wp, vy;
@@ -828,12 +837,12 @@ struct PlaceGeo {
     int tx0;            // target column of lane 0
     int ulo, Wr, Wq;    // row window (clamped to the strip, start aligned), length, rounded to 4
     int vlo, vhi, Wc;   // column window (clamped to the map +- 1 row) and its length
-    int CH, SH, RB;     // staged float4 per row, floats per parity half-row, rows per round
+    int CH, SH;         // staged float4 per row, floats per parity half-row
+    int lrb, RB;        // rows per round RB = 2^lrb
     int ry0, ry1, rounds;
     int X0;             // first staged column (multiple of 4)
     int nq;             // float4 loads per thread and round
-    int lrow, lcol;     // this thread's first staged (row, float4) of a round
-    int drow, dcol;     // step of the flat index by 256 threads
+    int lrow, lcol, tpr;// this thread's staged row and first float4; threads per row
     int live;
 };
 
@@ -855,57 +864,48 @@ __device__ __forceinline__ PlaceGeo place_geo(const MapPart& P, const MapDesc& M
     const float range = hi >= lo ? hi - lo : 0.f;
     G.tx0 = 2 * xs + P.vx;
     int ulo, uhi;
-    line_window(G.ax, G.bx, range, P.Wp, ulo, uhi);
+    line_window_r(G.ax, G.bx, P.inv2ax, range, P.Wp, ulo, uhi);
     ulo = max(ulo, -(G.tx0 + 2 * (CW - 1)));              // beyond: left of every map column
     uhi = min(uhi, P.Wp - 1 - G.tx0);                     // beyond: right of every map column
     ulo -= (G.tx0 + ulo) & 3;                             // staged rows start 16-byte aligned
     G.ulo = ulo;
     G.Wr = uhi - ulo + 1;
     G.Wq = (G.Wr + 3) & ~3;
-    line_window(G.ay, G.by, range + G.bx * G.bx / (4.f * G.ax), P.Hp, G.vlo, G.vhi);
+    line_window_r(G.ay, G.by, P.inv2ay, range + P.bb4a, P.Hp, G.vlo, G.vhi);
     G.vlo = max(G.vlo, -(P.Hp + 1));
     G.vhi = min(G.vhi, P.Hp + 1);
     G.Wc = G.vhi - G.vlo + 1;
     G.live = P.Hp > 0 && P.Wp > 0 && G.Wr > 0;
     G.CH = (2 * (CW - 1) + G.Wq + 3) >> 2;
     G.SH = 2 * G.CH;
-    int RB = PLACE_RB;
-    while (RB > 1 && RB * 2 * G.SH > stage_words) RB >>= 1;
-    G.RB = RB;
+    int lrb = 5;                                          // up to 32 rows per round
+    while (lrb > 0 && (2 * G.SH << lrb) > stage_words) --lrb;
+    G.lrb = lrb;
+    G.RB = 1 << lrb;
     G.ry0 = max(0, P.vy + G.vlo);
     G.ry1 = min(P.Hp - 1, 2 * (M.Ho - 1) + P.vy + G.vhi);
-    G.rounds = (G.live && G.ry1 >= G.ry0) ? (G.ry1 - G.ry0 + RB) / RB : 0;
+    G.rounds = (G.live && G.ry1 >= G.ry0) ? (G.ry1 - G.ry0 + G.RB) >> lrb : 0;
     G.X0 = G.tx0 + ulo;
-    G.nq = (RB * G.CH + 255) / 256;
-    G.lrow = threadIdx.x / G.CH;
-    G.lcol = threadIdx.x - G.lrow * G.CH;
-    G.drow = 256 / G.CH;
-    G.dcol = 256 - G.drow * G.CH;
+    G.tpr = 256 >> lrb;
+    G.nq = (G.CH + G.tpr - 1) >> (8 - lrb);               // <= PLACE_LOADS since RB * CH <= 512
+    G.lrow = (int)threadIdx.x >> (8 - lrb);
+    G.lcol = (int)threadIdx.x & (G.tpr - 1);
     return G;
 }
 
-// Loads of one round of staged response rows into registers: flat index
-// i = tid + 256 q over [rows of the round][CH float4 runs].  Every load is
-// issued at a clamped, aligned address with nothing depending on it until the
-// store, so that all of them are in flight together; out-of-map columns are
-// masked at the store (a clamped run lies wholly outside the map).
+// Loads of one round of staged response rows into registers: thread (row
+// lrow, float4 runs lcol + q * tpr).  Every load is issued at a clamped,
+// aligned address with nothing depending on it until the store, so that all
+// of them are in flight together; out-of-map columns are masked at the store
+// (a clamped run lies wholly outside the map).
 __device__ __forceinline__ void place_load(const PlaceGeo& G, const float* __restrict__ resp,
                                            int round, float4 (&pf)[PLACE_LOADS]) {
-    const int y0 = G.ry0 + round * G.RB;
-    const int last = min(G.RB, G.ry1 - y0 + 1) - 1;       // last row of the round
-    const float* base = resp + G.plane + (int64_t)y0 * G.ld;
-    int row = G.lrow, col = G.lcol;
+    const int y = min(G.ry0 + (round << G.lrb) + G.lrow, G.ry1);
+    const float* base = resp + G.plane + (int64_t)y * G.ld;
 #pragma unroll
     for (int q = 0; q < PLACE_LOADS; ++q) {
-        const int x = G.X0 + 4 * col;
-        const int xc = min(max(x, 0), G.ld - 4);
-        pf[q] = *reinterpret_cast<const float4*>(base + min(row, last) * G.ld + xc);
-        col += G.dcol;
-        row += G.drow;
-        if (col >= G.CH) {
-            col -= G.CH;
-            ++row;
-        }
+        const int x = G.X0 + 4 * (G.lcol + q * G.tpr);
+        pf[q] = *reinterpret_cast<const float4*>(base + min(max(x, 0), G.ld - 4));
     }
 }
 
@@ -913,25 +913,20 @@ __device__ __forceinline__ void place_load(const PlaceGeo& G, const float* __res
 // run x, x+1, x+2, x+3 (x even) goes to even[x/2 .. x/2+1], odd[x/2 .. x/2+1].
 __device__ __forceinline__ void place_store(const PlaceGeo& G, float* stage,
                                             const float4 (&pf)[PLACE_LOADS]) {
-    int row = G.lrow, col = G.lcol;
+    if (G.lrow >= G.RB) return;
 #pragma unroll
     for (int q = 0; q < PLACE_LOADS; ++q) {
-        if (q < G.nq && row < G.RB) {
-            const int x = G.X0 + 4 * col;
+        const int c = G.lcol + q * G.tpr;
+        if (q < G.nq && c < G.CH) {
+            const int x = G.X0 + 4 * c;
             const float4 v = pf[q];
             const float v0 = (unsigned)x < (unsigned)G.Wp ? v.x : -INFINITY;
             const float v1 = (unsigned)(x + 1) < (unsigned)G.Wp ? v.y : -INFINITY;
             const float v2 = (unsigned)(x + 2) < (unsigned)G.Wp ? v.z : -INFINITY;
             const float v3 = (unsigned)(x + 3) < (unsigned)G.Wp ? v.w : -INFINITY;
-            float* even = stage + row * 2 * G.SH + 2 * col;
+            float* even = stage + G.lrow * 2 * G.SH + 2 * c;
             *reinterpret_cast<float2*>(even) = make_float2(v0, v2);
             *reinterpret_cast<float2*>(even + G.SH) = make_float2(v1, v3);
-        }
-        col += G.dcol;
-        row += G.drow;
-        if (col >= G.CH) {
-            col -= G.CH;
-            ++row;
         }
     }
 }
@@ -959,7 +954,8 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
     const int xs = bm.y * CW;
     const int ncol = min(CW, M.Wo - xs);
     const int tid = threadIdx.x;
-    const int w = tid >> 6, j = tid % CW, rr = tid / CW, hr = rr % RPW;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);    // wavefront-uniform
+    const int j = tid % CW, rr = tid / CW, hr = rr % RPW;
 
     float4 pf[PLACE_LOADS];
     PlaceGeo G = place_geo(parts[M.part_base], M, xs, rmax, rmin, L.stage_words);
@@ -986,23 +982,30 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
                 const bool more = r + 1 < G.rounds;
                 if (more) place_load(G, resp, r + 1, pf);
                 else if (has_next && Gn.rounds > 0) place_load(Gn, resp, 0, pf);
-                const int yr = G.ry0 + r * G.RB;
+                const int yr = G.ry0 + (r << G.lrb);
                 for (int q = rr; q < G.RB; q += ROWS) {
                     const int y = yr + q;
                     if (y > G.ry1) break;
                     const float* SE = stage + q * 2 * G.SH + j;
                     const float* SO = SE + G.SH;
+                    // running maximum per group of 4 offsets; the first group
+                    // that reaches the maximum holds the smallest maximiser
                     float best = -INFINITY;
-                    int arg = 0;
+                    int garg = 0;
                     for (int e = 0; e < G.Wq; e += 4) {
                         const int k = e >> 1;
                         const float4 c = *reinterpret_cast<const float4*>(crow + e);
                         const float v0 = SE[k] - c.x, v1 = SO[k] - c.y;
                         const float v2 = SE[k + 1] - c.z, v3 = SO[k + 1] - c.w;
-                        if (v0 > best) { best = v0; arg = e; }
-                        if (v1 > best) { best = v1; arg = e + 1; }
-                        if (v2 > best) { best = v2; arg = e + 2; }
-                        if (v3 > best) { best = v3; arg = e + 3; }
+                        const float m = fmaxf(fmaxf(v0, v1), fmaxf(v2, v3));
+                        if (m > best) { best = m; garg = e; }
+                    }
+                    int arg;
+                    {   // recompute the winning group: its first offset equal to the maximum
+                        const int k = garg >> 1;
+                        const float4 c = *reinterpret_cast<const float4*>(crow + garg);
+                        const float v0 = SE[k] - c.x, v1 = SO[k] - c.y, v2 = SE[k + 1] - c.z;
+                        arg = v0 == best ? garg : v1 == best ? garg + 1 : v2 == best ? garg + 2 : garg + 3;
                     }
                     const bool ok = G.tx0 + 2 * j < G.Wp;
                     r1v[(y + PAD) * CW + j] = ok ? best : -INFINITY;
@@ -1026,16 +1029,19 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
                 if (ulw <= uhw) {
                     const int e0 = (ulw - G.vlo) & ~3, e1 = uhw - G.vlo;
                     const float* col = r1v + (tya + 2 * hr + G.vlo + PAD) * CW + j;
+                    int garg = e0;
                     for (int e = e0; e <= e1; e += 4) {
                         const float4 c = *reinterpret_cast<const float4*>(ccol + e);
                         const float* q = col + e * CW;
                         const float v0 = q[0] - c.x, v1 = q[CW] - c.y;
                         const float v2 = q[2 * CW] - c.z, v3 = q[3 * CW] - c.w;
-                        if (v0 > best) { best = v0; arg = e; }
-                        if (v1 > best) { best = v1; arg = e + 1; }
-                        if (v2 > best) { best = v2; arg = e + 2; }
-                        if (v3 > best) { best = v3; arg = e + 3; }
+                        const float m = fmaxf(fmaxf(v0, v1), fmaxf(v2, v3));
+                        if (m > best) { best = m; garg = e; }
                     }
+                    const float4 c = *reinterpret_cast<const float4*>(ccol + garg);
+                    const float* q = col + garg * CW;
+                    const float v0 = q[0] - c.x, v1 = q[CW] - c.y, v2 = q[2 * CW] - c.z;
+                    arg = v0 == best ? garg : v1 == best ? garg + 1 : v2 == best ? garg + 2 : garg + 3;
                 }
                 const int y0 = y0a + hr;
                 if (y0 < M.Ho && j < ncol) {
