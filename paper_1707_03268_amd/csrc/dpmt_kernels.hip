@@ -160,7 +160,10 @@ __device__ __forceinline__ typename FragT<KIND>::type lds_frag(const char* p, in
     }
 }
 
-template <CorrKind KIND, int PB, int TY, int BB, int WY, int HMAX>
+// HS > 0: the tile's filters have exactly HS rows, and the filter-row loop is
+// fully unrolled over a static ring of A fragments (no register rotation, exact
+// LDS waits); HS = 0: any height up to HMAX with a rolled loop.
+template <CorrKind KIND, int PB, int TY, int BB, int WY, int HMAX, int HS>
 __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __restrict__ groups,
                                           const char* __restrict__ Z, const char* __restrict__ G,
                                           const float* __restrict__ tk, float* __restrict__ out,
@@ -178,7 +181,7 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
     constexpr int WBATCH = 4;                      // window loads in flight per thread
 
     const GroupDesc g = groups[t.group];
-    const int h = g.h, S = g.S;
+    const int h = HS > 0 ? HS : g.h, S = g.S;
     const int WC = 31 + (KS * S) / PB;             // window cells per row
     const int pitch = WC * PB;
     const int nrows = TYWG + h - 1;
@@ -301,7 +304,30 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
         const u32x4* gb = (step & 1) ? gbuf1 : gbuf0;
         const char* abase = win + (wv * TY) * pitch + p * PB + KS * s + FB * j;
         const char* gbb = reinterpret_cast<const char*>(gb) + lane * FB;
-        {
+        if constexpr (HS > 0) {
+            // window row n + i feeds output row i at filter row n; the TY live
+            // rows and the one being fetched sit in ring slots (row % (TY + 1))
+            Frag Ar[TY + 1];
+            Frag Br[2][BB];
+#pragma unroll
+            for (int i = 0; i < TY; ++i) Ar[i] = lds_frag<KIND>(abase + i * pitch, PB);
+#pragma unroll
+            for (int b = 0; b < BB; ++b) Br[0][b] = *reinterpret_cast<const Frag*>(gbb + (b * HS) * chunk_bytes);
+#pragma unroll
+            for (int n = 0; n < HS; ++n) {
+                if (n + 1 < HS) {
+#pragma unroll
+                    for (int b = 0; b < BB; ++b)
+                        Br[(n + 1) & 1][b] = *reinterpret_cast<const Frag*>(gbb + (b * HS + n + 1) * chunk_bytes);
+                    Ar[(n + TY) % (TY + 1)] = lds_frag<KIND>(abase + (n + TY) * pitch, PB);
+                }
+#pragma unroll
+                for (int i = 0; i < TY; ++i)
+#pragma unroll
+                    for (int b = 0; b < BB; ++b)
+                        acc[i][b] = mfma_step<KIND>(Ar[(n + i) % (TY + 1)], Br[n & 1][b], acc[i][b]);
+            }
+        } else {
             Frag A[TY];
 #pragma unroll
             for (int i = 0; i < TY; ++i) A[i] = lds_frag<KIND>(abase + i * pitch, PB);
@@ -405,8 +431,19 @@ __global__ __launch_bounds__(64 * WY) __attribute__((amdgpu_waves_per_eu((HMAX <
                                                        int Q, int win_bytes) {
     for (int i = blockIdx.x; i < n_tiles; i += gridDim.x) {
         const CorrTile t = tiles[i];
-        corr_tile<KIND, PB, TY, BB, WY, HMAX>(t, groups, Z, G, tk, out, rmax, rmin, cell_bytes, Q,
-                                              win_bytes);
+        const int h = groups[t.group].h;
+        // the DPM filter heights get unrolled bodies where that costs no
+        // occupancy (FP8 fragments and 64-filter tiles of 32-byte planes would
+        // need too many registers)
+        constexpr bool UNROLL = KIND != CORR_FP8 && HMAX >= 8 && !(PB == 32 && BB == 2);
+        if (UNROLL && h == 6)
+            corr_tile<KIND, PB, TY, BB, WY, HMAX, 6>(t, groups, Z, G, tk, out, rmax, rmin, cell_bytes, Q, win_bytes);
+        else if (UNROLL && h == 7)
+            corr_tile<KIND, PB, TY, BB, WY, HMAX, 7>(t, groups, Z, G, tk, out, rmax, rmin, cell_bytes, Q, win_bytes);
+        else if (UNROLL && h == 8)
+            corr_tile<KIND, PB, TY, BB, WY, HMAX, 8>(t, groups, Z, G, tk, out, rmax, rmin, cell_bytes, Q, win_bytes);
+        else
+            corr_tile<KIND, PB, TY, BB, WY, HMAX, 0>(t, groups, Z, G, tk, out, rmax, rmin, cell_bytes, Q, win_bytes);
         if (i + (int)gridDim.x < n_tiles) __syncthreads();   // LDS reused by the next tile
     }
 }
