@@ -24,14 +24,18 @@ thread_local std::string g_free_error;   // errors of calls without a context
 // them accumulate every response in the same order, so they give equal bits.
 struct TileCfg {
     int ty, bb, wy, persistent;
+    int nfb;           // groups of bb filter blocks a tile walks over one window
     const char* name;
 };
 constexpr TileCfg TILE_CFGS[] = {
-    {4, 2, 4, 0, "16 rows x 32 cols x 64 filters, 256 threads, one workgroup per tile"},
-    {4, 2, 4, 1, "16 rows x 32 cols x 64 filters, 256 threads, resident grid"},
-    {2, 2, 4, 0, "8 rows x 32 cols x 64 filters, 256 threads, one workgroup per tile"},
-    {4, 1, 4, 0, "16 rows x 32 cols x 32 filters, 256 threads, one workgroup per tile"},
-    {2, 2, 4, 1, "8 rows x 32 cols x 64 filters, 256 threads, resident grid"},
+    {4, 2, 4, 0, 1, "16 rows x 32 cols x 64 filters, 256 threads, one workgroup per tile"},
+    {4, 2, 4, 1, 1, "16 rows x 32 cols x 64 filters, 256 threads, resident grid"},
+    {2, 2, 4, 0, 1, "8 rows x 32 cols x 64 filters, 256 threads, one workgroup per tile"},
+    {4, 1, 4, 0, 1, "16 rows x 32 cols x 32 filters, 256 threads, one workgroup per tile"},
+    {2, 2, 4, 1, 1, "8 rows x 32 cols x 64 filters, 256 threads, resident grid"},
+    {4, 1, 4, 0, 6, "16 rows x 32 cols x 6 x 32 filters over one window, 256 threads"},
+    {4, 1, 4, 0, 3, "16 rows x 32 cols x 3 x 32 filters over one window, 256 threads"},
+    {4, 2, 4, 0, 3, "16 rows x 32 cols x 3 x 64 filters over one window, 256 threads"},
 };
 constexpr int N_TILE_CFGS = (int)(sizeof(TILE_CFGS) / sizeof(TILE_CFGS[0]));
 constexpr int MAX_BB = 2;                 // most filter blocks per tile over TILE_CFGS
@@ -71,7 +75,7 @@ struct ModeData {
         int n_tiles = 0;
         std::vector<std::array<int, 4>> lvl;   // (image, level, begin, end)
     };
-    std::map<std::pair<int, int>, TileSet> tilesets;
+    std::map<std::array<int, 3>, TileSet> tilesets;
 };
 
 void free_tilesets(ModeData& m);
@@ -516,13 +520,13 @@ void build_groups(dpmt_ctx* c) {
 }
 
 void add_tiles(std::vector<CorrTile>& tiles, const GroupDesc& gd, int group, int64_t z_cell,
-               int64_t out_off, int rng, int H, int W, int rows, int bb) {
+               int64_t out_off, int rng, int H, int W, int rows, int bb, int nfb) {
     const int Ho = H - gd.h + 1, Wo = W - gd.w + 1;
     if (Ho <= 0 || Wo <= 0) return;
     const int nblk = (gd.ng + 31) / 32;
     for (int y0 = 0; y0 < Ho; y0 += rows)
         for (int x0 = 0; x0 < Wo; x0 += 32)
-            for (int fb = 0; fb < nblk; fb += bb) {
+            for (int fb = 0; fb < nblk; fb += bb * nfb) {
                 CorrTile t{};
                 t.z_cell = z_cell;
                 t.out_off = out_off;
@@ -536,6 +540,7 @@ void add_tiles(std::vector<CorrTile>& tiles, const GroupDesc& gd, int group, int
                 t.x0 = x0;
                 t.fb0 = fb;
                 t.group = group;
+                t.nfb = std::min(nfb, (nblk - fb + bb - 1) / bb);
                 tiles.push_back(t);
             }
 }
@@ -544,7 +549,7 @@ void add_tiles(std::vector<CorrTile>& tiles, const GroupDesc& gd, int group, int
 dpmt_status prepare_tiles(dpmt_ctx* c, dpmt_mode mode, ModeData::TileSet** out) {
     ModeData& md = c->modes[mode];
     const TileCfg& tc = TILE_CFGS[md.tile_cfg];
-    const std::pair<int, int> key{tc.ty * tc.wy, tc.bb};
+    const std::array<int, 3> key{tc.ty * tc.wy, tc.bb, tc.nfb};
     ModeData::TileSet& ts = md.tilesets[key];
     *out = &ts;
     if (ts.plan_id == c->plan_id && (ts.dTiles || ts.n_tiles == 0)) return DPMT_OK;
@@ -557,7 +562,7 @@ dpmt_status prepare_tiles(dpmt_ctx* c, dpmt_mode mode, ModeData::TileSet** out) 
         const LevelInfo& lv = c->pyr[k.img][k.level];
         const size_t b0 = tiles.size();
         add_tiles(tiles, md.groups[k.group], k.group, lv.cell_offset, kv.second.off,
-                  (int)kv.second.rng, lv.rows, lv.cols, key.first, key.second);
+                  (int)kv.second.rng, lv.rows, lv.cols, key[0], key[1], key[2]);
         if (tiles.size() == b0) continue;
         if (!ts.lvl.empty() && ts.lvl.back()[0] == k.img && ts.lvl.back()[1] == k.level)
             ts.lvl.back()[3] = (int)tiles.size();
@@ -617,7 +622,7 @@ dpmt_status score_prepare(dpmt_ctx* c, dpmt_mode mode, hipStream_t st) {
 ModeData::TileSet& current_tiles(dpmt_ctx* c, dpmt_mode mode) {
     ModeData& md = c->modes[mode];
     const TileCfg& tc = TILE_CFGS[md.tile_cfg];
-    return md.tilesets[{tc.ty * tc.wy, tc.bb}];
+    return md.tilesets[{tc.ty * tc.wy, tc.bb, tc.nfb}];
 }
 
 CorrLaunch corr_launch(const ModeData& md) {
@@ -1311,7 +1316,7 @@ dpmt_status dpmt_level_responses(dpmt_ctx* c, dpmt_mode mode, const float* featu
         const GroupDesc& gd = md.groups[g];
         const int Ho = lv.rows - gd.h + 1, Wo = lv.cols - gd.w + 1;
         if (Ho <= 0 || Wo <= 0) continue;
-        add_tiles(tiles, gd, (int)g, 0, blk_total, -1, lv.rows, lv.cols, 16, 2);
+        add_tiles(tiles, gd, (int)g, 0, blk_total, -1, lv.rows, lv.cols, 16, 2, 1);
         gblocks.push_back({(int)g, blk_total, Ho, Wo, pitch_of(Wo)});
         blk_total += (int64_t)Ho * pitch_of(Wo) * gd.ng;
         max_h = std::max(max_h, gd.h);

@@ -41,7 +41,7 @@ struct RequantBlock {
 };
 
 // One workgroup tile of the correlation: TYWG output rows x 32 output cols x
-// (BB * 32) filters of one group on one level.
+// nfb * BB * 32 filters of one group on one level (BB * 32 at a time).
 struct CorrTile {
     int64_t z_cell;    // first cell of the level in the feature / projected buffer
     int64_t out_off;   // element offset of the group's first response plane on this level
@@ -52,6 +52,8 @@ struct CorrTile {
     int32_t y0, x0;    // first output row, col
     int32_t fb0;       // first 32-filter block
     int32_t group;
+    int32_t nfb;       // groups of BB filter blocks the tile walks over the same window
+    int32_t pad;
 };
 
 // One part of one score map: where its response plane lives, its anchor and

@@ -160,6 +160,67 @@ __device__ __forceinline__ typename FragT<KIND>::type lds_frag(const char* p, in
     }
 }
 
+// Epilogue of one group of BB filter blocks (first block fbb): lane holds
+// filter column p, positions x0 + 8*(k/4) + 4*j + k%4, i.e. four runs of 4
+// consecutive positions stored as 16-byte vectors into the filter's plane (the
+// pitch is a multiple of 4, so a run that starts inside the map ends inside
+// the pitch).  The value range of every plane over its valid positions goes to
+// the range slots.
+template <CorrKind KIND, int TY, int BB, int WY>
+__device__ __forceinline__ void corr_epilogue(const CorrTile& t, const GroupDesc& g, int fbb,
+                                              const v16f (&acc)[TY][BB],
+                                              const float* __restrict__ tk, float* __restrict__ out,
+                                              int* __restrict__ rmax, int* __restrict__ rmin) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int p = lane & 31, j = lane >> 5;
+    float vmax[BB], vmin[BB];
+#pragma unroll
+    for (int b = 0; b < BB; ++b) {
+        vmax[b] = -INFINITY;
+        vmin[b] = INFINITY;
+    }
+#pragma unroll
+    for (int i = 0; i < TY; ++i) {
+        const int y = t.y0 + wv * TY + i;
+        if (y >= t.Ho) continue;
+#pragma unroll
+        for (int b = 0; b < BB; ++b) {
+            const int f = (fbb + b) * 32 + p;
+            if (f >= g.ng) continue;
+            float* orow = out + t.out_off + ((int64_t)f * t.Ho + y) * t.ld + t.x0 + 4 * j;
+            const float sc = (KIND == CORR_FP8) ? tk[g.t_off + f] : 1.f;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int x = t.x0 + 8 * m + 4 * j;
+                if (x >= t.Wo) continue;
+                float4 v;
+                v.x = acc[i][b][4 * m + 0] * sc;
+                v.y = acc[i][b][4 * m + 1] * sc;
+                v.z = acc[i][b][4 * m + 2] * sc;
+                v.w = acc[i][b][4 * m + 3] * sc;
+                *reinterpret_cast<float4*>(orow + 8 * m) = v;
+                vmax[b] = fmaxf(vmax[b], v.x);
+                vmin[b] = fminf(vmin[b], v.x);
+                if (x + 1 < t.Wo) { vmax[b] = fmaxf(vmax[b], v.y); vmin[b] = fminf(vmin[b], v.y); }
+                if (x + 2 < t.Wo) { vmax[b] = fmaxf(vmax[b], v.z); vmin[b] = fminf(vmin[b], v.z); }
+                if (x + 3 < t.Wo) { vmax[b] = fmaxf(vmax[b], v.w); vmin[b] = fminf(vmin[b], v.w); }
+            }
+        }
+    }
+    if (rmax != nullptr && t.rng >= 0) {
+#pragma unroll
+        for (int b = 0; b < BB; ++b) {
+            const float hi = fmaxf(vmax[b], __shfl_xor(vmax[b], 32, 64));
+            const float lo = fminf(vmin[b], __shfl_xor(vmin[b], 32, 64));
+            const int f = (fbb + b) * 32 + p;
+            if (j == 0 && f < g.ng && hi >= lo) {
+                atomicMax(rmax + t.rng + f, range_key(hi));
+                atomicMin(rmin + t.rng + f, range_key(lo));
+            }
+        }
+    }
+}
+
 // HS > 0: the tile's filters have exactly HS rows, and the filter-row loop is
 // fully unrolled over a static ring of A fragments (no register rotation, exact
 // LDS waits); HS = 0: any height up to HMAX with a rolled loop.
@@ -243,9 +304,15 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
         for (int k = 0; k < PFMAX; ++k) gbuf0[pf_dst[k]] = pf[k];
     }
 
-    for (int step = 0; step < total; ++step) {
+    // The tile walks t.nfb groups of BB filter blocks over the same window:
+    // global step gs = (group fbi, step st); the window of plane q is loaded
+    // at the first group only when the level has one plane.  Each group ends
+    // with its epilogue, whose stores drain while the next group computes.
+    const int nsteps = t.nfb * total;
+    int step = 0, fbi = 0;
+    for (int gs = 0; gs < nsteps; ++gs) {
         const int q = step / S, s = step - q * S;
-        if (s == 0) {
+        if (s == 0 && (fbi == 0 || Q > 1)) {
             __syncthreads();                       // previous plane fully consumed
             if (cpr <= NT) {
                 for (int rb = 0; rb < nrows; rb += WBATCH * rpp) {
@@ -296,12 +363,18 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
         // issue the loads of the next chunk before this step's MFMAs (the last
         // step reloads its own chunk and does not store it)
         u32x4 pf[PFMAX];
-        const bool more = step + 1 < total;
-        const int nstep = more ? step + 1 : step;
+        const bool more = gs + 1 < nsteps;
+        int nstep = step + 1, nfbi = fbi;
+        if (nstep == total) {
+            nstep = 0;
+            ++nfbi;
+        }
+        const int cur = fbi * BB * total + step;       // chunk index within the tile's blocks
+        const int nxt = more ? nfbi * BB * total + nstep : cur;
 #pragma unroll
-        for (int k = 0; k < PFMAX; ++k) pf[k] = chunk_ld(nstep, k);
+        for (int k = 0; k < PFMAX; ++k) pf[k] = chunk_ld(nxt, k);
 
-        const u32x4* gb = (step & 1) ? gbuf1 : gbuf0;
+        const u32x4* gb = (gs & 1) ? gbuf1 : gbuf0;
         const char* abase = win + (wv * TY) * pitch + p * PB + KS * s + FB * j;
         const char* gbb = reinterpret_cast<const char*>(gb) + lane * FB;
         if constexpr (HS > 0) {
@@ -358,63 +431,23 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
         }
 
         if (more) {
-            u32x4* nb = (step & 1) ? gbuf0 : gbuf1;
+            u32x4* nb = (gs & 1) ? gbuf0 : gbuf1;
 #pragma unroll
             for (int k = 0; k < PFMAX; ++k) nb[pf_dst[k]] = pf[k];
         }
+        if (step == total - 1) {
+            corr_epilogue<KIND, TY, BB, WY>(t, g, t.fb0 + fbi * BB, acc, tk, out, rmax, rmin);
+#pragma unroll
+            for (int i = 0; i < TY; ++i)
+#pragma unroll
+                for (int b = 0; b < BB; ++b)
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) acc[i][b][k] = 0.f;
+        }
+        step = nstep;
+        fbi = nfbi;
     }
 
-    // epilogue: lane holds filter column p, positions x0 + 8*(k/4) + 4*j + k%4,
-    // i.e. four runs of 4 consecutive positions stored as 16-byte vectors into
-    // the filter's plane (the pitch is a multiple of 4, so a run that starts
-    // inside the map ends inside the pitch).  The value range of every plane
-    // over its valid positions goes to the range slots.
-    float vmax[BB], vmin[BB];
-#pragma unroll
-    for (int b = 0; b < BB; ++b) {
-        vmax[b] = -INFINITY;
-        vmin[b] = INFINITY;
-    }
-#pragma unroll
-    for (int i = 0; i < TY; ++i) {
-        const int y = t.y0 + wv * TY + i;
-        if (y >= t.Ho) continue;
-#pragma unroll
-        for (int b = 0; b < BB; ++b) {
-            const int f = (t.fb0 + b) * 32 + p;
-            if (f >= g.ng) continue;
-            float* orow = out + t.out_off + ((int64_t)f * t.Ho + y) * t.ld + t.x0 + 4 * j;
-            const float sc = (KIND == CORR_FP8) ? tk[g.t_off + f] : 1.f;
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const int x = t.x0 + 8 * m + 4 * j;
-                if (x >= t.Wo) continue;
-                float4 v;
-                v.x = acc[i][b][4 * m + 0] * sc;
-                v.y = acc[i][b][4 * m + 1] * sc;
-                v.z = acc[i][b][4 * m + 2] * sc;
-                v.w = acc[i][b][4 * m + 3] * sc;
-                *reinterpret_cast<float4*>(orow + 8 * m) = v;
-                vmax[b] = fmaxf(vmax[b], v.x);
-                vmin[b] = fminf(vmin[b], v.x);
-                if (x + 1 < t.Wo) { vmax[b] = fmaxf(vmax[b], v.y); vmin[b] = fminf(vmin[b], v.y); }
-                if (x + 2 < t.Wo) { vmax[b] = fmaxf(vmax[b], v.z); vmin[b] = fminf(vmin[b], v.z); }
-                if (x + 3 < t.Wo) { vmax[b] = fmaxf(vmax[b], v.w); vmin[b] = fminf(vmin[b], v.w); }
-            }
-        }
-    }
-    if (rmax != nullptr && t.rng >= 0) {
-#pragma unroll
-        for (int b = 0; b < BB; ++b) {
-            const float hi = fmaxf(vmax[b], __shfl_xor(vmax[b], 32, 64));
-            const float lo = fminf(vmin[b], __shfl_xor(vmin[b], 32, 64));
-            const int f = (t.fb0 + b) * 32 + p;
-            if (j == 0 && f < g.ng && hi >= lo) {
-                atomicMax(rmax + t.rng + f, range_key(hi));
-                atomicMin(rmin + t.rng + f, range_key(lo));
-            }
-        }
-    }
 }
 
 // One workgroup per tile (grid = tiles), or a persistent grid that strides
