@@ -218,11 +218,12 @@ def main() -> None:
     ap.add_argument("--rank", type=int, default=16)
     ap.add_argument("--no-direct", action="store_true", help="skip the direct FP32 comparison run")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work (0: skip)")
-    ap.add_argument("--launch", default="batched", choices=["batched", "per_level", "graph"],
+    ap.add_argument("--launch", default="batched", choices=["batched", "per_level", "graph", "overlap"],
                     help="launch strategy of the timed steps")
     ap.add_argument("--compare-launch", action="store_true",
                     help="also time every launch strategy (batched, per level, graph)")
-    ap.add_argument("--autotune", action="store_true", help="pick the correlation tile configuration by timing")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="keep the default correlation tile configuration instead of timing them all")
     ap.add_argument("--tile-config", type=int, default=None, help="correlation tile configuration index")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device to device three times (a known-size copy kernel "
@@ -284,7 +285,7 @@ def main() -> None:
     launches = None
     if args.compare_launch:
         launches = {}
-        for launch in ("batched", "per_level", "graph"):
+        for launch in ("batched", "per_level", "graph", "overlap"):
             lms, _, lpct, _, _ = run_mode(ctx, args.mode, feats, max(2, min(args.steps, 10)), 1,
                                           torch, launch=launch)
             launches[launch] = {"ms_per_step": lms, "resp_per_s": lay.n_resp / (lms * 1e-3), **lpct}

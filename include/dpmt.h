@@ -72,9 +72,13 @@ typedef enum {
     DPMT_LAUNCH_PER_LEVEL = 1,/* projection and correlation launched per (image, level),
                                  placement per (image, root level): the reference for
                                  what batching saves                                     */
-    DPMT_LAUNCH_GRAPH = 2     /* the batched launches captured once into a HIP graph and
+    DPMT_LAUNCH_GRAPH = 2,    /* the batched launches captured once into a HIP graph and
                                  replayed; re-captured when the mode, plan, tile
                                  configuration or a device pointer changes               */
+    DPMT_LAUNCH_OVERLAP = 3   /* (image, root level) dependency groups cut into chunks:
+                                 correlation chunks on hip_stream, each chunk's placement
+                                 on a second stream of the context once that chunk is
+                                 done, joined back into hip_stream before the call ends  */
 } dpmt_launch;
 
 typedef struct { int32_t h, w; } dpmt_shape;          /* filter rows, cols; 32 channels */

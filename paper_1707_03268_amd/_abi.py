@@ -26,7 +26,9 @@ MODES = {"direct_fp32": DIRECT_FP32, "tensor_fp32": TENSOR_FP32,
 LAUNCH_BATCHED = 0
 LAUNCH_PER_LEVEL = 1
 LAUNCH_GRAPH = 2
-LAUNCHES = {"batched": LAUNCH_BATCHED, "per_level": LAUNCH_PER_LEVEL, "graph": LAUNCH_GRAPH}
+LAUNCH_OVERLAP = 3
+LAUNCHES = {"batched": LAUNCH_BATCHED, "per_level": LAUNCH_PER_LEVEL, "graph": LAUNCH_GRAPH,
+            "overlap": LAUNCH_OVERLAP}
 
 
 class Shape(ctypes.Structure):

@@ -39,6 +39,7 @@ constexpr TileCfg TILE_CFGS[] = {
 };
 constexpr int N_TILE_CFGS = (int)(sizeof(TILE_CFGS) / sizeof(TILE_CFGS[0]));
 constexpr int MAX_BB = 2;                 // most filter blocks per tile over TILE_CFGS
+constexpr int PLACE_CHUNKS = 8;           // dependency chunks of the overlapped strategy
 constexpr int MAX_FILTER_H = 16;
 constexpr int MAX_FILTER_W = 32;
 
@@ -72,8 +73,10 @@ struct ModeData {
         int plan_id = -1;
         CorrTile* dTiles = nullptr;
         CorrTile* dTilesLvl = nullptr;
+        CorrTile* dTilesChunk = nullptr;
         int n_tiles = 0;
         std::vector<std::array<int, 4>> lvl;   // (image, level, begin, end)
+        std::vector<std::array<int, 2>> chunk; // (begin, end) into dTilesChunk per chunk
     };
     std::map<std::array<int, 3>, TileSet> tilesets;
 };
@@ -173,6 +176,12 @@ struct dpmt_ctx {
     std::vector<int2> place_blk;        // per placement block: (map, strip), work order
     std::vector<int2> place_blk_lvl;    // the same blocks in (image, level) order
     std::vector<std::array<int, 4>> place_lvl;   // (image, level, begin, end) into place_blk_lvl
+    // overlapped strategy: (image, root level) dependency groups cut into
+    // chunks; a chunk's placement needs only its own correlation tiles
+    std::map<std::pair<int, int>, int> chunk_of;  // (image, root level) -> chunk
+    int n_chunks = 0;
+    std::vector<int2> place_blk_chunk;            // placement blocks in chunk order
+    std::vector<std::array<int, 2>> place_chunk;  // (begin, end) per chunk
     PlaceLds place_lds{};
     dpmt_layout layout{};
 
@@ -185,6 +194,9 @@ struct dpmt_ctx {
     MapPart* d_parts = nullptr;
     int2* d_place_blk = nullptr;
     int2* d_place_blk_lvl = nullptr;
+    int2* d_place_blk_chunk = nullptr;
+    hipStream_t aux_stream = nullptr;             // placement chunks of the overlapped strategy
+    std::vector<hipEvent_t> chunk_ev;             // chunk done, fork, join
 
     // launch strategy and the captured graph of the batched launches
     int launch = DPMT_LAUNCH_BATCHED;
@@ -233,6 +245,7 @@ void free_tilesets(ModeData& m) {
     for (auto& kv : m.tilesets) {
         dfree(kv.second.dTiles);
         dfree(kv.second.dTilesLvl);
+        dfree(kv.second.dTilesChunk);
     }
     m.tilesets.clear();
 }
@@ -265,6 +278,7 @@ void free_plan(dpmt_ctx* c) {
     dfree(c->d_parts); c->d_parts = nullptr;
     dfree(c->d_place_blk); c->d_place_blk = nullptr;
     dfree(c->d_place_blk_lvl); c->d_place_blk_lvl = nullptr;
+    dfree(c->d_place_blk_chunk); c->d_place_blk_chunk = nullptr;
     for (auto& m : c->modes) free_tilesets(m);
     drop_graph(c);
     c->planned = false;
@@ -571,6 +585,33 @@ dpmt_status prepare_tiles(dpmt_ctx* c, dpmt_mode mode, ModeData::TileSet** out) 
     }
     if (tiles.size() > (size_t)INT32_MAX) return fail(c, DPMT_E_UNSUPPORTED, "batch too large for one launch");
     HIP_TRY(c, upload(&ts.dTilesLvl, tiles), "upload tiles");
+    {   // chunk order for the overlapped strategy, most expensive first within a chunk
+        std::vector<std::pair<int, CorrTile>> keyed;
+        keyed.reserve(tiles.size());
+        for (const auto& r : ts.lvl)                       // tiles of (image r[0], level r[1])
+            for (int i = r[2]; i < r[3]; ++i) {
+                const CorrTile& t = tiles[i];
+                const bool root = c->groups[t.group].role == ROLE_ROOT;
+                auto it = c->chunk_of.find({r[0], root ? r[1] : r[1] + c->octave[r[0]]});
+                keyed.push_back({it == c->chunk_of.end() ? 0 : it->second, t});
+            }
+        std::stable_sort(keyed.begin(), keyed.end(), [&](const std::pair<int, CorrTile>& a,
+                                                         const std::pair<int, CorrTile>& b) {
+            if (a.first != b.first) return a.first < b.first;
+            const GroupDesc& ga = md.groups[a.second.group];
+            const GroupDesc& gb = md.groups[b.second.group];
+            return (int64_t)ga.h * ga.S > (int64_t)gb.h * gb.S;
+        });
+        std::vector<CorrTile> ct;
+        ct.reserve(keyed.size());
+        ts.chunk.assign(std::max(c->n_chunks, 1), {0, 0});
+        for (size_t i = 0; i < keyed.size(); ++i) {
+            if (i == 0 || keyed[i].first != keyed[i - 1].first) ts.chunk[keyed[i].first][0] = (int)i;
+            ts.chunk[keyed[i].first][1] = (int)i + 1;
+            ct.push_back(keyed[i].second);
+        }
+        HIP_TRY(c, upload(&ts.dTilesChunk, ct), "upload tiles");
+    }
     // most expensive groups first so that the tail of the batched launch is short tiles
     std::stable_sort(tiles.begin(), tiles.end(), [&](const CorrTile& a, const CorrTile& b) {
         const GroupDesc& ga = md.groups[a.group];
@@ -603,6 +644,12 @@ dpmt_status score_prepare(dpmt_ctx* c, dpmt_mode mode, hipStream_t st) {
     if (s != DPMT_OK) return s;
     ModeData::TileSet* ts = nullptr;
     if ((s = prepare_tiles(c, mode, &ts)) != DPMT_OK) return s;
+    if (!c->aux_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking), "hipStreamCreate");
+    while ((int)c->chunk_ev.size() < c->n_chunks + 2) {
+        hipEvent_t e = nullptr;
+        HIP_TRY(c, hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
+        c->chunk_ev.push_back(e);
+    }
     ModeData& md = c->modes[mode];
     if (mode != DPMT_DIRECT_FP32) {
         const size_t need = (size_t)c->n_cells * md.pk.RP * md.pk.esz;
@@ -695,6 +742,44 @@ hipError_t enqueue_per_level(dpmt_ctx* c, dpmt_mode mode, const float* X, float*
     return e;
 }
 
+// Correlation chunks on the caller's stream; the placement of each chunk on a
+// second stream once that chunk's responses are complete, so that placement
+// (VALU bound) runs while the next chunks' correlation (MFMA bound) runs.
+hipError_t enqueue_overlap(dpmt_ctx* c, dpmt_mode mode, const float* X, float* scores,
+                           int16_t* offs, hipStream_t st, hipEvent_t* ev) {
+    ModeData& md = c->modes[mode];
+    ModeData::TileSet& ts = current_tiles(c, mode);
+    const bool tensor = mode != DPMT_DIRECT_FP32;
+    const void* Z = tensor ? c->d_Z : static_cast<const void*>(X);
+    const int K = c->n_chunks;
+    hipError_t e = ev ? hipEventRecord(ev[0], st) : hipSuccess;
+    if (e == hipSuccess) e = launch_range_init(c->d_rkeys, c->n_slots, st);
+    if (e == hipSuccess) {
+        if (mode == DPMT_TENSOR_FP8) e = fp8_operands(c, md, X, c->n_cells, c->d_Z, st);
+        else if (tensor) e = launch_project(md.pk.esz == 2, X, c->n_cells, md.dU, md.pk.RP, c->d_Z, st);
+    }
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[1], st);
+    hipEvent_t fork = c->chunk_ev[K], join = c->chunk_ev[K + 1];
+    if (e == hipSuccess) e = hipEventRecord(fork, st);
+    if (e == hipSuccess) e = hipStreamWaitEvent(c->aux_stream, fork, 0);
+    const CorrLaunch cl = corr_launch(md);
+    for (int k = 0; k < K && e == hipSuccess; ++k) {
+        e = launch_corr(cl, ts.dTilesChunk + ts.chunk[k][0], ts.chunk[k][1] - ts.chunk[k][0], md.dGroups,
+                        Z, md.dG, md.dTk, c->d_resp, c->d_rkeys, c->n_slots, md.max_h, md.max_S, st);
+        if (e == hipSuccess) e = hipEventRecord(c->chunk_ev[k], st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(c->aux_stream, c->chunk_ev[k], 0);
+        if (e == hipSuccess)
+            e = launch_place(c->d_maps, c->d_parts, c->d_place_blk_chunk + c->place_chunk[k][0],
+                             c->place_chunk[k][1] - c->place_chunk[k][0], c->d_resp, c->d_rkeys,
+                             c->n_slots, scores, offs, c->place_lds, c->aux_stream);
+    }
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[2], st);
+    if (e == hipSuccess) e = hipEventRecord(join, c->aux_stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, join, 0);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[3], st);
+    return e;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -751,6 +836,8 @@ void dpmt_destroy(dpmt_ctx* c) {
         free_plan(c);
         for (auto& m : c->modes) free_mode(m);
         if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+        if (c->aux_stream) (void)hipStreamDestroy(c->aux_stream);
+        for (hipEvent_t e : c->chunk_ev) (void)hipEventDestroy(e);
         for (auto& set : c->ev_sets)
             for (auto& e : set) (void)hipEventDestroy(e);
     }
@@ -1042,6 +1129,46 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
             else
                 c->place_lvl.push_back({img, lvl, b0, (int)c->place_blk_lvl.size()});
         }
+        // dependency groups (image, root level): the responses of root level l
+        // and of its part level l - octave, and the score maps of level l.
+        // Cheapest first, cut into chunks of about equal response count.
+        {
+            std::map<std::pair<int, int>, int64_t> work;
+            for (size_t k = 0; k < c->maps.size(); ++k) work[{c->m_image[k], c->m_level[k]}] += 0;
+            for (const auto& kv : c->blocks) {
+                const HostGroup& hg = c->groups[kv.first.group];
+                const int lvl = hg.role == ROLE_ROOT ? kv.first.level : kv.first.level + c->octave[kv.first.img];
+                work[{kv.first.img, lvl}] += (int64_t)kv.second.Ho * kv.second.Wo * (int64_t)hg.filters.size();
+            }
+            std::vector<std::pair<int64_t, std::pair<int, int>>> order;
+            int64_t total_work = 0;
+            for (const auto& kv : work) {
+                order.push_back({kv.second, kv.first});
+                total_work += kv.second;
+            }
+            std::stable_sort(order.begin(), order.end());
+            const int K = (int)std::min<size_t>(PLACE_CHUNKS, std::max<size_t>(order.size(), 1));
+            c->chunk_of.clear();
+            int64_t acc_work = 0;
+            for (const auto& o : order) {
+                const int k = total_work > 0 ? (int)std::min<int64_t>(K - 1, acc_work * K / total_work) : 0;
+                c->chunk_of[o.second] = k;
+                acc_work += o.first;
+            }
+            c->n_chunks = K;
+            c->place_blk_chunk.clear();
+            c->place_chunk.assign(K, {0, 0});
+            std::vector<std::vector<int2>> per(K);
+            for (const int2& b : c->place_blk) {            // keeps the work order within a chunk
+                const int k = c->chunk_of[{c->m_image[b.x], c->m_level[b.x]}];
+                per[k].push_back(b);
+            }
+            for (int k = 0; k < K; ++k) {
+                c->place_chunk[k][0] = (int)c->place_blk_chunk.size();
+                c->place_blk_chunk.insert(c->place_blk_chunk.end(), per[k].begin(), per[k].end());
+                c->place_chunk[k][1] = (int)c->place_blk_chunk.size();
+            }
+        }
         const int span = place_span_max(max_Wp);
         if (span > PLACE_STAGE)
             return fail(c, DPMT_E_UNSUPPORTED, "part level wider than the placement staging supports");
@@ -1088,6 +1215,7 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
         HIP_TRY(c, upload(&c->d_parts, c->map_parts), "upload map parts");
         HIP_TRY(c, upload(&c->d_place_blk, c->place_blk), "upload block map");
         HIP_TRY(c, upload(&c->d_place_blk_lvl, c->place_blk_lvl), "upload block map");
+        HIP_TRY(c, upload(&c->d_place_blk_chunk, c->place_blk_chunk), "upload block map");
     }
     c->planned = true;
     *out = &c->layout;
@@ -1175,16 +1303,17 @@ dpmt_status dpmt_score_pyramid(dpmt_ctx* c, dpmt_mode mode, const float* feature
         if (ev) HIP_TRY(c, hipEventRecord(ev[N_STAGES], st), "hipEventRecord");
         return DPMT_OK;
     }
-    const hipError_t e = c->launch == DPMT_LAUNCH_PER_LEVEL
-                             ? enqueue_per_level(c, mode, features_dev, scores_dev, offsets_dev, st, ev)
-                             : enqueue_batched(c, mode, features_dev, scores_dev, offsets_dev, st, ev);
+    const hipError_t e =
+        c->launch == DPMT_LAUNCH_PER_LEVEL ? enqueue_per_level(c, mode, features_dev, scores_dev, offsets_dev, st, ev)
+        : c->launch == DPMT_LAUNCH_OVERLAP ? enqueue_overlap(c, mode, features_dev, scores_dev, offsets_dev, st, ev)
+                                           : enqueue_batched(c, mode, features_dev, scores_dev, offsets_dev, st, ev);
     if (e != hipSuccess) return hip_fail(c, e, "score launch");
     return DPMT_OK;
 }
 
 dpmt_status dpmt_set_launch(dpmt_ctx* c, int32_t launch) {
     if (!c) return fail(nullptr, DPMT_E_INVALID, "ctx is NULL");
-    if (launch < DPMT_LAUNCH_BATCHED || launch > DPMT_LAUNCH_GRAPH) return fail(c, DPMT_E_INVALID, "unknown launch strategy");
+    if (launch < DPMT_LAUNCH_BATCHED || launch > DPMT_LAUNCH_OVERLAP) return fail(c, DPMT_E_INVALID, "unknown launch strategy");
     if (c->has_device() && c->graph_exec) {
         (void)hipSetDevice(c->device);
         (void)hipDeviceSynchronize();

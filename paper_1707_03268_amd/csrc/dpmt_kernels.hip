@@ -249,6 +249,12 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
     char* win = smem;
     u32x4* gbuf0 = reinterpret_cast<u32x4*>(smem + win_bytes);
     u32x4* gbuf1 = gbuf0 + BB * h * CU;
+    u32x4* gbuf2 = gbuf1 + BB * h * CU;
+    // Unrolled heights stage the filter chunks with direct global-to-LDS loads,
+    // three buffers deep (the chunk of step gs + 2 is in flight while step gs
+    // computes); each wavefront loads UPW 1 KB units of a chunk.
+    constexpr bool DMA = HS > 0 && FragT<KIND>::bytes == 16;
+    constexpr int UPW = DMA ? (BB * HS + WY - 1) / WY : 1;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
@@ -295,8 +301,27 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
     const bool wact = wr0 < rpp;
     const int wx = t.x0 + wcc;
 
-    // prologue: chunk 0 straight into buffer 0
-    {
+    // chunk cidx = group * BB * total + step: unit (b, n) of the packed operand
+    // of block fb0 + b lies at ((fb0 + b) * total + cidx) * h + n units of 1 KB
+    const int wvu = __builtin_amdgcn_readfirstlane(wv);
+    auto dma_chunk = [&](int cidx, u32x4* dst) {
+#pragma unroll
+        for (int m = 0; m < UPW; ++m) {
+            const int u = min(wvu + WY * m, BB * HS - 1);  // surplus waves reload the last unit
+            const int b = u / (HS > 0 ? HS : 1), n = u - b * (HS > 0 ? HS : 1);
+            const char* src = G + g.g_off +
+                              ((int64_t)((t.fb0 + b) * total + cidx) * (HS > 0 ? HS : 1) + n) * 1024 + lane * 16;
+            __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void*)src,
+                                             (__attribute__((address_space(3))) void*)(reinterpret_cast<char*>(dst) + u * 1024),
+                                             16, 0, 0);
+        }
+    };
+
+    // prologue: chunk 0 (and 1) into buffer 0 (and 1)
+    if constexpr (DMA) {
+        dma_chunk(0, gbuf0);
+        if (t.nfb * total > 1) dma_chunk(1, gbuf1);
+    } else {
         u32x4 pf[PFMAX];
 #pragma unroll
         for (int k = 0; k < PFMAX; ++k) pf[k] = chunk_ld(0, k);
@@ -309,7 +334,7 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
     // at the first group only when the level has one plane.  Each group ends
     // with its epilogue, whose stores drain while the next group computes.
     const int nsteps = t.nfb * total;
-    int step = 0, fbi = 0;
+    int step = 0, fbi = 0, bi = 0;                 // bi = gs % 3 (staging buffer of step gs)
     for (int gs = 0; gs < nsteps; ++gs) {
         const int q = step / S, s = step - q * S;
         if (s == 0 && (fbi == 0 || Q > 1)) {
@@ -358,10 +383,18 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
                 }
             }
         }
+        if constexpr (DMA) {
+            // chunk gs has landed once at most the UPW loads of chunk gs + 1
+            // (issued after it) are outstanding; vmcnt(N) keeps expcnt and
+            // lgkmcnt at their maxima
+            if (gs + 1 < nsteps) __builtin_amdgcn_s_waitcnt(0xF70 | UPW);
+            else __builtin_amdgcn_s_waitcnt(0xF70);
+        }
         __syncthreads();                           // window and chunk `step` visible
 
-        // issue the loads of the next chunk before this step's MFMAs (the last
-        // step reloads its own chunk and does not store it)
+        // issue the loads of a later chunk before this step's MFMAs (without
+        // DMA: the next chunk through registers; the last step reloads its own
+        // chunk and does not store it)
         u32x4 pf[PFMAX];
         const bool more = gs + 1 < nsteps;
         int nstep = step + 1, nfbi = fbi;
@@ -369,12 +402,23 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
             nstep = 0;
             ++nfbi;
         }
-        const int cur = fbi * BB * total + step;       // chunk index within the tile's blocks
-        const int nxt = more ? nfbi * BB * total + nstep : cur;
+        if constexpr (DMA) {
+            if (gs + 2 < nsteps) {
+                int st2 = step + 2, f2 = fbi;
+                while (st2 >= total) {
+                    st2 -= total;
+                    ++f2;
+                }
+                dma_chunk(f2 * BB * total + st2, bi == 0 ? gbuf2 : (bi == 1 ? gbuf0 : gbuf1));
+            }
+        } else {
+            const int cur = fbi * BB * total + step;   // chunk index within the tile's blocks
+            const int nxt = more ? nfbi * BB * total + nstep : cur;
 #pragma unroll
-        for (int k = 0; k < PFMAX; ++k) pf[k] = chunk_ld(nxt, k);
+            for (int k = 0; k < PFMAX; ++k) pf[k] = chunk_ld(nxt, k);
+        }
 
-        const u32x4* gb = (gs & 1) ? gbuf1 : gbuf0;
+        const u32x4* gb = DMA ? (bi == 0 ? gbuf0 : (bi == 1 ? gbuf1 : gbuf2)) : ((gs & 1) ? gbuf1 : gbuf0);
         const char* abase = win + (wv * TY) * pitch + p * PB + KS * s + FB * j;
         const char* gbb = reinterpret_cast<const char*>(gb) + lane * FB;
         if constexpr (HS > 0) {
@@ -430,7 +474,7 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
             }
         }
 
-        if (more) {
+        if (!DMA && more) {
             u32x4* nb = (gs & 1) ? gbuf0 : gbuf1;
 #pragma unroll
             for (int k = 0; k < PFMAX; ++k) nb[pf_dst[k]] = pf[k];
@@ -446,6 +490,7 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
         }
         step = nstep;
         fbi = nfbi;
+        bi = bi == 2 ? 0 : bi + 1;
     }
 
 }
@@ -453,7 +498,7 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
 // One workgroup per tile (grid = tiles), or a persistent grid that strides
 // over the cost-sorted tile list; both produce the same bits.
 template <CorrKind KIND, int PB, int TY, int BB, int WY, int HMAX>
-__global__ __launch_bounds__(64 * WY) __attribute__((amdgpu_waves_per_eu((HMAX <= 8 && KIND != CORR_FP8 && TY * BB <= 8) ? 2 : 1))) void corr_kernel(const CorrTile* __restrict__ tiles, int n_tiles,
+__global__ __launch_bounds__(64 * WY) __attribute__((amdgpu_waves_per_eu((HMAX <= 8 && KIND != CORR_FP8) ? (TY * BB <= 4 ? 3 : 2) : 1))) void corr_kernel(const CorrTile* __restrict__ tiles, int n_tiles,
                                                        const GroupDesc* __restrict__ groups,
                                                        const char* __restrict__ Z,
                                                        const char* __restrict__ G,
@@ -488,7 +533,7 @@ size_t corr_lds_bytes(const CorrLaunch& cfg, int h, int S) {
     const int WC = 31 + (2 * FB * S) / cfg.pk.PB;
     const size_t win = (size_t)(cfg.ty * cfg.wy + h - 1) * WC * cfg.pk.PB;
     const size_t winal = (win + 15) & ~size_t(15);
-    return winal + 2 * (size_t)cfg.bb * h * 64 * FB;
+    return winal + 3 * (size_t)cfg.bb * h * 64 * FB;      // up to three staging buffers
 }
 
 template <CorrKind KIND, int PB, int TY, int BB, int WY, int HMAX>

@@ -205,10 +205,10 @@ def test_launch_strategy_and_tile_config_validation():
     wl, fs, comps = _tiny_bank()
     ctx = Context(device=-1)
     ctx.load_filters(fs, comps)
-    for launch in ("batched", "per_level", "graph"):
+    for launch in ("batched", "per_level", "graph", "overlap"):
         ctx.set_launch(launch)
     with pytest.raises(DpmtError) as e:
-        ctx.set_launch(3)
+        ctx.set_launch(4)
     assert e.value.status == _abi.DPMT_E_INVALID
     assert ctx.get_tile_config("tensor_bf16") == 0
     ctx.set_tile_config("tensor_bf16", n - 1)

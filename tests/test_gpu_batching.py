@@ -88,10 +88,11 @@ def test_launch_strategies_bitwise_equal(batch, mode, rank):
     note(f"launch strategies {mode}")
     ctx, lay, _ = _context(wl, rank)
     ref_s, ref_o = _score(ctx, mode, feats, lay)
-    ctx.set_launch("per_level")
-    s, o = _score(ctx, mode, feats, lay)
-    np.testing.assert_array_equal(s, ref_s)
-    np.testing.assert_array_equal(o, ref_o)
+    for launch in ("per_level", "overlap"):
+        ctx.set_launch(launch)
+        s, o = _score(ctx, mode, feats, lay)
+        np.testing.assert_array_equal(s, ref_s, err_msg=launch)
+        np.testing.assert_array_equal(o, ref_o, err_msg=launch)
     # graph: replayed several times with eager work in between, each replay checked
     ctx.set_launch("graph")
     scores, offs = _outputs(lay)
