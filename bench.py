@@ -82,20 +82,21 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(kernel: str, config: int, mode: str, rank) -> "int | None":
+def recorded_traffic(kernel: str, config: int, mode: str, rank, tile_config: int) -> "int | None":
     """HBM bytes per launch of `kernel` measured with rocprofv3 FETCH_SIZE and
     WRITE_SIZE (scaled by a plain copy's counter reading), from the summary in
-    profiles/, if it was taken on the current kernel sources."""
+    profiles/, if it was taken on the current kernel sources with the same
+    correlation tile configuration."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
     if not os.path.exists(path):
         return None
     digest = kernel_source_digest()
-    want = [kernel, f"c{config}", mode, str(rank if mode != "direct_fp32" else 0), digest]
+    want = [kernel, f"c{config}", mode, str(rank if mode != "direct_fp32" else 0), str(tile_config), digest]
     with open(path) as f:
         for line in f:
             t = line.split()
-            if len(t) == 8 and t[0] == "traffic" and t[1:6] == want:
-                return int(float(t[6]) + float(t[7]))
+            if len(t) == 9 and t[0] == "traffic" and t[1:7] == want:
+                return int(float(t[7]) + float(t[8]))
     return None
 
 
@@ -316,13 +317,15 @@ def main() -> None:
     # target the tensor form is judged on), the placement against HBM
     rf_corr = {"bound": "mfma", "achieved": corr["tflops"], "peak": peak_mfma, "unit": "TFLOP/s",
                "frac": corr["frac_mfma"], "kernel": "corr_kernel", "bytes": cbytes,
-               "traffic": recorded_traffic("corr_kernel", args.config, args.mode, args.rank)}
+               "traffic": recorded_traffic("corr_kernel", args.config, args.mode, args.rank,
+                                           ctx.get_tile_config(args.mode))}
     pbytes = place_bytes(lay)
     place_ms = stages["placement"]
     pgbs = pbytes / (place_ms * 1e-3) / 1e9
     rf_place = {"bound": "hbm", "achieved": pgbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": pgbs / PEAK_HBM_GBS, "kernel": "place_kernel", "bytes": pbytes,
-                "traffic": recorded_traffic("place_kernel", args.config, args.mode, args.rank)}
+                "traffic": recorded_traffic("place_kernel", args.config, args.mode, args.rank,
+                                            ctx.get_tile_config(args.mode))}
     roof = dict(rf_corr if corr_ms >= place_ms else rf_place)
 
     cpu = None

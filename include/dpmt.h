@@ -173,6 +173,23 @@ dpmt_status dpmt_plan(dpmt_ctx* ctx, int32_t n_images, const dpmt_pyramid* pyrs,
 dpmt_status dpmt_score_pyramid(dpmt_ctx* ctx, dpmt_mode mode, const float* features_dev,
                                float* scores_dev, int16_t* offsets_dev, void* hip_stream);
 
+/* One detection: root position (y, x) of score map `map` (a layout index)
+ * and its score; the parts' placements are the map's offsets at (y, x). */
+typedef struct {
+    int32_t map;
+    int32_t y, x;
+    float   score;
+} dpmt_detection;
+
+/* Detection set of Algorithm 1: every root position of every planned score
+ * map whose score is >= tau (finite), in (map, row, column) order, from the
+ * scores of a dpmt_score_pyramid call enqueued before it on the same stream.
+ * dets_dev receives the first min(count, capacity) records; count_dev (device,
+ * one int64) receives the full count.  Asynchronous on hip_stream; uses the
+ * context's scratch, so calls on one context must not overlap. */
+dpmt_status dpmt_detect(dpmt_ctx* ctx, const float* scores_dev, float tau, dpmt_detection* dets_dev,
+                        int64_t capacity, int64_t* count_dev, void* hip_stream);
+
 /* Filter responses of every filter of the bank on one planned level (for
  * checking the correlation stage on its own).  out_dev receives, for filter
  * k = 0 .. n_filters-1 in order, its (rows - h_k + 1) x (cols - w_k + 1)

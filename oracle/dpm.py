@@ -295,6 +295,112 @@ def score_pyramid(levels: Sequence[np.ndarray], filters: Sequence[np.ndarray],
 # --------------------------------------------------------------------------
 # Section 4 accounting: multiplication counts and formula (1)
 # --------------------------------------------------------------------------
+# --------------------------------------------------------------------------
+# Per-filter CP form (Section 4): f ~ sum_r a_r (x) b_r (x) c_r, fitted by
+# alternating least squares, and the decomposed correlation
+# I o T = sum_r ((I o c_r) o b_r) o a_r  (feature contraction first, then the
+# 1-D correlations along x with b_r and along y with a_r).
+# --------------------------------------------------------------------------
+@dataclass
+class CPForm:
+    A: np.ndarray            # (N, R) filter-row factors a_r
+    B: np.ndarray            # (M, R) filter-column factors b_r
+    C: np.ndarray            # (L, R) channel factors c_r
+    errors: List[float]      # Frobenius error after each ALS cycle
+
+
+def cp_reconstruct(A: np.ndarray, B: np.ndarray, C: np.ndarray) -> np.ndarray:
+    """sum_r a_r (x) b_r (x) c_r as an (N, M, L) array."""
+    return np.einsum("nr,mr,lr->nml", A, B, C)
+
+
+def _leading_vectors(X: np.ndarray, R: int) -> np.ndarray:
+    """R leading left singular vectors of X (columns beyond rank(X) stay as
+    the SVD returns them; extra columns beyond X's row count are zero)."""
+    U, _, _ = np.linalg.svd(X, full_matrices=True)
+    out = np.zeros((X.shape[0], R))
+    k = min(R, U.shape[1])
+    out[:, :k] = U[:, :k]
+    return out
+
+
+def cp_als(f: np.ndarray, R: int, iters: int = 500, eps: float = 1e-13) -> CPForm:
+    """Rank-R CP of an order-3 tensor by alternating least squares.
+
+    One cycle solves, in turn, A = argmin ||f - CP(A, B, C)||_F, then B, then
+    C, each an ordinary least-squares problem on the matching unfolding of f
+    with a Khatri-Rao design matrix (numpy.linalg.lstsq).  Starts from the
+    leading singular vectors of the three unfoldings.  Stops after `iters`
+    cycles, when the error falls below eps * ||f||_F, or when a cycle no longer
+    lowers it (relative change below 1e-12).
+    """
+    f = np.asarray(f, np.float64)
+    N, M, L = f.shape
+    X1 = f.reshape(N, M * L)                         # [n, m*L + l]
+    X2 = f.transpose(1, 0, 2).reshape(M, N * L)      # [m, n*L + l]
+    X3 = f.transpose(2, 0, 1).reshape(L, N * M)      # [l, n*M + m]
+    A = _leading_vectors(X1, R)
+    B = _leading_vectors(X2, R)
+    C = _leading_vectors(X3, R)
+    nf = np.linalg.norm(f)
+    errors: List[float] = []
+
+    def kr(P, Q):                                    # rows (p, q) -> P[p] * Q[q]
+        return np.einsum("pr,qr->pqr", P, Q).reshape(P.shape[0] * Q.shape[0], -1)
+
+    for _ in range(iters):
+        A = np.linalg.lstsq(kr(B, C), X1.T, rcond=None)[0].T
+        B = np.linalg.lstsq(kr(A, C), X2.T, rcond=None)[0].T
+        C = np.linalg.lstsq(kr(A, B), X3.T, rcond=None)[0].T
+        err = float(np.linalg.norm(f - cp_reconstruct(A, B, C)))
+        errors.append(err)
+        if err <= eps * nf:
+            break
+        if len(errors) > 1 and errors[-2] - err <= 1e-12 * max(errors[-2], 1e-300):
+            break
+    return CPForm(A, B, C, errors)
+
+
+def cp_response(X: np.ndarray, A: np.ndarray, B: np.ndarray, C: np.ndarray) -> np.ndarray:
+    """Decomposed correlation of one level with a CP filter: per rank term,
+    P = X o c_r (channel contraction), Q = P o b_r along x, S = Q o a_r along
+    y; the terms are summed.  Valid placements only, as in correlate()."""
+    X = np.asarray(X, np.float64)
+    H, W, _ = X.shape
+    N, R = A.shape
+    M = B.shape[0]
+    Ho, Wo = H - N + 1, W - M + 1
+    if Ho <= 0 or Wo <= 0:
+        return np.zeros((max(Ho, 0), max(Wo, 0)))
+    out = np.zeros((Ho, Wo))
+    for r in range(R):
+        P = X @ C[:, r]                              # (H, W)
+        Q = np.zeros((H, Wo))
+        for m in range(M):
+            Q += B[m, r] * P[:, m:m + Wo]
+        S = np.zeros((Ho, Wo))
+        for n in range(N):
+            S += A[n, r] * Q[n:n + Ho, :]
+        out += S
+    return out
+
+
+# --------------------------------------------------------------------------
+# Detection set (Algorithm 1: a hypothesis joins D when its score reaches tau)
+# --------------------------------------------------------------------------
+def detections(score_maps: Sequence[np.ndarray], tau: float) -> List[Tuple[int, int, int, float]]:
+    """Every (map, y, x, score) with score >= tau, maps in the given order,
+    positions row by row."""
+    out = []
+    for k, S in enumerate(score_maps):
+        S = np.asarray(S)
+        for y in range(S.shape[0]):
+            for x in range(S.shape[1]):
+                if S[y, x] >= tau:
+                    out.append((k, y, x, float(S[y, x])))
+    return out
+
+
 def mults_direct(Np: int, Mp: int, N: int, M: int, L: int) -> int:
     """alpha = N' M' N M L multiplications for one filter on one image."""
     return Np * Mp * N * M * L

@@ -80,6 +80,7 @@ SIGNATURES = {
     "dpmt_get_tile_config": (c_int32, [c_void_p, c_int32]),
     "dpmt_autotune": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_int32,
                                 POINTER(c_float), POINTER(c_int32), c_void_p]),
+    "dpmt_detect": (c_int32, [c_void_p, c_void_p, c_float, c_void_p, c_int64, c_void_p, c_void_p]),
     "dpmt_status_string": (c_char_p, [c_int32]),
     "dpmt_last_error": (c_char_p, [c_void_p]),
 }

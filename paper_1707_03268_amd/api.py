@@ -215,6 +215,23 @@ class Context:
                self._h, "dpmt_level_responses")
         return out, n.value
 
+    def detect(self, scores, tau: float, capacity: Optional[int] = None, stream=None):
+        """Detection set (score >= tau) of the planned maps from ``scores``.
+        Returns (records int32 tensor (n, 4) = (map, y, x, score bits),
+        scores float32 tensor (n,), count) with n = min(count, capacity)."""
+        import torch
+        if capacity is None:
+            capacity = max(self.layout.n_score, 1)
+        rec = torch.empty((max(int(capacity), 1), 4), dtype=torch.int32, device=scores.device)
+        cnt = torch.zeros(1, dtype=torch.int64, device=scores.device)
+        _check(_lib().dpmt_detect(self._h, _dev_ptr(scores, torch.float32, "scores"), float(tau),
+                                  rec.data_ptr(), int(capacity), cnt.data_ptr(), _stream_ptr(stream)),
+               self._h, "dpmt_detect")
+        n = int(cnt.item())
+        m = min(n, int(capacity))
+        rec = rec[:m]
+        return rec, rec[:, 3].contiguous().view(torch.float32), n
+
     # ------------------------------------------------------ launch strategy
     def set_launch(self, launch) -> None:
         """'batched' (default), 'per_level' or 'graph' (see dpmt_launch)."""

@@ -195,6 +195,7 @@ struct dpmt_ctx {
     int2* d_place_blk = nullptr;
     int2* d_place_blk_lvl = nullptr;
     int2* d_place_blk_chunk = nullptr;
+    int64_t* d_det_counts = nullptr;              // detection compaction scratch
     hipStream_t aux_stream = nullptr;             // placement chunks of the overlapped strategy
     std::vector<hipEvent_t> chunk_ev;             // chunk done, fork, join
 
@@ -279,6 +280,7 @@ void free_plan(dpmt_ctx* c) {
     dfree(c->d_place_blk); c->d_place_blk = nullptr;
     dfree(c->d_place_blk_lvl); c->d_place_blk_lvl = nullptr;
     dfree(c->d_place_blk_chunk); c->d_place_blk_chunk = nullptr;
+    dfree(c->d_det_counts); c->d_det_counts = nullptr;
     for (auto& m : c->modes) free_tilesets(m);
     drop_graph(c);
     c->planned = false;
@@ -1199,7 +1201,7 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
     lay.n_resp = n_root + n_part;
     lay.n_resp_root = n_root;
     lay.n_resp_part = n_part;
-    lay.workspace_bytes = c->resp_elems * 4 + c->n_slots * 8;
+    lay.workspace_bytes = c->resp_elems * 4 + c->n_slots * 8 + (det_blocks(score_off) + 1) * 8;
 
     if (c->has_device()) {
         auto alloc = [&](void** p, int64_t bytes, const char* what) -> dpmt_status {
@@ -1216,6 +1218,7 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
         HIP_TRY(c, upload(&c->d_place_blk, c->place_blk), "upload block map");
         HIP_TRY(c, upload(&c->d_place_blk_lvl, c->place_blk_lvl), "upload block map");
         HIP_TRY(c, upload(&c->d_place_blk_chunk, c->place_blk_chunk), "upload block map");
+        if ((s = alloc((void**)&c->d_det_counts, (det_blocks(score_off) + 1) * 8, "allocate detection scratch")) != DPMT_OK) return s;
     }
     c->planned = true;
     *out = &c->layout;
@@ -1401,6 +1404,24 @@ dpmt_status dpmt_autotune(dpmt_ctx* c, dpmt_mode mode, const float* features_dev
     }
     md.tile_cfg = best >= 0 ? best : keep;
     if (best_out) *best_out = md.tile_cfg;
+    return DPMT_OK;
+}
+
+dpmt_status dpmt_detect(dpmt_ctx* c, const float* scores_dev, float tau, dpmt_detection* dets_dev,
+                        int64_t capacity, int64_t* count_dev, void* hip_stream) {
+    if (!c) return fail(nullptr, DPMT_E_INVALID, "ctx is NULL");
+    if (!c->planned) return fail(c, DPMT_E_STATE, "dpmt_detect before dpmt_plan");
+    if (!c->has_device()) return fail(c, DPMT_E_STATE, "host-only context cannot detect");
+    if (!std::isfinite(tau)) return fail(c, DPMT_E_INVALID, "tau must be finite");
+    if (capacity < 0) return fail(c, DPMT_E_INVALID, "capacity must be >= 0");
+    if (!count_dev || (!scores_dev && c->layout.n_score > 0) || (!dets_dev && capacity > 0))
+        return fail(c, DPMT_E_INVALID, "scores_dev, count_dev and (for capacity > 0) dets_dev are required");
+    HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
+    hipStream_t st = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
+    static_assert(sizeof(dpmt_detection) == sizeof(Detection), "detection record layout");
+    HIP_TRY(c, launch_detect(scores_dev, c->layout.n_score, tau, c->d_maps, (int)c->maps.size(),
+                             c->d_det_counts, count_dev, reinterpret_cast<Detection*>(dets_dev), capacity, st),
+            "detection launch");
     return DPMT_OK;
 }
 

@@ -83,6 +83,13 @@ struct MapDesc {
     int32_t pad;
 };
 
+// One detection (the C ABI's dpmt_detection).
+struct Detection {
+    int32_t map;
+    int32_t y, x;
+    float score;
+};
+
 // Correlation kernel flavours.
 enum CorrKind { CORR_F32 = 0, CORR_BF16 = 1, CORR_FP8 = 2 };
 
@@ -143,6 +150,11 @@ hipError_t launch_place(const MapDesc* maps, const MapPart* parts, const int2* b
                         float* scores, int16_t* offs, const PlaceLds& lds, hipStream_t st);
 hipError_t launch_planes_to_maps(const float* planes, int ng, int Ho, int Wo, int ld,
                                  const int64_t* dst_off, float* out, hipStream_t st);
+// Detections: counts holds det_blocks(n) int64 of scratch.
+constexpr int64_t det_blocks(int64_t n) { return (n + 1023) / 1024; }
+hipError_t launch_detect(const float* scores, int64_t n, float tau, const MapDesc* maps, int n_maps,
+                         int64_t* counts, int64_t* count, Detection* dets, int64_t capacity,
+                         hipStream_t st);
 hipError_t launch_dt_single(const float* resp, int rows, int cols, int ld, const float* d,
                             float* lmax, float* r1v, int32_t* r1a, float* out, int32_t* ay,
                             int32_t* ax, hipStream_t st);

@@ -1232,6 +1232,121 @@ hipError_t launch_place(const MapDesc* maps, const MapPart* parts, const int2* b
 }
 
 // ---------------------------------------------------------------------------
+// Detections (Algorithm 1: keep every hypothesis with score >= tau), as a
+// deterministic stream compaction over the concatenated score maps: counts per
+// block of DET_SPAN positions, an exclusive scan of the counts, then every
+// block writes its detections in position order at its offset.
+// ---------------------------------------------------------------------------
+constexpr int DET_PER_THREAD = 4;
+constexpr int DET_SPAN = 256 * DET_PER_THREAD;
+
+__device__ __forceinline__ int block_exclusive_scan(int v, int* sh, int& total) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int x = v;                                         // inclusive scan within the wavefront
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) sh[w] = x;
+    __syncthreads();
+    int before = 0;
+    total = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int t = sh[i];
+        if (i < w) before += t;
+        total += t;
+    }
+    __syncthreads();
+    return before + x - v;
+}
+
+__global__ __launch_bounds__(256) void detect_count_kernel(const float* __restrict__ scores, int64_t n,
+                                                           float tau, int64_t* __restrict__ counts) {
+    __shared__ int sh[4];
+    const int64_t p0 = (int64_t)blockIdx.x * DET_SPAN + (int64_t)threadIdx.x * DET_PER_THREAD;
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < DET_PER_THREAD; ++k) c += (p0 + k < n && scores[p0 + k] >= tau) ? 1 : 0;
+    int total;
+    block_exclusive_scan(c, sh, total);
+    if (threadIdx.x == 0) counts[blockIdx.x] = total;
+}
+
+// Exclusive scan of the block counts in place (one workgroup, chunks of 256),
+// total count to *count.
+__global__ __launch_bounds__(256) void detect_scan_kernel(int64_t* __restrict__ counts, int nb,
+                                                          int64_t* __restrict__ count) {
+    __shared__ int sh[4];
+    int64_t carry = 0;
+    for (int base = 0; base < nb; base += 256) {
+        const int i = base + (int)threadIdx.x;
+        const int v = i < nb ? (int)counts[i] : 0;     // at most DET_SPAN
+        int total;
+        const int ex = block_exclusive_scan(v, sh, total);
+        if (i < nb) counts[i] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) *count = carry;
+}
+
+__global__ __launch_bounds__(256) void detect_write_kernel(const float* __restrict__ scores, int64_t n,
+                                                           float tau, const int64_t* __restrict__ counts,
+                                                           const MapDesc* __restrict__ maps, int n_maps,
+                                                           Detection* __restrict__ dets, int64_t capacity) {
+    __shared__ int sh[4];
+    const int64_t p0 = (int64_t)blockIdx.x * DET_SPAN + (int64_t)threadIdx.x * DET_PER_THREAD;
+    bool hit[DET_PER_THREAD];
+    float val[DET_PER_THREAD];
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < DET_PER_THREAD; ++k) {
+        val[k] = p0 + k < n ? scores[p0 + k] : -INFINITY;
+        hit[k] = p0 + k < n && val[k] >= tau;
+        c += hit[k] ? 1 : 0;
+    }
+    int total;
+    int64_t out = counts[blockIdx.x] + block_exclusive_scan(c, sh, total);
+#pragma unroll
+    for (int k = 0; k < DET_PER_THREAD; ++k) {
+        if (!hit[k]) continue;
+        if (out < capacity) {
+            const int64_t p = p0 + k;
+            int lo = 0, hi = n_maps - 1;              // last map whose scores start at or before p
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (maps[mid].score_off <= p) lo = mid;
+                else hi = mid - 1;
+            }
+            const MapDesc M = maps[lo];
+            const int64_t r = p - M.score_off;
+            Detection d;
+            d.map = lo;
+            d.y = (int32_t)(r / M.Wo);
+            d.x = (int32_t)(r - (int64_t)d.y * M.Wo);
+            d.score = val[k];
+            dets[out] = d;
+        }
+        ++out;
+    }
+}
+
+hipError_t launch_detect(const float* scores, int64_t n, float tau, const MapDesc* maps, int n_maps,
+                         int64_t* counts, int64_t* count, Detection* dets, int64_t capacity,
+                         hipStream_t st) {
+    const int64_t nb = (n + DET_SPAN - 1) / DET_SPAN;
+    if (nb > INT32_MAX) return hipErrorInvalidValue;
+    if (nb > 0)
+        hipLaunchKernelGGL(detect_count_kernel, dim3((unsigned)nb), dim3(256), 0, st, scores, n, tau, counts);
+    hipLaunchKernelGGL(detect_scan_kernel, dim3(1), dim3(256), 0, st, counts, (int)nb, count);
+    if (nb > 0 && capacity > 0)
+        hipLaunchKernelGGL(detect_write_kernel, dim3((unsigned)nb), dim3(256), 0, st, scores, n, tau,
+                           counts, maps, n_maps, dets, capacity);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // filter planes of one group (pitch ld) -> one row-major map per filter
 // ---------------------------------------------------------------------------
 __global__ void planes_to_maps_kernel(const float* __restrict__ planes, int ng, int Ho, int Wo,

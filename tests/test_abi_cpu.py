@@ -244,3 +244,17 @@ def test_tall_filters_restrict_tile_configs():
             rejected += 1
     assert rejected >= 1
     ctx.close()
+
+
+def test_detect_validation():
+    lib = _abi.load()
+    wl, fs, comps = _tiny_bank()
+    ctx = Context(device=-1)
+    st = lib.dpmt_detect(ctx._h, ctypes.c_void_p(16), 0.0, None, 0, ctypes.c_void_p(16), None)
+    assert st == _abi.DPMT_E_STATE                       # no plan
+    ctx.load_filters(fs, comps)
+    ctx.plan(wl.pyramids)
+    st = lib.dpmt_detect(ctx._h, ctypes.c_void_p(16), 0.0, None, 0, ctypes.c_void_p(16), None)
+    assert st == _abi.DPMT_E_STATE                       # host-only context
+    assert lib.dpmt_detect(None, None, 0.0, None, 0, None, None) == _abi.DPMT_E_INVALID
+    ctx.close()

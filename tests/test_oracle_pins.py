@@ -280,3 +280,75 @@ def test_multiplication_counts_by_counting():
         count += Np * Mp * N      # y-direction 1D correlation with a_r
     assert count == oracle.mults_cp(Np, Mp, N, M, L, R)
     assert oracle.mults_direct(Np, Mp, N, M, L) == Np * Mp * N * M * L
+
+
+def test_detections_of_the_worked_example():
+    """Algorithm 1's detection set on the hand-derived score map."""
+    g = _load("worked_example.json")
+    S = np.array(g["score"], float)
+    assert oracle.detections([S], 5.0) == [(0, 0, 1, 10.0), (0, 0, 2, 5.0), (0, 1, 2, 5.0)]
+    assert oracle.detections([S, S], 10.0) == [(0, 0, 1, 10.0), (1, 0, 1, 10.0)]
+    assert oracle.detections([S], 10.5) == []
+    assert oracle.detections([np.full((2, 2), -np.inf)], -1e30) == []
+
+
+# ---------------------------------------------------------------- per-filter CP form
+def _planted_cp(rng, N, M, L, R):
+    return rng.standard_normal((N, R)), rng.standard_normal((M, R)), rng.standard_normal((L, R))
+
+
+@pytest.mark.parametrize("R", [1, 2, 3])
+def test_cp_als_recovers_planted_rank(R):
+    """An exact rank-R tensor is fitted to rounding by rank-R ALS."""
+    rng = np.random.default_rng(40 + R)
+    A, B, C = _planted_cp(rng, 6, 6, 32, R)
+    f = oracle.cp_reconstruct(A, B, C)
+    cp = oracle.cp_als(f, R, iters=2000)
+    rel = np.linalg.norm(f - oracle.cp_reconstruct(cp.A, cp.B, cp.C)) / np.linalg.norm(f)
+    assert rel < 1e-8, rel
+
+
+def test_cp_als_error_never_increases():
+    """Every ALS micro-step is an exact least-squares minimisation, so the
+    error after each cycle is non-increasing; more terms never fit worse."""
+    rng = np.random.default_rng(5)
+    f = rng.standard_normal((6, 6, 32))
+    errs = {}
+    for R in (1, 3, 6):
+        cp = oracle.cp_als(f, R, iters=60)
+        e = np.array(cp.errors)
+        assert np.all(np.diff(e) <= 1e-12 * e[:-1] + 1e-14), R
+        errs[R] = e[-1]
+    assert errs[1] >= errs[3] >= errs[6]
+    # rank 1 with a planted rank-1 tensor is exact
+    a, b, c = rng.standard_normal(6), rng.standard_normal(11), rng.standard_normal(32)
+    f1 = np.einsum("n,m,l->nml", a, b, c)
+    cp1 = oracle.cp_als(f1, 1)
+    assert np.allclose(oracle.cp_reconstruct(cp1.A, cp1.B, cp1.C), f1, atol=1e-12)
+
+
+def test_cp_response_is_correlation_with_reconstruction():
+    """Closed form: the separable sum of 1-D correlations equals the direct
+    correlation with the reconstructed filter (Section 4's identity)."""
+    rng = np.random.default_rng(9)
+    A, B, C = _planted_cp(rng, 5, 7, 32, 4)
+    X = rng.uniform(0, 0.4, size=(19, 23, 32))
+    got = oracle.cp_response(X, A, B, C)
+    want = oracle.correlate(X, oracle.cp_reconstruct(A, B, C))
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-12)
+
+
+def test_cp_response_bruteforce_tiny():
+    """The order of the 1-D passes by direct summation on a tiny input."""
+    rng = np.random.default_rng(10)
+    A, B, C = _planted_cp(rng, 2, 3, 32, 2)
+    X = rng.standard_normal((4, 5, 32))
+    got = oracle.cp_response(X, A, B, C)
+    want = np.zeros((3, 3))
+    for y in range(3):
+        for x in range(3):
+            for r in range(2):
+                for n in range(2):
+                    for m in range(3):
+                        want[y, x] += A[n, r] * B[m, r] * float(np.dot(X[y + n, x + m], C[:, r]))
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-12)
