@@ -60,8 +60,11 @@ typedef enum {
     DPMT_DIRECT_FP32 = 0,     /* 32-channel correlation, FP32 MFMA, FP32 accumulation    */
     DPMT_TENSOR_FP32 = 1,     /* rank-R tensor form, FP32 projection and MFMA            */
     DPMT_TENSOR_BF16 = 2,     /* rank-R tensor form, BF16 operands, FP32 accumulation    */
-    DPMT_TENSOR_FP8 = 3       /* rank-R tensor form, FP8 e4m3 operands with per-channel
+    DPMT_TENSOR_FP8 = 3,      /* rank-R tensor form, FP8 e4m3 operands with per-channel
                                  scales, FP32 accumulation                               */
+    DPMT_CP_FP32 = 4          /* per-filter CP form (Section 4): each filter a sum of R_k
+                                 outer products a (x) b (x) c; channel contraction on FP32
+                                 MFMA, then 1-D correlations along x and y, FP32        */
 } dpmt_mode;
 
 /* How dpmt_score_pyramid issues its work (dpmt_set_launch).  Every strategy
@@ -157,6 +160,34 @@ dpmt_status dpmt_load_filters(dpmt_ctx* ctx, int32_t n_filters, const dpmt_shape
  * when the context has a device. */
 dpmt_status dpmt_decompose(dpmt_ctx* ctx, int32_t rank, double* sigma_out, double* basis_out);
 
+/* Per-filter CP form (Section 4).  Filter k (h x w x 32) is approximated by
+ *     sum_{r < R_k} a_r (x) b_r (x) c_r,   a_r in R^h, b_r in R^w, c_r in R^32,
+ * and its response by the decomposed correlation: per term, the channel
+ * contraction X . c_r, a 1-D correlation along x with b_r and one along y
+ * with a_r, summed over r.  Factor layout (host float32, used by
+ * dpmt_load_cp and dpmt_get_cp): filter after filter in bank order, each as
+ * A (h x R_k), then B (w x R_k), then C (32 x R_k), all row major (A[n][r],
+ * B[m][r], C[l][r]); sum_k R_k (h_k + w_k + 32) floats in all.
+ *
+ * dpmt_decompose_cp fits the factors in FP64 on the host by alternating least
+ * squares: starting from the leading left singular vectors of the three
+ * unfoldings, each cycle solves A, then B, then C as linear least-squares
+ * problems (minimum-norm solutions) with the other two fixed; it stops after
+ * max_iters (>= 1) cycles, once ||f - CP(f)||_F <= tol * ||f||_F (tol >= 0),
+ * or when a cycle no longer lowers that error.  ranks: [n_filters] values in
+ * [1, 32] (DPMT_E_RANK otherwise).  rel_err_out (host, may be NULL) receives
+ * ||f_k - CP(f_k)||_F / ||f_k||_F per filter.  dpmt_load_cp takes factors
+ * computed elsewhere instead (every value finite).  Either call replaces the
+ * previous CP factors; dpmt_load_filters drops them. */
+dpmt_status dpmt_decompose_cp(dpmt_ctx* ctx, const int32_t* ranks, int32_t max_iters, double tol,
+                              double* rel_err_out);
+dpmt_status dpmt_load_cp(dpmt_ctx* ctx, const int32_t* ranks, const float* factors_host);
+/* Current CP factors: *n_floats receives their count; ranks_out ([n_filters])
+ * and factors_out (that many floats) may be NULL.  DPMT_E_STATE without CP
+ * factors. */
+dpmt_status dpmt_get_cp(const dpmt_ctx* ctx, int32_t* ranks_out, float* factors_out,
+                        int64_t* n_floats);
+
 /* Plan a batch of n_images pyramids (host descriptors, copied): output layout,
  * work lists and device workspace.  *out points at the context-owned layout.
  * Limits (DPMT_E_UNSUPPORTED beyond them): level sides up to 16384 cells,
@@ -169,7 +200,8 @@ dpmt_status dpmt_plan(dpmt_ctx* ctx, int32_t n_images, const dpmt_pyramid* pyrs,
 /* Score the planned batch.  features_dev: packed float32 HWC cells (at least
  * layout->n_cells x 32).  scores_dev: layout->n_score float32.  offsets_dev:
  * layout->n_offsets int16 (may be NULL to skip placements).  Tensor modes need
- * dpmt_decompose first (else DPMT_E_STATE). */
+ * dpmt_decompose first, DPMT_CP_FP32 dpmt_decompose_cp or dpmt_load_cp
+ * (else DPMT_E_STATE). */
 dpmt_status dpmt_score_pyramid(dpmt_ctx* ctx, dpmt_mode mode, const float* features_dev,
                                float* scores_dev, int16_t* offsets_dev, void* hip_stream);
 
@@ -237,7 +269,8 @@ int32_t     dpmt_tile_config_count(void);
 const char* dpmt_tile_config_name(int32_t config);
 /* Select the configuration a mode uses (DPMT_E_UNSUPPORTED if the loaded
  * filters are too tall for it); dpmt_get_tile_config returns it (-1 on a bad
- * argument). */
+ * argument).  DPMT_CP_FP32 has one tile shape of its own: it accepts only
+ * configuration 0, and dpmt_autotune times only that. */
 dpmt_status dpmt_set_tile_config(dpmt_ctx* ctx, dpmt_mode mode, int32_t config);
 int32_t     dpmt_get_tile_config(const dpmt_ctx* ctx, dpmt_mode mode);
 

@@ -315,12 +315,16 @@ def cp_reconstruct(A: np.ndarray, B: np.ndarray, C: np.ndarray) -> np.ndarray:
 
 
 def _leading_vectors(X: np.ndarray, R: int) -> np.ndarray:
-    """R leading left singular vectors of X (columns beyond rank(X) stay as
-    the SVD returns them; extra columns beyond X's row count are zero)."""
+    """R leading left singular vectors of X.  Columns beyond X's row count get
+    fixed pseudo-random values: the paper does not say how ALS starts, and a
+    zero column would stay zero under every update (its Gram rows vanish)."""
     U, _, _ = np.linalg.svd(X, full_matrices=True)
-    out = np.zeros((X.shape[0], R))
+    n = X.shape[0]
+    out = np.zeros((n, R))
     k = min(R, U.shape[1])
     out[:, :k] = U[:, :k]
+    if R > k:
+        out[:, k:] = np.random.default_rng([n, R]).uniform(-1.0, 1.0, size=(n, R - k))
     return out
 
 

@@ -19,9 +19,10 @@ DIRECT_FP32 = 0
 TENSOR_FP32 = 1
 TENSOR_BF16 = 2
 TENSOR_FP8 = 3
+CP_FP32 = 4
 
 MODES = {"direct_fp32": DIRECT_FP32, "tensor_fp32": TENSOR_FP32,
-         "tensor_bf16": TENSOR_BF16, "tensor_fp8": TENSOR_FP8}
+         "tensor_bf16": TENSOR_BF16, "tensor_fp8": TENSOR_FP8, "cp_fp32": CP_FP32}
 
 LAUNCH_BATCHED = 0
 LAUNCH_PER_LEVEL = 1
@@ -65,6 +66,9 @@ SIGNATURES = {
     "dpmt_load_filters": (c_int32, [c_void_p, c_int32, POINTER(Shape), POINTER(c_float), c_int32,
                                     POINTER(Component)]),
     "dpmt_decompose": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_double)]),
+    "dpmt_decompose_cp": (c_int32, [c_void_p, POINTER(c_int32), c_int32, c_double, POINTER(c_double)]),
+    "dpmt_load_cp": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_float)]),
+    "dpmt_get_cp": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_float), POINTER(c_int64)]),
     "dpmt_plan": (c_int32, [c_void_p, c_int32, POINTER(PyramidDesc), POINTER(POINTER(Layout))]),
     "dpmt_score_pyramid": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p]),
     "dpmt_level_responses": (c_int32, [c_void_p, c_int32, c_void_p, c_int32, c_int32, c_void_p,

@@ -169,6 +169,52 @@ class Context:
                "dpmt_decompose")
         return sigma, basis
 
+    # -------------------------------------------------- per-filter CP form
+    def _ranks(self, ranks) -> np.ndarray:
+        r = np.asarray(ranks, dtype=np.int32).reshape(-1)
+        if r.size == 1 and self.n_filters > 1:
+            r = np.full(self.n_filters, int(r[0]), np.int32)
+        if r.size != self.n_filters and self.n_filters > 0:
+            raise ValueError(f"need {self.n_filters} ranks, got {r.size}")
+        return np.ascontiguousarray(r)
+
+    def decompose_cp(self, ranks, max_iters: int = 100, tol: float = 1e-6) -> np.ndarray:
+        """Fit every filter's rank-R_k CP form by ALS (FP64, on the host).
+        ``ranks``: one rank for all filters or one per filter.  Returns the
+        relative Frobenius error per filter."""
+        r = self._ranks(ranks)
+        err = np.zeros(self.n_filters, np.float64)
+        _check(_lib().dpmt_decompose_cp(self._h, r.ctypes.data_as(POINTER(c_int32)), int(max_iters),
+                                        float(tol), err.ctypes.data_as(POINTER(c_double))),
+               self._h, "dpmt_decompose_cp")
+        return err
+
+    def load_cp(self, ranks, factors) -> None:
+        """factors: per filter (A (h, R), B (w, R), C (32, R))."""
+        r = self._ranks(ranks)
+        flat = np.ascontiguousarray(np.concatenate(
+            [np.asarray(m, np.float32).ravel() for abc in factors for m in abc]) if len(factors)
+            else np.zeros(0, np.float32))
+        _check(_lib().dpmt_load_cp(self._h, r.ctypes.data_as(POINTER(c_int32)),
+                                   flat.ctypes.data_as(POINTER(c_float))), self._h, "dpmt_load_cp")
+
+    def get_cp(self, shapes):
+        """Current CP factors as (ranks, [(A, B, C)]) for filters of the given
+        (h, w) shapes (float32 arrays)."""
+        n = c_int64(0)
+        _check(_lib().dpmt_get_cp(self._h, None, None, byref(n)), self._h, "dpmt_get_cp")
+        ranks = np.zeros(self.n_filters, np.int32)
+        flat = np.zeros(max(n.value, 1), np.float32)
+        _check(_lib().dpmt_get_cp(self._h, ranks.ctypes.data_as(POINTER(c_int32)),
+                                  flat.ctypes.data_as(POINTER(c_float)), byref(n)), self._h, "dpmt_get_cp")
+        out, o = [], 0
+        for (h, w), R in zip(shapes, ranks):
+            A = flat[o:o + h * R].reshape(h, R); o += h * R
+            B = flat[o:o + w * R].reshape(w, R); o += w * R
+            C = flat[o:o + 32 * R].reshape(32, R); o += 32 * R
+            out.append((A.copy(), B.copy(), C.copy()))
+        return ranks, out
+
     def plan(self, pyramids) -> Layout:
         """pyramids: objects with ``levels`` (each with cell_offset, rows, cols) and ``octave``."""
         arrs = []

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <map>
 #include <string>
+#include <thread>
 #include <vector>
 
 using namespace dpmt;
@@ -42,6 +43,8 @@ constexpr int MAX_BB = 2;                 // most filter blocks per tile over TI
 constexpr int PLACE_CHUNKS = 8;           // dependency chunks of the overlapped strategy
 constexpr int MAX_FILTER_H = 16;
 constexpr int MAX_FILTER_W = 32;
+constexpr int N_MODES = DPMT_CP_FP32 + 1;
+constexpr int CP_CHUNKS_PER_TILE = 8;     // 4-filter chunks a CP tile walks over its halo
 
 enum Role { ROLE_ROOT = 0, ROLE_PART = 1, ROLE_ALL = 2 };
 
@@ -79,6 +82,21 @@ struct ModeData {
         std::vector<std::array<int, 2>> chunk; // (begin, end) into dTilesChunk per chunk
     };
     std::map<std::array<int, 3>, TileSet> tilesets;
+    // CP mode: chunk table and packed factors, first chunk of every group,
+    // and its tiles (cost order, (image, level) order, chunk order)
+    CpChunk* dCpChunks = nullptr;
+    float* dCpFac = nullptr;
+    std::vector<int> cp_chunk0;
+    struct CpTileSet {
+        int plan_id = -1;
+        CpTile* dTiles = nullptr;
+        CpTile* dTilesLvl = nullptr;
+        CpTile* dTilesChunk = nullptr;
+        int n_tiles = 0;
+        size_t lds = 0;
+        std::vector<std::array<int, 4>> lvl;
+        std::vector<std::array<int, 2>> chunk;
+    } cp;
 };
 
 void free_tilesets(ModeData& m);
@@ -103,6 +121,8 @@ struct BlockInfo {
 };
 
 int pitch_of(int Wo) { return (Wo + 3) & ~3; }
+
+bool is_tensor(dpmt_mode m) { return m >= DPMT_TENSOR_FP32 && m <= DPMT_TENSOR_FP8; }
 
 template <typename T>
 hipError_t upload(T** dptr, const std::vector<T>& v) {
@@ -158,7 +178,14 @@ struct dpmt_ctx {
     std::vector<double> sigma;          // 32
     std::vector<double> Ufull;          // 32 x 32 row major, columns = eigenvectors
 
-    ModeData modes[4];
+    ModeData modes[N_MODES];
+
+    // per-filter CP form: ranks, and factors A (h x R), B (w x R), C (32 x R)
+    // row major per filter at cp_off[k]
+    bool cp_ready = false;
+    std::vector<int> cp_rank;
+    std::vector<int64_t> cp_off;
+    std::vector<float> cp_fac;
 
     // plan
     int plan_id = 0;
@@ -249,6 +276,10 @@ void free_tilesets(ModeData& m) {
         dfree(kv.second.dTilesChunk);
     }
     m.tilesets.clear();
+    dfree(m.cp.dTiles);
+    dfree(m.cp.dTilesLvl);
+    dfree(m.cp.dTilesChunk);
+    m.cp = ModeData::CpTileSet{};
 }
 
 void free_mode(ModeData& m) {
@@ -259,6 +290,8 @@ void free_mode(ModeData& m) {
     dfree(m.dG);
     dfree(m.dGroups);
     dfree(m.dU);
+    dfree(m.dCpChunks);
+    dfree(m.dCpFac);
     free_tilesets(m);
     const int cfg = m.tile_cfg;
     m = ModeData{};
@@ -349,6 +382,181 @@ void jacobi_eigen(std::vector<double>& A, std::vector<double>& V, int n) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Per-filter CP form by alternating least squares (Section 4), FP64.
+// The tensor is n1 x n2 x n3 row major (f[i][j][k] at (i * n2 + j) * n3 + k);
+// factors are row major n_d x R.
+// ---------------------------------------------------------------------------
+struct CpFit {
+    std::vector<double> A, B, C;
+    double rel_err = 0;
+};
+
+// Symmetric pseudo-inverse of an R x R positive semi-definite matrix:
+// eigenvalues below 1e-13 of the largest are treated as zero.
+std::vector<double> psd_pinv(std::vector<double> G, int R) {
+    std::vector<double> V;
+    jacobi_eigen(G, V, R);
+    double lmax = 0;
+    for (int i = 0; i < R; ++i) lmax = std::max(lmax, G[i * R + i]);
+    std::vector<double> P((size_t)R * R, 0.0);
+    for (int e = 0; e < R; ++e) {
+        const double l = G[e * R + e];
+        if (!(l > 1e-13 * lmax)) continue;
+        for (int i = 0; i < R; ++i)
+            for (int j = 0; j < R; ++j) P[i * R + j] += V[i * R + e] * V[j * R + e] / l;
+    }
+    return P;
+}
+
+// Starting factor for mode d: leading R left singular vectors of the mode-d
+// unfolding (eigenvectors of its Gram matrix by decreasing eigenvalue); the
+// columns beyond the mode size are filled with a fixed pseudo-random pattern
+// (zero columns would stay zero under the updates).
+std::vector<double> cp_start(const std::vector<double>& G, int n, int R) {
+    std::vector<double> g = G, V;
+    jacobi_eigen(g, V, n);
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return g[a * n + a] > g[b * n + b]; });
+    std::vector<double> F((size_t)n * R, 0.0);
+    for (int r = 0; r < R; ++r)
+        for (int i = 0; i < n; ++i) {
+            if (r < n) {
+                F[(size_t)i * R + r] = V[i * n + order[r]];
+            } else {
+                uint64_t z = (uint64_t)(r * 131 + i) * 0x9E3779B97F4A7C15ull;
+                z = (z ^ (z >> 31)) * 0xBF58476D1CE4E5B9ull;
+                z ^= z >> 29;
+                F[(size_t)i * R + r] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+            }
+        }
+    return F;
+}
+
+// One mode update: F = M (Gram_1 * Gram_2)^+, M the MTTKRP of that mode.
+void cp_solve(std::vector<double>& F, const std::vector<double>& M, const std::vector<double>& P1,
+              const std::vector<double>& P2, int n, int R) {
+    std::vector<double> G((size_t)R * R);
+    for (int i = 0; i < R * R; ++i) G[i] = P1[i] * P2[i];
+    const std::vector<double> Gi = psd_pinv(G, R);
+    for (int i = 0; i < n; ++i)
+        for (int r = 0; r < R; ++r) {
+            double v = 0;
+            for (int q = 0; q < R; ++q) v += M[(size_t)i * R + q] * Gi[q * R + r];
+            F[(size_t)i * R + r] = v;
+        }
+}
+
+std::vector<double> gram_cols(const std::vector<double>& F, int n, int R) {
+    std::vector<double> G((size_t)R * R, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int a = 0; a < R; ++a)
+            for (int b = 0; b < R; ++b) G[a * R + b] += F[(size_t)i * R + a] * F[(size_t)i * R + b];
+    return G;
+}
+
+CpFit cp_als(const float* f32, int n1, int n2, int n3, int R, int max_iters, double tol) {
+    const size_t N = (size_t)n1 * n2 * n3;
+    std::vector<double> f(f32, f32 + N);
+    double nf2 = 0;
+    for (double v : f) nf2 += v * v;
+    const double nf = std::sqrt(nf2);
+    // Gram matrices of the three unfoldings for the starting factors
+    std::vector<double> G1((size_t)n1 * n1, 0.0), G2((size_t)n2 * n2, 0.0), G3((size_t)n3 * n3, 0.0);
+    auto at = [&](int i, int j, int k) { return f[((size_t)i * n2 + j) * n3 + k]; };
+    for (int i = 0; i < n1; ++i)
+        for (int i2 = 0; i2 < n1; ++i2) {
+            double v = 0;
+            for (int j = 0; j < n2; ++j)
+                for (int k = 0; k < n3; ++k) v += at(i, j, k) * at(i2, j, k);
+            G1[i * n1 + i2] = v;
+        }
+    for (int j = 0; j < n2; ++j)
+        for (int j2 = 0; j2 < n2; ++j2) {
+            double v = 0;
+            for (int i = 0; i < n1; ++i)
+                for (int k = 0; k < n3; ++k) v += at(i, j, k) * at(i, j2, k);
+            G2[j * n2 + j2] = v;
+        }
+    for (int k = 0; k < n3; ++k)
+        for (int k2 = 0; k2 < n3; ++k2) {
+            double v = 0;
+            for (int i = 0; i < n1; ++i)
+                for (int j = 0; j < n2; ++j) v += at(i, j, k) * at(i, j, k2);
+            G3[k * n3 + k2] = v;
+        }
+    CpFit fit;
+    fit.A = cp_start(G1, n1, R);
+    fit.B = cp_start(G2, n2, R);
+    fit.C = cp_start(G3, n3, R);
+    std::vector<double>& A = fit.A;
+    std::vector<double>& B = fit.B;
+    std::vector<double>& C = fit.C;
+    std::vector<double> M;
+    auto error = [&]() {
+        double e2 = 0;
+        for (int i = 0; i < n1; ++i)
+            for (int j = 0; j < n2; ++j)
+                for (int k = 0; k < n3; ++k) {
+                    double v = 0;
+                    for (int r = 0; r < R; ++r) v += A[(size_t)i * R + r] * B[(size_t)j * R + r] * C[(size_t)k * R + r];
+                    const double d = at(i, j, k) - v;
+                    e2 += d * d;
+                }
+        return std::sqrt(e2);
+    };
+    double prev = -1;
+    for (int it = 0; it < max_iters; ++it) {
+        // A: M[i][r] = sum_jk f[i][j][k] B[j][r] C[k][r]
+        M.assign((size_t)n1 * R, 0.0);
+        for (int i = 0; i < n1; ++i)
+            for (int j = 0; j < n2; ++j)
+                for (int k = 0; k < n3; ++k) {
+                    const double v = at(i, j, k);
+                    for (int r = 0; r < R; ++r) M[(size_t)i * R + r] += v * B[(size_t)j * R + r] * C[(size_t)k * R + r];
+                }
+        cp_solve(A, M, gram_cols(B, n2, R), gram_cols(C, n3, R), n1, R);
+        M.assign((size_t)n2 * R, 0.0);
+        for (int i = 0; i < n1; ++i)
+            for (int j = 0; j < n2; ++j)
+                for (int k = 0; k < n3; ++k) {
+                    const double v = at(i, j, k);
+                    for (int r = 0; r < R; ++r) M[(size_t)j * R + r] += v * A[(size_t)i * R + r] * C[(size_t)k * R + r];
+                }
+        cp_solve(B, M, gram_cols(A, n1, R), gram_cols(C, n3, R), n2, R);
+        M.assign((size_t)n3 * R, 0.0);
+        for (int i = 0; i < n1; ++i)
+            for (int j = 0; j < n2; ++j)
+                for (int k = 0; k < n3; ++k) {
+                    const double v = at(i, j, k);
+                    for (int r = 0; r < R; ++r) M[(size_t)k * R + r] += v * A[(size_t)i * R + r] * B[(size_t)j * R + r];
+                }
+        cp_solve(C, M, gram_cols(A, n1, R), gram_cols(B, n2, R), n3, R);
+        const double err = error();
+        if (err <= tol * nf) break;
+        if (prev >= 0 && prev - err <= 1e-12 * prev) break;
+        prev = err;
+    }
+    // balance the three factor norms of every term (the tensor is unchanged)
+    for (int r = 0; r < R; ++r) {
+        double na = 0, nb = 0, nc = 0;
+        for (int i = 0; i < n1; ++i) na += A[(size_t)i * R + r] * A[(size_t)i * R + r];
+        for (int j = 0; j < n2; ++j) nb += B[(size_t)j * R + r] * B[(size_t)j * R + r];
+        for (int k = 0; k < n3; ++k) nc += C[(size_t)k * R + r] * C[(size_t)k * R + r];
+        na = std::sqrt(na);
+        nb = std::sqrt(nb);
+        nc = std::sqrt(nc);
+        if (na == 0 || nb == 0 || nc == 0) continue;
+        const double g = std::cbrt(na * nb * nc);
+        for (int i = 0; i < n1; ++i) A[(size_t)i * R + r] *= g / na;
+        for (int j = 0; j < n2; ++j) B[(size_t)j * R + r] *= g / nb;
+        for (int k = 0; k < n3; ++k) C[(size_t)k * R + r] *= g / nc;
+    }
+    fit.rel_err = nf > 0 ? error() / nf : 0.0;
+    return fit;
+}
+
 // Operand weights of filter k for a mode: h x w x RP values in float64
 // (original weights for the direct mode, G_k = f_k x_3 U_R for tensor modes).
 std::vector<double> operand_weights(const dpmt_ctx* c, int k, const Packing& pk, bool tensor) {
@@ -376,7 +584,69 @@ std::vector<double> operand_weights(const dpmt_ctx* c, int k, const Packing& pk,
 // fragment width: 16 bytes for FP32/BF16, 32 for FP8.  FP8 operands are made
 // on the device at every call (their scales depend on the features), from an
 // FP32 master copy in the same element order.
+// CP mode: every group cut into chunks of 4 filter columns; per chunk the
+// channel factors in MFMA B-operand order (batches of 4 filters x 4 terms),
+// then each filter's row and column factors transposed (a_r[n] at r*h + n,
+// then b_r[m] at R*h + r*w + m).
+dpmt_status prepare_cp(dpmt_ctx* c) {
+    ModeData& md = c->modes[DPMT_CP_FP32];
+    if (md.ready) return DPMT_OK;
+    if (!c->cp_ready) return fail(c, DPMT_E_STATE, "CP mode needs dpmt_decompose_cp or dpmt_load_cp first");
+    std::vector<CpChunk> chunks;
+    std::vector<float> fac;
+    md.cp_chunk0.assign(c->groups.size(), 0);
+    md.max_h = 0;
+    for (size_t gi = 0; gi < c->groups.size(); ++gi) {
+        const HostGroup& hg = c->groups[gi];
+        md.cp_chunk0[gi] = (int)chunks.size();
+        if (hg.role != ROLE_ALL) md.max_h = std::max(md.max_h, hg.h);
+        const int ng = (int)hg.filters.size();
+        for (int f0 = 0; f0 < ng; f0 += 4) {
+            CpChunk ch{};
+            int kk[4] = {-1, -1, -1, -1};
+            for (int j = 0; j < 4; ++j)
+                if (f0 + j < ng) {
+                    kk[j] = hg.filters[f0 + j];
+                    ch.R[j] = c->cp_rank[kk[j]];
+                    ch.nq = std::max(ch.nq, (ch.R[j] + 3) / 4);
+                }
+            ch.c_off = (int64_t)fac.size();
+            fac.resize(fac.size() + (size_t)ch.nq * 64 * 8, 0.f);
+            for (int q = 0; q < ch.nq; ++q)
+                for (int lane = 0; lane < 64; ++lane) {
+                    const int col = lane & 15, j = col >> 2, r = 4 * q + (col & 3);
+                    if (kk[j] < 0 || r >= ch.R[j]) continue;
+                    const int k = kk[j], R = ch.R[j];
+                    const float* Ck = c->cp_fac.data() + c->cp_off[k] + (int64_t)(hg.h + hg.w) * R;
+                    for (int st = 0; st < 8; ++st)
+                        fac[ch.c_off + ((size_t)q * 64 + lane) * 8 + st] = Ck[(8 * (lane >> 4) + st) * R + r];
+                }
+            for (int j = 0; j < 4; ++j) {
+                if (kk[j] < 0) continue;
+                const int k = kk[j], R = ch.R[j];
+                const float* Ak = c->cp_fac.data() + c->cp_off[k];
+                const float* Bk = Ak + (int64_t)hg.h * R;
+                ch.ab_off[j] = (int64_t)fac.size();
+                for (int r = 0; r < R; ++r)
+                    for (int n = 0; n < hg.h; ++n) fac.push_back(Ak[n * R + r]);
+                for (int r = 0; r < R; ++r)
+                    for (int m = 0; m < hg.w; ++m) fac.push_back(Bk[m * R + r]);
+            }
+            chunks.push_back(ch);
+        }
+    }
+    fac.resize(fac.size() + 8, 0.f);
+    if (c->has_device()) {
+        HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
+        HIP_TRY(c, upload(&md.dCpChunks, chunks), "upload CP chunk table");
+        HIP_TRY(c, upload(&md.dCpFac, fac), "upload CP factors");
+    }
+    md.ready = true;
+    return DPMT_OK;
+}
+
 dpmt_status prepare_mode(dpmt_ctx* c, dpmt_mode mode) {
+    if (mode == DPMT_CP_FP32) return prepare_cp(c);
     ModeData& md = c->modes[mode];
     if (md.ready) return DPMT_OK;
     const bool tensor = mode != DPMT_DIRECT_FP32;
@@ -626,12 +896,102 @@ dpmt_status prepare_tiles(dpmt_ctx* c, dpmt_mode mode, ModeData::TileSet** out) 
     return DPMT_OK;
 }
 
+// CP tiles of one (level, group) block: 32 output columns by as many rows as
+// the 1024-cell halo allows, each walking up to CP_CHUNKS_PER_TILE chunks.
+void add_cp_tiles(std::vector<CpTile>& tiles, const HostGroup& hg, int chunk0, int64_t x_cell,
+                  int64_t out_off, int rng, int H, int W) {
+    const int Ho = H - hg.h + 1, Wo = W - hg.w + 1;
+    if (Ho <= 0 || Wo <= 0) return;
+    const int HX = cp_halo_cols(hg.w), HY = cp_halo_rows(hg.w), TYo = HY - hg.h + 1;
+    const int nch = ((int)hg.filters.size() + 3) / 4;
+    for (int y0 = 0; y0 < Ho; y0 += TYo)
+        for (int x0 = 0; x0 < Wo; x0 += CP_TX)
+            for (int q = 0; q < nch; q += CP_CHUNKS_PER_TILE) {
+                CpTile t{};
+                t.x_cell = x_cell;
+                t.out_off = out_off;
+                t.H = H;
+                t.W = W;
+                t.Ho = Ho;
+                t.Wo = Wo;
+                t.ld = pitch_of(Wo);
+                t.rng = rng;
+                t.y0 = y0;
+                t.x0 = x0;
+                t.h = hg.h;
+                t.w = hg.w;
+                t.HY = HY;
+                t.HX = HX;
+                t.chunk0 = chunk0 + q;
+                t.nchunk = std::min(CP_CHUNKS_PER_TILE, nch - q);
+                t.col0 = 4 * q;
+                tiles.push_back(t);
+            }
+}
+
+// CP tiles for the current plan, in the three orders of the launch strategies.
+dpmt_status prepare_cp_tiles(dpmt_ctx* c, ModeData::CpTileSet** out) {
+    ModeData& md = c->modes[DPMT_CP_FP32];
+    ModeData::CpTileSet& ts = md.cp;
+    *out = &ts;
+    if (ts.plan_id == c->plan_id && (ts.dTiles || ts.n_tiles == 0)) return DPMT_OK;
+    dfree(ts.dTiles);
+    dfree(ts.dTilesLvl);
+    dfree(ts.dTilesChunk);
+    ts = ModeData::CpTileSet{};
+    std::vector<CpTile> tiles;                     // blocks are ordered by (image, level, group)
+    std::vector<int> chunk_key;                    // per tile: dependency chunk of the overlapped strategy
+    for (const auto& kv : c->blocks) {
+        const BlockKey& k = kv.first;
+        const LevelInfo& lv = c->pyr[k.img][k.level];
+        const HostGroup& hg = c->groups[k.group];
+        const size_t b0 = tiles.size();
+        add_cp_tiles(tiles, hg, md.cp_chunk0[k.group], lv.cell_offset, kv.second.off, (int)kv.second.rng,
+                     lv.rows, lv.cols);
+        if (tiles.size() == b0) continue;
+        auto it = c->chunk_of.find({k.img, hg.role == ROLE_ROOT ? k.level : k.level + c->octave[k.img]});
+        chunk_key.resize(tiles.size(), it == c->chunk_of.end() ? 0 : it->second);
+        if (!ts.lvl.empty() && ts.lvl.back()[0] == k.img && ts.lvl.back()[1] == k.level)
+            ts.lvl.back()[3] = (int)tiles.size();
+        else
+            ts.lvl.push_back({k.img, k.level, (int)b0, (int)tiles.size()});
+    }
+    if (tiles.size() > (size_t)INT32_MAX) return fail(c, DPMT_E_UNSUPPORTED, "batch too large for one launch");
+    for (const CpTile& t : tiles) ts.lds = std::max(ts.lds, cp_lds_bytes(t.HX, t.HY));
+    HIP_TRY(c, upload(&ts.dTilesLvl, tiles), "upload CP tiles");
+    auto cost = [](const CpTile& t) { return (int64_t)t.h * t.w; };
+    {   // chunk order for the overlapped strategy, most expensive first within a chunk
+        std::vector<int> idx(tiles.size());
+        for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
+        std::stable_sort(idx.begin(), idx.end(), [&](int a, int b) {
+            if (chunk_key[a] != chunk_key[b]) return chunk_key[a] < chunk_key[b];
+            return cost(tiles[a]) > cost(tiles[b]);
+        });
+        std::vector<CpTile> ct;
+        ct.reserve(idx.size());
+        ts.chunk.assign(std::max(c->n_chunks, 1), {0, 0});
+        for (size_t j = 0; j < idx.size(); ++j) {
+            const int ck = chunk_key[idx[j]];
+            if (j == 0 || ck != chunk_key[idx[j - 1]]) ts.chunk[ck][0] = (int)j;
+            ts.chunk[ck][1] = (int)j + 1;
+            ct.push_back(tiles[idx[j]]);
+        }
+        HIP_TRY(c, upload(&ts.dTilesChunk, ct), "upload CP tiles");
+    }
+    std::stable_sort(tiles.begin(), tiles.end(), [&](const CpTile& a, const CpTile& b) { return cost(a) > cost(b); });
+    HIP_TRY(c, upload(&ts.dTiles, tiles), "upload CP tiles");
+    ts.n_tiles = (int)tiles.size();
+    ts.plan_id = c->plan_id;
+    return DPMT_OK;
+}
+
 dpmt_status score_checks(dpmt_ctx* c, dpmt_mode mode, const float* features_dev,
                          const float* scores_dev) {
     if (!c) return fail(nullptr, DPMT_E_INVALID, "ctx is NULL");
-    if (mode < DPMT_DIRECT_FP32 || mode > DPMT_TENSOR_FP8) return fail(c, DPMT_E_INVALID, "unknown mode");
+    if (mode < DPMT_DIRECT_FP32 || mode > DPMT_CP_FP32) return fail(c, DPMT_E_INVALID, "unknown mode");
     if (!c->loaded) return fail(c, DPMT_E_STATE, "score call before dpmt_load_filters");
-    if (mode != DPMT_DIRECT_FP32 && !c->decomposed) return fail(c, DPMT_E_STATE, "tensor mode needs dpmt_decompose first");
+    if (is_tensor(mode) && !c->decomposed) return fail(c, DPMT_E_STATE, "tensor mode needs dpmt_decompose first");
+    if (mode == DPMT_CP_FP32 && !c->cp_ready) return fail(c, DPMT_E_STATE, "CP mode needs dpmt_decompose_cp or dpmt_load_cp first");
     if (!c->planned) return fail(c, DPMT_E_STATE, "score call before dpmt_plan");
     if (!c->has_device()) return fail(c, DPMT_E_STATE, "host-only context cannot score");
     if (!features_dev || (!scores_dev && c->layout.n_score > 0)) return fail(c, DPMT_E_INVALID, "features_dev and scores_dev are required");
@@ -644,8 +1004,13 @@ dpmt_status score_prepare(dpmt_ctx* c, dpmt_mode mode, hipStream_t st) {
     HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
     dpmt_status s = prepare_mode(c, mode);
     if (s != DPMT_OK) return s;
-    ModeData::TileSet* ts = nullptr;
-    if ((s = prepare_tiles(c, mode, &ts)) != DPMT_OK) return s;
+    if (mode == DPMT_CP_FP32) {
+        ModeData::CpTileSet* cts = nullptr;
+        if ((s = prepare_cp_tiles(c, &cts)) != DPMT_OK) return s;
+    } else {
+        ModeData::TileSet* ts = nullptr;
+        if ((s = prepare_tiles(c, mode, &ts)) != DPMT_OK) return s;
+    }
     if (!c->aux_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->aux_stream, hipStreamNonBlocking), "hipStreamCreate");
     while ((int)c->chunk_ev.size() < c->n_chunks + 2) {
         hipEvent_t e = nullptr;
@@ -653,7 +1018,7 @@ dpmt_status score_prepare(dpmt_ctx* c, dpmt_mode mode, hipStream_t st) {
         c->chunk_ev.push_back(e);
     }
     ModeData& md = c->modes[mode];
-    if (mode != DPMT_DIRECT_FP32) {
+    if (is_tensor(mode)) {
         const size_t need = (size_t)c->n_cells * md.pk.RP * md.pk.esz;
         if (need > c->Z_bytes) {
             HIP_TRY(c, hipStreamSynchronize(st), "hipStreamSynchronize");
@@ -679,24 +1044,47 @@ CorrLaunch corr_launch(const ModeData& md) {
     return CorrLaunch{md.kind, md.pk, tc.ty, tc.bb, tc.wy, tc.persistent};
 }
 
+// Correlation of the tiles [b, e) of one order of the current tile set
+// (0: cost order, 1: (image, level) order, 2: chunk order).
+hipError_t corr_tiles(dpmt_ctx* c, dpmt_mode mode, int order, int b, int e, const float* X,
+                      hipStream_t st) {
+    ModeData& md = c->modes[mode];
+    if (mode == DPMT_CP_FP32) {
+        ModeData::CpTileSet& ts = md.cp;
+        const CpTile* t = order == 0 ? ts.dTiles : order == 1 ? ts.dTilesLvl : ts.dTilesChunk;
+        return launch_cp_corr(t + b, e - b, md.dCpChunks, X, md.dCpFac, c->d_resp, c->d_rkeys, c->n_slots,
+                              ts.lds, st);
+    }
+    ModeData::TileSet& ts = current_tiles(c, mode);
+    const CorrTile* t = order == 0 ? ts.dTiles : order == 1 ? ts.dTilesLvl : ts.dTilesChunk;
+    const void* Z = is_tensor(mode) ? c->d_Z : static_cast<const void*>(X);
+    return launch_corr(corr_launch(md), t + b, e - b, md.dGroups, Z, md.dG, md.dTk, c->d_resp, c->d_rkeys,
+                       c->n_slots, md.max_h, md.max_S, st);
+}
+
+int n_corr_tiles(dpmt_ctx* c, dpmt_mode mode) {
+    return mode == DPMT_CP_FP32 ? c->modes[mode].cp.n_tiles : current_tiles(c, mode).n_tiles;
+}
+const std::vector<std::array<int, 4>>& corr_levels(dpmt_ctx* c, dpmt_mode mode) {
+    return mode == DPMT_CP_FP32 ? c->modes[mode].cp.lvl : current_tiles(c, mode).lvl;
+}
+const std::vector<std::array<int, 2>>& corr_chunks(dpmt_ctx* c, dpmt_mode mode) {
+    return mode == DPMT_CP_FP32 ? c->modes[mode].cp.chunk : current_tiles(c, mode).chunk;
+}
+
 // The whole call as one launch per stage: value-range reset, projection of
 // every level, correlation of every tile, placement of every score map.
 hipError_t enqueue_batched(dpmt_ctx* c, dpmt_mode mode, const float* X, float* scores,
                            int16_t* offs, hipStream_t st, hipEvent_t* ev) {
     ModeData& md = c->modes[mode];
-    ModeData::TileSet& ts = current_tiles(c, mode);
-    const bool tensor = mode != DPMT_DIRECT_FP32;
-    const void* Z = tensor ? c->d_Z : static_cast<const void*>(X);
     hipError_t e = ev ? hipEventRecord(ev[0], st) : hipSuccess;
     if (e == hipSuccess) e = launch_range_init(c->d_rkeys, c->n_slots, st);
     if (e == hipSuccess) {
         if (mode == DPMT_TENSOR_FP8) e = fp8_operands(c, md, X, c->n_cells, c->d_Z, st);
-        else if (tensor) e = launch_project(md.pk.esz == 2, X, c->n_cells, md.dU, md.pk.RP, c->d_Z, st);
+        else if (is_tensor(mode)) e = launch_project(md.pk.esz == 2, X, c->n_cells, md.dU, md.pk.RP, c->d_Z, st);
     }
     if (e == hipSuccess && ev) e = hipEventRecord(ev[1], st);
-    if (e == hipSuccess)
-        e = launch_corr(corr_launch(md), ts.dTiles, ts.n_tiles, md.dGroups, Z, md.dG, md.dTk, c->d_resp,
-                        c->d_rkeys, c->n_slots, md.max_h, md.max_S, st);
+    if (e == hipSuccess) e = corr_tiles(c, mode, 0, 0, n_corr_tiles(c, mode), X, st);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[2], st);
     if (e == hipSuccess)
         e = launch_place(c->d_maps, c->d_parts, c->d_place_blk, (int)c->place_blk.size(), c->d_resp,
@@ -711,14 +1099,11 @@ hipError_t enqueue_batched(dpmt_ctx* c, dpmt_mode mode, const float* X, float* s
 hipError_t enqueue_per_level(dpmt_ctx* c, dpmt_mode mode, const float* X, float* scores,
                              int16_t* offs, hipStream_t st, hipEvent_t* ev) {
     ModeData& md = c->modes[mode];
-    ModeData::TileSet& ts = current_tiles(c, mode);
-    const bool tensor = mode != DPMT_DIRECT_FP32;
-    const void* Z = tensor ? c->d_Z : static_cast<const void*>(X);
     const size_t zcell = (size_t)md.pk.RP * md.pk.esz;
     hipError_t e = ev ? hipEventRecord(ev[0], st) : hipSuccess;
     if (e == hipSuccess) e = launch_range_init(c->d_rkeys, c->n_slots, st);
     if (e == hipSuccess && mode == DPMT_TENSOR_FP8) e = fp8_prepare(md, X, c->n_cells, st);
-    for (size_t i = 0; i < c->pyr.size() && e == hipSuccess && tensor; ++i)
+    for (size_t i = 0; i < c->pyr.size() && e == hipSuccess && is_tensor(mode); ++i)
         for (const LevelInfo& lv : c->pyr[i]) {
             if (e != hipSuccess) break;
             const int64_t n = (int64_t)lv.rows * lv.cols;
@@ -728,11 +1113,9 @@ hipError_t enqueue_per_level(dpmt_ctx* c, dpmt_mode mode, const float* X, float*
                                         : launch_project(md.pk.esz == 2, Xl, n, md.dU, md.pk.RP, Zl, st);
         }
     if (e == hipSuccess && ev) e = hipEventRecord(ev[1], st);
-    const CorrLaunch cl = corr_launch(md);
-    for (const auto& r : ts.lvl) {
+    for (const auto& r : corr_levels(c, mode)) {
         if (e != hipSuccess) break;
-        e = launch_corr(cl, ts.dTilesLvl + r[2], r[3] - r[2], md.dGroups, Z, md.dG, md.dTk, c->d_resp,
-                        c->d_rkeys, c->n_slots, md.max_h, md.max_S, st);
+        e = corr_tiles(c, mode, 1, r[2], r[3], X, st);
     }
     if (e == hipSuccess && ev) e = hipEventRecord(ev[2], st);
     for (const auto& r : c->place_lvl) {
@@ -750,24 +1133,20 @@ hipError_t enqueue_per_level(dpmt_ctx* c, dpmt_mode mode, const float* X, float*
 hipError_t enqueue_overlap(dpmt_ctx* c, dpmt_mode mode, const float* X, float* scores,
                            int16_t* offs, hipStream_t st, hipEvent_t* ev) {
     ModeData& md = c->modes[mode];
-    ModeData::TileSet& ts = current_tiles(c, mode);
-    const bool tensor = mode != DPMT_DIRECT_FP32;
-    const void* Z = tensor ? c->d_Z : static_cast<const void*>(X);
     const int K = c->n_chunks;
     hipError_t e = ev ? hipEventRecord(ev[0], st) : hipSuccess;
     if (e == hipSuccess) e = launch_range_init(c->d_rkeys, c->n_slots, st);
     if (e == hipSuccess) {
         if (mode == DPMT_TENSOR_FP8) e = fp8_operands(c, md, X, c->n_cells, c->d_Z, st);
-        else if (tensor) e = launch_project(md.pk.esz == 2, X, c->n_cells, md.dU, md.pk.RP, c->d_Z, st);
+        else if (is_tensor(mode)) e = launch_project(md.pk.esz == 2, X, c->n_cells, md.dU, md.pk.RP, c->d_Z, st);
     }
     if (e == hipSuccess && ev) e = hipEventRecord(ev[1], st);
     hipEvent_t fork = c->chunk_ev[K], join = c->chunk_ev[K + 1];
     if (e == hipSuccess) e = hipEventRecord(fork, st);
     if (e == hipSuccess) e = hipStreamWaitEvent(c->aux_stream, fork, 0);
-    const CorrLaunch cl = corr_launch(md);
+    const auto& chunks = corr_chunks(c, mode);
     for (int k = 0; k < K && e == hipSuccess; ++k) {
-        e = launch_corr(cl, ts.dTilesChunk + ts.chunk[k][0], ts.chunk[k][1] - ts.chunk[k][0], md.dGroups,
-                        Z, md.dG, md.dTk, c->d_resp, c->d_rkeys, c->n_slots, md.max_h, md.max_S, st);
+        e = corr_tiles(c, mode, 2, chunks[k][0], chunks[k][1], X, st);
         if (e == hipSuccess) e = hipEventRecord(c->chunk_ev[k], st);
         if (e == hipSuccess) e = hipStreamWaitEvent(c->aux_stream, c->chunk_ev[k], 0);
         if (e == hipSuccess)
@@ -890,6 +1269,10 @@ dpmt_status dpmt_load_filters(dpmt_ctx* c, int32_t n_filters, const dpmt_shape* 
     for (auto& m : c->modes) m.tile_cfg = 0;
     c->planned = false;
     c->decomposed = false;
+    c->cp_ready = false;
+    c->cp_rank.clear();
+    c->cp_off.clear();
+    c->cp_fac.clear();
     c->shapes.assign(shapes, shapes + n_filters);
     c->woff.resize(n_filters);
     int64_t off = 0;
@@ -965,6 +1348,98 @@ dpmt_status dpmt_decompose(dpmt_ctx* c, int32_t rank, double* sigma_out, double*
         if (s != DPMT_OK) return s;
     }
     c->err.clear();
+    return DPMT_OK;
+}
+
+namespace {
+// Replace the CP factors and drop what was built from the previous ones.
+void set_cp(dpmt_ctx* c, std::vector<int> rank, std::vector<int64_t> off, std::vector<float> fac) {
+    if (c->has_device()) {
+        (void)hipSetDevice(c->device);
+        (void)hipDeviceSynchronize();
+    }
+    drop_graph(c);
+    free_mode(c->modes[DPMT_CP_FP32]);
+    c->cp_rank = std::move(rank);
+    c->cp_off = std::move(off);
+    c->cp_fac = std::move(fac);
+    c->cp_ready = true;
+}
+
+dpmt_status cp_ranks_check(dpmt_ctx* c, const int32_t* ranks, std::vector<int64_t>& off, int64_t& total) {
+    if (!ranks) return fail(c, DPMT_E_INVALID, "ranks is NULL");
+    off.assign(c->shapes.size(), 0);
+    total = 0;
+    for (size_t k = 0; k < c->shapes.size(); ++k) {
+        if (ranks[k] < 1 || ranks[k] > 32) return fail(c, DPMT_E_RANK, "rank of filter " + std::to_string(k) + " outside [1, 32]");
+        off[k] = total;
+        total += (int64_t)ranks[k] * (c->shapes[k].h + c->shapes[k].w + 32);
+    }
+    return DPMT_OK;
+}
+}  // namespace
+
+dpmt_status dpmt_decompose_cp(dpmt_ctx* c, const int32_t* ranks, int32_t max_iters, double tol,
+                              double* rel_err_out) {
+    if (!c) return fail(nullptr, DPMT_E_INVALID, "ctx is NULL");
+    if (!c->loaded) return fail(c, DPMT_E_STATE, "dpmt_decompose_cp before dpmt_load_filters");
+    if (max_iters < 1) return fail(c, DPMT_E_INVALID, "max_iters must be >= 1");
+    if (!(tol >= 0) || !std::isfinite(tol)) return fail(c, DPMT_E_INVALID, "tol must be finite and >= 0");
+    std::vector<int64_t> off;
+    int64_t total = 0;
+    dpmt_status s = cp_ranks_check(c, ranks, off, total);
+    if (s != DPMT_OK) return s;
+    const int nf = (int)c->shapes.size();
+    std::vector<float> fac((size_t)total);
+    std::vector<double> err(nf);
+    // filters are independent: fitted on up to 16 host threads
+    const int nt = std::max(1, std::min<int>({16, nf, (int)std::max(1u, std::thread::hardware_concurrency())}));
+    auto work = [&](int t0) {
+        for (int k = t0; k < nf; k += nt) {
+            const int h = c->shapes[k].h, w = c->shapes[k].w, R = ranks[k];
+            const CpFit fit = cp_als(c->weights.data() + c->woff[k], h, w, 32, R, max_iters, tol);
+            float* dst = fac.data() + off[k];
+            for (size_t i = 0; i < fit.A.size(); ++i) dst[i] = (float)fit.A[i];
+            dst += fit.A.size();
+            for (size_t i = 0; i < fit.B.size(); ++i) dst[i] = (float)fit.B[i];
+            dst += fit.B.size();
+            for (size_t i = 0; i < fit.C.size(); ++i) dst[i] = (float)fit.C[i];
+            err[k] = fit.rel_err;
+        }
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t) pool.emplace_back(work, t);
+    work(0);
+    for (auto& th : pool) th.join();
+    set_cp(c, std::vector<int>(ranks, ranks + nf), std::move(off), std::move(fac));
+    if (rel_err_out) std::memcpy(rel_err_out, err.data(), nf * sizeof(double));
+    c->err.clear();
+    return DPMT_OK;
+}
+
+dpmt_status dpmt_load_cp(dpmt_ctx* c, const int32_t* ranks, const float* factors_host) {
+    if (!c) return fail(nullptr, DPMT_E_INVALID, "ctx is NULL");
+    if (!c->loaded) return fail(c, DPMT_E_STATE, "dpmt_load_cp before dpmt_load_filters");
+    std::vector<int64_t> off;
+    int64_t total = 0;
+    dpmt_status s = cp_ranks_check(c, ranks, off, total);
+    if (s != DPMT_OK) return s;
+    if (!factors_host) return fail(c, DPMT_E_INVALID, "factors_host is NULL");
+    for (int64_t i = 0; i < total; ++i)
+        if (!std::isfinite(factors_host[i])) return fail(c, DPMT_E_INVALID, "non-finite CP factor at element " + std::to_string(i));
+    set_cp(c, std::vector<int>(ranks, ranks + c->shapes.size()), std::move(off),
+           std::vector<float>(factors_host, factors_host + total));
+    c->err.clear();
+    return DPMT_OK;
+}
+
+dpmt_status dpmt_get_cp(const dpmt_ctx* c, int32_t* ranks_out, float* factors_out, int64_t* n_floats) {
+    if (!c) return fail(nullptr, DPMT_E_INVALID, "ctx is NULL");
+    if (!c->cp_ready) return fail(const_cast<dpmt_ctx*>(c), DPMT_E_STATE, "no CP factors");
+    if (n_floats) *n_floats = (int64_t)c->cp_fac.size();
+    if (ranks_out)
+        for (size_t k = 0; k < c->cp_rank.size(); ++k) ranks_out[k] = c->cp_rank[k];
+    if (factors_out) std::memcpy(factors_out, c->cp_fac.data(), c->cp_fac.size() * sizeof(float));
     return DPMT_OK;
 }
 
@@ -1334,8 +1809,9 @@ const char* dpmt_tile_config_name(int32_t config) {
 
 dpmt_status dpmt_set_tile_config(dpmt_ctx* c, dpmt_mode mode, int32_t config) {
     if (!c) return fail(nullptr, DPMT_E_INVALID, "ctx is NULL");
-    if (mode < DPMT_DIRECT_FP32 || mode > DPMT_TENSOR_FP8) return fail(c, DPMT_E_INVALID, "unknown mode");
+    if (mode < DPMT_DIRECT_FP32 || mode > DPMT_CP_FP32) return fail(c, DPMT_E_INVALID, "unknown mode");
     if (config < 0 || config >= N_TILE_CFGS) return fail(c, DPMT_E_INVALID, "tile configuration out of range");
+    if (mode == DPMT_CP_FP32 && config != 0) return fail(c, DPMT_E_UNSUPPORTED, "the CP mode has one tile shape (configuration 0)");
     const TileCfg& tc = TILE_CFGS[config];
     int max_h = 0;
     for (const auto& sh : c->shapes) max_h = std::max(max_h, sh.h);
@@ -1346,7 +1822,7 @@ dpmt_status dpmt_set_tile_config(dpmt_ctx* c, dpmt_mode mode, int32_t config) {
 }
 
 int32_t dpmt_get_tile_config(const dpmt_ctx* c, dpmt_mode mode) {
-    if (!c || mode < DPMT_DIRECT_FP32 || mode > DPMT_TENSOR_FP8) return -1;
+    if (!c || mode < DPMT_DIRECT_FP32 || mode > DPMT_CP_FP32) return -1;
     return c->modes[mode].tile_cfg;
 }
 
@@ -1371,6 +1847,7 @@ dpmt_status dpmt_autotune(dpmt_ctx* c, dpmt_mode mode, const float* features_dev
         if (ms_out) ms_out[k] = -1.f;
         const TileCfg& tc = TILE_CFGS[k];
         if (!corr_shape_supported(tc.ty, tc.bb, tc.wy, max_h)) continue;
+        if (mode == DPMT_CP_FP32 && k != 0) continue;
         md.tile_cfg = k;
         if ((s = score_prepare(c, mode, st)) != DPMT_OK) break;
         std::vector<float> t;
@@ -1429,9 +1906,10 @@ dpmt_status dpmt_level_responses(dpmt_ctx* c, dpmt_mode mode, const float* featu
                                  int32_t image, int32_t level, float* out_dev, int64_t capacity,
                                  int64_t* n_written, void* hip_stream) {
     if (!c) return fail(nullptr, DPMT_E_INVALID, "ctx is NULL");
-    if (mode < DPMT_DIRECT_FP32 || mode > DPMT_TENSOR_FP8) return fail(c, DPMT_E_INVALID, "unknown mode");
+    if (mode < DPMT_DIRECT_FP32 || mode > DPMT_CP_FP32) return fail(c, DPMT_E_INVALID, "unknown mode");
     if (!c->loaded) return fail(c, DPMT_E_STATE, "dpmt_level_responses before dpmt_load_filters");
-    if (mode != DPMT_DIRECT_FP32 && !c->decomposed) return fail(c, DPMT_E_STATE, "tensor mode needs dpmt_decompose first");
+    if (is_tensor(mode) && !c->decomposed) return fail(c, DPMT_E_STATE, "tensor mode needs dpmt_decompose first");
+    if (mode == DPMT_CP_FP32 && !c->cp_ready) return fail(c, DPMT_E_STATE, "CP mode needs dpmt_decompose_cp or dpmt_load_cp first");
     if (!c->planned) return fail(c, DPMT_E_STATE, "dpmt_level_responses before dpmt_plan");
     if (!c->has_device()) return fail(c, DPMT_E_STATE, "host-only context cannot compute");
     if (image < 0 || image >= (int)c->pyr.size()) return fail(c, DPMT_E_INVALID, "image out of range");
@@ -1454,33 +1932,40 @@ dpmt_status dpmt_level_responses(dpmt_ctx* c, dpmt_mode mode, const float* featu
     if (s != DPMT_OK) return s;
     ModeData& md = c->modes[mode];
     hipStream_t st = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
-    const bool tensor = mode != DPMT_DIRECT_FP32;
+    const bool tensor = is_tensor(mode);
     // per-group planes in a temporary buffer, then copied to per-filter maps
     std::vector<CorrTile> tiles;
+    std::vector<CpTile> cp_tiles;
     struct GB { int g; int64_t off; int Ho, Wo, ld; };
     std::vector<GB> gblocks;
     int64_t blk_total = 0;
     int max_h = 0, max_S = 0;
     for (size_t g = 0; g < c->groups.size(); ++g) {
         if (c->groups[g].role != ROLE_ALL) continue;
-        const GroupDesc& gd = md.groups[g];
-        const int Ho = lv.rows - gd.h + 1, Wo = lv.cols - gd.w + 1;
+        const HostGroup& hg = c->groups[g];
+        const int Ho = lv.rows - hg.h + 1, Wo = lv.cols - hg.w + 1;
         if (Ho <= 0 || Wo <= 0) continue;
-        add_tiles(tiles, gd, (int)g, 0, blk_total, -1, lv.rows, lv.cols, 16, 2, 1);
+        if (mode == DPMT_CP_FP32) {
+            add_cp_tiles(cp_tiles, hg, md.cp_chunk0[g], lv.cell_offset, blk_total, -1, lv.rows, lv.cols);
+        } else {
+            const GroupDesc& gd = md.groups[g];
+            add_tiles(tiles, gd, (int)g, 0, blk_total, -1, lv.rows, lv.cols, 16, 2, 1);
+            max_S = std::max(max_S, gd.S);
+        }
         gblocks.push_back({(int)g, blk_total, Ho, Wo, pitch_of(Wo)});
-        blk_total += (int64_t)Ho * pitch_of(Wo) * gd.ng;
-        max_h = std::max(max_h, gd.h);
-        max_S = std::max(max_S, gd.S);
+        blk_total += (int64_t)Ho * pitch_of(Wo) * (int64_t)hg.filters.size();
+        max_h = std::max(max_h, hg.h);
     }
-    if (tiles.empty()) return DPMT_OK;
+    if (tiles.empty() && cp_tiles.empty()) return DPMT_OK;
     const int64_t cells = (int64_t)lv.rows * lv.cols;
     void* dZ = nullptr;
     float* dblk = nullptr;
     CorrTile* dtiles = nullptr;
+    CpTile* dcp = nullptr;
     int64_t* doff = nullptr;
     auto cleanup = [&]() {
         (void)hipStreamSynchronize(st);
-        dfree(dZ); dfree(dblk); dfree(dtiles); dfree(doff);
+        dfree(dZ); dfree(dblk); dfree(dtiles); dfree(dcp); dfree(doff);
     };
     hipError_t e = hipSuccess;
     const void* Zsrc = features_dev + lv.cell_offset * 32;
@@ -1493,9 +1978,16 @@ dpmt_status dpmt_level_responses(dpmt_ctx* c, dpmt_mode mode, const float* featu
         Zsrc = dZ;
     }
     if (e == hipSuccess) e = hipMalloc((void**)&dblk, (size_t)blk_total * 4);
-    if (e == hipSuccess) e = upload(&dtiles, tiles);
-    CorrLaunch cl{md.kind, md.pk, 4, 2, 4, 0};
-    if (e == hipSuccess) e = launch_corr(cl, dtiles, (int)tiles.size(), md.dGroups, Zsrc, md.dG, md.dTk, dblk, nullptr, 0, max_h, max_S, st);
+    if (mode == DPMT_CP_FP32) {
+        size_t lds = 0;
+        for (const CpTile& t : cp_tiles) lds = std::max(lds, cp_lds_bytes(t.HX, t.HY));
+        if (e == hipSuccess) e = upload(&dcp, cp_tiles);
+        if (e == hipSuccess) e = launch_cp_corr(dcp, (int)cp_tiles.size(), md.dCpChunks, features_dev, md.dCpFac, dblk, nullptr, 0, lds, st);
+    } else {
+        if (e == hipSuccess) e = upload(&dtiles, tiles);
+        CorrLaunch cl{md.kind, md.pk, 4, 2, 4, 0};
+        if (e == hipSuccess) e = launch_corr(cl, dtiles, (int)tiles.size(), md.dGroups, Zsrc, md.dG, md.dTk, dblk, nullptr, 0, max_h, max_S, st);
+    }
     for (const auto& gb : gblocks) {
         if (e != hipSuccess) break;
         const HostGroup& hg = c->groups[gb.g];

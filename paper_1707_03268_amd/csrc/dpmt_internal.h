@@ -90,6 +90,47 @@ struct Detection {
     float score;
 };
 
+// Per-filter CP form (Section 4): filter k ~ sum_r a_r (x) b_r (x) c_r with
+// its own rank R_k.  Responses go to the same filter-major planes as the
+// other flavours.  A chunk is 4 consecutive filter columns of a group; its
+// channel factors are packed for the MFMA B operand in batches of 16 columns
+// (4 filters x 4 rank terms): [batch][lane][8] floats, lane = column + 16 * g
+// holding c[8g + s] of column (filter lane%16 / 4, term 4*batch + lane%4) at
+// K-step s.  Row and column factors of filter j: R_j x h floats a_r[n], then
+// R_j x w floats b_r[m], at ab_off[j].
+struct CpChunk {
+    int64_t c_off;     // float offset of the chunk's packed channel factors
+    int64_t ab_off[4]; // float offset of each filter's row / column factors
+    int32_t R[4];      // ranks (0: no filter in that slot)
+    int32_t nq;        // batches of 4 rank terms: max ceil(R / 4)
+    int32_t pad;
+};
+
+// One workgroup tile of the CP correlation: up to 32 output cols x TYo rows of
+// one level, the halo (HY x HX cells, HX a multiple of 4, HX * HY <= 1024)
+// held in registers while the tile walks nchunk chunks of one group.
+struct CpTile {
+    int64_t x_cell;    // first cell of the level in the feature buffer
+    int64_t out_off;   // element offset of the group's first response plane
+    int32_t H, W;      // level rows, cols
+    int32_t Ho, Wo;    // response rows, cols
+    int32_t ld;        // plane row pitch
+    int32_t rng;       // range slot of the group's first plane (-1: no ranges)
+    int32_t y0, x0;    // first output row, col (x0 a multiple of 32)
+    int32_t h, w;      // filter rows, cols
+    int32_t HY, HX;    // halo rows, cols
+    int32_t chunk0;    // first chunk (index into the chunk table)
+    int32_t nchunk;    // chunks walked
+    int32_t col0;      // filter column of the first chunk's first filter
+    int32_t pad;
+};
+constexpr int CP_HALO = 1024;             // halo cells per CP tile
+constexpr int CP_TX = 32;                 // output cols per CP tile
+// halo geometry of a CP tile for a filter of w columns
+inline int cp_halo_cols(int w) { return (CP_TX + w - 1 + 3) & ~3; }
+inline int cp_halo_rows(int w) { return CP_HALO / cp_halo_cols(w); }
+size_t cp_lds_bytes(int HX, int HY);
+
 // Correlation kernel flavours.
 enum CorrKind { CORR_F32 = 0, CORR_BF16 = 1, CORR_FP8 = 2 };
 
@@ -136,6 +177,11 @@ hipError_t launch_corr(const CorrLaunch& cfg, const CorrTile* tiles, int n_tiles
                        const GroupDesc* groups, const void* Z, const void* G, const float* tk,
                        float* out, int* rkeys, int64_t n_slots, int max_h, int max_S,
                        hipStream_t st);
+// CP correlation of every tile (one workgroup per tile).  lds_bytes: the
+// largest cp_lds_bytes over the tiles.
+hipError_t launch_cp_corr(const CpTile* tiles, int n_tiles, const CpChunk* chunks, const float* X,
+                          const float* fac, float* out, int* rkeys, int64_t n_slots, size_t lds_bytes,
+                          hipStream_t st);
 hipError_t launch_fp8_prepare(const float* X, int64_t n_cells, const float* U, int RP,
                               float* partial, float* scales, const RequantBlock* blocks,
                               int n_blocks, const float* master, uint8_t* G, float* tk,

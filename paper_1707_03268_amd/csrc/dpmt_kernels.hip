@@ -629,6 +629,173 @@ hipError_t launch_corr(const CorrLaunch& cfg, const CorrTile* tiles, int n_tiles
 }
 
 // ---------------------------------------------------------------------------
+// CP correlation (Section 4).  For every rank term r of filter k:
+//   P_r = X x_3 c_r     channel contraction, MFMA 16x16x4 FP32: halo cells x
+//                       16 columns (4 filters x 4 terms) x 32 channels
+//   Q_r = P_r o_x b_r   1-D correlation along x (VALU, P from LDS)
+//   S_k += Q_r o_y a_r  1-D correlation along y (VALU, registers)
+// A tile loads its halo (HY x HX cells, 32 channels) into registers once and
+// walks its chunks of 4 filters.  The 16 P planes of a batch live in LDS from
+// the contraction to the end of the 1-D passes.  In the 1-D passes wave v owns
+// filter v of the chunk; lane (cq = lane % 8, rg = lane / 8) owns output cols
+// 4cq .. 4cq+3 of tile rows rg*RG .. rg*RG+RG-1, RG = ceil(TYo / 8) <= 4.
+// ---------------------------------------------------------------------------
+typedef float v4f __attribute__((ext_vector_type(4)));
+constexpr int CP_RBW = CP_HALO / 16 / 4;   // 16-cell row blocks per wave
+
+size_t cp_lds_bytes(int HX, int HY) {
+    // 16 planes, plus the rows past the halo that lanes beyond the tile's last
+    // output row read (their values are never stored) and the x-window overrun
+    return ((size_t)16 * HX * HY + 8 * (size_t)HX + 8) * 4;
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void cp_corr_kernel(
+    const CpTile* __restrict__ tiles, const CpChunk* __restrict__ chunks, const float* __restrict__ X,
+    const float* __restrict__ fac, float* __restrict__ out, int* __restrict__ rmax,
+    int* __restrict__ rmin) {
+    extern __shared__ __align__(16) float cp_lds[];
+    const CpTile& t = tiles[blockIdx.x];
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int HX = t.HX, NPX = t.HX * t.HY, h = t.h, w = t.w;
+    const float inv_hx = 1.f / (float)HX;
+    // halo cell of row block b = wv + 4i: 16b + lane % 16, channels
+    // 8 (lane / 16) .. +7 (the K index of step s is channel 8 (lane / 16) + s)
+    float xr[CP_RBW][8];
+#pragma unroll
+    for (int i = 0; i < CP_RBW; ++i) {
+        const int px = (wv + 4 * i) * 16 + (lane & 15);
+        const int row = (int)(((float)px + 0.5f) * inv_hx);   // exact: px < 2^11, HX <= 64
+        const int col = px - row * HX;
+        const int gy = t.y0 + row, gx = t.x0 + col;
+        const bool ok = px < NPX && gy < t.H && gx < t.W;
+        const int cy = min(gy, t.H - 1), cx = min(gx, t.W - 1);
+        const float4* src = reinterpret_cast<const float4*>(X + (t.x_cell + (int64_t)cy * t.W + cx) * 32 +
+                                                            8 * (lane >> 4));
+        const float4 v0 = src[0], v1 = src[1];
+        xr[i][0] = ok ? v0.x : 0.f;
+        xr[i][1] = ok ? v0.y : 0.f;
+        xr[i][2] = ok ? v0.z : 0.f;
+        xr[i][3] = ok ? v0.w : 0.f;
+        xr[i][4] = ok ? v1.x : 0.f;
+        xr[i][5] = ok ? v1.y : 0.f;
+        xr[i][6] = ok ? v1.z : 0.f;
+        xr[i][7] = ok ? v1.w : 0.f;
+    }
+    const int TYo = t.HY - h + 1;
+    const int RG = (TYo + 7) >> 3;
+    const int cq = lane & 7, ry = (lane >> 3) * RG;
+    for (int ci = 0; ci < t.nchunk; ++ci) {
+        const CpChunk& ch = chunks[t.chunk0 + ci];
+        const int R = ch.R[wv];
+        const float* fa = fac + ch.ab_off[wv];          // a_r[n] at r*h + n
+        const float* fb = fa + R * h;                   // b_r[m] at r*w + m
+        float acc[4][4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int c = 0; c < 4; ++c) acc[j][c] = 0.f;
+        for (int q = 0; q < ch.nq; ++q) {
+            {   // contraction: P planes of the batch's 16 columns at every halo cell
+                const float4* bs = reinterpret_cast<const float4*>(fac + ch.c_off + ((int64_t)q * 64 + lane) * 8);
+                const float4 b0 = bs[0], b1 = bs[1];
+                const float bv[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+#pragma unroll
+                for (int i = 0; i < CP_RBW; ++i) {
+                    v4f d = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int s = 0; s < 8; ++s) d = __builtin_amdgcn_mfma_f32_16x16x4f32(xr[i][s], bv[s], d, 0, 0, 0);
+                    // D[cell 16b + 4 (lane / 16) + v][column lane % 16]
+                    const int px = (wv + 4 * i) * 16 + 4 * (lane >> 4);
+                    if (px < NPX)
+                        *reinterpret_cast<float4*>(cp_lds + (lane & 15) * NPX + px) = make_float4(d[0], d[1], d[2], d[3]);
+                }
+            }
+            __syncthreads();
+            for (int rr = 0; rr < 4; ++rr) {            // 1-D passes of this wave's filter
+                const int r = 4 * q + rr;
+                if (r >= R) break;
+                const float* P = cp_lds + (4 * wv + rr) * NPX + ry * HX + 4 * cq;
+                const float* ar = fa + r * h;
+                const float* br = fb + r * w;
+                for (int hr = 0; hr < RG + h - 1; ++hr) {
+                    const float* prow = P + hr * HX;
+                    float qv[4] = {0.f, 0.f, 0.f, 0.f};
+                    float4 lo = *reinterpret_cast<const float4*>(prow);
+                    for (int m0 = 0; m0 < w; m0 += 4) {
+                        const float4 hi = *reinterpret_cast<const float4*>(prow + m0 + 4);
+                        const float win[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            if (m0 + e < w) {
+                                const float bm = br[m0 + e];
+#pragma unroll
+                                for (int c = 0; c < 4; ++c) qv[c] = fmaf(bm, win[e + c], qv[c]);
+                            }
+                        }
+                        lo = hi;
+                    }
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int n = hr - j;
+                        if (j < RG && n >= 0 && n < h) {
+                            const float an = ar[n];
+#pragma unroll
+                            for (int c = 0; c < 4; ++c) acc[j][c] = fmaf(an, qv[c], acc[j][c]);
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if (R > 0) {                                    // filter column col0 + 4 ci + wv
+            const int f = t.col0 + 4 * ci + wv;
+            const int x = t.x0 + 4 * cq;
+            float vmax = -INFINITY, vmin = INFINITY;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int yr = ry + j, y = t.y0 + yr;
+                if (j >= RG || yr >= TYo || y >= t.Ho || x >= t.Wo) continue;
+                *reinterpret_cast<float4*>(out + t.out_off + ((int64_t)f * t.Ho + y) * t.ld + x) =
+                    make_float4(acc[j][0], acc[j][1], acc[j][2], acc[j][3]);
+#pragma unroll
+                for (int c = 0; c < 4; ++c)
+                    if (x + c < t.Wo) {
+                        vmax = fmaxf(vmax, acc[j][c]);
+                        vmin = fminf(vmin, acc[j][c]);
+                    }
+            }
+            if (rmax != nullptr && t.rng >= 0) {
+#pragma unroll
+                for (int o = 32; o >= 1; o >>= 1) {
+                    vmax = fmaxf(vmax, __shfl_xor(vmax, o, 64));
+                    vmin = fminf(vmin, __shfl_xor(vmin, o, 64));
+                }
+                if (lane == 0 && vmax >= vmin) {
+                    atomicMax(rmax + t.rng + f, range_key(vmax));
+                    atomicMin(rmin + t.rng + f, range_key(vmin));
+                }
+            }
+        }
+    }
+}
+
+hipError_t launch_cp_corr(const CpTile* tiles, int n_tiles, const CpChunk* chunks, const float* X,
+                          const float* fac, float* out, int* rkeys, int64_t n_slots, size_t lds_bytes,
+                          hipStream_t st) {
+    if (n_tiles <= 0) return hipSuccess;
+    if (lds_bytes > 160 * 1024) return hipErrorInvalidValue;
+    if (lds_bytes > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(cp_corr_kernel),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(cp_corr_kernel, dim3(n_tiles), dim3(256), lds_bytes, st, tiles, chunks, X, fac, out,
+                       rkeys, rkeys ? rkeys + n_slots : nullptr);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // FP8 (OCP e4m3) operands with per-channel scales
 //
 // The contraction runs over projected channels r, so a scale per channel

@@ -258,3 +258,84 @@ def test_detect_validation():
     assert st == _abi.DPMT_E_STATE                       # host-only context
     assert lib.dpmt_detect(None, None, 0.0, None, 0, None, None) == _abi.DPMT_E_INVALID
     ctx.close()
+
+
+# ------------------------------------------------------------ per-filter CP form
+def test_cp_validation_host_only():
+    wl, fs, comps = _tiny_bank()
+    ctx = Context(device=-1)
+    with pytest.raises(DpmtError) as e:
+        ctx.decompose_cp(4)
+    assert e.value.status == _abi.DPMT_E_STATE
+    ctx.load_filters(fs, comps)
+    n = len(fs)
+    for bad in (0, 33):
+        with pytest.raises(DpmtError) as e:
+            ctx.decompose_cp(bad)
+        assert e.value.status == _abi.DPMT_E_RANK
+    lib = _abi.load()
+    r = np.full(n, 3, np.int32)
+    rp = r.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    assert lib.dpmt_decompose_cp(ctx._h, rp, 0, 1e-6, None) == _abi.DPMT_E_INVALID
+    assert lib.dpmt_decompose_cp(ctx._h, rp, 5, -1.0, None) == _abi.DPMT_E_INVALID
+    assert lib.dpmt_decompose_cp(ctx._h, rp, 5, float("nan"), None) == _abi.DPMT_E_INVALID
+    assert lib.dpmt_decompose_cp(ctx._h, None, 5, 1e-6, None) == _abi.DPMT_E_INVALID
+    with pytest.raises(DpmtError) as e:
+        ctx.get_cp(wl.bank.shapes)
+    assert e.value.status == _abi.DPMT_E_STATE
+    ctx.plan(wl.pyramids)
+    # the CP mode without factors is out of order
+    st = lib.dpmt_score_pyramid(ctx._h, _abi.CP_FP32, ctypes.c_void_p(16), ctypes.c_void_p(16), None, None)
+    assert st == _abi.DPMT_E_STATE
+    # non-finite factors are refused, finite ones round-trip exactly
+    rng = np.random.default_rng(0)
+    fac = [(rng.standard_normal((h, 3)), rng.standard_normal((w, 3)), rng.standard_normal((32, 3)))
+           for (h, w) in wl.bank.shapes]
+    bad = [tuple(m.copy() for m in abc) for abc in fac]
+    bad[2][1][0, 0] = np.inf
+    with pytest.raises(DpmtError) as e:
+        ctx.load_cp(3, bad)
+    assert e.value.status == _abi.DPMT_E_INVALID
+    ctx.load_cp(3, fac)
+    ranks, got = ctx.get_cp(wl.bank.shapes)
+    assert np.all(ranks == 3)
+    for a, b in zip(fac, got):
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x.astype(np.float32), y)
+    # only tile configuration 0 exists for the CP mode
+    with pytest.raises(DpmtError) as e:
+        ctx.set_tile_config("cp_fp32", 1)
+    assert e.value.status == _abi.DPMT_E_UNSUPPORTED
+    ctx.set_tile_config("cp_fp32", 0)
+    assert ctx.get_tile_config("cp_fp32") == 0
+    ctx.close()
+
+
+def test_cp_als_matches_oracle_and_recovers_planted_rank():
+    """The library's host ALS against the oracle's pins: a planted rank-R bank
+    is fitted to rounding, and on the synthetic bank both reach the same error."""
+    wl, fs, comps = _tiny_bank()
+    rng = np.random.default_rng(3)
+    planted = []
+    for f in fs:
+        h, w, _ = f.shape
+        A, B, C = rng.standard_normal((h, 3)), rng.standard_normal((w, 3)), rng.standard_normal((32, 3))
+        planted.append(oracle.cp_reconstruct(A, B, C).astype(np.float32))
+    ctx = Context(device=-1)
+    ctx.load_filters(planted, comps)
+    err = ctx.decompose_cp(3, max_iters=3000, tol=1e-7)
+    assert err.max() < 1e-6, err
+    ranks, fac = ctx.get_cp(wl.bank.shapes)
+    for f, (A, B, C) in zip(planted, fac):
+        rec = oracle.cp_reconstruct(A.astype(np.float64), B.astype(np.float64), C.astype(np.float64))
+        assert np.linalg.norm(rec - f) <= 1e-5 * np.linalg.norm(f)
+    # the synthetic bank at ranks 2, 6 and 9 (beyond the 6-row mode)
+    ctx.load_filters(fs, comps)
+    for R in (2, 6, 9):
+        err = ctx.decompose_cp(R, max_iters=200, tol=1e-12)
+        for k in (0, 1, 4):
+            f = fs[k].astype(np.float64)
+            cp = oracle.cp_als(f, R, iters=200, eps=1e-12)
+            e_or = cp.errors[-1] / np.linalg.norm(f)
+            assert abs(err[k] - e_or) <= 0.02 * e_or + 1e-9, (R, k, err[k], e_or)
+    ctx.close()

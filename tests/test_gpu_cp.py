@@ -1,0 +1,162 @@
+"""GPU parity of the per-filter CP form (Section 4): the decomposed
+correlation (channel contraction, then 1-D correlations along x and y) and the
+scores built on it, against the oracle's FP64 decomposed correlation with the
+same factors.
+
+The factors are the library's own ALS fit read back (or random factors loaded
+through dpmt_load_cp), so the comparison isolates the GPU arithmetic: FP32
+products and sums against FP64, well inside 1e-4 on these magnitudes.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+from _gpu_common import Cmp, GpuRun, compare_map, note
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+TOL_CP = 1e-4
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _cp_context(wl, ranks, factors=None):
+    from paper_1707_03268_amd import Context
+    ctx = Context(0)
+    ctx.load_filters(wl.bank.filters, wl.bank.components)
+    if factors is None:
+        ctx.decompose_cp(ranks, max_iters=60, tol=1e-9)
+    else:
+        ctx.load_cp(ranks, factors)
+    _, fac = ctx.get_cp(wl.bank.shapes)
+    fac64 = [tuple(m.astype(np.float64) for m in abc) for abc in fac]
+    return ctx, fac64
+
+
+def _check_level_responses(ctx, wl, fac64, feats, levels):
+    worst = 0.0
+    n = 0
+    for (img, lvl) in levels:
+        out, total = ctx.level_responses("cp_fp32", feats, img, lvl)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        X = wl.level_features(img, lvl).astype(np.float64)
+        H, W = X.shape[:2]
+        off = 0
+        for k, (h, w) in enumerate(wl.bank.shapes):
+            Ho, Wo = H - h + 1, W - w + 1
+            if Ho <= 0 or Wo <= 0:
+                continue
+            want = oracle.cp_response(X, *fac64[k])
+            g = got[off:off + Ho * Wo].reshape(Ho, Wo)
+            off += Ho * Wo
+            err = float(np.max(np.abs(g - want)))
+            worst = max(worst, err)
+            n += Ho * Wo
+            assert err <= TOL_CP, f"image {img} level {lvl} filter {k} ({h}x{w}): max |err| {err:.3g}"
+        assert off == total
+    return worst, n
+
+
+@pytest.mark.parametrize("R", [1, 5, 8])
+def test_cp_level_responses_c1(R):
+    """Every filter on both c1 levels (80x60 and 40x30 cells: several tiles,
+    ragged tails in both directions); R = 5 leaves a partial batch of terms,
+    R = 8 needs two."""
+    wl = workloads.config1()
+    note(f"cp level responses c1 R={R}")
+    ctx, fac = _cp_context(wl, R)
+    feats = torch.from_numpy(wl.features()).cuda()
+    worst, n = _check_level_responses(ctx, wl, fac, feats, [(0, 0), (0, 1)])
+    note(f"  {n} responses, max |err| {worst:.3g}")
+    ctx.close()
+
+
+def test_cp_random_factors_mixed_ranks_c2():
+    """Factors loaded from outside with per-filter ranks across [1, 32] (all
+    eight batches of terms, chunks whose filters differ in rank), on c2 levels
+    from the largest down to ones smaller than a filter."""
+    wl = workloads.config2()
+    rng = np.random.default_rng(11)
+    ranks = rng.integers(1, 33, size=len(wl.bank.filters))
+    ranks[:3] = [32, 1, 17]
+    fac = [(rng.standard_normal((h, R)) * 0.5, rng.standard_normal((w, R)) * 0.5,
+            rng.standard_normal((32, R)) * 0.3) for (h, w), R in zip(wl.bank.shapes, ranks)]
+    note(f"cp random factors c2, ranks {ranks.min()}..{ranks.max()}")
+    ctx, fac64 = _cp_context(wl, ranks, fac)
+    feats = torch.from_numpy(wl.features()).cuda()
+    lv = wl.pyramids[0].levels
+    picks = [0, 3, 17, len(lv) - 6, len(lv) - 1]
+    worst, n = _check_level_responses(ctx, wl, fac64, feats, [(0, l) for l in picks])
+    note(f"  {n} responses, max |err| {worst:.3g}")
+    ctx.close()
+
+
+def _oracle_cp_map(wl, fac, image, level, comp, cache):
+    pyr = wl.pyramids[image]
+    for l in (level, level - pyr.octave):
+        if (image, l) not in cache:
+            cache[(image, l)] = wl.level_features(image, l).astype(np.float64)
+    c = wl.bank.components[comp]
+    rr = oracle.cp_response(cache[(image, level)], *fac[c.root])
+    prs = [oracle.cp_response(cache[(image, level - pyr.octave)], *fac[k]) for k in c.parts]
+    return oracle.score_component(rr, prs, c.anchors, c.deform)
+
+
+def _scores(ctx, lay, feats):
+    scores = torch.full((max(lay.n_score, 1),), float("nan"), dtype=torch.float32, device="cuda")
+    offs = torch.full((max(lay.n_offsets, 1),), -32768, dtype=torch.int16, device="cuda")
+    ctx.score_pyramid("cp_fp32", feats, scores, offs)
+    torch.cuda.synchronize()
+    return scores.cpu().numpy(), offs.cpu().numpy()
+
+
+@pytest.mark.parametrize("cfg,R,every", [(1, 6, 1), (2, 6, 3)])
+def test_cp_scores_against_oracle(cfg, R, every):
+    """Scores and placements of the CP mode (every map of c1, every third of
+    c2) against the oracle's star-model scores over its CP responses."""
+    wl = workloads.config1() if cfg == 1 else workloads.config2()
+    note(f"cp scores c{cfg} R={R}")
+    ctx, fac = _cp_context(wl, R)
+    lay = ctx.plan(wl.pyramids)
+    feats = torch.from_numpy(wl.features()).cuda()
+    s, o = _scores(ctx, lay, feats)
+    run = GpuRun(lay, s, o, None, None)
+    cmp = Cmp()
+    cache = {}
+    for k in range(0, lay.n_maps, every):
+        img, lvl, comp = int(lay.map_image[k]), int(lay.map_level[k]), int(lay.map_comp[k])
+        if lay.map_rows[k] == 0 or lay.map_cols[k] == 0:
+            continue
+        sm = _oracle_cp_map(wl, fac, img, lvl, comp, cache)
+        compare_map(run, wl, img, lvl, comp, sm, TOL_CP, cmp)
+    note(f"  {cmp.n_pos} positions, max |err| {cmp.max_err:.3g}, placements checked "
+         f"{cmp.n_arg_checked}/{cmp.n_arg}")
+    assert cmp.n_pos > 0
+    ctx.close()
+
+
+def test_cp_launch_strategies_bitwise_equal():
+    wl = workloads.uneven_batch()
+    note("cp launch strategies")
+    ctx, _ = _cp_context(wl, 6)
+    lay = ctx.plan(wl.pyramids)
+    feats = torch.from_numpy(wl.features()).cuda()
+    ref_s, ref_o = _scores(ctx, lay, feats)
+    assert np.isfinite(ref_s).any()
+    for launch in ("per_level", "overlap", "graph", "graph"):
+        ctx.set_launch(launch)
+        s, o = _scores(ctx, lay, feats)
+        np.testing.assert_array_equal(s, ref_s, err_msg=launch)
+        np.testing.assert_array_equal(o, ref_o, err_msg=launch)
+        torch.randn(1 << 18, device="cuda").mul_(2.0).sum().item()     # eager work between replays
+    ctx.set_launch("batched")
+    ctx.close()

@@ -320,6 +320,9 @@ def test_cp_als_error_never_increases():
         assert np.all(np.diff(e) <= 1e-12 * e[:-1] + 1e-14), R
         errs[R] = e[-1]
     assert errs[1] >= errs[3] >= errs[6]
+    # terms beyond a mode's size (6 rows, 6 cols) still lower the error
+    e8 = oracle.cp_als(f, 8, iters=60).errors[-1]
+    assert e8 < errs[6] * 0.98, (e8, errs[6])
     # rank 1 with a planted rank-1 tensor is exact
     a, b, c = rng.standard_normal(6), rng.standard_normal(11), rng.standard_normal(32)
     f1 = np.einsum("n,m,l->nml", a, b, c)
