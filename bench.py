@@ -71,6 +71,35 @@ def corr_work(wl, mode: str, rank: int):
     return flops, feat_bytes + filt_bytes + 4 * resp, resp
 
 
+def mult_counts(wl, rank: int, cp_rank: int) -> dict:
+    """Multiplications per step of the three ways to correlate (Section 4's
+    counting): direct h*w*32 per response; per-filter CP form R*(32 + h + w)
+    per response (channel contraction, then 1-D correlations along x and y);
+    shared feature-mode basis h*w*R per response plus 32*R per projected cell."""
+    shapes = wl.bank.shapes
+    roots = [c.root for c in wl.bank.components]
+    parts = sorted({p for c in wl.bank.components for p in c.parts})
+    out = {"direct": 0, "cp": 0, "shared_basis": 0}
+    for pyr in wl.pyramids:
+        L = len(pyr.levels)
+        for l, lv in enumerate(pyr.levels):
+            used = False
+            for ks, ok in ((roots, l >= pyr.octave), (parts, l + pyr.octave < L)):
+                if not ok:
+                    continue
+                for k in ks:
+                    h, w = shapes[k]
+                    if lv.rows >= h and lv.cols >= w:
+                        n = (lv.rows - h + 1) * (lv.cols - w + 1)
+                        out["direct"] += n * h * w * 32
+                        out["cp"] += n * cp_rank * (32 + h + w)
+                        out["shared_basis"] += n * h * w * rank
+                        used = True
+            if used:
+                out["shared_basis"] += lv.rows * lv.cols * 32 * rank
+    return out
+
+
 def kernel_source_digest() -> str:
     """SHA-256 of the kernel sources; byte counters recorded for another
     digest describe other kernels and are not reported."""
@@ -218,6 +247,8 @@ def main() -> None:
     ap.add_argument("--mode", default="tensor_bf16", choices=list(TOL))
     ap.add_argument("--rank", type=int, default=16)
     ap.add_argument("--no-direct", action="store_true", help="skip the direct FP32 comparison run")
+    ap.add_argument("--cp-rank", type=int, default=6,
+                    help="rank of the per-filter CP form timed for comparison (0: skip)")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work (0: skip)")
     ap.add_argument("--launch", default="batched", choices=["batched", "per_level", "graph", "overlap"],
                     help="launch strategy of the timed steps")
@@ -303,6 +334,26 @@ def main() -> None:
                   "correlation_frac_fp32_mfma": dflops / (dstages["correlation"] * 1e-3) / 1e12 / PEAK_FP32_TFLOPS}
         log(f"direct_fp32: {dms:.3f} ms/step")
 
+    cp = None
+    if args.cp_rank > 0:
+        t0 = time.time()
+        cp_err = ctx.decompose_cp(args.cp_rank, max_iters=60, tol=1e-9)
+        als_s = time.time() - t0
+        cms, cstages, _, _, _ = run_mode(ctx, "cp_fp32", feats, max(2, min(args.steps, 5)), 1, torch)
+        mults = mult_counts(wl, args.rank, args.cp_rank)
+        ctf = 2 * mults["cp"] / (cstages["correlation"] * 1e-3) / 1e12
+        cp = {"rank": args.cp_rank, "value": lay.n_resp / (cms * 1e-3), "ms_per_step": cms,
+              "stages_ms": {k: round(v, 4) for k, v in cstages.items()},
+              "als_seconds": als_s, "als_rel_err_mean": float(cp_err.mean()),
+              "als_rel_err_max": float(cp_err.max()),
+              "roofline": {"bound": "alu", "achieved": ctf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                           "frac": ctf / PEAK_FP32_TFLOPS, "kernel": "cp_corr_kernel",
+                           "flops": 2 * mults["cp"]},
+              "multiplies": mults,
+              "formula1_gain_6x6_parts": 6 * 6 * 32 / (args.cp_rank * (6 + 6 + 32))}
+        log(f"cp_fp32 R={args.cp_rank}: {cms:.3f} ms/step (ALS {als_s:.1f} s, mean rel err "
+            f"{cp_err.mean():.3g}), stages {cstages}")
+
     # roofline of each kernel; the headline object is the dominant one
     flops, cbytes, cresp = corr_work(wl, args.mode, args.rank)
     peak_mfma = {"tensor_bf16": PEAK_BF16_TFLOPS, "tensor_fp8": PEAK_FP8_TFLOPS}.get(args.mode, PEAK_FP32_TFLOPS)
@@ -354,6 +405,7 @@ def main() -> None:
         "placement_roofline": rf_place,
         "direct_fp32": direct,
         "tensor_vs_direct": (value / direct["value"]) if direct else None,
+        "cp_fp32": cp,
         "score_error_vs_oracle": err,
     }
     print(json.dumps(out), flush=True)

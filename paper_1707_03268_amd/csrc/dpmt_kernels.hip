@@ -649,15 +649,24 @@ size_t cp_lds_bytes(int HX, int HY) {
     return ((size_t)16 * HX * HY + 8 * (size_t)HX + 8) * 4;
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void cp_corr_kernel(
-    const CpTile* __restrict__ tiles, const CpChunk* __restrict__ chunks, const float* __restrict__ X,
-    const float* __restrict__ fac, float* __restrict__ out, int* __restrict__ rmax,
-    int* __restrict__ rmin) {
-    extern __shared__ __align__(16) float cp_lds[];
-    const CpTile& t = tiles[blockIdx.x];
+// One CP tile.  HS, WS > 0: a filter shape known at compile time (halo
+// geometry, loop trip counts and the filter's row and column factors in
+// registers, both 1-D passes fully unrolled); HS = WS = 0: any shape, with
+// rolled loops and factors read as they are used.
+template <int HS, int WS>
+__device__ __forceinline__ void cp_tile(const CpTile& t, const CpChunk* __restrict__ chunks,
+                                        const float* __restrict__ X, const float* __restrict__ fac,
+                                        float* __restrict__ out, int* __restrict__ rmax,
+                                        int* __restrict__ rmin, float* __restrict__ lds) {
+    constexpr bool FIXED = HS > 0 && WS > 0;
+    constexpr int HXc = FIXED ? ((CP_TX + WS - 1 + 3) & ~3) : 4;
+    constexpr int HYc = FIXED ? CP_HALO / HXc : 1;
+    constexpr int RGc = FIXED ? (HYc - HS + 1 + 7) / 8 : 4;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int HX = t.HX, NPX = t.HX * t.HY, h = t.h, w = t.w;
+    const int h = FIXED ? HS : t.h, w = FIXED ? WS : t.w;
+    const int HX = FIXED ? HXc : t.HX, HY = FIXED ? HYc : t.HY;
+    const int NPX = HX * HY;
     const float inv_hx = 1.f / (float)HX;
     // halo cell of row block b = wv + 4i: 16b + lane % 16, channels
     // 8 (lane / 16) .. +7 (the K index of step s is channel 8 (lane / 16) + s)
@@ -682,8 +691,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
         xr[i][6] = ok ? v1.z : 0.f;
         xr[i][7] = ok ? v1.w : 0.f;
     }
-    const int TYo = t.HY - h + 1;
-    const int RG = (TYo + 7) >> 3;
+    const int TYo = HY - h + 1;
+    const int RG = FIXED ? RGc : (TYo + 7) >> 3;
     const int cq = lane & 7, ry = (lane >> 3) * RG;
     for (int ci = 0; ci < t.nchunk; ++ci) {
         const CpChunk& ch = chunks[t.chunk0 + ci];
@@ -708,40 +717,76 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
                     // D[cell 16b + 4 (lane / 16) + v][column lane % 16]
                     const int px = (wv + 4 * i) * 16 + 4 * (lane >> 4);
                     if (px < NPX)
-                        *reinterpret_cast<float4*>(cp_lds + (lane & 15) * NPX + px) = make_float4(d[0], d[1], d[2], d[3]);
+                        *reinterpret_cast<float4*>(lds + (lane & 15) * NPX + px) = make_float4(d[0], d[1], d[2], d[3]);
                 }
             }
             __syncthreads();
             for (int rr = 0; rr < 4; ++rr) {            // 1-D passes of this wave's filter
                 const int r = 4 * q + rr;
                 if (r >= R) break;
-                const float* P = cp_lds + (4 * wv + rr) * NPX + ry * HX + 4 * cq;
+                const float* P = lds + (4 * wv + rr) * NPX + ry * HX + 4 * cq;
                 const float* ar = fa + r * h;
                 const float* br = fb + r * w;
-                for (int hr = 0; hr < RG + h - 1; ++hr) {
-                    const float* prow = P + hr * HX;
-                    float qv[4] = {0.f, 0.f, 0.f, 0.f};
-                    float4 lo = *reinterpret_cast<const float4*>(prow);
-                    for (int m0 = 0; m0 < w; m0 += 4) {
-                        const float4 hi = *reinterpret_cast<const float4*>(prow + m0 + 4);
-                        const float win[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+                if constexpr (FIXED) {
+                    constexpr int NW = (WS + 3 + 3) / 4;    // 16-byte reads covering x .. x+3+WS-1
+                    float ac[HS], bc[WS];
 #pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            if (m0 + e < w) {
-                                const float bm = br[m0 + e];
+                    for (int n = 0; n < HS; ++n) ac[n] = ar[n];
 #pragma unroll
-                                for (int c = 0; c < 4; ++c) qv[c] = fmaf(bm, win[e + c], qv[c]);
+                    for (int m = 0; m < WS; ++m) bc[m] = br[m];
+#pragma unroll
+                    for (int hr = 0; hr < RGc + HS - 1; ++hr) {
+                        float win[4 * NW];
+#pragma unroll
+                        for (int u = 0; u < NW; ++u) {
+                            const float4 v = *reinterpret_cast<const float4*>(P + hr * HXc + 4 * u);
+                            win[4 * u] = v.x;
+                            win[4 * u + 1] = v.y;
+                            win[4 * u + 2] = v.z;
+                            win[4 * u + 3] = v.w;
+                        }
+                        float qv[4];
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            qv[c] = 0.f;
+#pragma unroll
+                            for (int m = 0; m < WS; ++m) qv[c] = fmaf(bc[m], win[c + m], qv[c]);
+                        }
+#pragma unroll
+                        for (int j = 0; j < RGc; ++j) {
+                            const int n = hr - j;
+                            if (n >= 0 && n < HS) {
+#pragma unroll
+                                for (int c = 0; c < 4; ++c) acc[j][c] = fmaf(ac[n], qv[c], acc[j][c]);
                             }
                         }
-                        lo = hi;
                     }
+                } else {
+                    for (int hr = 0; hr < RG + h - 1; ++hr) {
+                        const float* prow = P + hr * HX;
+                        float qv[4] = {0.f, 0.f, 0.f, 0.f};
+                        float4 lo = *reinterpret_cast<const float4*>(prow);
+                        for (int m0 = 0; m0 < w; m0 += 4) {
+                            const float4 hi = *reinterpret_cast<const float4*>(prow + m0 + 4);
+                            const float win[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int n = hr - j;
-                        if (j < RG && n >= 0 && n < h) {
-                            const float an = ar[n];
+                            for (int e = 0; e < 4; ++e) {
+                                if (m0 + e < w) {
+                                    const float bm = br[m0 + e];
 #pragma unroll
-                            for (int c = 0; c < 4; ++c) acc[j][c] = fmaf(an, qv[c], acc[j][c]);
+                                    for (int c = 0; c < 4; ++c) qv[c] = fmaf(bm, win[e + c], qv[c]);
+                                }
+                            }
+                            lo = hi;
+                        }
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const int n = hr - j;
+                            if (j < RG && n >= 0 && n < h) {
+                                const float an = ar[n];
+#pragma unroll
+                                for (int c = 0; c < 4; ++c) acc[j][c] = fmaf(an, qv[c], acc[j][c]);
+                            }
                         }
                     }
                 }
@@ -778,6 +823,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void c
             }
         }
     }
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void cp_corr_kernel(
+    const CpTile* __restrict__ tiles, const CpChunk* __restrict__ chunks, const float* __restrict__ X,
+    const float* __restrict__ fac, float* __restrict__ out, int* __restrict__ rmax,
+    int* __restrict__ rmin) {
+    extern __shared__ __align__(16) float cp_lds[];
+    const CpTile& t = tiles[blockIdx.x];
+    // compiled shapes: the DPM part filter and the usual root filters
+    if (t.h == 6 && t.w == 6) cp_tile<6, 6>(t, chunks, X, fac, out, rmax, rmin, cp_lds);
+    else if (t.h == 6 && t.w == 11) cp_tile<6, 11>(t, chunks, X, fac, out, rmax, rmin, cp_lds);
+    else if (t.h == 7 && t.w == 13) cp_tile<7, 13>(t, chunks, X, fac, out, rmax, rmin, cp_lds);
+    else if (t.h == 8 && t.w == 15) cp_tile<8, 15>(t, chunks, X, fac, out, rmax, rmin, cp_lds);
+    else cp_tile<0, 0>(t, chunks, X, fac, out, rmax, rmin, cp_lds);
 }
 
 hipError_t launch_cp_corr(const CpTile* tiles, int n_tiles, const CpChunk* chunks, const float* X,

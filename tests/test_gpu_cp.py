@@ -38,6 +38,7 @@ def _cp_context(wl, ranks, factors=None):
         ctx.load_cp(ranks, factors)
     _, fac = ctx.get_cp(wl.bank.shapes)
     fac64 = [tuple(m.astype(np.float64) for m in abc) for abc in fac]
+    ctx.plan(wl.pyramids)
     return ctx, fac64
 
 
