@@ -115,16 +115,18 @@ def recorded_traffic(kernel: str, config: int, mode: str, rank, tile_config: int
     """HBM bytes per launch of `kernel` measured with rocprofv3 FETCH_SIZE and
     WRITE_SIZE (scaled by a plain copy's counter reading), from the summary in
     profiles/, if it was taken on the current kernel sources with the same
-    correlation tile configuration."""
+    correlation tile configuration (tile_config None: any, for kernels that do
+    not depend on it)."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
     if not os.path.exists(path):
         return None
     digest = kernel_source_digest()
-    want = [kernel, f"c{config}", mode, str(rank if mode != "direct_fp32" else 0), str(tile_config), digest]
+    want = [kernel, f"c{config}", mode, str(rank if mode != "direct_fp32" else 0),
+            None if tile_config is None else str(tile_config), digest]
     with open(path) as f:
         for line in f:
             t = line.split()
-            if len(t) == 9 and t[0] == "traffic" and t[1:7] == want:
+            if len(t) == 9 and t[0] == "traffic" and all(w is None or w == v for w, v in zip(want, t[1:7])):
                 return int(float(t[7]) + float(t[8]))
     return None
 
@@ -348,7 +350,9 @@ def main() -> None:
               "als_rel_err_max": float(cp_err.max()),
               "roofline": {"bound": "alu", "achieved": ctf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                            "frac": ctf / PEAK_FP32_TFLOPS, "kernel": "cp_corr_kernel",
-                           "flops": 2 * mults["cp"]},
+                           "flops": 2 * mults["cp"],
+                           "traffic": recorded_traffic("cp_corr_kernel", args.config, "cp_fp32",
+                                                       args.cp_rank, 0)},
               "multiplies": mults,
               "formula1_gain_6x6_parts": 6 * 6 * 32 / (args.cp_rank * (6 + 6 + 32))}
         log(f"cp_fp32 R={args.cp_rank}: {cms:.3f} ms/step (ALS {als_s:.1f} s, mean rel err "
@@ -375,8 +379,7 @@ def main() -> None:
     pgbs = pbytes / (place_ms * 1e-3) / 1e9
     rf_place = {"bound": "hbm", "achieved": pgbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": pgbs / PEAK_HBM_GBS, "kernel": "place_kernel", "bytes": pbytes,
-                "traffic": recorded_traffic("place_kernel", args.config, args.mode, args.rank,
-                                            ctx.get_tile_config(args.mode))}
+                "traffic": recorded_traffic("place_kernel", args.config, args.mode, args.rank, None)}
     roof = dict(rf_corr if corr_ms >= place_ms else rf_place)
 
     cpu = None

@@ -389,6 +389,37 @@ def cp_response(X: np.ndarray, A: np.ndarray, B: np.ndarray, C: np.ndarray) -> n
     return out
 
 
+def rank_bound(e: float, r: int, N: int, M: int, L: int) -> float:
+    """Right-hand side of the rank criterion of Section 4:
+    e * (r (N + M + L) / (N M L))^2."""
+    return e * (r * (N + M + L) / (N * M * L)) ** 2
+
+
+def select_rank(f: np.ndarray, e: float, r_max: int, iters: int = 200) -> Tuple[int, List[float]]:
+    """Smallest r in [1, r_max] with ||f - CP(f, r)||_F < rank_bound(e, r, ...)
+    (Section 4), by binary search over r (the error falls and the bound grows
+    with r, so the predicate switches from false to true once); r_max when no
+    r satisfies it.  Returns (r, relative errors of the fits tried)."""
+    f = np.asarray(f, np.float64)
+    N, M, L = f.shape
+    tried = {}
+
+    def ok(r):
+        if r not in tried:
+            cp = cp_als(f, r, iters=iters, eps=1e-13)
+            tried[r] = cp.errors[-1]
+        return tried[r] < rank_bound(e, r, N, M, L)
+
+    lo, hi = 1, r_max
+    while lo < hi:
+        mid = (lo + hi) // 2
+        if ok(mid):
+            hi = mid
+        else:
+            lo = mid + 1
+    return lo, [tried[r] for r in sorted(tried)]
+
+
 # --------------------------------------------------------------------------
 # Detection set (Algorithm 1: a hypothesis joins D when its score reaches tau)
 # --------------------------------------------------------------------------

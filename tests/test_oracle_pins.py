@@ -355,3 +355,37 @@ def test_cp_response_bruteforce_tiny():
                     for m in range(3):
                         want[y, x] += A[n, r] * B[m, r] * float(np.dot(X[y + n, x + m], C[:, r]))
     np.testing.assert_allclose(got, want, rtol=0, atol=1e-12)
+
+
+# ------------------------------------------------------------ rank selection
+def test_rank_bound_closed_form():
+    # e (r (N+M+L) / (N M L))^2 at N = M = 6, L = 32, r = 6 (Section 5's example size)
+    assert oracle.rank_bound(2.0, 6, 6, 6, 32) == pytest.approx(2.0 * (6 * 44 / 1152) ** 2, rel=1e-15)
+    # formula (1) of Section 4 is the inverse ratio without the square
+    assert oracle.gain_formula1(6, 6, 32, 6) == pytest.approx(1152 / 264, rel=1e-15)
+
+
+def test_select_rank_finds_planted_rank():
+    """A planted rank-3 filter: every fit below rank 3 leaves a large error,
+    rank 3 fits to rounding, so the criterion picks exactly 3."""
+    rng = np.random.default_rng(21)
+    A, B, C = rng.standard_normal((6, 3)), rng.standard_normal((6, 3)), rng.standard_normal((32, 3))
+    f = oracle.cp_reconstruct(A, B, C)
+    f /= np.linalg.norm(f)
+    r, errs = oracle.select_rank(f, 1.0, 16, iters=2000)
+    assert r == 3, (r, errs)
+
+
+def test_select_rank_extremes_and_linear_scan():
+    """A huge e accepts rank 1, e = 0 accepts nothing (r_max); in between the
+    binary search returns the same rank as a scan of every r (the error falls
+    and the bound grows with r)."""
+    wl = workloads.config1()
+    f = wl.bank.filters[1].astype(np.float64)
+    assert oracle.select_rank(f, 1e9, 12)[0] == 1
+    assert oracle.select_rank(f, 0.0, 12)[0] == 12
+    N, M, L = f.shape
+    errs = [oracle.cp_als(f, r, iters=200, eps=1e-13).errors[-1] for r in range(1, 13)]
+    for e in (5.0, 20.0, 80.0):
+        scan = next((r for r in range(1, 13) if errs[r - 1] < oracle.rank_bound(e, r, N, M, L)), 12)
+        assert oracle.select_rank(f, e, 12)[0] == scan, e
