@@ -182,6 +182,16 @@ dpmt_status dpmt_decompose(dpmt_ctx* ctx, int32_t rank, double* sigma_out, doubl
 dpmt_status dpmt_decompose_cp(dpmt_ctx* ctx, const int32_t* ranks, int32_t max_iters, double tol,
                               double* rel_err_out);
 dpmt_status dpmt_load_cp(dpmt_ctx* ctx, const int32_t* ranks, const float* factors_host);
+/* Per-filter rank selection (Section 4 criterion): for every filter the
+ * smallest r in [1, r_max] (r_max <= 32) with
+ *     ||f - CP(f, r)||_F < e * (r (h + w + 32) / (h w 32))^2,
+ * found by binary search over r (each probe an ALS fit as in
+ * dpmt_decompose_cp with tol 1e-13 and max_iters cycles); r_max when no
+ * rank meets it.  The fits of the chosen ranks become the CP factors, as
+ * after dpmt_decompose_cp.  ranks_out ([n_filters]) and rel_err_out
+ * ([n_filters], relative Frobenius errors) may be NULL. */
+dpmt_status dpmt_select_ranks(dpmt_ctx* ctx, double e, int32_t r_max, int32_t max_iters,
+                              int32_t* ranks_out, double* rel_err_out);
 /* Current CP factors: *n_floats receives their count; ranks_out ([n_filters])
  * and factors_out (that many floats) may be NULL.  DPMT_E_STATE without CP
  * factors. */

@@ -67,6 +67,7 @@ SIGNATURES = {
                                     POINTER(Component)]),
     "dpmt_decompose": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_double)]),
     "dpmt_decompose_cp": (c_int32, [c_void_p, POINTER(c_int32), c_int32, c_double, POINTER(c_double)]),
+    "dpmt_select_ranks": (c_int32, [c_void_p, c_double, c_int32, c_int32, POINTER(c_int32), POINTER(c_double)]),
     "dpmt_load_cp": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_float)]),
     "dpmt_get_cp": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_float), POINTER(c_int64)]),
     "dpmt_plan": (c_int32, [c_void_p, c_int32, POINTER(PyramidDesc), POINTER(POINTER(Layout))]),

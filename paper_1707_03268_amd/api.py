@@ -189,6 +189,17 @@ class Context:
                self._h, "dpmt_decompose_cp")
         return err
 
+    def select_ranks(self, e: float, r_max: int = 32, max_iters: int = 200):
+        """Per-filter ranks by the Section 4 criterion (binary search), fitted
+        and kept as the CP factors.  Returns (ranks, relative errors)."""
+        ranks = np.zeros(max(self.n_filters, 1), np.int32)
+        err = np.zeros(max(self.n_filters, 1), np.float64)
+        _check(_lib().dpmt_select_ranks(self._h, float(e), int(r_max), int(max_iters),
+                                        ranks.ctypes.data_as(POINTER(c_int32)),
+                                        err.ctypes.data_as(POINTER(c_double))), self._h,
+               "dpmt_select_ranks")
+        return ranks[:self.n_filters], err[:self.n_filters]
+
     def load_cp(self, ranks, factors) -> None:
         """factors: per filter (A (h, R), B (w, R), C (32, R))."""
         r = self._ranks(ranks)

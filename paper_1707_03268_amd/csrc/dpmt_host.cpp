@@ -1417,6 +1417,66 @@ dpmt_status dpmt_decompose_cp(dpmt_ctx* c, const int32_t* ranks, int32_t max_ite
     return DPMT_OK;
 }
 
+dpmt_status dpmt_select_ranks(dpmt_ctx* c, double e, int32_t r_max, int32_t max_iters,
+                              int32_t* ranks_out, double* rel_err_out) {
+    if (!c) return fail(nullptr, DPMT_E_INVALID, "ctx is NULL");
+    if (!c->loaded) return fail(c, DPMT_E_STATE, "dpmt_select_ranks before dpmt_load_filters");
+    if (!(e >= 0) || !std::isfinite(e)) return fail(c, DPMT_E_INVALID, "e must be finite and >= 0");
+    if (r_max < 1 || r_max > 32) return fail(c, DPMT_E_RANK, "r_max must be in [1, 32]");
+    if (max_iters < 1) return fail(c, DPMT_E_INVALID, "max_iters must be >= 1");
+    const int nf = (int)c->shapes.size();
+    std::vector<int> rank(nf, 1);
+    std::vector<CpFit> chosen(nf);
+    const int nt = std::max(1, std::min<int>({16, nf, (int)std::max(1u, std::thread::hardware_concurrency())}));
+    auto work = [&](int t0) {
+        for (int k = t0; k < nf; k += nt) {
+            const int h = c->shapes[k].h, w = c->shapes[k].w;
+            const float* f = c->weights.data() + c->woff[k];
+            double nrm = 0;
+            for (int i = 0; i < h * w * 32; ++i) nrm += (double)f[i] * f[i];
+            nrm = std::sqrt(nrm);
+            std::map<int, CpFit> fits;
+            auto ok = [&](int r) {
+                auto it = fits.find(r);
+                if (it == fits.end()) it = fits.emplace(r, cp_als(f, h, w, 32, r, max_iters, 1e-13)).first;
+                const double g = (double)r * (h + w + 32) / ((double)h * w * 32);
+                return it->second.rel_err * nrm < e * g * g;       // Section 4 rank criterion
+            };
+            int lo = 1, hi = r_max;
+            while (lo < hi) {
+                const int mid = (lo + hi) / 2;
+                if (ok(mid)) hi = mid;
+                else lo = mid + 1;
+            }
+            if (!fits.count(lo)) fits.emplace(lo, cp_als(f, h, w, 32, lo, max_iters, 1e-13));
+            rank[k] = lo;
+            chosen[k] = std::move(fits[lo]);
+        }
+    };
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t) pool.emplace_back(work, t);
+    work(0);
+    for (auto& th : pool) th.join();
+    std::vector<int64_t> off(nf);
+    int64_t total = 0;
+    for (int k = 0; k < nf; ++k) {
+        off[k] = total;
+        total += (int64_t)rank[k] * (c->shapes[k].h + c->shapes[k].w + 32);
+    }
+    std::vector<float> fac((size_t)total);
+    for (int k = 0; k < nf; ++k) {
+        float* dst = fac.data() + off[k];
+        for (double v : chosen[k].A) *dst++ = (float)v;
+        for (double v : chosen[k].B) *dst++ = (float)v;
+        for (double v : chosen[k].C) *dst++ = (float)v;
+        if (ranks_out) ranks_out[k] = rank[k];
+        if (rel_err_out) rel_err_out[k] = chosen[k].rel_err;
+    }
+    set_cp(c, std::move(rank), std::move(off), std::move(fac));
+    c->err.clear();
+    return DPMT_OK;
+}
+
 dpmt_status dpmt_load_cp(dpmt_ctx* c, const int32_t* ranks, const float* factors_host) {
     if (!c) return fail(nullptr, DPMT_E_INVALID, "ctx is NULL");
     if (!c->loaded) return fail(c, DPMT_E_STATE, "dpmt_load_cp before dpmt_load_filters");

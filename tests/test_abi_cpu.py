@@ -339,3 +339,33 @@ def test_cp_als_matches_oracle_and_recovers_planted_rank():
             e_or = cp.errors[-1] / np.linalg.norm(f)
             assert abs(err[k] - e_or) <= 0.02 * e_or + 1e-9, (R, k, err[k], e_or)
     ctx.close()
+
+
+def test_select_ranks_matches_oracle():
+    """The library's rank selection (binary search over ALS fits, Section 4
+    criterion) against the oracle's on the c1 bank, at several e; the chosen
+    fits become the CP factors."""
+    wl, fs, comps = _tiny_bank()
+    ctx = Context(device=-1)
+    with pytest.raises(DpmtError) as e:
+        ctx.select_ranks(1.0)
+    assert e.value.status == _abi.DPMT_E_STATE
+    ctx.load_filters(fs, comps)
+    for bad in (0, 33):
+        with pytest.raises(DpmtError) as e:
+            ctx.select_ranks(1.0, r_max=bad)
+        assert e.value.status == _abi.DPMT_E_RANK
+    with pytest.raises(DpmtError) as e:
+        ctx.select_ranks(-1.0)
+    assert e.value.status == _abi.DPMT_E_INVALID
+    for e in (5.0, 40.0):
+        ranks, err = ctx.select_ranks(e, r_max=12, max_iters=200)
+        for k in range(len(fs)):
+            want, _ = oracle.select_rank(fs[k].astype(np.float64), e, 12, iters=200)
+            assert ranks[k] == want, (e, k, ranks[k], want)
+        got_r, fac = ctx.get_cp(wl.bank.shapes)
+        np.testing.assert_array_equal(got_r, ranks)
+        for f, (A, B, C), rel in zip(fs, fac, err):
+            rec = oracle.cp_reconstruct(A.astype(np.float64), B.astype(np.float64), C.astype(np.float64))
+            assert abs(np.linalg.norm(rec - f) / np.linalg.norm(f) - rel) < 1e-5
+    ctx.close()
