@@ -156,6 +156,18 @@ constexpr int PLACE_RPW = 64 / PLACE_CW;  // rows per wavefront
 // window clamp spans its PLACE_RPW target rows, plus 3 for the unroll by 4
 constexpr int PLACE_PAD = 2 * (PLACE_RPW - 1) + 3;
 constexpr int PLACE_STAGE = 2048;         // floats of the staging buffer (32 rows of 64)
+// Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by
+// launch index.  The placement's neighbouring strips stage overlapping
+// response rows, so it remaps the launch index: clusters of 2^xcl consecutive
+// strips run on one XCD, while the clusters still interleave over the XCDs in
+// work order; the grid is padded to a multiple of 8 * 2^xcl and the padding
+// exits.  (Clusters of 4 halve the kernel's HBM fetch.)
+constexpr int N_XCD = 8;
+constexpr int PLACE_XCL = 2;
+inline int xcd_grid(int n, int xcl) {
+    const int g = N_XCD << xcl;
+    return (n + g - 1) / g * g;
+}
 struct PlaceLds {
     int acc_rows;      // largest map height
     int r1_rows;       // largest part map height + 2 * PLACE_PAD

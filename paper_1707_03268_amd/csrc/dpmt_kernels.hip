@@ -24,6 +24,14 @@ namespace dpmt {
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
+// Launch index -> work item for a grid padded by xcd_grid (clusters of 2^XCL
+// consecutive items on one XCD); items >= n are padding.
+template <int XCL>
+__device__ __forceinline__ int xcd_item(int g) {
+    const int xcd = g & (N_XCD - 1), k = g / N_XCD;
+    return (((k >> XCL) * N_XCD + xcd) << XCL) + (k & ((1 << XCL) - 1));
+}
+
 // Order-preserving map between float32 and int32, so that integer atomic
 // max / min keep float value ranges.
 __device__ __forceinline__ int range_key(float f) {
@@ -1279,7 +1287,8 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
                                                     const int* __restrict__ rmax,
                                                     const int* __restrict__ rmin,
                                                     float* __restrict__ scores,
-                                                    int16_t* __restrict__ offs, PlaceLds L) {
+                                                    int16_t* __restrict__ offs, PlaceLds L,
+                                                    int n_blocks) {
     constexpr int CW = PLACE_CW, PAD = PLACE_PAD, RPW = PLACE_RPW;
     constexpr int ROWS = 256 / CW;                         // row slots of the workgroup
     extern __shared__ __align__(16) float psm[];
@@ -1290,7 +1299,9 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
     float* ccol = crow + L.ctab_words;                     // column-pass cost table
     int16_t* r1a = reinterpret_cast<int16_t*>(ccol + L.ctab_words);   // [r1_rows][CW]
 
-    const int2 bm = blkmap[blockIdx.x];                    // (map, strip)
+    const int item = xcd_item<PLACE_XCL>(blockIdx.x);
+    if (item >= n_blocks) return;
+    const int2 bm = blkmap[item];                          // (map, strip)
     const MapDesc M = maps[bm.x];
     const int xs = bm.y * CW;
     const int ncol = min(CW, M.Wo - xs);
@@ -1452,8 +1463,8 @@ hipError_t launch_place(const MapDesc* maps, const MapPart* parts, const int2* b
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(place_kernel, dim3(n_blocks), dim3(256), bytes, st, maps, parts, blkmap, resp,
-                       rkeys, rkeys + n_slots, scores, offs, lds);
+    hipLaunchKernelGGL(place_kernel, dim3(xcd_grid(n_blocks, PLACE_XCL)), dim3(256), bytes, st, maps, parts,
+                       blkmap, resp, rkeys, rkeys + n_slots, scores, offs, lds, n_blocks);
     return hipGetLastError();
 }
 
