@@ -389,6 +389,60 @@ def cp_response(X: np.ndarray, A: np.ndarray, B: np.ndarray, C: np.ndarray) -> n
     return out
 
 
+def cp_terms(X: np.ndarray, A: np.ndarray, B: np.ndarray, C: np.ndarray) -> np.ndarray:
+    """Response of each rank-1 term of a CP filter on its own, shape
+    (R, Ho, Wo): term r is ((X o c_r) o_x b_r) o_y a_r; their sum over r is
+    cp_response."""
+    R = A.shape[1]
+    return np.stack([cp_response(X, A[:, r:r + 1], B[:, r:r + 1], C[:, r:r + 1]) for r in range(R)])
+
+
+# --------------------------------------------------------------------------
+# Convolution shortening (Section 4 thresholds, Algorithm 1 early exit).
+# A hypothesis is a root position p0 of one component on one root level.  For
+# each of its filters (root at p0, part i at its anchor 2 p0 + v_i on the part
+# level) the partial response after r terms is compared with t_r of that
+# filter; falling below any of them rejects the hypothesis (score -inf).
+# --------------------------------------------------------------------------
+def partial_sums(terms: np.ndarray, y: int, x: int) -> np.ndarray:
+    """p_r = sum of the first r terms' responses at (y, x), r = 1..R."""
+    return np.cumsum(terms[:, y, x])
+
+
+def fit_thresholds(partials: Sequence[np.ndarray]) -> np.ndarray:
+    """t_r = min over the positives' partial sums p_r (Section 4: the tightest
+    thresholds that reject no positive).  partials: one (R,) array per positive."""
+    return np.min(np.stack(partials), axis=0)
+
+
+def prune_component(score: np.ndarray, root_terms: np.ndarray, part_terms: Sequence[np.ndarray],
+                    anchors: np.ndarray, t_root: np.ndarray, t_parts: Sequence[np.ndarray]):
+    """Apply Algorithm 1's early exit to one score map.
+
+    Returns (pruned score map, pruned mask, margin): margin[y0, x0] is the
+    smallest |p_r - t_r| over every test the hypothesis went through (inf when
+    none), so that callers comparing against another arithmetic can skip
+    near-ties.  A part whose anchor is outside its map is not tested (the
+    score is -inf already)."""
+    Ho, Wo = score.shape
+    pruned = np.zeros((Ho, Wo), bool)
+    margin = np.full((Ho, Wo), np.inf)
+    for y0 in range(Ho):
+        for x0 in range(Wo):
+            tests = [(root_terms, y0, x0, t_root)]
+            for i, terms in enumerate(part_terms):
+                ay, ax = 2 * y0 + int(anchors[i][0]), 2 * x0 + int(anchors[i][1])
+                if 0 <= ay < terms.shape[1] and 0 <= ax < terms.shape[2]:
+                    tests.append((terms, ay, ax, t_parts[i]))
+            for terms, y, x, t in tests:
+                p = partial_sums(terms, y, x)
+                margin[y0, x0] = min(margin[y0, x0], float(np.min(np.abs(p - t))))
+                if np.any(p < t):
+                    pruned[y0, x0] = True
+    out = np.where(pruned, -np.inf, score)
+    return out, pruned, margin
+
+
 def rank_bound(e: float, r: int, N: int, M: int, L: int) -> float:
     """Right-hand side of the rank criterion of Section 4:
     e * (r (N + M + L) / (N M L))^2."""

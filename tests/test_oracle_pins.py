@@ -389,3 +389,74 @@ def test_select_rank_extremes_and_linear_scan():
     for e in (5.0, 20.0, 80.0):
         scan = next((r for r in range(1, 13) if errs[r - 1] < oracle.rank_bound(e, r, N, M, L)), 12)
         assert oracle.select_rank(f, e, 12)[0] == scan, e
+
+
+# ------------------------------------------------------- convolution shortening
+def test_cp_terms_are_rank_one_correlations():
+    """Each term equals the direct correlation with its rank-1 filter
+    a_r (x) b_r (x) c_r, and the terms sum to the CP response."""
+    rng = np.random.default_rng(31)
+    A, B, C = rng.standard_normal((4, 3)), rng.standard_normal((5, 3)), rng.standard_normal((32, 3))
+    X = rng.uniform(0, 0.4, size=(11, 13, 32))
+    T = oracle.cp_terms(X, A, B, C)
+    assert T.shape == (3, 8, 9)
+    for r in range(3):
+        f = np.einsum("n,m,l->nml", A[:, r], B[:, r], C[:, r])
+        np.testing.assert_allclose(T[r], oracle.correlate(X, f), rtol=0, atol=1e-12)
+    np.testing.assert_allclose(T.sum(0), oracle.cp_response(X, A, B, C), rtol=0, atol=1e-12)
+
+
+def test_pruning_hand_example():
+    """One hypothesis, a root of two terms with responses 1 and 2 (partial
+    sums 1, 3) and no parts: strict comparison p_r < t_r."""
+    terms = np.array([[[1.0]], [[2.0]]])
+    score = np.array([[7.0]])
+    cases = [([0.0, 4.0], True), ([2.0, 0.0], True), ([1.0, 3.0], False), ([-np.inf, -np.inf], False)]
+    for t, want in cases:
+        out, pruned, margin = oracle.prune_component(score, terms, [], np.zeros((0, 2)), np.array(t), [])
+        assert bool(pruned[0, 0]) == want, t
+        assert out[0, 0] == (-np.inf if want else 7.0)
+    _, _, margin = oracle.prune_component(score, terms, [], np.zeros((0, 2)), np.array([0.5, 2.0]), [])
+    assert margin[0, 0] == pytest.approx(0.5)
+
+
+def test_pruning_keeps_positives_and_is_monotone():
+    """Thresholds fitted on a set of positives never reject one of them
+    (Section 4: the tightest such thresholds); raising every threshold only
+    rejects more; -inf rejects nothing and +inf everything; a part is tested
+    at its anchor only while the anchor is inside its map."""
+    wl = workloads.config1()
+    c = wl.bank.components[0]
+    rng = np.random.default_rng(5)
+    Xr, Xp = wl.level_features(0, 1).astype(np.float64), wl.level_features(0, 0).astype(np.float64)
+    fac = {}
+    for k in [c.root] + list(c.parts):
+        cp = oracle.cp_als(wl.bank.filters[k].astype(np.float64), 4, iters=30)
+        fac[k] = (cp.A, cp.B, cp.C)
+    rt = oracle.cp_terms(Xr, *fac[c.root])
+    pt = [oracle.cp_terms(Xp, *fac[k]) for k in c.parts]
+    Ho, Wo = rt.shape[1:]
+    score = rng.standard_normal((Ho, Wo))
+    pos = [(int(rng.integers(0, Ho)), int(rng.integers(0, Wo))) for _ in range(12)]
+    t_root = oracle.fit_thresholds([oracle.partial_sums(rt, y, x) for y, x in pos])
+    t_parts = []
+    for i, terms in enumerate(pt):
+        ps = []
+        for y, x in pos:
+            ay, ax = 2 * y + c.anchors[i][0], 2 * x + c.anchors[i][1]
+            if 0 <= ay < terms.shape[1] and 0 <= ax < terms.shape[2]:
+                ps.append(oracle.partial_sums(terms, ay, ax))
+        t_parts.append(oracle.fit_thresholds(ps) if ps else np.full(4, -np.inf))
+    out, pruned, _ = oracle.prune_component(score, rt, pt, c.anchors, t_root, t_parts)
+    for y, x in pos:
+        assert not pruned[y, x]
+    assert pruned.any() and not pruned.all()
+    _, pruned_hi, _ = oracle.prune_component(score, rt, pt, c.anchors, t_root + 0.05,
+                                            [t + 0.05 for t in t_parts])
+    assert np.all(pruned_hi >= pruned) and pruned_hi.sum() > pruned.sum()
+    _, none, _ = oracle.prune_component(score, rt, pt, c.anchors, np.full(4, -np.inf),
+                                       [np.full(4, -np.inf)] * len(pt))
+    assert not none.any()
+    _, every, _ = oracle.prune_component(score, rt, pt, c.anchors, np.full(4, np.inf),
+                                        [np.full(4, -np.inf)] * len(pt))
+    assert every.all()
