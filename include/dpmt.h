@@ -198,6 +198,35 @@ dpmt_status dpmt_select_ranks(dpmt_ctx* ctx, double e, int32_t r_max, int32_t ma
 dpmt_status dpmt_get_cp(const dpmt_ctx* ctx, int32_t* ranks_out, float* factors_out,
                         int64_t* n_floats);
 
+/* Convolution shortening (Section 4 thresholds, Algorithm 1's early exit),
+ * for DPMT_CP_FP32.  Filter k has thresholds t_1 .. t_{R_k}; a root position
+ * is rejected (score -inf, every offset 0) when, for its root filter at the
+ * position or for a part filter at its anchor 2 p0 + v_i (when inside the
+ * part map), the sum of the first r terms' responses is below t_r for some r.
+ * Other positions keep the scores and offsets the CP mode computes without
+ * thresholds.  Layout: filter after filter in bank order, R_k floats each
+ * (sum_k R_k in all); -inf disables a test, NaN is rejected.
+ * dpmt_set_thresholds copies them (NULL clears them); new CP factors clear
+ * them too.  Rejection is decided in FP32 partial sums, in term order. */
+dpmt_status dpmt_set_thresholds(dpmt_ctx* ctx, const float* thresholds_host);
+
+/* One hypothesis: root position (y, x) of component `comp` on root level
+ * `level` of image `image` of the current plan. */
+typedef struct {
+    int32_t image, level, comp, y, x;
+} dpmt_hypothesis;
+
+/* Thresholds from positives (Section 4): t_r of filter k = the smallest
+ * partial sum p_r of k over the positives whose component uses it (the root
+ * at the position, each part at its anchor when inside the part map),
+ * computed in FP64 on the host from features_host (the packed FP32 cells of
+ * the plan), minus margin (>= 0, so that FP32 partial sums on the GPU do not
+ * reject a positive); -inf for filters no positive covers.  Sets them as
+ * dpmt_set_thresholds does; thresholds_out (host, sum_k R_k floats, may be
+ * NULL) receives them.  Needs CP factors and a plan. */
+dpmt_status dpmt_fit_thresholds(dpmt_ctx* ctx, const float* features_host, int32_t n_pos,
+                                const dpmt_hypothesis* positives, float margin, float* thresholds_out);
+
 /* Plan a batch of n_images pyramids (host descriptors, copied): output layout,
  * work lists and device workspace.  *out points at the context-owned layout.
  * Limits (DPMT_E_UNSUPPORTED beyond them): level sides up to 16384 cells,

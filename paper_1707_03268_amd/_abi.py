@@ -49,6 +49,10 @@ class PyramidDesc(ctypes.Structure):
     _fields_ = [("n_levels", c_int32), ("levels", POINTER(LevelDesc)), ("octave", c_int32)]
 
 
+class Hypothesis(ctypes.Structure):
+    _fields_ = [("image", c_int32), ("level", c_int32), ("comp", c_int32), ("y", c_int32), ("x", c_int32)]
+
+
 class Layout(ctypes.Structure):
     _fields_ = [("n_score", c_int64), ("n_offsets", c_int64), ("n_maps", c_int32),
                 ("map_image", POINTER(c_int32)), ("map_level", POINTER(c_int32)),
@@ -68,6 +72,9 @@ SIGNATURES = {
     "dpmt_decompose": (c_int32, [c_void_p, c_int32, POINTER(c_double), POINTER(c_double)]),
     "dpmt_decompose_cp": (c_int32, [c_void_p, POINTER(c_int32), c_int32, c_double, POINTER(c_double)]),
     "dpmt_select_ranks": (c_int32, [c_void_p, c_double, c_int32, c_int32, POINTER(c_int32), POINTER(c_double)]),
+    "dpmt_set_thresholds": (c_int32, [c_void_p, POINTER(c_float)]),
+    "dpmt_fit_thresholds": (c_int32, [c_void_p, POINTER(c_float), c_int32, POINTER(Hypothesis), c_float,
+                                      POINTER(c_float)]),
     "dpmt_load_cp": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_float)]),
     "dpmt_get_cp": (c_int32, [c_void_p, POINTER(c_int32), POINTER(c_float), POINTER(c_int64)]),
     "dpmt_plan": (c_int32, [c_void_p, c_int32, POINTER(PyramidDesc), POINTER(POINTER(Layout))]),

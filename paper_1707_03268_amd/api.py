@@ -226,6 +226,37 @@ class Context:
             out.append((A.copy(), B.copy(), C.copy()))
         return ranks, out
 
+    # ------------------------------------------------ convolution shortening
+    def set_thresholds(self, thresholds) -> None:
+        """Per-filter thresholds t_1..t_R (list of arrays in filter order, or
+        one flat array); None clears them."""
+        if thresholds is None:
+            _check(_lib().dpmt_set_thresholds(self._h, None), self._h, "dpmt_set_thresholds")
+            return
+        if not isinstance(thresholds, np.ndarray):
+            thresholds = np.concatenate([np.asarray(t, np.float32).ravel() for t in thresholds])
+        flat = np.ascontiguousarray(thresholds, dtype=np.float32)
+        _check(_lib().dpmt_set_thresholds(self._h, flat.ctypes.data_as(POINTER(c_float))), self._h,
+               "dpmt_set_thresholds")
+
+    def fit_thresholds(self, features: np.ndarray, positives, margin: float = 1e-4) -> np.ndarray:
+        """Thresholds from positives ((image, level, comp, y, x) tuples) over the
+        host feature buffer; sets and returns them (flat, filter order)."""
+        feats = np.ascontiguousarray(features, dtype=np.float32)
+        hyp = (_abi.Hypothesis * max(len(positives), 1))()
+        for i, g in enumerate(positives):
+            hyp[i].image, hyp[i].level, hyp[i].comp, hyp[i].y, hyp[i].x = (int(v) for v in g)
+        n = c_int64(0)
+        _check(_lib().dpmt_get_cp(self._h, None, None, byref(n)), self._h, "dpmt_get_cp")
+        ranks = np.zeros(max(self.n_filters, 1), np.int32)
+        _check(_lib().dpmt_get_cp(self._h, ranks.ctypes.data_as(POINTER(c_int32)), None, byref(n)),
+               self._h, "dpmt_get_cp")
+        out = np.zeros(max(int(ranks[:self.n_filters].sum()), 1), np.float32)
+        _check(_lib().dpmt_fit_thresholds(self._h, feats.ctypes.data_as(POINTER(c_float)), len(positives),
+                                          hyp, float(margin), out.ctypes.data_as(POINTER(c_float))),
+               self._h, "dpmt_fit_thresholds")
+        return out[:int(ranks[:self.n_filters].sum())]
+
     def plan(self, pyramids) -> Layout:
         """pyramids: objects with ``levels`` (each with cell_offset, rows, cols) and ``octave``."""
         arrs = []

@@ -186,6 +186,11 @@ struct dpmt_ctx {
     std::vector<int> cp_rank;
     std::vector<int64_t> cp_off;
     std::vector<float> cp_fac;
+    // convolution shortening: thresholds t_r per filter (R_k each, in filter
+    // order) and the rejection bytes the CP correlation writes per response
+    bool thr_set = false;
+    std::vector<float> cp_thr;
+    std::vector<int64_t> thr_off;
 
     // plan
     int plan_id = 0;
@@ -223,6 +228,8 @@ struct dpmt_ctx {
     int2* d_place_blk_lvl = nullptr;
     int2* d_place_blk_chunk = nullptr;
     int64_t* d_det_counts = nullptr;              // detection compaction scratch
+    uint8_t* d_flags = nullptr;                   // rejection bytes, one per response element
+    size_t flags_bytes = 0;
     hipStream_t aux_stream = nullptr;             // placement chunks of the overlapped strategy
     std::vector<hipEvent_t> chunk_ev;             // chunk done, fork, join
 
@@ -314,6 +321,7 @@ void free_plan(dpmt_ctx* c) {
     dfree(c->d_place_blk_lvl); c->d_place_blk_lvl = nullptr;
     dfree(c->d_place_blk_chunk); c->d_place_blk_chunk = nullptr;
     dfree(c->d_det_counts); c->d_det_counts = nullptr;
+    dfree(c->d_flags); c->d_flags = nullptr; c->flags_bytes = 0;
     for (auto& m : c->modes) free_tilesets(m);
     drop_graph(c);
     c->planned = false;
@@ -631,6 +639,8 @@ dpmt_status prepare_cp(dpmt_ctx* c) {
                     for (int n = 0; n < hg.h; ++n) fac.push_back(Ak[n * R + r]);
                 for (int r = 0; r < R; ++r)
                     for (int m = 0; m < hg.w; ++m) fac.push_back(Bk[m * R + r]);
+                if (c->thr_set)
+                    for (int r = 0; r < R; ++r) fac.push_back(c->cp_thr[c->thr_off[k] + r]);
             }
             chunks.push_back(ch);
         }
@@ -998,6 +1008,9 @@ dpmt_status score_checks(dpmt_ctx* c, dpmt_mode mode, const float* features_dev,
     return DPMT_OK;
 }
 
+// Algorithm 1's early exit applies to the CP form once thresholds are set.
+bool pruning(const dpmt_ctx* c, dpmt_mode mode) { return mode == DPMT_CP_FP32 && c->thr_set; }
+
 // Operands, tiles and the projected-feature buffer of a mode for the plan;
 // allocates, so it never runs while a graph is being captured.
 dpmt_status score_prepare(dpmt_ctx* c, dpmt_mode mode, hipStream_t st) {
@@ -1016,6 +1029,15 @@ dpmt_status score_prepare(dpmt_ctx* c, dpmt_mode mode, hipStream_t st) {
         hipEvent_t e = nullptr;
         HIP_TRY(c, hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate");
         c->chunk_ev.push_back(e);
+    }
+    if (pruning(c, mode) && c->flags_bytes < (size_t)c->resp_elems) {
+        HIP_TRY(c, hipStreamSynchronize(st), "hipStreamSynchronize");
+        drop_graph(c);
+        dfree(c->d_flags);
+        c->d_flags = nullptr;
+        c->flags_bytes = 0;
+        HIP_TRY(c, hipMalloc((void**)&c->d_flags, std::max<size_t>((size_t)c->resp_elems, 16)), "allocate rejection flags");
+        c->flags_bytes = (size_t)c->resp_elems;
     }
     ModeData& md = c->modes[mode];
     if (is_tensor(mode)) {
@@ -1053,7 +1075,7 @@ hipError_t corr_tiles(dpmt_ctx* c, dpmt_mode mode, int order, int b, int e, cons
         ModeData::CpTileSet& ts = md.cp;
         const CpTile* t = order == 0 ? ts.dTiles : order == 1 ? ts.dTilesLvl : ts.dTilesChunk;
         return launch_cp_corr(t + b, e - b, md.dCpChunks, X, md.dCpFac, c->d_resp, c->d_rkeys, c->n_slots,
-                              ts.lds, st);
+                              pruning(c, mode) ? c->d_flags : nullptr, ts.lds, st);
     }
     ModeData::TileSet& ts = current_tiles(c, mode);
     const CorrTile* t = order == 0 ? ts.dTiles : order == 1 ? ts.dTilesLvl : ts.dTilesChunk;
@@ -1088,7 +1110,8 @@ hipError_t enqueue_batched(dpmt_ctx* c, dpmt_mode mode, const float* X, float* s
     if (e == hipSuccess && ev) e = hipEventRecord(ev[2], st);
     if (e == hipSuccess)
         e = launch_place(c->d_maps, c->d_parts, c->d_place_blk, (int)c->place_blk.size(), c->d_resp,
-                         c->d_rkeys, c->n_slots, scores, offs, c->place_lds, st);
+                         c->d_rkeys, c->n_slots, scores, offs, c->place_lds,
+                         pruning(c, mode) ? c->d_flags : nullptr, st);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[3], st);
     return e;
 }
@@ -1121,7 +1144,8 @@ hipError_t enqueue_per_level(dpmt_ctx* c, dpmt_mode mode, const float* X, float*
     for (const auto& r : c->place_lvl) {
         if (e != hipSuccess) break;
         e = launch_place(c->d_maps, c->d_parts, c->d_place_blk_lvl + r[2], r[3] - r[2], c->d_resp,
-                         c->d_rkeys, c->n_slots, scores, offs, c->place_lds, st);
+                         c->d_rkeys, c->n_slots, scores, offs, c->place_lds,
+                         pruning(c, mode) ? c->d_flags : nullptr, st);
     }
     if (e == hipSuccess && ev) e = hipEventRecord(ev[3], st);
     return e;
@@ -1152,7 +1176,8 @@ hipError_t enqueue_overlap(dpmt_ctx* c, dpmt_mode mode, const float* X, float* s
         if (e == hipSuccess)
             e = launch_place(c->d_maps, c->d_parts, c->d_place_blk_chunk + c->place_chunk[k][0],
                              c->place_chunk[k][1] - c->place_chunk[k][0], c->d_resp, c->d_rkeys,
-                             c->n_slots, scores, offs, c->place_lds, c->aux_stream);
+                             c->n_slots, scores, offs, c->place_lds,
+                             pruning(c, mode) ? c->d_flags : nullptr, c->aux_stream);
     }
     if (e == hipSuccess && ev) e = hipEventRecord(ev[2], st);
     if (e == hipSuccess) e = hipEventRecord(join, c->aux_stream);
@@ -1273,6 +1298,9 @@ dpmt_status dpmt_load_filters(dpmt_ctx* c, int32_t n_filters, const dpmt_shape* 
     c->cp_rank.clear();
     c->cp_off.clear();
     c->cp_fac.clear();
+    c->thr_set = false;
+    c->cp_thr.clear();
+    c->thr_off.clear();
     c->shapes.assign(shapes, shapes + n_filters);
     c->woff.resize(n_filters);
     int64_t off = 0;
@@ -1364,6 +1392,9 @@ void set_cp(dpmt_ctx* c, std::vector<int> rank, std::vector<int64_t> off, std::v
     c->cp_off = std::move(off);
     c->cp_fac = std::move(fac);
     c->cp_ready = true;
+    c->thr_set = false;
+    c->cp_thr.clear();
+    c->thr_off.clear();
 }
 
 dpmt_status cp_ranks_check(dpmt_ctx* c, const int32_t* ranks, std::vector<int64_t>& off, int64_t& total) {
@@ -1473,6 +1504,118 @@ dpmt_status dpmt_select_ranks(dpmt_ctx* c, double e, int32_t r_max, int32_t max_
         if (rel_err_out) rel_err_out[k] = chosen[k].rel_err;
     }
     set_cp(c, std::move(rank), std::move(off), std::move(fac));
+    c->err.clear();
+    return DPMT_OK;
+}
+
+namespace {
+// Replace the thresholds (empty: none) and drop what was packed with the old ones.
+void set_thresholds(dpmt_ctx* c, std::vector<float> t) {
+    if (c->has_device()) {
+        (void)hipSetDevice(c->device);
+        (void)hipDeviceSynchronize();
+    }
+    drop_graph(c);
+    free_mode(c->modes[DPMT_CP_FP32]);
+    c->thr_set = !t.empty();
+    c->cp_thr = std::move(t);
+    c->thr_off.assign(c->shapes.size(), 0);
+    int64_t o = 0;
+    for (size_t k = 0; k < c->shapes.size(); ++k) {
+        c->thr_off[k] = o;
+        o += c->cp_rank[k];
+    }
+}
+
+// Partial sums p_r (r = 1..R) of filter k's CP terms at (y, x) of a level
+// (FP64 over the stored FP32 factors): term r = sum_n a_r[n] sum_m b_r[m]
+// (X[y+n][x+m] . c_r).
+void cp_partials(const dpmt_ctx* c, int k, const float* X, int cols, int y, int x, std::vector<double>& p) {
+    const int h = c->shapes[k].h, w = c->shapes[k].w, R = c->cp_rank[k];
+    const float* A = c->cp_fac.data() + c->cp_off[k];
+    const float* B = A + (int64_t)h * R;
+    const float* C = B + (int64_t)w * R;
+    p.assign(R, 0.0);
+    double run = 0;
+    for (int r = 0; r < R; ++r) {
+        double term = 0;
+        for (int n = 0; n < h; ++n) {
+            double row = 0;
+            for (int m = 0; m < w; ++m) {
+                const float* cell = X + ((int64_t)(y + n) * cols + (x + m)) * 32;
+                double z = 0;
+                for (int l = 0; l < 32; ++l) z += (double)cell[l] * C[l * R + r];
+                row += (double)B[m * R + r] * z;
+            }
+            term += (double)A[n * R + r] * row;
+        }
+        run += term;
+        p[r] = run;
+    }
+}
+}  // namespace
+
+dpmt_status dpmt_set_thresholds(dpmt_ctx* c, const float* thresholds_host) {
+    if (!c) return fail(nullptr, DPMT_E_INVALID, "ctx is NULL");
+    if (!c->cp_ready) return fail(c, DPMT_E_STATE, "thresholds need CP factors first");
+    if (!thresholds_host) {
+        set_thresholds(c, {});
+        return DPMT_OK;
+    }
+    int64_t n = 0;
+    for (int r : c->cp_rank) n += r;
+    for (int64_t i = 0; i < n; ++i)
+        if (std::isnan(thresholds_host[i])) return fail(c, DPMT_E_INVALID, "NaN threshold at element " + std::to_string(i));
+    set_thresholds(c, std::vector<float>(thresholds_host, thresholds_host + n));
+    c->err.clear();
+    return DPMT_OK;
+}
+
+dpmt_status dpmt_fit_thresholds(dpmt_ctx* c, const float* features_host, int32_t n_pos,
+                                const dpmt_hypothesis* pos, float margin, float* thresholds_out) {
+    if (!c) return fail(nullptr, DPMT_E_INVALID, "ctx is NULL");
+    if (!c->cp_ready) return fail(c, DPMT_E_STATE, "thresholds need CP factors first");
+    if (!c->planned) return fail(c, DPMT_E_STATE, "dpmt_fit_thresholds before dpmt_plan");
+    if (!features_host || !pos || n_pos < 1) return fail(c, DPMT_E_INVALID, "need features_host and n_pos >= 1 positives");
+    if (!std::isfinite(margin) || margin < 0) return fail(c, DPMT_E_INVALID, "margin must be finite and >= 0");
+    for (int i = 0; i < n_pos; ++i) {
+        const dpmt_hypothesis& g = pos[i];
+        const std::string ps = "positive " + std::to_string(i) + ": ";
+        if (g.image < 0 || g.image >= (int)c->pyr.size()) return fail(c, DPMT_E_INVALID, ps + "image out of range");
+        const int oct = c->octave[g.image];
+        if (g.level < oct || g.level >= (int)c->pyr[g.image].size()) return fail(c, DPMT_E_INVALID, ps + "not a root level");
+        if (g.comp < 0 || g.comp >= (int)c->comps.size()) return fail(c, DPMT_E_INVALID, ps + "component out of range");
+        const LevelInfo& lv = c->pyr[g.image][g.level];
+        const dpmt_shape& r0 = c->shapes[c->comps[g.comp].root];
+        if (g.y < 0 || g.x < 0 || g.y > lv.rows - r0.h || g.x > lv.cols - r0.w)
+            return fail(c, DPMT_E_INVALID, ps + "position outside the score map");
+    }
+    const int nf = (int)c->shapes.size();
+    std::vector<std::vector<double>> lo(nf);
+    std::vector<double> p;
+    auto take = [&](int k, const LevelInfo& lv, int y, int x) {
+        cp_partials(c, k, features_host + lv.cell_offset * 32, lv.cols, y, x, p);
+        if (lo[k].empty()) lo[k] = p;
+        else
+            for (size_t r = 0; r < p.size(); ++r) lo[k][r] = std::min(lo[k][r], p[r]);
+    };
+    for (int i = 0; i < n_pos; ++i) {
+        const dpmt_hypothesis& g = pos[i];
+        const dpmt_ctx::Comp& cm = c->comps[g.comp];
+        take(cm.root, c->pyr[g.image][g.level], g.y, g.x);
+        const LevelInfo& pl = c->pyr[g.image][g.level - c->octave[g.image]];
+        for (size_t s = 0; s < cm.parts.size(); ++s) {
+            const int k = cm.parts[s];
+            const int ay = 2 * g.y + cm.anchors[s][0], ax = 2 * g.x + cm.anchors[s][1];
+            if (ay <= pl.rows - c->shapes[k].h && ax <= pl.cols - c->shapes[k].w) take(k, pl, ay, ax);
+        }
+    }
+    std::vector<float> t;
+    for (int k = 0; k < nf; ++k)
+        for (int r = 0; r < c->cp_rank[k]; ++r)
+            t.push_back(lo[k].empty() ? -INFINITY : (float)(lo[k][r] - (double)margin));
+    if (thresholds_out) std::memcpy(thresholds_out, t.data(), t.size() * sizeof(float));
+    set_thresholds(c, std::move(t));
     c->err.clear();
     return DPMT_OK;
 }
@@ -2042,7 +2185,7 @@ dpmt_status dpmt_level_responses(dpmt_ctx* c, dpmt_mode mode, const float* featu
         size_t lds = 0;
         for (const CpTile& t : cp_tiles) lds = std::max(lds, cp_lds_bytes(t.HX, t.HY));
         if (e == hipSuccess) e = upload(&dcp, cp_tiles);
-        if (e == hipSuccess) e = launch_cp_corr(dcp, (int)cp_tiles.size(), md.dCpChunks, features_dev, md.dCpFac, dblk, nullptr, 0, lds, st);
+        if (e == hipSuccess) e = launch_cp_corr(dcp, (int)cp_tiles.size(), md.dCpChunks, features_dev, md.dCpFac, dblk, nullptr, 0, nullptr, lds, st);
     } else {
         if (e == hipSuccess) e = upload(&dtiles, tiles);
         CorrLaunch cl{md.kind, md.pk, 4, 2, 4, 0};

@@ -191,9 +191,12 @@ hipError_t launch_corr(const CorrLaunch& cfg, const CorrTile* tiles, int n_tiles
                        hipStream_t st);
 // CP correlation of every tile (one workgroup per tile).  lds_bytes: the
 // largest cp_lds_bytes over the tiles.
+// flags (may be NULL): one byte per response, set where a partial sum fell
+// below the filter's threshold (the thresholds follow each filter's column
+// factors in fac).
 hipError_t launch_cp_corr(const CpTile* tiles, int n_tiles, const CpChunk* chunks, const float* X,
-                          const float* fac, float* out, int* rkeys, int64_t n_slots, size_t lds_bytes,
-                          hipStream_t st);
+                          const float* fac, float* out, int* rkeys, int64_t n_slots, uint8_t* flags,
+                          size_t lds_bytes, hipStream_t st);
 hipError_t launch_fp8_prepare(const float* X, int64_t n_cells, const float* U, int RP,
                               float* partial, float* scales, const RequantBlock* blocks,
                               int n_blocks, const float* master, uint8_t* G, float* tk,
@@ -203,9 +206,12 @@ hipError_t launch_project_fp8(const float* X, int64_t n_cells, const float* U, i
 constexpr int FP8_PARTIALS = 512 * 32;   // floats of the channel-max scratch
 size_t corr_lds_bytes(const CorrLaunch& cfg, int h, int S);
 hipError_t launch_range_init(int* rkeys, int64_t n_slots, hipStream_t st);
+// flags (may be NULL): the CP correlation's rejection bytes; rejected root
+// positions get score -inf and offsets 0.
 hipError_t launch_place(const MapDesc* maps, const MapPart* parts, const int2* blkmap,
                         int n_blocks, const float* resp, const int* rkeys, int64_t n_slots,
-                        float* scores, int16_t* offs, const PlaceLds& lds, hipStream_t st);
+                        float* scores, int16_t* offs, const PlaceLds& lds, const uint8_t* flags,
+                        hipStream_t st);
 hipError_t launch_planes_to_maps(const float* planes, int ng, int Ho, int Wo, int ld,
                                  const int64_t* dst_off, float* out, hipStream_t st);
 // Detections: counts holds det_blocks(n) int64 of scratch.

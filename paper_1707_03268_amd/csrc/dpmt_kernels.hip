@@ -665,7 +665,8 @@ template <int HS, int WS>
 __device__ __forceinline__ void cp_tile(const CpTile& t, const CpChunk* __restrict__ chunks,
                                         const float* __restrict__ X, const float* __restrict__ fac,
                                         float* __restrict__ out, int* __restrict__ rmax,
-                                        int* __restrict__ rmin, float* __restrict__ lds) {
+                                        int* __restrict__ rmin, uint8_t* __restrict__ flags,
+                                        float* __restrict__ lds) {
     constexpr bool FIXED = HS > 0 && WS > 0;
     constexpr int HXc = FIXED ? ((CP_TX + WS - 1 + 3) & ~3) : 4;
     constexpr int HYc = FIXED ? CP_HALO / HXc : 1;
@@ -707,6 +708,8 @@ __device__ __forceinline__ void cp_tile(const CpTile& t, const CpChunk* __restri
         const int R = ch.R[wv];
         const float* fa = fac + ch.ab_off[wv];          // a_r[n] at r*h + n
         const float* fb = fa + R * h;                   // b_r[m] at r*w + m
+        const float* ft = fb + R * w;                   // thresholds t_r (with flags)
+        uint32_t below = 0;                             // bit 4j+c: a partial sum fell below its t_r
         float acc[4][4];
 #pragma unroll
         for (int j = 0; j < 4; ++j)
@@ -798,6 +801,14 @@ __device__ __forceinline__ void cp_tile(const CpTile& t, const CpChunk* __restri
                         }
                     }
                 }
+                if (flags != nullptr) {                 // Algorithm 1: partial sum after term r
+                    const float tr = ft[r];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+#pragma unroll
+                        for (int c = 0; c < 4; ++c)
+                            if (acc[j][c] < tr) below |= 1u << (4 * j + c);
+                }
             }
             __syncthreads();
         }
@@ -809,8 +820,13 @@ __device__ __forceinline__ void cp_tile(const CpTile& t, const CpChunk* __restri
             for (int j = 0; j < 4; ++j) {
                 const int yr = ry + j, y = t.y0 + yr;
                 if (j >= RG || yr >= TYo || y >= t.Ho || x >= t.Wo) continue;
-                *reinterpret_cast<float4*>(out + t.out_off + ((int64_t)f * t.Ho + y) * t.ld + x) =
-                    make_float4(acc[j][0], acc[j][1], acc[j][2], acc[j][3]);
+                const int64_t o = t.out_off + ((int64_t)f * t.Ho + y) * t.ld + x;
+                *reinterpret_cast<float4*>(out + o) = make_float4(acc[j][0], acc[j][1], acc[j][2], acc[j][3]);
+                if (flags != nullptr)
+                    *reinterpret_cast<uint32_t*>(flags + o) = ((below >> (4 * j)) & 1u) |
+                                                               (((below >> (4 * j + 1)) & 1u) << 8) |
+                                                               (((below >> (4 * j + 2)) & 1u) << 16) |
+                                                               (((below >> (4 * j + 3)) & 1u) << 24);
 #pragma unroll
                 for (int c = 0; c < 4; ++c)
                     if (x + c < t.Wo) {
@@ -836,20 +852,20 @@ __device__ __forceinline__ void cp_tile(const CpTile& t, const CpChunk* __restri
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void cp_corr_kernel(
     const CpTile* __restrict__ tiles, const CpChunk* __restrict__ chunks, const float* __restrict__ X,
     const float* __restrict__ fac, float* __restrict__ out, int* __restrict__ rmax,
-    int* __restrict__ rmin) {
+    int* __restrict__ rmin, uint8_t* __restrict__ flags) {
     extern __shared__ __align__(16) float cp_lds[];
     const CpTile& t = tiles[blockIdx.x];
     // compiled shapes: the DPM part filter and the usual root filters
-    if (t.h == 6 && t.w == 6) cp_tile<6, 6>(t, chunks, X, fac, out, rmax, rmin, cp_lds);
-    else if (t.h == 6 && t.w == 11) cp_tile<6, 11>(t, chunks, X, fac, out, rmax, rmin, cp_lds);
-    else if (t.h == 7 && t.w == 13) cp_tile<7, 13>(t, chunks, X, fac, out, rmax, rmin, cp_lds);
-    else if (t.h == 8 && t.w == 15) cp_tile<8, 15>(t, chunks, X, fac, out, rmax, rmin, cp_lds);
-    else cp_tile<0, 0>(t, chunks, X, fac, out, rmax, rmin, cp_lds);
+    if (t.h == 6 && t.w == 6) cp_tile<6, 6>(t, chunks, X, fac, out, rmax, rmin, flags, cp_lds);
+    else if (t.h == 6 && t.w == 11) cp_tile<6, 11>(t, chunks, X, fac, out, rmax, rmin, flags, cp_lds);
+    else if (t.h == 7 && t.w == 13) cp_tile<7, 13>(t, chunks, X, fac, out, rmax, rmin, flags, cp_lds);
+    else if (t.h == 8 && t.w == 15) cp_tile<8, 15>(t, chunks, X, fac, out, rmax, rmin, flags, cp_lds);
+    else cp_tile<0, 0>(t, chunks, X, fac, out, rmax, rmin, flags, cp_lds);
 }
 
 hipError_t launch_cp_corr(const CpTile* tiles, int n_tiles, const CpChunk* chunks, const float* X,
-                          const float* fac, float* out, int* rkeys, int64_t n_slots, size_t lds_bytes,
-                          hipStream_t st) {
+                          const float* fac, float* out, int* rkeys, int64_t n_slots, uint8_t* flags,
+                          size_t lds_bytes, hipStream_t st) {
     if (n_tiles <= 0) return hipSuccess;
     if (lds_bytes > 160 * 1024) return hipErrorInvalidValue;
     if (lds_bytes > 65536) {
@@ -858,7 +874,7 @@ hipError_t launch_cp_corr(const CpTile* tiles, int n_tiles, const CpChunk* chunk
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(cp_corr_kernel, dim3(n_tiles), dim3(256), lds_bytes, st, tiles, chunks, X, fac, out,
-                       rkeys, rkeys ? rkeys + n_slots : nullptr);
+                       rkeys, rkeys ? rkeys + n_slots : nullptr, flags);
     return hipGetLastError();
 }
 
@@ -1162,7 +1178,7 @@ __device__ __forceinline__ float quad_cost(float a, float b, int u) {
 size_t place_lds_bytes(const PlaceLds& l) {
     return (size_t)4 * ((size_t)l.acc_rows * PLACE_CW + (size_t)l.r1_rows * PLACE_CW +
                         (size_t)l.stage_words + 2 * (size_t)l.ctab_words) +
-           (size_t)2 * l.r1_rows * PLACE_CW;
+           (size_t)2 * l.r1_rows * PLACE_CW + (size_t)l.acc_rows * PLACE_CW;
 }
 
 constexpr int PLACE_LOADS = PLACE_STAGE / 1024;        // staged float4 per thread and round
@@ -1288,7 +1304,7 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
                                                     const int* __restrict__ rmin,
                                                     float* __restrict__ scores,
                                                     int16_t* __restrict__ offs, PlaceLds L,
-                                                    int n_blocks) {
+                                                    int n_blocks, const uint8_t* __restrict__ flags) {
     constexpr int CW = PLACE_CW, PAD = PLACE_PAD, RPW = PLACE_RPW;
     constexpr int ROWS = 256 / CW;                         // row slots of the workgroup
     extern __shared__ __align__(16) float psm[];
@@ -1298,6 +1314,7 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
     float* crow = stage + L.stage_words;                   // row-pass cost table
     float* ccol = crow + L.ctab_words;                     // column-pass cost table
     int16_t* r1a = reinterpret_cast<int16_t*>(ccol + L.ctab_words);   // [r1_rows][CW]
+    uint8_t* rej = reinterpret_cast<uint8_t*>(r1a + L.r1_rows * CW); // [acc_rows][CW] rejected
 
     const int item = xcd_item<PLACE_XCL>(blockIdx.x);
     if (item >= n_blocks) return;
@@ -1308,6 +1325,34 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
     const int tid = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);    // wavefront-uniform
     const int j = tid % CW, rr = tid / CW, hr = rr % RPW;
+
+    // Algorithm 1's early exit: a root position is rejected when a partial CP
+    // sum of its root (at the position) or of a part (at its anchor) fell
+    // below that filter's threshold; its score is -inf and its offsets 0.  A
+    // strip whose every position is rejected skips the transform.
+    if (flags != nullptr) {
+        int live = 0;
+        for (int y0 = rr; y0 < M.Ho; y0 += ROWS) {
+            if (j >= ncol) continue;
+            bool out = flags[M.root_plane + (int64_t)y0 * M.ldr + xs + j] != 0;
+            for (int s = 0; s < M.n_parts && !out; ++s) {
+                const MapPart& P = parts[M.part_base + s];
+                const int ay = 2 * y0 + P.vy, ax = 2 * (xs + j) + P.vx;
+                if (ay < P.Hp && ax < P.Wp) out = flags[P.plane + (int64_t)ay * P.ld + ax] != 0;
+            }
+            rej[y0 * CW + j] = out;
+            live |= !out;
+        }
+        if (!__syncthreads_or(live)) {
+            for (int y0 = rr; y0 < M.Ho; y0 += ROWS) {
+                if (j >= ncol) continue;
+                scores[M.score_off + (int64_t)y0 * M.Wo + xs + j] = -INFINITY;
+                for (int s = 0; s < M.n_parts && offs; ++s)
+                    reinterpret_cast<uint32_t*>(offs + M.offs_off)[((int64_t)s * M.Ho + y0) * M.Wo + xs + j] = 0u;
+            }
+            return;
+        }
+    }
 
     float4 pf[PLACE_LOADS];
     PlaceGeo G = place_geo(parts[M.part_base], M, xs, rmax, rmin, L.stage_words);
@@ -1408,6 +1453,7 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
                     }
                     float* a = acc + y0 * CW + j;
                     *a = s == 0 ? D : *a + D;
+                    if (flags != nullptr && rej[y0 * CW + j]) packed = 0u;
                     if (offs)
                         reinterpret_cast<uint32_t*>(offs + M.offs_off)[((int64_t)s * M.Ho + y0) * M.Wo + xs + j] = packed;
                 }
@@ -1431,7 +1477,8 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
         const int y0 = y0a + hr;
         if (y0 < M.Ho && j < ncol)
             scores[M.score_off + (int64_t)y0 * M.Wo + xs + j] =
-                resp[M.root_plane + (int64_t)y0 * M.ldr + xs + j] + acc[y0 * CW + j];
+                (flags != nullptr && rej[y0 * CW + j]) ? -INFINITY
+                                                       : resp[M.root_plane + (int64_t)y0 * M.ldr + xs + j] + acc[y0 * CW + j];
     }
 }
 
@@ -1452,7 +1499,8 @@ hipError_t launch_range_init(int* rkeys, int64_t n_slots, hipStream_t st) {
 
 hipError_t launch_place(const MapDesc* maps, const MapPart* parts, const int2* blkmap,
                         int n_blocks, const float* resp, const int* rkeys, int64_t n_slots,
-                        float* scores, int16_t* offs, const PlaceLds& lds, hipStream_t st) {
+                        float* scores, int16_t* offs, const PlaceLds& lds, const uint8_t* flags,
+                        hipStream_t st) {
     if (n_blocks <= 0) return hipSuccess;
     if (lds.stage_words != PLACE_STAGE || lds.ctab_words % 4)
         return hipErrorInvalidValue;
@@ -1464,7 +1512,7 @@ hipError_t launch_place(const MapDesc* maps, const MapPart* parts, const int2* b
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(place_kernel, dim3(xcd_grid(n_blocks, PLACE_XCL)), dim3(256), bytes, st, maps, parts,
-                       blkmap, resp, rkeys, rkeys + n_slots, scores, offs, lds, n_blocks);
+                       blkmap, resp, rkeys, rkeys + n_slots, scores, offs, lds, n_blocks, flags);
     return hipGetLastError();
 }
 

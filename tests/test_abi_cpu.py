@@ -369,3 +369,60 @@ def test_select_ranks_matches_oracle():
             rec = oracle.cp_reconstruct(A.astype(np.float64), B.astype(np.float64), C.astype(np.float64))
             assert abs(np.linalg.norm(rec - f) / np.linalg.norm(f) - rel) < 1e-5
     ctx.close()
+
+
+def test_fit_thresholds_matches_oracle_and_validates():
+    """The library's FP64 threshold fit (min over positives of the partial CP
+    sums, root at the position, parts at their anchors) against the oracle."""
+    wl, fs, comps = _tiny_bank()
+    ctx = Context(device=-1)
+    ctx.load_filters(fs, comps)
+    with pytest.raises(DpmtError) as e:
+        ctx.set_thresholds(np.zeros(4, np.float32))
+    assert e.value.status == _abi.DPMT_E_STATE
+    ctx.decompose_cp(4, max_iters=30)
+    X = wl.features()
+    with pytest.raises(DpmtError) as e:                     # needs a plan
+        ctx.fit_thresholds(X, [(0, 1, 0, 0, 0)])
+    assert e.value.status == _abi.DPMT_E_STATE
+    ctx.plan(wl.pyramids)
+    ranks, fac = ctx.get_cp(wl.bank.shapes)
+    fac64 = [tuple(m.astype(np.float64) for m in abc) for abc in fac]
+    c = comps[0]
+    Ho, Wo = 30 - 6 + 1, 40 - 11 + 1
+    rng = np.random.default_rng(8)
+    pos = [(0, 1, 0, int(rng.integers(0, Ho)), int(rng.integers(0, Wo))) for _ in range(9)]
+    t = ctx.fit_thresholds(X, pos, margin=0.0)
+    Xr = wl.level_features(0, 1).astype(np.float64)
+    Xp = wl.level_features(0, 0).astype(np.float64)
+    off = np.concatenate([[0], np.cumsum(ranks)])
+    rt = oracle.cp_terms(Xr, *fac64[c.root])
+    want = oracle.fit_thresholds([oracle.partial_sums(rt, y, x) for (_, _, _, y, x) in pos])
+    np.testing.assert_allclose(t[off[c.root]:off[c.root + 1]], want, rtol=1e-6, atol=1e-6)
+    for i, k in enumerate(c.parts):
+        pt = oracle.cp_terms(Xp, *fac64[k])
+        ps = [oracle.partial_sums(pt, 2 * y + c.anchors[i][0], 2 * x + c.anchors[i][1])
+              for (_, _, _, y, x) in pos
+              if 2 * y + c.anchors[i][0] < pt.shape[1] and 2 * x + c.anchors[i][1] < pt.shape[2]]
+        got = t[off[k]:off[k + 1]]
+        if ps:
+            np.testing.assert_allclose(got, oracle.fit_thresholds(ps), rtol=1e-6, atol=1e-6)
+        else:
+            assert np.all(np.isneginf(got))
+    # the margin is subtracted
+    t2 = ctx.fit_thresholds(X, pos, margin=0.25)
+    np.testing.assert_allclose(t2, t - 0.25, rtol=0, atol=1e-6)
+    for bad in ([(0, 0, 0, 0, 0)], [(0, 1, 0, Ho, 0)], [(1, 1, 0, 0, 0)], [(0, 1, 1, 0, 0)]):
+        with pytest.raises(DpmtError) as e:
+            ctx.fit_thresholds(X, bad)
+        assert e.value.status == _abi.DPMT_E_INVALID, bad
+    with pytest.raises(DpmtError) as e:
+        ctx.fit_thresholds(X, pos, margin=float("nan"))
+    assert e.value.status == _abi.DPMT_E_INVALID
+    bad = np.zeros(int(ranks.sum()), np.float32)
+    bad[3] = np.nan
+    with pytest.raises(DpmtError) as e:
+        ctx.set_thresholds(bad)
+    assert e.value.status == _abi.DPMT_E_INVALID
+    ctx.set_thresholds(None)
+    ctx.close()

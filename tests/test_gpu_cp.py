@@ -145,14 +145,31 @@ def test_cp_scores_against_oracle(cfg, R, every):
     ctx.close()
 
 
-def test_cp_launch_strategies_bitwise_equal():
+@pytest.mark.parametrize("prune", [False, True])
+def test_cp_launch_strategies_bitwise_equal(prune):
     wl = workloads.uneven_batch()
-    note("cp launch strategies")
+    note(f"cp launch strategies, pruning {prune}")
     ctx, _ = _cp_context(wl, 6)
     lay = ctx.plan(wl.pyramids)
     feats = torch.from_numpy(wl.features()).cuda()
+    if prune:
+        ref_s, _ = _scores(ctx, lay, feats)
+        pos = []
+        for k in range(0, lay.n_maps, 4):
+            n = int(lay.map_rows[k]) * int(lay.map_cols[k])
+            if n == 0:
+                continue
+            m = ref_s[lay.map_score_off[k]:lay.map_score_off[k] + n]
+            if not np.isfinite(m).any():
+                continue
+            i = int(np.argmax(m))
+            pos.append((int(lay.map_image[k]), int(lay.map_level[k]), int(lay.map_comp[k]),
+                        i // int(lay.map_cols[k]), i % int(lay.map_cols[k])))
+        ctx.fit_thresholds(wl.features(), pos, margin=1e-3)
     ref_s, ref_o = _scores(ctx, lay, feats)
     assert np.isfinite(ref_s).any()
+    if prune:
+        assert np.isneginf(ref_s).sum() > 0
     for launch in ("per_level", "overlap", "graph", "graph"):
         ctx.set_launch(launch)
         s, o = _scores(ctx, lay, feats)
@@ -160,4 +177,93 @@ def test_cp_launch_strategies_bitwise_equal():
         np.testing.assert_array_equal(o, ref_o, err_msg=launch)
         torch.randn(1 << 18, device="cuda").mul_(2.0).sum().item()     # eager work between replays
     ctx.set_launch("batched")
+    ctx.close()
+
+
+def _oracle_thresholds(wl, fac, positives):
+    """Per-filter thresholds (filter order) from positives (image, level,
+    comp, y, x), in the oracle, less 1e-3; filters no positive covers get -inf."""
+    parts_of = {k: [] for k in range(len(wl.bank.filters))}
+    cache = {}
+
+    def terms(img, lvl, k):
+        key = (img, lvl, k)
+        if key not in cache:
+            cache[key] = oracle.cp_terms(wl.level_features(img, lvl).astype(np.float64), *fac[k])
+        return cache[key]
+    for (img, lvl, comp, y, x) in positives:
+        c = wl.bank.components[comp]
+        oct_ = wl.pyramids[img].octave
+        parts_of[c.root].append(oracle.partial_sums(terms(img, lvl, c.root), y, x))
+        for i, k in enumerate(c.parts):
+            T = terms(img, lvl - oct_, k)
+            ay, ax = 2 * y + int(c.anchors[i][0]), 2 * x + int(c.anchors[i][1])
+            if ay < T.shape[1] and ax < T.shape[2]:
+                parts_of[k].append(oracle.partial_sums(T, ay, ax))
+    # lowered by 1e-3 so that FP32 partial sums decide every positive clearly
+    return [oracle.fit_thresholds(ps) - 1e-3 if ps else np.full(fac[k][0].shape[1], -np.inf)
+            for k, ps in parts_of.items()], terms
+
+
+@pytest.mark.parametrize("cfg,every", [(1, 1), (2, 4)])
+def test_cp_pruning_against_oracle(cfg, every):
+    """Algorithm 1's early exit: thresholds fitted in the oracle on positives
+    (each sampled map's best hypotheses, by the oracle's own CP scores), then
+    the GPU's rejected set and surviving scores against the oracle's pruned
+    maps, wherever every test of a hypothesis is decided by more than the
+    tolerance.  Survivors keep their unpruned scores bit for bit."""
+    wl = workloads.config1() if cfg == 1 else workloads.config2()
+    note(f"cp pruning c{cfg}")
+    ctx, fac = _cp_context(wl, 4)
+    lay = ctx.plan(wl.pyramids)
+    feats = torch.from_numpy(wl.features()).cuda()
+    free_s, free_o = _scores(ctx, lay, feats)
+    maps = [k for k in range(0, lay.n_maps, every) if lay.map_rows[k] > 0 and lay.map_cols[k] > 0]
+    cache = {}
+    sms = {}
+    positives = []
+    for k in maps:
+        img, lvl, comp = int(lay.map_image[k]), int(lay.map_level[k]), int(lay.map_comp[k])
+        sm = _oracle_cp_map(wl, fac, img, lvl, comp, cache)
+        sms[k] = sm
+        fin = np.isfinite(sm.score)
+        if fin.sum() >= 3:
+            flat = np.where(fin, sm.score, -np.inf).ravel()
+            for i in np.argsort(-flat)[:3]:
+                positives.append((img, lvl, comp, int(i) // sm.score.shape[1], int(i) % sm.score.shape[1]))
+    thr, terms = _oracle_thresholds(wl, fac, positives)
+    ctx.set_thresholds(thr)
+    s, o = _scores(ctx, lay, feats)
+    n_cmp = n_pruned = n_skip = 0
+    for k in maps:
+        img, lvl, comp = int(lay.map_image[k]), int(lay.map_level[k]), int(lay.map_comp[k])
+        c = wl.bank.components[comp]
+        oct_ = wl.pyramids[img].octave
+        sm = sms[k]
+        pscore, pruned, margin = oracle.prune_component(
+            sm.score, terms(img, lvl, c.root), [terms(img, lvl - oct_, q) for q in c.parts], c.anchors,
+            thr[c.root], [thr[q] for q in c.parts])
+        Ho, Wo = sm.score.shape
+        n = Ho * Wo
+        g = s[lay.map_score_off[k]:lay.map_score_off[k] + n].reshape(Ho, Wo)
+        g0 = free_s[lay.map_score_off[k]:lay.map_score_off[k] + n].reshape(Ho, Wo)
+        go = o[lay.map_offs_off[k]:lay.map_offs_off[k] + n * len(c.parts) * 2].reshape(len(c.parts), Ho, Wo, 2)
+        decided = margin > TOL_CP
+        n_skip += int((~decided).sum())
+        gp = np.isneginf(g) & np.isfinite(g0)
+        assert np.array_equal(gp[decided], (pruned & np.isfinite(sm.score))[decided]), f"map {k}: rejected sets differ"
+        keep = ~np.isneginf(g)
+        np.testing.assert_array_equal(g[keep], g0[keep])
+        assert np.all(go[:, np.isneginf(g) & np.isfinite(g0)] == 0)
+        n_cmp += int(decided.sum())
+        n_pruned += int(gp.sum())
+    for (img, lvl, comp, y, x) in positives:
+        k = lay.find(img, lvl, comp)
+        assert np.isfinite(s[lay.map_score_off[k] + y * int(lay.map_cols[k]) + x]), "a positive was rejected"
+    note(f"  {n_cmp} decisions compared ({n_skip} near-ties skipped), {n_pruned} rejected, "
+         f"{len(positives)} positives")
+    assert n_pruned > 0
+    ctx.set_thresholds(None)
+    s2, _ = _scores(ctx, lay, feats)
+    np.testing.assert_array_equal(s2, free_s)
     ctx.close()
