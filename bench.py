@@ -251,6 +251,9 @@ def main() -> None:
     ap.add_argument("--no-direct", action="store_true", help="skip the direct FP32 comparison run")
     ap.add_argument("--cp-rank", type=int, default=6,
                     help="rank of the per-filter CP form timed for comparison (0: skip)")
+    ap.add_argument("--plant", type=int, default=1,
+                    help="objects of every component planted per image as positives for the CP form's pruning "
+                         "thresholds (0: skip pruning)")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work (0: skip)")
     ap.add_argument("--launch", default="batched", choices=["batched", "per_level", "graph", "overlap"],
                     help="launch strategy of the timed steps")
@@ -357,6 +360,36 @@ def main() -> None:
               "formula1_gain_6x6_parts": 6 * 6 * 32 / (args.cp_rank * (6 + 6 + 32))}
         log(f"cp_fp32 R={args.cp_rank}: {cms:.3f} ms/step (ALS {als_s:.1f} s, mean rel err "
             f"{cp_err.mean():.3g}), stages {cstages}")
+        if args.plant > 0:
+            # convolution shortening: objects planted into a copy of the
+            # features are the positives the thresholds are fitted on
+            pfeat_host, pos = workloads.plant_objects(wl, wl.features(), args.plant)
+            pfeat = torch.from_numpy(pfeat_host).cuda()
+            ums, ustages, _, uscores, _ = run_mode(ctx, "cp_fp32", pfeat, max(2, min(args.steps, 5)), 1, torch)
+            t0 = time.time()
+            ctx.fit_thresholds(pfeat_host, pos, margin=1e-3)
+            fit_s = time.time() - t0
+            pms, pstages, _, pscores, _ = run_mode(ctx, "cp_fp32", pfeat, max(2, min(args.steps, 5)), 1, torch)
+            us, ps = uscores.cpu().numpy(), pscores.cpu().numpy()
+            fin = np.isfinite(us)
+            rejected = int((np.isneginf(ps) & fin).sum())
+            kept = ~np.isneginf(ps)
+            pos_ok = all(np.isfinite(ps[lay.map_score_off[lay.find(i, l, c)] + y * int(lay.map_cols[lay.find(i, l, c)]) + x])
+                         for (i, l, c, y, x) in pos)
+            cp["pruning"] = {"positives": len(pos), "positive_rule": f"{args.plant} planted object(s) of every component per image",
+                             "threshold_margin": 1e-3, "fit_seconds": fit_s,
+                             "rejected_fraction": rejected / max(int(fin.sum()), 1),
+                             "positives_kept": bool(pos_ok),
+                             "survivors_equal_unpruned": bool(np.array_equal(ps[kept], us[kept])),
+                             "unpruned_ms_per_step": ums,
+                             "unpruned_stages_ms": {k: round(v, 4) for k, v in ustages.items()},
+                             "ms_per_step": pms, "stages_ms": {k: round(v, 4) for k, v in pstages.items()},
+                             "speedup_vs_unpruned": ums / pms}
+            ctx.set_thresholds(None)
+            del pfeat
+            log(f"cp_fp32 on planted features: {ums:.3f} ms/step unpruned, {pms:.3f} pruned, "
+                f"{100 * rejected / max(int(fin.sum()), 1):.1f}% rejected, positives kept {pos_ok}, "
+                f"stages {pstages}")
 
     # roofline of each kernel; the headline object is the dominant one
     flops, cbytes, cresp = corr_work(wl, args.mode, args.rank)

@@ -316,6 +316,62 @@ def uneven_batch(n_images: int = 3, n_classes: int = 2, size_lo=(160, 120),
 PRESETS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}
 
 
+def plant_objects(wl: Workload, features: np.ndarray, per_comp: int, seed: int = 0):
+    """Synthetic positives: a copy of the packed features with ``per_comp``
+    objects of every component planted into every image, and their
+    hypotheses (image, root level, component, y, x).
+
+    An object of component c at root position (y, x) of root level l writes
+    the root filter's positive weights, scaled to a peak of 0.4 (the feature
+    range), into the root window at (y, x), and each part filter's likewise
+    into its window at the anchor (2y + v_y, 2x + v_x) of level l - octave.
+    Root windows stay inside the unpadded interior, part windows inside their
+    level; a root window avoids every window planted before it for up to 100
+    draws, after which overlaps are allowed (a later object then overwrites
+    part of an earlier one, which can only lower the thresholds fitted on
+    them).  Only inputs are drawn here: no response is computed."""
+    rng = seed_rng(wl.config, 10 + seed)
+    out = features.copy()
+    positives = []
+    for img, pyr in enumerate(wl.pyramids):
+        L = len(pyr.levels)
+        used = [np.zeros((lv.rows, lv.cols), bool) for lv in pyr.levels]
+        pr, pc = (PAD_ROWS, PAD_COLS) if wl.padded else (0, 0)
+        for ci, c in enumerate(wl.bank.components):
+            h0, w0 = wl.bank.shapes[c.root]
+            for _ in range(per_comp):
+                for _try in range(200):
+                    l = int(rng.integers(pyr.octave, L))
+                    lv, pl = pyr.levels[l], pyr.levels[l - pyr.octave]
+                    ylo, yhi = pr, lv.rows - pr - h0
+                    xlo, xhi = pc, lv.cols - pc - w0
+                    if yhi < ylo or xhi < xlo:
+                        continue
+                    y, x = int(rng.integers(ylo, yhi + 1)), int(rng.integers(xlo, xhi + 1))
+                    wins = [(l, y, x, wl.bank.filters[c.root])]
+                    ok = True
+                    for i, k in enumerate(c.parts):
+                        ay, ax = 2 * y + int(c.anchors[i][0]), 2 * x + int(c.anchors[i][1])
+                        f = wl.bank.filters[k]
+                        if not (ay <= pl.rows - f.shape[0] and ax <= pl.cols - f.shape[1]):
+                            ok = False
+                            break
+                        wins.append((l - pyr.octave, ay, ax, f))
+                    if not ok or (_try < 100 and used[l][y:y + h0, x:x + w0].any()):
+                        continue
+                    for (ll, wy, wx, f) in wins:
+                        L_ = pyr.levels[ll]
+                        pat = np.maximum(f, 0.0)
+                        pat = (0.4 / max(float(pat.max()), 1e-30)) * pat
+                        view = out[L_.cell_offset:L_.cell_offset + L_.rows * L_.cols].reshape(
+                            L_.rows, L_.cols, N_CHANNELS)
+                        view[wy:wy + f.shape[0], wx:wx + f.shape[1], :] = pat.astype(np.float32)
+                        used[ll][wy:wy + f.shape[0], wx:wx + f.shape[1]] = True
+                    positives.append((img, l, ci, y, x))
+                    break
+    return out, positives
+
+
 def count_responses(wl: Workload) -> dict:
     """Response cells the hot path computes: root filters on levels >= octave,
     part filters on the level one octave below, valid placements only."""
