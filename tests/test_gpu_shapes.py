@@ -1,0 +1,126 @@
+"""GPU parity on filter shapes outside the DPM defaults: 1x1 up to the
+16 x 32 maximum, tall (> 8 rows) and wide filters, in every correlation
+flavour.  These run the kernels' generic instances (the rolled filter-row
+loop of the shift-GEMM for tall filters, the runtime-shape CP tile) that the
+DPM-shaped workloads never reach."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+from _gpu_common import TOL, note
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+SHAPES = [(5, 7), (1, 1), (3, 5), (9, 4), (16, 32), (12, 20), (16, 1), (2, 32), (6, 6), (11, 13)]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _odd_workload():
+    rng = workloads.seed_rng(77, 1)
+    q, _ = np.linalg.qr(rng.standard_normal((32, 32)))
+    basis = q[:, :8]
+    filters = [workloads.draw_filter(rng, h, w, basis) for (h, w) in SHAPES]
+    comps = [workloads.Component(0, [1, 2, 3], np.array([[0, 0], [3, 2], [1, 9]], np.int32),
+                                 np.array([[0.02, 0.05, -0.01, 0.08]] * 3, np.float32)),
+             workloads.Component(4, [5, 6, 7, 8, 9], np.array([[4, 10], [0, 31], [30, 0], [20, 25], [7, 3]],
+                                                                np.int32),
+                                 np.array([[0.05, 0.03, 0.02, 0.04]] * 5, np.float32))]
+    levels = [workloads.Level(0, 70, 90), workloads.Level(70 * 90, 40, 50)]
+    pyr = workloads.Pyramid(levels, octave=1)
+    bank = workloads.Bank(filters, comps)
+    return workloads.Workload("odd shapes", 77, [pyr], bank, 70 * 90 + 40 * 50,
+                              workloads.feature_seed(77), False, [(90, 70)])
+
+
+def _ctx(wl, mode, rank):
+    from paper_1707_03268_amd import Context
+    ctx = Context(0)
+    ctx.load_filters(wl.bank.filters, wl.bank.components)
+    ref = None
+    if mode == "cp_fp32":
+        ctx.decompose_cp(rank, max_iters=40)
+        _, fac = ctx.get_cp(wl.bank.shapes)
+        ref = [tuple(m.astype(np.float64) for m in abc) for abc in fac]
+    elif mode != "direct_fp32":
+        _, ref = ctx.decompose(rank)
+    ctx.plan(wl.pyramids)
+    return ctx, ref
+
+
+def _ref_response(mode, X, f, k, ref):
+    if mode == "direct_fp32":
+        return oracle.correlate(X, f)
+    if mode == "cp_fp32":
+        return oracle.cp_response(X, *ref[k])
+    return oracle.tensor_response(X, f, ref)
+
+
+@pytest.mark.parametrize("mode,rank", [("direct_fp32", None), ("tensor_fp32", 8), ("tensor_bf16", 16),
+                                       ("cp_fp32", 3), ("cp_fp32", 7)])
+def test_odd_shapes_level_responses(mode, rank):
+    wl = _odd_workload()
+    note(f"odd shapes responses {mode} R={rank}")
+    ctx, ref = _ctx(wl, mode, rank)
+    feats = torch.from_numpy(wl.features()).cuda()
+    tol = TOL.get(mode, 1e-4)
+    for level in (0, 1):
+        out, total = ctx.level_responses(mode, feats, 0, level)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        X = wl.level_features(0, level).astype(np.float64)
+        off = 0
+        for k, f in enumerate(wl.bank.filters):
+            Ho, Wo = X.shape[0] - f.shape[0] + 1, X.shape[1] - f.shape[1] + 1
+            if Ho <= 0 or Wo <= 0:
+                continue
+            want = _ref_response(mode, X, f.astype(np.float64), k, ref)
+            g = got[off:off + Ho * Wo].reshape(Ho, Wo)
+            off += Ho * Wo
+            err = float(np.max(np.abs(g - want)))
+            assert err <= tol, f"level {level} filter {k} {f.shape[:2]}: max |err| {err:.3g} > {tol}"
+        assert off == total
+    ctx.close()
+
+
+@pytest.mark.parametrize("mode,rank", [("direct_fp32", None), ("cp_fp32", 5)])
+def test_odd_shapes_scores(mode, rank):
+    """Score maps of both components (a 5x7 root with 1x1, 3x5 and 9x4 parts;
+    the 16x32 root with 12x20, 16x1, 2x32, 6x6 and 11x13 parts)."""
+    wl = _odd_workload()
+    note(f"odd shapes scores {mode}")
+    ctx, ref = _ctx(wl, mode, rank)
+    lay = ctx.layout
+    feats = torch.from_numpy(wl.features()).cuda()
+    scores = torch.full((max(lay.n_score, 1),), float("nan"), dtype=torch.float32, device="cuda")
+    offs = torch.full((max(lay.n_offsets, 1),), -32768, dtype=torch.int16, device="cuda")
+    ctx.score_pyramid(mode, feats, scores, offs)
+    torch.cuda.synchronize()
+    s, o = scores.cpu().numpy(), offs.cpu().numpy()
+    Xr = wl.level_features(0, 1).astype(np.float64)
+    Xp = wl.level_features(0, 0).astype(np.float64)
+    tol = TOL.get(mode, 1e-4)
+    for ci, c in enumerate(wl.bank.components):
+        k = lay.find(0, 1, ci)
+        Ho, Wo = int(lay.map_rows[k]), int(lay.map_cols[k])
+        rr = _ref_response(mode, Xr, wl.bank.filters[c.root].astype(np.float64), c.root, ref)
+        prs = [_ref_response(mode, Xp, wl.bank.filters[q].astype(np.float64), q, ref) for q in c.parts]
+        sm = oracle.score_component(rr, prs, c.anchors, c.deform)
+        assert sm.score.shape == (Ho, Wo)
+        g = s[lay.map_score_off[k]:lay.map_score_off[k] + Ho * Wo].reshape(Ho, Wo)
+        fin = np.isfinite(sm.score)
+        assert np.array_equal(np.isfinite(g), fin)
+        if fin.any():
+            assert np.max(np.abs(g[fin] - sm.score[fin])) <= tol
+        go = o[lay.map_offs_off[k]:lay.map_offs_off[k] + Ho * Wo * len(c.parts) * 2].reshape(len(c.parts), Ho, Wo, 2)
+        check = sm.margin > tol
+        assert not (check[..., None] & (go != sm.offsets)).any()
+    ctx.close()
