@@ -116,6 +116,7 @@ hipError_t launch_project(bool bf16, const float* X, int64_t n_cells, const floa
 // through a double-buffered LDS chunk per K-step.
 // ---------------------------------------------------------------------------
 constexpr int CORR_MAX_H = 16;
+constexpr int CORR_NBUF = 3;                   // filter-chunk staging depth of the unrolled tiles
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
@@ -257,12 +258,15 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
     char* win = smem;
     u32x4* gbuf0 = reinterpret_cast<u32x4*>(smem + win_bytes);
     u32x4* gbuf1 = gbuf0 + BB * h * CU;
-    u32x4* gbuf2 = gbuf1 + BB * h * CU;
     // Unrolled heights stage the filter chunks with direct global-to-LDS loads,
-    // three buffers deep (the chunk of step gs + 2 is in flight while step gs
-    // computes); each wavefront loads UPW 1 KB units of a chunk.
+    // CORR_NBUF buffers deep (the chunks of steps gs + 1 .. gs + CORR_NBUF - 1
+    // are in flight while step gs computes); each wavefront loads UPW 1 KB
+    // units of a chunk.  Other tiles stage through registers, two buffers.
     constexpr bool DMA = HS > 0 && FragT<KIND>::bytes == 16;
     constexpr int UPW = DMA ? (BB * HS + WY - 1) / WY : 1;
+    constexpr int NB = DMA ? CORR_NBUF : 2;
+    static_assert(!DMA || (NB - 2) * UPW <= 15, "outstanding chunk loads must fit the vmcnt immediate");
+    auto gbuf = [&](int k) { return gbuf0 + k * (BB * h * CU); };
 
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
@@ -325,10 +329,16 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
         }
     };
 
-    // prologue: chunk 0 (and 1) into buffer 0 (and 1)
+    // chunk index of global step gs2 (group gs2 / total, step gs2 % total)
+    auto chunk_of = [&](int gs2) {
+        const int f = gs2 / total;
+        return f * BB * total + (gs2 - f * total);
+    };
+    // prologue: the chunks of steps 0 .. NB - 2 into buffers 0 .. NB - 2
     if constexpr (DMA) {
-        dma_chunk(0, gbuf0);
-        if (t.nfb * total > 1) dma_chunk(1, gbuf1);
+#pragma unroll
+        for (int k = 0; k + 1 < NB; ++k)
+            if (k < t.nfb * total) dma_chunk(chunk_of(k), gbuf(k));
     } else {
         u32x4 pf[PFMAX];
 #pragma unroll
@@ -342,7 +352,7 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
     // at the first group only when the level has one plane.  Each group ends
     // with its epilogue, whose stores drain while the next group computes.
     const int nsteps = t.nfb * total;
-    int step = 0, fbi = 0, bi = 0;                 // bi = gs % 3 (staging buffer of step gs)
+    int step = 0, fbi = 0, bi = 0;                 // bi = gs % NB (staging buffer of step gs)
     for (int gs = 0; gs < nsteps; ++gs) {
         const int q = step / S, s = step - q * S;
         if (s == 0 && (fbi == 0 || Q > 1)) {
@@ -392,10 +402,12 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
             }
         }
         if constexpr (DMA) {
-            // chunk gs has landed once at most the UPW loads of chunk gs + 1
-            // (issued after it) are outstanding; vmcnt(N) keeps expcnt and
-            // lgkmcnt at their maxima
-            if (gs + 1 < nsteps) __builtin_amdgcn_s_waitcnt(0xF70 | UPW);
+            // chunk gs has landed once at most the UPW loads of each later
+            // chunk already issued (gs + 1 .. gs + NB - 2) are outstanding;
+            // vmcnt(N) keeps expcnt and lgkmcnt at their maxima
+            const int later = min(NB - 2, nsteps - 1 - gs);
+            if (NB >= 4 && later >= 2) __builtin_amdgcn_s_waitcnt(0xF70 | (2 * UPW));
+            else if (later >= 1) __builtin_amdgcn_s_waitcnt(0xF70 | UPW);
             else __builtin_amdgcn_s_waitcnt(0xF70);
         }
         __syncthreads();                           // window and chunk `step` visible
@@ -411,13 +423,14 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
             ++nfbi;
         }
         if constexpr (DMA) {
-            if (gs + 2 < nsteps) {
-                int st2 = step + 2, f2 = fbi;
+            if (gs + NB - 1 < nsteps) {
+                int st2 = step + NB - 1, f2 = fbi;
                 while (st2 >= total) {
                     st2 -= total;
                     ++f2;
                 }
-                dma_chunk(f2 * BB * total + st2, bi == 0 ? gbuf2 : (bi == 1 ? gbuf0 : gbuf1));
+                // into the buffer step gs - 1 used, free since the barrier above
+                dma_chunk(f2 * BB * total + st2, gbuf(bi == 0 ? NB - 1 : bi - 1));
             }
         } else {
             const int cur = fbi * BB * total + step;   // chunk index within the tile's blocks
@@ -426,7 +439,7 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
             for (int k = 0; k < PFMAX; ++k) pf[k] = chunk_ld(nxt, k);
         }
 
-        const u32x4* gb = DMA ? (bi == 0 ? gbuf0 : (bi == 1 ? gbuf1 : gbuf2)) : ((gs & 1) ? gbuf1 : gbuf0);
+        const u32x4* gb = DMA ? gbuf(bi) : ((gs & 1) ? gbuf1 : gbuf0);
         const char* abase = win + (wv * TY) * pitch + p * PB + KS * s + FB * j;
         const char* gbb = reinterpret_cast<const char*>(gb) + lane * FB;
         if constexpr (HS > 0) {
@@ -451,6 +464,9 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
 #pragma unroll
                     for (int b = 0; b < BB; ++b)
                         acc[i][b] = mfma_step<KIND>(Ar[(n + i) % (TY + 1)], Br[n & 1][b], acc[i][b]);
+                // keep the source order: the next row's LDS reads are issued
+                // ahead of this row's MFMAs and their latency hides behind them
+                __builtin_amdgcn_sched_barrier(0);
             }
         } else {
             Frag A[TY];
@@ -498,7 +514,7 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
         }
         step = nstep;
         fbi = nfbi;
-        bi = bi == 2 ? 0 : bi + 1;
+        bi = bi == NB - 1 ? 0 : bi + 1;
     }
 
 }
@@ -506,7 +522,7 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
 // One workgroup per tile (grid = tiles), or a persistent grid that strides
 // over the cost-sorted tile list; both produce the same bits.
 template <CorrKind KIND, int PB, int TY, int BB, int WY, int HMAX>
-__global__ __launch_bounds__(64 * WY) __attribute__((amdgpu_waves_per_eu((HMAX <= 8 && KIND != CORR_FP8) ? (TY * BB <= 4 ? 3 : 2) : 1))) void corr_kernel(const CorrTile* __restrict__ tiles, int n_tiles,
+__global__ __launch_bounds__(64 * WY) __attribute__((amdgpu_waves_per_eu((HMAX <= 8 && KIND != CORR_FP8) ? 2 : 1))) void corr_kernel(const CorrTile* __restrict__ tiles, int n_tiles,
                                                        const GroupDesc* __restrict__ groups,
                                                        const char* __restrict__ Z,
                                                        const char* __restrict__ G,
@@ -541,7 +557,8 @@ size_t corr_lds_bytes(const CorrLaunch& cfg, int h, int S) {
     const int WC = 31 + (2 * FB * S) / cfg.pk.PB;
     const size_t win = (size_t)(cfg.ty * cfg.wy + h - 1) * WC * cfg.pk.PB;
     const size_t winal = (win + 15) & ~size_t(15);
-    return winal + 3 * (size_t)cfg.bb * h * 64 * FB;      // up to three staging buffers
+    const int nb = (h <= 8 && cfg.kind != CORR_FP8) ? std::max(CORR_NBUF, 2) : 2;   // staging buffers
+    return winal + (size_t)nb * cfg.bb * h * 64 * FB;
 }
 
 template <CorrKind KIND, int PB, int TY, int BB, int WY, int HMAX>
