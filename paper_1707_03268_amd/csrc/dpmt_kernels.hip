@@ -357,7 +357,28 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
         const int q = step / S, s = step - q * S;
         if (s == 0 && (fbi == 0 || Q > 1)) {
             __syncthreads();                       // previous plane fully consumed
-            if (cpr <= NT) {
+            if constexpr (DMA && PB >= 16) {
+                // the whole window by direct global-to-LDS loads, 1 KB units
+                // dealt to the wavefronts: lane byte o of the window is row
+                // o / pitch, cell (o % pitch) / PB, byte o % PB of the cell's
+                // plane-q run (16-byte pieces never straddle a cell).  Cells
+                // beyond the level only feed outputs that are never kept, so
+                // their addresses are clamped into the level.  One round trip,
+                // then everything this wave issued has landed.
+                const int nunits = (nrows * pitch + 1023) >> 10;
+                const float inv_pitch = 1.f / (float)pitch;
+                for (int u = wvu; u < nunits; u += WY) {
+                    const int o = u * 1024 + lane * 16;
+                    const int rr = (int)(((float)o + 0.5f) * inv_pitch);   // exact: o < 2^17
+                    const int rem = o - rr * pitch;
+                    const int y = min(t.y0 + rr, t.H - 1), x = min(t.x0 + rem / PB, t.W - 1);
+                    const char* src = Z + ((t.z_cell + (int64_t)y * t.W + x) * cell_bytes + q * PB + (rem & (PB - 1)));
+                    __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void*)src,
+                                                     (__attribute__((address_space(3))) void*)(win + u * 1024),
+                                                     16, 0, 0);
+                }
+                __builtin_amdgcn_s_waitcnt(0xF70);                     // vmcnt(0)
+            } else if (cpr <= NT) {
                 for (int rb = 0; rb < nrows; rb += WBATCH * rpp) {
                     u32x4 r[WBATCH];
 #pragma unroll
@@ -556,7 +577,7 @@ size_t corr_lds_bytes(const CorrLaunch& cfg, int h, int S) {
     const int FB = frag_bytes(cfg.kind);
     const int WC = 31 + (2 * FB * S) / cfg.pk.PB;
     const size_t win = (size_t)(cfg.ty * cfg.wy + h - 1) * WC * cfg.pk.PB;
-    const size_t winal = (win + 15) & ~size_t(15);
+    const size_t winal = (win + 1023) & ~size_t(1023);   // whole 1 KB units (window DMA)
     const int nb = (h <= 8 && cfg.kind != CORR_FP8) ? std::max(CORR_NBUF, 2) : 2;   // staging buffers
     return winal + (size_t)nb * cfg.bb * h * 64 * FB;
 }
@@ -570,7 +591,7 @@ static hipError_t launch_corr_h(const CorrLaunch& cfg, const CorrTile* tiles, in
     const int FB = FragT<KIND>::bytes;
     const int WC = 31 + (2 * FB * max_S) / PB;
     const size_t win = (size_t)(TY * WY + max_h - 1) * WC * PB;
-    const int win_bytes = (int)((win + 15) & ~size_t(15));
+    const int win_bytes = (int)((win + 1023) & ~size_t(1023));
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     auto kern = corr_kernel<KIND, PB, TY, BB, WY, HMAX>;
     if (lds > 65536) {
