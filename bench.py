@@ -138,10 +138,12 @@ def place_bytes(lay) -> int:
     return 4 * lay.n_resp_part + 4 * lay.n_resp_root + 4 * lay.n_score + 2 * lay.n_offsets
 
 
-def run_mode(ctx, mode, feats, steps, warmup, torch, launch="batched"):
+def run_mode(ctx, mode, feats, steps, warmup, torch, launch="batched", profile=False):
     """Warm up, then time exactly `steps` calls on torch's current stream with
-    an event between consecutive calls.  Returns (mean ms, per-stage ms, step
-    percentiles, scores, offsets)."""
+    an event between consecutive calls.  With `profile` the library also
+    records events between its stages, for the per-stage split (a run of its
+    own: those events sit inside the timed calls).  Returns (mean ms,
+    per-stage ms, step percentiles, scores, offsets)."""
     lay = ctx.layout
     scores = torch.empty(max(lay.n_score, 1), dtype=torch.float32, device="cuda")
     offs = torch.empty(max(lay.n_offsets, 1), dtype=torch.int16, device="cuda")
@@ -150,7 +152,7 @@ def run_mode(ctx, mode, feats, steps, warmup, torch, launch="batched"):
     for _ in range(warmup):
         ctx.score_pyramid(mode, feats, scores, offs, stream=stream)
     torch.cuda.synchronize()
-    ctx.set_profiling(True)
+    ctx.set_profiling(profile)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
     ev[0].record(stream)
@@ -162,9 +164,17 @@ def run_mode(ctx, mode, feats, steps, warmup, torch, launch="batched"):
     per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
     pct = {"p10": float(np.percentile(per, 10)), "p50": float(np.percentile(per, 50)),
            "p90": float(np.percentile(per, 90))}
-    stages, calls = ctx.stage_times()
+    stages = ctx.stage_times()[0] if profile else {}
     ctx.set_profiling(False)
     ctx.set_launch("batched")
+    return ms, stages, pct, scores, offs
+
+
+def measure(ctx, mode, feats, steps, warmup, torch, launch="batched"):
+    """The stage split from a profiled pass, then the step time (with its
+    percentiles and the outputs) from a pass with no events inside the calls."""
+    _, stages, _, _, _ = run_mode(ctx, mode, feats, steps, warmup, torch, profile=True)
+    ms, _, pct, scores, offs = run_mode(ctx, mode, feats, steps, warmup, torch, launch=launch)
     return ms, stages, pct, scores, offs
 
 
@@ -311,10 +321,9 @@ def main() -> None:
     elif args.tile_config is not None:
         ctx.set_tile_config(args.mode, args.tile_config)
 
-    # stage split from the batched strategy (a graph launch has none)
-    ms, stages, pct, scores, offs = run_mode(ctx, args.mode, feats, args.steps, args.warmup, torch)
-    if args.launch != "batched":
-        ms, _, pct, scores, offs = run_mode(ctx, args.mode, feats, args.steps, args.warmup, torch,
+    # stage split from a profiled pass of the batched strategy (a graph launch
+    # has none), then the timed steps with no events inside the calls
+    ms, stages, pct, scores, offs = measure(ctx, args.mode, feats, args.steps, args.warmup, torch,
                                             launch=args.launch)
     value = lay.n_resp / (ms * 1e-3)
     log(f"{args.mode} ({args.launch}): {ms:.3f} ms/step, {value:.4g} resp/s, stages {stages}")
@@ -331,7 +340,7 @@ def main() -> None:
     direct = None
     if not args.no_direct and args.mode != "direct_fp32":
         dsteps = max(2, min(args.steps, 5))
-        dms, dstages, _, _, _ = run_mode(ctx, "direct_fp32", feats, dsteps, 1, torch)
+        dms, dstages, _, _, _ = measure(ctx, "direct_fp32", feats, dsteps, 1, torch)
         dflops, dbytes, _ = corr_work(wl, "direct_fp32", 32)
         direct = {"value": lay.n_resp / (dms * 1e-3), "ms_per_step": dms,
                   "stages_ms": {k: round(v, 4) for k, v in dstages.items()},
@@ -344,7 +353,7 @@ def main() -> None:
         t0 = time.time()
         cp_err = ctx.decompose_cp(args.cp_rank, max_iters=60, tol=1e-9)
         als_s = time.time() - t0
-        cms, cstages, _, _, _ = run_mode(ctx, "cp_fp32", feats, max(2, min(args.steps, 5)), 1, torch)
+        cms, cstages, _, _, _ = measure(ctx, "cp_fp32", feats, max(2, min(args.steps, 5)), 1, torch)
         mults = mult_counts(wl, args.rank, args.cp_rank)
         ctf = 2 * mults["cp"] / (cstages["correlation"] * 1e-3) / 1e12
         cp = {"rank": args.cp_rank, "value": lay.n_resp / (cms * 1e-3), "ms_per_step": cms,
@@ -365,11 +374,11 @@ def main() -> None:
             # features are the positives the thresholds are fitted on
             pfeat_host, pos = workloads.plant_objects(wl, wl.features(), args.plant)
             pfeat = torch.from_numpy(pfeat_host).cuda()
-            ums, ustages, _, uscores, _ = run_mode(ctx, "cp_fp32", pfeat, max(2, min(args.steps, 5)), 1, torch)
+            ums, ustages, _, uscores, _ = measure(ctx, "cp_fp32", pfeat, max(2, min(args.steps, 5)), 1, torch)
             t0 = time.time()
             ctx.fit_thresholds(pfeat_host, pos, margin=1e-3)
             fit_s = time.time() - t0
-            pms, pstages, _, pscores, _ = run_mode(ctx, "cp_fp32", pfeat, max(2, min(args.steps, 5)), 1, torch)
+            pms, pstages, _, pscores, _ = measure(ctx, "cp_fp32", pfeat, max(2, min(args.steps, 5)), 1, torch)
             us, ps = uscores.cpu().numpy(), pscores.cpu().numpy()
             fin = np.isfinite(us)
             rejected = int((np.isneginf(ps) & fin).sum())
