@@ -173,6 +173,7 @@ struct PlaceLds {
     int r1_rows;       // largest part map height + 2 * PLACE_PAD
     int stage_words;   // floats of the staging buffer (PLACE_STAGE)
     int ctab_words;    // floats per cost table (multiple of 4)
+    int max_parts;     // most parts of one map
 };
 size_t place_lds_bytes(const PlaceLds& l);
 // Row span (floats) a part of response width Wp can need in the staging

@@ -1216,7 +1216,8 @@ __device__ __forceinline__ float quad_cost(float a, float b, int u) {
 size_t place_lds_bytes(const PlaceLds& l) {
     return (size_t)4 * ((size_t)l.acc_rows * PLACE_CW + (size_t)l.r1_rows * PLACE_CW +
                         (size_t)l.stage_words + 2 * (size_t)l.ctab_words) +
-           (size_t)2 * l.r1_rows * PLACE_CW + (size_t)l.acc_rows * PLACE_CW;
+           (size_t)2 * l.r1_rows * PLACE_CW + (size_t)l.acc_rows * PLACE_CW +
+           (size_t)16 * l.max_parts;
 }
 
 constexpr int PLACE_LOADS = PLACE_STAGE / 1024;        // staged float4 per thread and round
@@ -1249,9 +1250,22 @@ struct PlaceGeo {
     int live;
 };
 
-__device__ __forceinline__ PlaceGeo place_geo(const MapPart& P, const MapDesc& M, int xs,
-                                              const int* __restrict__ rmax,
-                                              const int* __restrict__ rmin, int stage_words) {
+// Windows of a part that do not depend on the strip: the row window
+// [wx, wy] and the column window [wz, ww] (clamped to the map +- 1 row), from
+// the value range of the part's plane.
+__device__ __forceinline__ int4 part_windows(const MapPart& P, const int* __restrict__ rmax,
+                                             const int* __restrict__ rmin) {
+    const float hi = range_value(rmax[P.rng]), lo = range_value(rmin[P.rng]);
+    const float range = hi >= lo ? hi - lo : 0.f;
+    int ulo, uhi, vlo, vhi;
+    line_window_r(P.d[1], P.d[0], P.inv2ax, range, P.Wp, ulo, uhi);
+    line_window_r(P.d[3], P.d[2], P.inv2ay, range + P.bb4a, P.Hp, vlo, vhi);
+    return make_int4(ulo, uhi, max(vlo, -(P.Hp + 1)), min(vhi, P.Hp + 1));
+}
+
+// win: the part's part_windows, read from LDS by every lane (made uniform here).
+__device__ __forceinline__ PlaceGeo place_geo(const MapPart& P, const MapDesc& M, int xs, int4 win,
+                                              int stage_words) {
     constexpr int CW = PLACE_CW;
     PlaceGeo G;
     G.plane = P.plane;
@@ -1263,20 +1277,16 @@ __device__ __forceinline__ PlaceGeo place_geo(const MapPart& P, const MapDesc& M
     G.bx = P.d[0];
     G.ay = P.d[3];
     G.by = P.d[2];
-    const float hi = range_value(rmax[P.rng]), lo = range_value(rmin[P.rng]);
-    const float range = hi >= lo ? hi - lo : 0.f;
     G.tx0 = 2 * xs + P.vx;
-    int ulo, uhi;
-    line_window_r(G.ax, G.bx, P.inv2ax, range, P.Wp, ulo, uhi);
+    int ulo = __builtin_amdgcn_readfirstlane(win.x), uhi = __builtin_amdgcn_readfirstlane(win.y);
     ulo = max(ulo, -(G.tx0 + 2 * (CW - 1)));              // beyond: left of every map column
     uhi = min(uhi, P.Wp - 1 - G.tx0);                     // beyond: right of every map column
     ulo -= (G.tx0 + ulo) & 3;                             // staged rows start 16-byte aligned
     G.ulo = ulo;
     G.Wr = uhi - ulo + 1;
     G.Wq = (G.Wr + 3) & ~3;
-    line_window_r(G.ay, G.by, P.inv2ay, range + P.bb4a, P.Hp, G.vlo, G.vhi);
-    G.vlo = max(G.vlo, -(P.Hp + 1));
-    G.vhi = min(G.vhi, P.Hp + 1);
+    G.vlo = __builtin_amdgcn_readfirstlane(win.z);
+    G.vhi = __builtin_amdgcn_readfirstlane(win.w);
     G.Wc = G.vhi - G.vlo + 1;
     G.live = P.Hp > 0 && P.Wp > 0 && G.Wr > 0;
     G.CH = (2 * (CW - 1) + G.Wq + 3) >> 2;
@@ -1353,6 +1363,7 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
     float* ccol = crow + L.ctab_words;                     // column-pass cost table
     int16_t* r1a = reinterpret_cast<int16_t*>(ccol + L.ctab_words);   // [r1_rows][CW]
     uint8_t* rej = reinterpret_cast<uint8_t*>(r1a + L.r1_rows * CW); // [acc_rows][CW] rejected
+    int4* win = reinterpret_cast<int4*>(rej + L.acc_rows * CW);       // [max_parts] part_windows
 
     const int item = xcd_item<PLACE_XCL>(blockIdx.x);
     if (item >= n_blocks) return;
@@ -1392,8 +1403,11 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
         }
     }
 
+    for (int s = tid; s < M.n_parts; s += 256) win[s] = part_windows(parts[M.part_base + s], rmax, rmin);
+    __syncthreads();
+
     float4 pf[PLACE_LOADS];
-    PlaceGeo G = place_geo(parts[M.part_base], M, xs, rmax, rmin, L.stage_words);
+    PlaceGeo G = place_geo(parts[M.part_base], M, xs, win[0], L.stage_words);
     if (G.rounds > 0) place_load(G, resp, 0, pf);
 
     for (int s = 0; s < M.n_parts; ++s) {
@@ -1410,7 +1424,7 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
         __syncthreads();                                   // tables, pads, round 0 staged
         const bool has_next = s + 1 < M.n_parts;
         PlaceGeo Gn = G;
-        if (has_next) Gn = place_geo(parts[M.part_base + s + 1], M, xs, rmax, rmin, L.stage_words);
+        if (has_next) Gn = place_geo(parts[M.part_base + s + 1], M, xs, win[s + 1], L.stage_words);
         if (G.live) {
             // row pass
             for (int r = 0; r < G.rounds; ++r) {
