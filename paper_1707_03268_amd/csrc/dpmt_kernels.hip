@@ -1410,14 +1410,18 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
     PlaceGeo G = place_geo(parts[M.part_base], M, xs, win[0], L.stage_words);
     if (G.rounds > 0) place_load(G, resp, 0, pf);
 
+    int pad_hp = -1;                                       // part height the -inf pad rows are at
     for (int s = 0; s < M.n_parts; ++s) {
         // pf holds round 0 of part s (when it has rows)
         if (G.live) {
             for (int e = tid; e < G.Wq; e += 256) crow[e] = e < G.Wr ? quad_cost(G.ax, G.bx, G.ulo + e) : INFINITY;
             for (int e = tid; e < G.Wc + 4; e += 256) ccol[e] = e < G.Wc ? quad_cost(G.ay, G.by, G.vlo + e) : INFINITY;
-            for (int i = tid; i < 2 * PAD * CW; i += 256) {
-                const int r = i / CW;
-                r1v[(r < PAD ? r : G.Hp + r) * CW + (i - r * CW)] = -INFINITY;
+            if (G.Hp != pad_hp) {                          // the row pass writes rows [0, Hp) only
+                for (int i = tid; i < 2 * PAD * CW; i += 256) {
+                    const int r = i / CW;
+                    r1v[(r < PAD ? r : G.Hp + r) * CW + (i - r * CW)] = -INFINITY;
+                }
+                pad_hp = G.Hp;
             }
             if (G.rounds > 0) place_store(G, stage, pf);
         }
