@@ -184,6 +184,47 @@ def test_c3_sampled_bf16_r16():
     _check_all_maps(wl, run, "tensor_bf16", run.basis, want)
 
 
+def _sample_maps(wl, lay, images, comps):
+    """Maps of the given images and components on the first, a middle and the
+    last root level of each image (levels where the component has no map are
+    skipped)."""
+    want = []
+    for i in images:
+        L, o = len(wl.pyramids[i].levels), wl.pyramids[i].octave
+        for lvl in sorted({o, (o + L - 1) // 2, L - 1}):
+            for comp in comps:
+                try:
+                    want.append(lay.find(i, lvl, comp))
+                except KeyError:
+                    pass
+    return want
+
+
+def test_c4_sampled_bf16_r16():
+    """The 64-image batch of uneven sizes (320x240 .. 1280x960 px) in one
+    batched call; oracle on sampled maps of the first, last, largest and
+    smallest images."""
+    wl = workloads.config4()
+    note("c4 tensor bf16 R=16, 64 images, sampled maps")
+    run = run_gpu(wl, "tensor_bf16", 16)
+    area = [w * h for (w, h) in wl.image_sizes]
+    imgs = sorted({0, len(area) - 1, int(np.argmax(area)), int(np.argmin(area))})
+    want = _sample_maps(wl, run.layout, imgs, (0, 61, 119))
+    assert len(want) >= 24
+    _check_all_maps(wl, run, "tensor_bf16", run.basis, want)
+
+
+def test_c5_frames_sampled_bf16_r16():
+    """Two 1920x1080 frames of the video workload (frame size and bank at full
+    scale, fewer frames); oracle on sampled maps of both frames."""
+    wl = workloads.config5(n_frames=2)
+    note("c5 tensor bf16 R=16, 2 frames 1920x1080, sampled maps")
+    run = run_gpu(wl, "tensor_bf16", 16)
+    want = _sample_maps(wl, run.layout, (0, 1), (2, 60, 117))
+    assert len(want) >= 12
+    _check_all_maps(wl, run, "tensor_bf16", run.basis, want)
+
+
 def test_c3_sampled_direct():
     wl = workloads.config3()
     note("c3 direct fp32, sampled maps")
@@ -241,25 +282,22 @@ def test_level_responses_c2_fp8_within_rounding_bound(rank):
     note(f"  worst error / bound {worst:.3g}")
 
 
-@pytest.mark.parametrize("cfg,rank", [(1, 16), (2, 16)])
-def test_scores_fp8_within_propagated_bound(cfg, rank):
-    """FP8 scores against the FP64 tensor oracle: the distance transform is
-    1-Lipschitz, so a score errs by at most the root's response bound plus, per
-    part, the largest response bound over its part map; placements must match
-    where the oracle margin exceeds twice that part bound."""
+def _check_fp8_maps(wl, run, rank, maps):
+    """FP8 scores of `maps` against the FP64 tensor oracle: the distance
+    transform is 1-Lipschitz, so a score errs by at most the root's response
+    bound plus, per part, the largest response bound over its part map;
+    placements must match where the oracle margin exceeds twice that part
+    bound."""
     from _gpu_common import fp8_channel_scales, fp8_response_bound
-    wl = workloads.PRESETS[cfg]()
-    note(f"c{cfg} tensor_fp8 R={rank} scores")
-    run = run_gpu(wl, "tensor_fp8", rank)
     U = run.basis
     RP = 16 if rank <= 16 else 32
     feats = wl.features().astype(np.float64)
     s = fp8_channel_scales(np.abs(feats).max(0), U, RP)
+    del feats
     lay = run.layout
     cache = {}
     worst = 0.0
     checked = total = 0
-    maps = range(lay.n_maps) if cfg == 1 else range(0, lay.n_maps, 7)
     for k in maps:
         img, lvl, comp = int(lay.map_image[k]), int(lay.map_level[k]), int(lay.map_comp[k])
         sm = oracle_map(wl, img, lvl, comp, U, cache)
@@ -287,3 +325,23 @@ def test_scores_fp8_within_propagated_bound(cfg, rank):
             checked += int(chk.sum())
             assert np.array_equal(go[i][chk], sm.offsets[i][chk]), f"map {k} part {i}: placements differ"
     note(f"  worst score error / bound {worst:.3g}; placements checked {checked}/{total}")
+
+
+@pytest.mark.parametrize("cfg,rank", [(1, 16), (2, 16)])
+def test_scores_fp8_within_propagated_bound(cfg, rank):
+    wl = workloads.PRESETS[cfg]()
+    note(f"c{cfg} tensor_fp8 R={rank} scores")
+    run = run_gpu(wl, "tensor_fp8", rank)
+    lay = run.layout
+    _check_fp8_maps(wl, run, rank, range(lay.n_maps) if cfg == 1 else range(0, lay.n_maps, 7))
+
+
+def test_c5_frames_fp8_within_propagated_bound():
+    """FP8 e4m3 with per-channel scales on two full-size 1920x1080 frames of the
+    video workload, sampled maps, against the propagated rounding bound."""
+    wl = workloads.config5(n_frames=2)
+    note("c5 tensor_fp8 R=16, 2 frames 1920x1080, sampled maps")
+    run = run_gpu(wl, "tensor_fp8", 16)
+    want = _sample_maps(wl, run.layout, (0, 1), (4, 77))
+    assert len(want) >= 8
+    _check_fp8_maps(wl, run, 16, want)
