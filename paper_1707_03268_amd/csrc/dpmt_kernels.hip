@@ -1314,7 +1314,7 @@ __device__ __forceinline__ PlaceGeo place_geo(const MapPart& P, const MapDesc& M
 __device__ __forceinline__ void place_load(const PlaceGeo& G, const float* __restrict__ resp,
                                            int round, float4 (&pf)[PLACE_LOADS]) {
     const int y = min(G.ry0 + (round << G.lrb) + G.lrow, G.ry1);
-    const float* base = resp + G.plane + (int64_t)y * G.ld;
+    const float* base = resp + G.plane + __umul24(y, G.ld);     // full-rate 24-bit product
 #pragma unroll
     for (int q = 0; q < PLACE_LOADS; ++q) {
         const int x = G.X0 + 4 * (G.lcol + q * G.tpr);
@@ -1337,7 +1337,7 @@ __device__ __forceinline__ void place_store(const PlaceGeo& G, float* stage,
             const float v1 = (unsigned)(x + 1) < (unsigned)G.Wp ? v.y : -INFINITY;
             const float v2 = (unsigned)(x + 2) < (unsigned)G.Wp ? v.z : -INFINITY;
             const float v3 = (unsigned)(x + 3) < (unsigned)G.Wp ? v.w : -INFINITY;
-            float* even = stage + G.lrow * 2 * G.SH + 2 * c;
+            float* even = stage + __umul24(G.lrow, 2 * G.SH) + 2 * c;
             *reinterpret_cast<float2*>(even) = make_float2(v0, v2);
             *reinterpret_cast<float2*>(even + G.SH) = make_float2(v1, v3);
         }
@@ -1374,6 +1374,10 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
     const int tid = threadIdx.x;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);    // wavefront-uniform
     const int j = tid % CW, rr = tid / CW, hr = rr % RPW;
+    // position of (y0a + hr, xs + j) in a score map / the root plane: a
+    // wave-uniform y0a * Wo (scalar) plus these per-thread offsets
+    const uint32_t pos_hr = __umul24(hr, M.Wo) + xs + j;
+    const uint32_t rpos_hr = __umul24(hr, M.ldr) + xs + j;
 
     // Algorithm 1's early exit: a root position is rejected when a partial CP
     // sum of its root (at the position) or of a part (at its anchor) fell
@@ -1439,7 +1443,7 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
                 for (int q = rr; q < G.RB; q += ROWS) {
                     const int y = yr + q;
                     if (y > G.ry1) break;
-                    const float* SE = stage + q * 2 * G.SH + j;
+                    const float* SE = stage + __umul24(q, 2 * G.SH) + j;
                     const float* SO = SE + G.SH;
                     // running maximum per group of 4 offsets; the first group
                     // that reaches the maximum holds the smallest maximiser
@@ -1511,7 +1515,8 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
                     *a = s == 0 ? D : *a + D;
                     if (flags != nullptr && rej[y0 * CW + j]) packed = 0u;
                     if (offs)
-                        reinterpret_cast<uint32_t*>(offs + M.offs_off)[((int64_t)s * M.Ho + y0) * M.Wo + xs + j] = packed;
+                        (reinterpret_cast<uint32_t*>(offs + M.offs_off) + (int64_t)s * M.Ho * M.Wo +
+                         y0a * M.Wo)[pos_hr] = packed;
                 }
             }
         } else {
@@ -1522,7 +1527,8 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
                 if (y0 < M.Ho && j < ncol) {
                     acc[y0 * CW + j] = -INFINITY;
                     if (offs)
-                        reinterpret_cast<uint32_t*>(offs + M.offs_off)[((int64_t)s * M.Ho + y0) * M.Wo + xs + j] = 0u;
+                        (reinterpret_cast<uint32_t*>(offs + M.offs_off) + (int64_t)s * M.Ho * M.Wo +
+                         y0a * M.Wo)[pos_hr] = 0u;
                 }
             }
         }
@@ -1532,9 +1538,9 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
     for (int y0a = RPW * w; y0a < M.Ho; y0a += ROWS) {
         const int y0 = y0a + hr;
         if (y0 < M.Ho && j < ncol)
-            scores[M.score_off + (int64_t)y0 * M.Wo + xs + j] =
+            (scores + M.score_off + y0a * M.Wo)[pos_hr] =
                 (flags != nullptr && rej[y0 * CW + j]) ? -INFINITY
-                                                       : resp[M.root_plane + (int64_t)y0 * M.ldr + xs + j] + acc[y0 * CW + j];
+                                                       : (resp + M.root_plane + y0a * M.ldr)[rpos_hr] + acc[y0 * CW + j];
     }
 }
 
