@@ -1462,7 +1462,7 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
                         const int k = garg >> 1;
                         const float4 c = *reinterpret_cast<const float4*>(crow + garg);
                         const float v0 = SE[k] - c.x, v1 = SO[k] - c.y, v2 = SE[k + 1] - c.z;
-                        arg = v0 == best ? garg : v1 == best ? garg + 1 : v2 == best ? garg + 2 : garg + 3;
+                        arg = garg + min(min(v0 == best ? 0 : 3, v1 == best ? 1 : 3), v2 == best ? 2 : 3);
                     }
                     const bool ok = G.tx0 + 2 * j < G.Wp;
                     r1v[(y + PAD) * CW + j] = ok ? best : -INFINITY;
@@ -1498,7 +1498,7 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
                     const float4 c = *reinterpret_cast<const float4*>(ccol + garg);
                     const float* q = col + garg * CW;
                     const float v0 = q[0] - c.x, v1 = q[CW] - c.y, v2 = q[2 * CW] - c.z;
-                    arg = v0 == best ? garg : v1 == best ? garg + 1 : v2 == best ? garg + 2 : garg + 3;
+                    arg = garg + min(min(v0 == best ? 0 : 3, v1 == best ? 1 : 3), v2 == best ? 2 : 3);
                 }
                 const int y0 = y0a + hr;
                 if (y0 < M.Ho && j < ncol) {
