@@ -138,6 +138,47 @@ def test_plan_validation():
         ctx.plan([p])
 
 
+def _one_component_bank():
+    rng = np.random.default_rng(5)
+    fs = [rng.standard_normal((6, 11, 32)).astype(np.float32), rng.standard_normal((6, 6, 32)).astype(np.float32)]
+    comps = [workloads.Component(root=0, parts=[1], anchors=np.array([[2, 3]], np.int32),
+                                 deform=np.array([[0.05, 0.05, 0.05, 0.05]], np.float32))]
+    return fs, comps
+
+
+def _two_level_pyramid(part_rows, part_cols, root_rows, root_cols):
+    """Octave 1: parts on level 0, roots on level 1."""
+    return workloads.Pyramid([workloads.Level(0, part_rows, part_cols),
+                              workloads.Level(part_rows * part_cols, root_rows, root_cols)], octave=1)
+
+
+def test_plan_size_limits():
+    """The largest sizes plan; past them dpmt_plan fails with DPMT_E_UNSUPPORTED
+    and names the limit, and the context still plans a valid batch afterwards."""
+    fs, comps = _one_component_bank()
+    ctx = Context(device=-1)
+    ctx.load_filters(fs, comps)
+    # part response rows of up to 1976 cells fit the placement's staging
+    # (a row window spans the row plus 72 cells)
+    lay = ctx.plan([_two_level_pyramid(40, 1981, 20, 990)])
+    assert lay.n_maps == 1 and int(lay.map_cols[0]) == 990 - 11 + 1
+    with pytest.raises(DpmtError) as e:
+        ctx.plan([_two_level_pyramid(40, 1982, 20, 991)])
+    assert e.value.status == _abi.DPMT_E_UNSUPPORTED and "wider" in str(e.value)
+    # a placement block holds a whole strip of a score map in LDS (160 KB)
+    ctx.plan([_two_level_pyramid(800, 40, 400, 20)])
+    with pytest.raises(DpmtError) as e:
+        ctx.plan([_two_level_pyramid(1400, 40, 700, 20)])
+    assert e.value.status == _abi.DPMT_E_UNSUPPORTED and "tall" in str(e.value)
+    # level sides beyond 16384 cells
+    with pytest.raises(DpmtError) as e:
+        ctx.plan([_two_level_pyramid(20, 16385, 10, 100)])
+    assert e.value.status == _abi.DPMT_E_UNSUPPORTED
+    lay = ctx.plan([_two_level_pyramid(60, 80, 30, 40)])
+    assert lay.n_maps == 1
+    ctx.close()
+
+
 def test_null_pointer_rejected():
     lib = _abi.load()
     assert lib.dpmt_create(None, 0, None) == _abi.DPMT_E_INVALID

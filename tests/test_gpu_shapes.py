@@ -124,3 +124,45 @@ def test_odd_shapes_scores(mode, rank):
         check = sm.margin > tol
         assert not (check[..., None] & (go != sm.offsets)).any()
     ctx.close()
+
+
+# ------------------------------------------------------------ placement limits
+# (part level rows, cols, root level rows, cols): the widest part rows the
+# placement stages (1976 responses, plus a 72-cell window span = 2048 floats),
+# and the tallest score maps one placement block holds in its 160 KB of LDS.
+LIMITS = [("widest", 40, 1981, 20, 990), ("tallest", 1016, 40, 508, 20)]
+
+
+def _limit_workload(part_rows, part_cols, root_rows, root_cols):
+    """One component (a 6x11 root, three 6x6 parts) on a two-level pyramid at
+    one of the placement's limits.  The first part's quadratic terms are tiny,
+    so that its windows span whole rows and columns: the staged row span and
+    the cost tables reach the sizes the plan provisions for."""
+    rng = workloads.seed_rng(78, 1)
+    q, _ = np.linalg.qr(rng.standard_normal((32, 32)))
+    basis = q[:, :8]
+    filters = [workloads.draw_filter(rng, 6, 11, basis)] + [workloads.draw_filter(rng, 6, 6, basis) for _ in range(3)]
+    comps = [workloads.Component(0, [1, 2, 3], np.array([[0, 0], [4, 9], [6, 16]], np.int32),
+                                 np.array([[0.0, 1e-6, 0.0, 1e-6], [0.05, 0.02, 0.02, 0.01],
+                                           [0.0, 0.06, 0.01, 0.05]], np.float32))]
+    levels = [workloads.Level(0, part_rows, part_cols),
+              workloads.Level(part_rows * part_cols, root_rows, root_cols)]
+    pyr = workloads.Pyramid(levels, octave=1)
+    return workloads.Workload(f"placement limit {part_rows}x{part_cols}", 78, [pyr],
+                              workloads.Bank(filters, comps), part_rows * part_cols + root_rows * root_cols,
+                              workloads.feature_seed(78), False, [(part_cols, part_rows)])
+
+
+@pytest.mark.parametrize("name,pr,pc,rr,rc", LIMITS)
+@pytest.mark.parametrize("mode,rank", [("direct_fp32", None), ("tensor_bf16", 16)])
+def test_placement_limits_scores(name, pr, pc, rr, rc, mode, rank):
+    """The whole score map at the largest sizes dpmt_plan accepts."""
+    from _gpu_common import Cmp, compare_map, oracle_map, run_gpu
+    wl = _limit_workload(pr, pc, rr, rc)
+    note(f"placement limit {name}: part level {pr}x{pc}, {mode}")
+    run = run_gpu(wl, mode, rank)
+    cmp = Cmp()
+    sm = oracle_map(wl, 0, 1, 0, run.basis, {})
+    compare_map(run, wl, 0, 1, 0, sm, TOL[mode], cmp)
+    note(f"  {cmp.n_pos} positions, max |score err| {cmp.max_err:.3g}, argmax checked "
+         f"{cmp.n_arg_checked}/{cmp.n_arg}")
