@@ -1239,7 +1239,8 @@ struct PlaceGeo {
     int ld, Hp, Wp, vy;
     float ax, bx, ay, by;
     int tx0;            // target column of lane 0
-    int ulo, Wr, Wq;    // row window (clamped to the strip, start aligned), length, rounded to 4
+    int ulo, Wr, Wq;    // row window (clamped to the strip), length, rounded to 4
+    int offA, offB;     // staging offsets of the scan's even and odd offsets (parity halves)
     int vlo, vhi, Wc;   // column window (clamped to the map +- 1 row) and its length
     int CH, SH;         // staged float4 per row, floats per parity half-row
     int lrb, RB;        // rows per round RB = 2^lrb
@@ -1281,7 +1282,7 @@ __device__ __forceinline__ PlaceGeo place_geo(const MapPart& P, const MapDesc& M
     int ulo = __builtin_amdgcn_readfirstlane(win.x), uhi = __builtin_amdgcn_readfirstlane(win.y);
     ulo = max(ulo, -(G.tx0 + 2 * (CW - 1)));              // beyond: left of every map column
     uhi = min(uhi, P.Wp - 1 - G.tx0);                     // beyond: right of every map column
-    ulo -= (G.tx0 + ulo) & 3;                             // staged rows start 16-byte aligned
+    const int d = (G.tx0 + ulo) & 3;                      // staged rows start 16-byte aligned, d before the scan
     G.ulo = ulo;
     G.Wr = uhi - ulo + 1;
     G.Wq = (G.Wr + 3) & ~3;
@@ -1289,8 +1290,12 @@ __device__ __forceinline__ PlaceGeo place_geo(const MapPart& P, const MapDesc& M
     G.vhi = __builtin_amdgcn_readfirstlane(win.w);
     G.Wc = G.vhi - G.vlo + 1;
     G.live = P.Hp > 0 && P.Wp > 0 && G.Wr > 0;
-    G.CH = (2 * (CW - 1) + G.Wq + 3) >> 2;
+    G.CH = (2 * (CW - 1) + d + G.Wq + 3) >> 2;
     G.SH = 2 * G.CH;
+    // offset e of lane j is staged position 2 j + d + e: with e even it lies in
+    // the half of d's parity, from d / 2 on; with e odd in the other half
+    G.offA = (d & 1) ? G.SH + (d >> 1) : d >> 1;
+    G.offB = (d & 1) ? (d + 1) >> 1 : G.SH + (d >> 1);
     int lrb = 5;                                          // up to 32 rows per round
     while (lrb > 0 && (2 * G.SH << lrb) > stage_words) --lrb;
     G.lrb = lrb;
@@ -1298,7 +1303,7 @@ __device__ __forceinline__ PlaceGeo place_geo(const MapPart& P, const MapDesc& M
     G.ry0 = max(0, P.vy + G.vlo);
     G.ry1 = min(P.Hp - 1, 2 * (M.Ho - 1) + P.vy + G.vhi);
     G.rounds = (G.live && G.ry1 >= G.ry0) ? (G.ry1 - G.ry0 + G.RB) >> lrb : 0;
-    G.X0 = G.tx0 + ulo;
+    G.X0 = G.tx0 + ulo - d;
     G.tpr = 256 >> lrb;
     G.nq = (G.CH + G.tpr - 1) >> (8 - lrb);               // <= PLACE_LOADS since RB * CH <= 512
     G.lrow = (int)threadIdx.x >> (8 - lrb);
@@ -1443,8 +1448,8 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
                 for (int q = rr; q < G.RB; q += ROWS) {
                     const int y = yr + q;
                     if (y > G.ry1) break;
-                    const float* SE = stage + __umul24(q, 2 * G.SH) + j;
-                    const float* SO = SE + G.SH;
+                    const float* SE = stage + __umul24(q, 2 * G.SH) + j + G.offA;   // even offsets
+                    const float* SO = stage + __umul24(q, 2 * G.SH) + j + G.offB;   // odd offsets
                     // running maximum per group of 4 offsets; the first group
                     // that reaches the maximum holds the smallest maximiser
                     float best = -INFINITY;
@@ -1466,7 +1471,7 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
                     }
                     const bool ok = G.tx0 + 2 * j < G.Wp;
                     r1v[(y + PAD) * CW + j] = ok ? best : -INFINITY;
-                    r1a[(y + PAD) * CW + j] = (int16_t)(G.X0 + 2 * j + arg);
+                    r1a[(y + PAD) * CW + j] = (int16_t)(G.tx0 + G.ulo + 2 * j + arg);
                 }
                 __syncthreads();                           // stage consumed, R1 rows visible
                 if (more) {
