@@ -208,11 +208,15 @@ __device__ __forceinline__ void corr_epilogue(const CorrTile& t, const GroupDesc
                 v.z = acc[i][b][4 * m + 2] * sc;
                 v.w = acc[i][b][4 * m + 3] * sc;
                 *reinterpret_cast<float4*>(orow + 8 * m) = v;
-                vmax[b] = fmaxf(vmax[b], v.x);
-                vmin[b] = fminf(vmin[b], v.x);
-                if (x + 1 < t.Wo) { vmax[b] = fmaxf(vmax[b], v.y); vmin[b] = fminf(vmin[b], v.y); }
-                if (x + 2 < t.Wo) { vmax[b] = fmaxf(vmax[b], v.z); vmin[b] = fminf(vmin[b], v.z); }
-                if (x + 3 < t.Wo) { vmax[b] = fmaxf(vmax[b], v.w); vmin[b] = fminf(vmin[b], v.w); }
+                if (x + 3 < t.Wo) {                 // whole run inside the map: two 3-input max / min
+                    vmax[b] = fmaxf(fmaxf(vmax[b], v.x), fmaxf(v.y, fmaxf(v.z, v.w)));
+                    vmin[b] = fminf(fminf(vmin[b], v.x), fminf(v.y, fminf(v.z, v.w)));
+                } else {                            // the run that crosses the last column
+                    vmax[b] = fmaxf(vmax[b], v.x);
+                    vmin[b] = fminf(vmin[b], v.x);
+                    if (x + 1 < t.Wo) { vmax[b] = fmaxf(vmax[b], v.y); vmin[b] = fminf(vmin[b], v.y); }
+                    if (x + 2 < t.Wo) { vmax[b] = fmaxf(vmax[b], v.z); vmin[b] = fminf(vmin[b], v.z); }
+                }
             }
         }
     }
