@@ -869,12 +869,17 @@ __device__ __forceinline__ void cp_tile(const CpTile& t, const CpChunk* __restri
                                                                (((below >> (4 * j + 1)) & 1u) << 8) |
                                                                (((below >> (4 * j + 2)) & 1u) << 16) |
                                                                (((below >> (4 * j + 3)) & 1u) << 24);
+                if (x + 3 < t.Wo) {                  // whole run inside the map: 3-input max / min
+                    vmax = fmaxf(fmaxf(vmax, acc[j][0]), fmaxf(acc[j][1], fmaxf(acc[j][2], acc[j][3])));
+                    vmin = fminf(fminf(vmin, acc[j][0]), fminf(acc[j][1], fminf(acc[j][2], acc[j][3])));
+                } else {
 #pragma unroll
-                for (int c = 0; c < 4; ++c)
-                    if (x + c < t.Wo) {
-                        vmax = fmaxf(vmax, acc[j][c]);
-                        vmin = fminf(vmin, acc[j][c]);
-                    }
+                    for (int c = 0; c < 3; ++c)
+                        if (x + c < t.Wo) {
+                            vmax = fmaxf(vmax, acc[j][c]);
+                            vmin = fminf(vmin, acc[j][c]);
+                        }
+                }
             }
             if (rmax != nullptr && t.rng >= 0) {
 #pragma unroll
