@@ -1100,10 +1100,11 @@ hipError_t enqueue_batched(dpmt_ctx* c, dpmt_mode mode, const float* X, float* s
                            int16_t* offs, hipStream_t st, hipEvent_t* ev) {
     ModeData& md = c->modes[mode];
     hipError_t e = ev ? hipEventRecord(ev[0], st) : hipSuccess;
-    if (e == hipSuccess) e = launch_range_init(c->d_rkeys, c->n_slots, st);
-    if (e == hipSuccess) {
-        if (mode == DPMT_TENSOR_FP8) e = fp8_operands(c, md, X, c->n_cells, c->d_Z, st);
-        else if (is_tensor(mode)) e = launch_project(md.pk.esz == 2, X, c->n_cells, md.dU, md.pk.RP, c->d_Z, st);
+    if (e == hipSuccess) {                         // the projection also resets the value ranges
+        if (mode == DPMT_TENSOR_FP8 || !is_tensor(mode)) e = launch_range_init(c->d_rkeys, c->n_slots, st);
+        if (e == hipSuccess && mode == DPMT_TENSOR_FP8) e = fp8_operands(c, md, X, c->n_cells, c->d_Z, st);
+        else if (e == hipSuccess && is_tensor(mode))
+            e = launch_project(md.pk.esz == 2, X, c->n_cells, md.dU, md.pk.RP, c->d_Z, c->d_rkeys, c->n_slots, st);
     }
     if (e == hipSuccess && ev) e = hipEventRecord(ev[1], st);
     if (e == hipSuccess) e = corr_tiles(c, mode, 0, 0, n_corr_tiles(c, mode), X, st);
@@ -1133,7 +1134,7 @@ hipError_t enqueue_per_level(dpmt_ctx* c, dpmt_mode mode, const float* X, float*
             const float* Xl = X + lv.cell_offset * 32;
             void* Zl = static_cast<char*>(c->d_Z) + lv.cell_offset * zcell;
             e = mode == DPMT_TENSOR_FP8 ? launch_project_fp8(Xl, n, md.dU, md.pk.RP, md.dScales, Zl, st)
-                                        : launch_project(md.pk.esz == 2, Xl, n, md.dU, md.pk.RP, Zl, st);
+                                        : launch_project(md.pk.esz == 2, Xl, n, md.dU, md.pk.RP, Zl, nullptr, 0, st);
         }
     if (e == hipSuccess && ev) e = hipEventRecord(ev[1], st);
     for (const auto& r : corr_levels(c, mode)) {
@@ -1159,10 +1160,11 @@ hipError_t enqueue_overlap(dpmt_ctx* c, dpmt_mode mode, const float* X, float* s
     ModeData& md = c->modes[mode];
     const int K = c->n_chunks;
     hipError_t e = ev ? hipEventRecord(ev[0], st) : hipSuccess;
-    if (e == hipSuccess) e = launch_range_init(c->d_rkeys, c->n_slots, st);
-    if (e == hipSuccess) {
-        if (mode == DPMT_TENSOR_FP8) e = fp8_operands(c, md, X, c->n_cells, c->d_Z, st);
-        else if (is_tensor(mode)) e = launch_project(md.pk.esz == 2, X, c->n_cells, md.dU, md.pk.RP, c->d_Z, st);
+    if (e == hipSuccess) {                         // the projection also resets the value ranges
+        if (mode == DPMT_TENSOR_FP8 || !is_tensor(mode)) e = launch_range_init(c->d_rkeys, c->n_slots, st);
+        if (e == hipSuccess && mode == DPMT_TENSOR_FP8) e = fp8_operands(c, md, X, c->n_cells, c->d_Z, st);
+        else if (e == hipSuccess && is_tensor(mode))
+            e = launch_project(md.pk.esz == 2, X, c->n_cells, md.dU, md.pk.RP, c->d_Z, c->d_rkeys, c->n_slots, st);
     }
     if (e == hipSuccess && ev) e = hipEventRecord(ev[1], st);
     hipEvent_t fork = c->chunk_ev[K], join = c->chunk_ev[K + 1];
@@ -2178,7 +2180,8 @@ dpmt_status dpmt_level_responses(dpmt_ctx* c, dpmt_mode mode, const float* featu
         e = hipMalloc(&dZ, (size_t)cells * md.pk.RP * md.pk.esz);
         if (e == hipSuccess) {
             if (mode == DPMT_TENSOR_FP8) e = fp8_operands(c, md, features_dev + lv.cell_offset * 32, cells, dZ, st);
-            else e = launch_project(md.pk.esz == 2, features_dev + lv.cell_offset * 32, cells, md.dU, md.pk.RP, dZ, st);
+            else e = launch_project(md.pk.esz == 2, features_dev + lv.cell_offset * 32, cells, md.dU, md.pk.RP, dZ,
+                                    nullptr, 0, st);
         }
         Zsrc = dZ;
     }

@@ -182,8 +182,10 @@ size_t place_lds_bytes(const PlaceLds& l);
 inline int place_span_max(int Wp) { return Wp + 4 * (PLACE_CW - 1) + 12; }
 
 // --- kernel launchers (dpmt_kernels.hip) -----------------------------------
+// rkeys (may be NULL): 2 * n_slots range keys to reset along the way (as
+// launch_range_init does).
 hipError_t launch_project(bool bf16, const float* X, int64_t n_cells, const float* U,
-                          int RP, void* Z, hipStream_t st);
+                          int RP, void* Z, int* rkeys, int64_t n_slots, hipStream_t st);
 // rkeys (may be NULL): 2 * n_slots range keys, maxima then minima, updated
 // with the value range of every response plane whose tile names a slot.
 hipError_t launch_corr(const CorrLaunch& cfg, const CorrTile* tiles, int n_tiles,

@@ -45,11 +45,19 @@ __device__ __forceinline__ float range_value(int k) {
 // ---------------------------------------------------------------------------
 // projection: Z[c][r] = sum_l X[c][l] * U[l][r]   (U: 32 x RP fp32, row major)
 // ---------------------------------------------------------------------------
+// rkeys (may be NULL): the 2 * n_slots range keys, reset here (maxima to
+// INT_MIN, minima to INT_MAX) in place of a launch of their own.
 template <int RP, bool BF16>
 __global__ __launch_bounds__(256) void project_kernel(const float* __restrict__ X, int64_t n_cells,
                                                       const float* __restrict__ U,
-                                                      void* __restrict__ Zv) {
+                                                      void* __restrict__ Zv, int* __restrict__ rkeys,
+                                                      int64_t n_slots) {
     __shared__ float sU[32 * RP];
+    if (rkeys != nullptr)
+        for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n_slots; i += (int64_t)gridDim.x * 256) {
+            rkeys[i] = INT_MIN;
+            rkeys[n_slots + i] = INT_MAX;
+        }
     for (int i = threadIdx.x; i < 32 * RP; i += 256) sU[i] = U[i];
     __syncthreads();
     const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -81,15 +89,15 @@ __global__ __launch_bounds__(256) void project_kernel(const float* __restrict__ 
 }
 
 hipError_t launch_project(bool bf16, const float* X, int64_t n_cells, const float* U, int RP,
-                          void* Z, hipStream_t st) {
-    if (n_cells <= 0) return hipSuccess;
+                          void* Z, int* rkeys, int64_t n_slots, hipStream_t st) {
+    if (n_cells <= 0) return rkeys ? launch_range_init(rkeys, n_slots, st) : hipSuccess;
     const unsigned nb = (unsigned)((n_cells + 255) / 256);
 #define DPMT_PROJ(R)                                                                          \
     case R:                                                                                   \
         if (bf16) hipLaunchKernelGGL((project_kernel<R, true>), dim3(nb), dim3(256), 0, st,   \
-                                     X, n_cells, U, Z);                                       \
+                                     X, n_cells, U, Z, rkeys, n_slots);                       \
         else hipLaunchKernelGGL((project_kernel<R, false>), dim3(nb), dim3(256), 0, st, X,    \
-                                n_cells, U, Z);                                               \
+                                n_cells, U, Z, rkeys, n_slots);                               \
         break;
     switch (RP) {
         DPMT_PROJ(4)
