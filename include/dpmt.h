@@ -70,8 +70,10 @@ typedef enum {
 /* How dpmt_score_pyramid issues its work (dpmt_set_launch).  Every strategy
  * runs the same kernels on the same tiles and produces the same bits. */
 typedef enum {
-    DPMT_LAUNCH_BATCHED = 0,  /* one launch per stage over every level of every image
-                                 (value-range reset, projection, correlation, placement)  */
+    DPMT_LAUNCH_BATCHED = 0,  /* one launch per stage over every level of every image:
+                                 projection (which also resets the value ranges; a reset
+                                 kernel of its own in the direct, FP8 and CP modes),
+                                 correlation, placement                                  */
     DPMT_LAUNCH_PER_LEVEL = 1,/* projection and correlation launched per (image, level),
                                  placement per (image, root level): the reference for
                                  what batching saves                                     */
