@@ -949,7 +949,8 @@ hipError_t launch_cp_corr(const CpTile* tiles, int n_tiles, const CpChunk* chunk
 // hardware conversion does not saturate).
 // ---------------------------------------------------------------------------
 constexpr float FP8_MAX = 448.f;
-constexpr int CHANMAX_BLOCKS = 512;
+constexpr int CHANMAX_BLOCKS = 256;
+static_assert(CHANMAX_BLOCKS * 32 <= FP8_PARTIALS, "channel-max partials must fit their scratch");
 
 __device__ __forceinline__ uint32_t fp8x4(float a, float b, float c, float d) {
     a = fminf(fmaxf(a, -FP8_MAX), FP8_MAX);
@@ -961,19 +962,38 @@ __device__ __forceinline__ uint32_t fp8x4(float a, float b, float c, float d) {
     return (uint32_t)w;
 }
 
-// partial[b][l] = max |X[c][l]| over the cells of block b's stride
+// partial[b][l] = max |X[c][l]| over the cells of block b's stride: thread
+// (cell row cr, channel quad l4) reads 16-byte runs, four cells in flight
 __global__ __launch_bounds__(256) void fp8_chanmax_kernel(const float* __restrict__ X, int64_t n_cells,
                                                           float* __restrict__ partial) {
-    __shared__ float sm[8][32];
-    const int l = threadIdx.x & 31, r = threadIdx.x >> 5;
-    float m = 0.f;
-    for (int64_t c = (int64_t)blockIdx.x * 8 + r; c < n_cells; c += (int64_t)gridDim.x * 8)
-        m = fmaxf(m, fabsf(X[c * 32 + l]));
-    sm[r][l] = m;
+    __shared__ float4 sm[32][8];
+    const int l4 = threadIdx.x & 7, cr = threadIdx.x >> 3;
+    const int64_t stride = (int64_t)gridDim.x * 32;
+    float4 m = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int64_t c0 = (int64_t)blockIdx.x * 32 + cr; c0 < n_cells; c0 += 4 * stride) {
+        float4 v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t c = c0 + k * stride;
+            v[k] = c < n_cells ? reinterpret_cast<const float4*>(X + c * 32)[l4] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            m.x = fmaxf(m.x, fabsf(v[k].x));
+            m.y = fmaxf(m.y, fabsf(v[k].y));
+            m.z = fmaxf(m.z, fabsf(v[k].z));
+            m.w = fmaxf(m.w, fabsf(v[k].w));
+        }
+    }
+    sm[cr][l4] = m;
     __syncthreads();
     if (threadIdx.x < 32) {
-        float v = sm[0][l];
-        for (int i = 1; i < 8; ++i) v = fmaxf(v, sm[i][l]);
+        const int l = threadIdx.x, q = l >> 2, e = l & 3;
+        float v = 0.f;
+        for (int i = 0; i < 32; ++i) {
+            const float4 t = sm[i][q];
+            v = fmaxf(v, e == 0 ? t.x : e == 1 ? t.y : e == 2 ? t.z : t.w);
+        }
         partial[blockIdx.x * 32 + l] = v;
     }
 }
@@ -986,6 +1006,7 @@ __global__ __launch_bounds__(256) void fp8_scales_kernel(const float* __restrict
     __shared__ float red[8][32];
     const int l = threadIdx.x & 31, r = threadIdx.x >> 5;
     float m = 0.f;
+#pragma unroll 8
     for (int b = r; b < nb; b += 8) m = fmaxf(m, partial[b * 32 + l]);
     red[r][l] = m;
     __syncthreads();
@@ -1046,20 +1067,32 @@ __global__ __launch_bounds__(256) void fp8_requant_kernel(const RequantBlock* __
                                                           uint8_t* __restrict__ G,
                                                           float* __restrict__ tk) {
     __shared__ unsigned int tmax[32];
+    __shared__ float ss[64];                       // the channel scales (Q * PB <= 64)
     const RequantBlock B = blocks[blockIdx.x];
     if (threadIdx.x < 32) tmax[threadIdx.x] = 0u;
+    if (threadIdx.x < 64) ss[threadIdx.x] = s[min((int)threadIdx.x, 63)];
     __syncthreads();
-    // unit = (chunk, lane): 32 consecutive elements of one filter's flattened row
+    // unit = (chunk, lane): 32 consecutive elements of one filter's flattened
+    // row; element e of the unit is plane byte o0 + e of plane q, channel
+    // (o0 + e) % PB, stepped with a wrap instead of a division per element
     const int units = B.chunks * 64;
     for (int u = threadIdx.x; u < units; u += 256) {
         const int lane = u & 63, ch = u >> 6;
         const int sidx = (ch / B.h) % B.S;         // K-step of this chunk
         const int q = (ch / B.h) / B.S;            // plane
-        const float* src = master + B.m_off + (int64_t)u * 32;
+        const float4* src = reinterpret_cast<const float4*>(master + B.m_off + (int64_t)u * 32);
+        int o = (64 * sidx + 32 * (lane >> 5)) % PB;
+        const float* sq = ss + q * PB;
         float m = 0.f;
-        for (int e = 0; e < 32; ++e) {
-            const int o = 64 * sidx + 32 * (lane >> 5) + e;   // flattened plane byte
-            m = fmaxf(m, fabsf(src[e] * s[q * PB + o % PB]));
+#pragma unroll
+        for (int e4 = 0; e4 < 8; ++e4) {
+            const float4 v = src[e4];
+            const float a[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                m = fmaxf(m, fabsf(a[i] * sq[o]));
+                o = o + 1 == PB ? 0 : o + 1;
+            }
         }
         atomicMax(&tmax[lane & 31], __float_as_uint(m));
     }
@@ -1070,15 +1103,21 @@ __global__ __launch_bounds__(256) void fp8_requant_kernel(const RequantBlock* __
         const int q = (ch / B.h) / B.S;
         const float t = __uint_as_float(tmax[lane & 31]);
         const float inv = t > 0.f ? FP8_MAX / t : 0.f;
-        const float* src = master + B.m_off + (int64_t)u * 32;
+        const float4* src = reinterpret_cast<const float4*>(master + B.m_off + (int64_t)u * 32);
         uint32_t* dst = reinterpret_cast<uint32_t*>(G + B.g_off + (int64_t)u * 32);
-        for (int e = 0; e < 32; e += 4) {
-            float v[4];
+        int o = (64 * sidx + 32 * (lane >> 5)) % PB;
+        const float* sq = ss + q * PB;
+#pragma unroll
+        for (int e4 = 0; e4 < 8; ++e4) {
+            const float4 v = src[e4];
+            const float a[4] = {v.x, v.y, v.z, v.w};
+            float w[4];
+#pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int o = 64 * sidx + 32 * (lane >> 5) + e + i;
-                v[i] = src[e + i] * s[q * PB + o % PB] * inv;
+                w[i] = a[i] * sq[o] * inv;
+                o = o + 1 == PB ? 0 : o + 1;
             }
-            dst[e / 4] = fp8x4(v[0], v[1], v[2], v[3]);
+            dst[e4] = fp8x4(w[0], w[1], w[2], w[3]);
         }
     }
     if (threadIdx.x < 32 && B.f0 + (int)threadIdx.x < B.ng) {
