@@ -63,6 +63,7 @@ struct ModeData {
     std::vector<GroupDesc> groups;
     float* dU = nullptr;        // 32 x RP projection basis (tensor modes)
     float* dMaster = nullptr;   // FP8: FP32 factors in operand order
+    float* dChmax = nullptr;    // FP8: per filter slot, largest |factor| of each channel
     RequantBlock* dRequant = nullptr;
     int n_requant = 0;
     float* dTk = nullptr;       // FP8: per-filter scales
@@ -291,6 +292,7 @@ void free_tilesets(ModeData& m) {
 
 void free_mode(ModeData& m) {
     dfree(m.dMaster);
+    dfree(m.dChmax);
     dfree(m.dRequant);
     dfree(m.dTk);
     dfree(m.dScales);
@@ -739,11 +741,30 @@ dpmt_status prepare_mode(dpmt_ctx* c, dpmt_mode mode) {
         }
         md.groups.push_back(gd);
     }
+    // FP8: the largest |factor| of every channel of every filter slot, in the
+    // operand order the requantisation walks (element e of unit u of a block
+    // is channel q * PB + (64 sidx + 32 (lane / 32) + e) % PB)
+    std::vector<float> chmax;
+    if (fp8) {
+        chmax.assign((size_t)std::max(t_slots, 1) * pk.RP, 0.f);
+        for (const RequantBlock& r : rq)
+            for (int u = 0; u < r.chunks * 64; ++u) {
+                const int lane = u & 63, ch = u >> 6;
+                const int sidx = (ch / r.h) % r.S, q = (ch / r.h) / r.S;
+                float* mk = chmax.data() + (size_t)(r.t_off + (lane & 31)) * pk.RP;
+                for (int e = 0; e < 32; ++e) {
+                    const int o = (64 * sidx + 32 * (lane >> 5) + e) % pk.PB;
+                    float& m = mk[q * pk.PB + o];
+                    m = std::max(m, std::fabs(master[(size_t)r.m_off + (size_t)u * 32 + e]));
+                }
+            }
+    }
     if (c->has_device()) {
         HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
         HIP_TRY(c, upload(&md.dGroups, md.groups), "upload group table");
         if (fp8) {
             HIP_TRY(c, upload(&md.dMaster, master), "upload FP8 master factors");
+            HIP_TRY(c, upload(&md.dChmax, chmax), "upload FP8 channel maxima");
             HIP_TRY(c, upload(&md.dRequant, rq), "upload requant table");
             md.n_requant = (int)rq.size();
             HIP_TRY(c, hipMalloc(&md.dG, std::max<size_t>(master.size(), 16)), "allocate FP8 operand");
@@ -765,15 +786,17 @@ dpmt_status prepare_mode(dpmt_ctx* c, dpmt_mode mode) {
 
 // FP8 mode: channel maxima of the given cells, channel scales and the
 // requantised factors; then the scaled projection of cells into Z.
-hipError_t fp8_prepare(ModeData& md, const float* X, int64_t n_cells, hipStream_t st) {
+// rkeys (may be NULL): value-range keys reset along the way.
+hipError_t fp8_prepare(ModeData& md, const float* X, int64_t n_cells, int* rkeys, int64_t n_slots,
+                       hipStream_t st) {
     return launch_fp8_prepare(X, n_cells, md.dU, md.pk.RP, md.dScales + md.pk.RP, md.dScales,
-                              md.dRequant, md.n_requant, md.dMaster, static_cast<uint8_t*>(md.dG),
-                              md.dTk, st);
+                              md.dRequant, md.n_requant, md.dMaster, md.dChmax, static_cast<uint8_t*>(md.dG),
+                              md.dTk, rkeys, n_slots, st);
 }
 
-hipError_t fp8_operands(dpmt_ctx*, ModeData& md, const float* X, int64_t n_cells, void* Z,
+hipError_t fp8_operands(ModeData& md, const float* X, int64_t n_cells, void* Z, int* rkeys, int64_t n_slots,
                         hipStream_t st) {
-    hipError_t e = fp8_prepare(md, X, n_cells, st);
+    hipError_t e = fp8_prepare(md, X, n_cells, rkeys, n_slots, st);
     if (e != hipSuccess) return e;
     return launch_project_fp8(X, n_cells, md.dU, md.pk.RP, md.dScales, Z, st);
 }
@@ -1101,10 +1124,9 @@ hipError_t enqueue_batched(dpmt_ctx* c, dpmt_mode mode, const float* X, float* s
     ModeData& md = c->modes[mode];
     hipError_t e = ev ? hipEventRecord(ev[0], st) : hipSuccess;
     if (e == hipSuccess) {                         // the projection also resets the value ranges
-        if (mode == DPMT_TENSOR_FP8 || !is_tensor(mode)) e = launch_range_init(c->d_rkeys, c->n_slots, st);
-        if (e == hipSuccess && mode == DPMT_TENSOR_FP8) e = fp8_operands(c, md, X, c->n_cells, c->d_Z, st);
-        else if (e == hipSuccess && is_tensor(mode))
-            e = launch_project(md.pk.esz == 2, X, c->n_cells, md.dU, md.pk.RP, c->d_Z, c->d_rkeys, c->n_slots, st);
+        if (!is_tensor(mode)) e = launch_range_init(c->d_rkeys, c->n_slots, st);
+        else if (mode == DPMT_TENSOR_FP8) e = fp8_operands(md, X, c->n_cells, c->d_Z, c->d_rkeys, c->n_slots, st);
+        else e = launch_project(md.pk.esz == 2, X, c->n_cells, md.dU, md.pk.RP, c->d_Z, c->d_rkeys, c->n_slots, st);
     }
     if (e == hipSuccess && ev) e = hipEventRecord(ev[1], st);
     if (e == hipSuccess) e = corr_tiles(c, mode, 0, 0, n_corr_tiles(c, mode), X, st);
@@ -1126,7 +1148,7 @@ hipError_t enqueue_per_level(dpmt_ctx* c, dpmt_mode mode, const float* X, float*
     const size_t zcell = (size_t)md.pk.RP * md.pk.esz;
     hipError_t e = ev ? hipEventRecord(ev[0], st) : hipSuccess;
     if (e == hipSuccess) e = launch_range_init(c->d_rkeys, c->n_slots, st);
-    if (e == hipSuccess && mode == DPMT_TENSOR_FP8) e = fp8_prepare(md, X, c->n_cells, st);
+    if (e == hipSuccess && mode == DPMT_TENSOR_FP8) e = fp8_prepare(md, X, c->n_cells, nullptr, 0, st);
     for (size_t i = 0; i < c->pyr.size() && e == hipSuccess && is_tensor(mode); ++i)
         for (const LevelInfo& lv : c->pyr[i]) {
             if (e != hipSuccess) break;
@@ -1161,10 +1183,9 @@ hipError_t enqueue_overlap(dpmt_ctx* c, dpmt_mode mode, const float* X, float* s
     const int K = c->n_chunks;
     hipError_t e = ev ? hipEventRecord(ev[0], st) : hipSuccess;
     if (e == hipSuccess) {                         // the projection also resets the value ranges
-        if (mode == DPMT_TENSOR_FP8 || !is_tensor(mode)) e = launch_range_init(c->d_rkeys, c->n_slots, st);
-        if (e == hipSuccess && mode == DPMT_TENSOR_FP8) e = fp8_operands(c, md, X, c->n_cells, c->d_Z, st);
-        else if (e == hipSuccess && is_tensor(mode))
-            e = launch_project(md.pk.esz == 2, X, c->n_cells, md.dU, md.pk.RP, c->d_Z, c->d_rkeys, c->n_slots, st);
+        if (!is_tensor(mode)) e = launch_range_init(c->d_rkeys, c->n_slots, st);
+        else if (mode == DPMT_TENSOR_FP8) e = fp8_operands(md, X, c->n_cells, c->d_Z, c->d_rkeys, c->n_slots, st);
+        else e = launch_project(md.pk.esz == 2, X, c->n_cells, md.dU, md.pk.RP, c->d_Z, c->d_rkeys, c->n_slots, st);
     }
     if (e == hipSuccess && ev) e = hipEventRecord(ev[1], st);
     hipEvent_t fork = c->chunk_ev[K], join = c->chunk_ev[K + 1];
@@ -2179,7 +2200,7 @@ dpmt_status dpmt_level_responses(dpmt_ctx* c, dpmt_mode mode, const float* featu
     if (tensor) {
         e = hipMalloc(&dZ, (size_t)cells * md.pk.RP * md.pk.esz);
         if (e == hipSuccess) {
-            if (mode == DPMT_TENSOR_FP8) e = fp8_operands(c, md, features_dev + lv.cell_offset * 32, cells, dZ, st);
+            if (mode == DPMT_TENSOR_FP8) e = fp8_operands(md, features_dev + lv.cell_offset * 32, cells, dZ, nullptr, 0, st);
             else e = launch_project(md.pk.esz == 2, features_dev + lv.cell_offset * 32, cells, md.dU, md.pk.RP, dZ,
                                     nullptr, 0, st);
         }

@@ -200,10 +200,12 @@ hipError_t launch_corr(const CorrLaunch& cfg, const CorrTile* tiles, int n_tiles
 hipError_t launch_cp_corr(const CpTile* tiles, int n_tiles, const CpChunk* chunks, const float* X,
                           const float* fac, float* out, int* rkeys, int64_t n_slots, uint8_t* flags,
                           size_t lds_bytes, hipStream_t st);
+// chmax: per filter slot, the largest |factor| of each of the RP channels.
+// rkeys (may be NULL): 2 * n_slots range keys to reset along the way.
 hipError_t launch_fp8_prepare(const float* X, int64_t n_cells, const float* U, int RP,
                               float* partial, float* scales, const RequantBlock* blocks,
-                              int n_blocks, const float* master, uint8_t* G, float* tk,
-                              hipStream_t st);
+                              int n_blocks, const float* master, const float* chmax, uint8_t* G,
+                              float* tk, int* rkeys, int64_t n_slots, hipStream_t st);
 hipError_t launch_project_fp8(const float* X, int64_t n_cells, const float* U, int RP,
                               const float* scales, void* Z, hipStream_t st);
 constexpr int FP8_PARTIALS = 512 * 32;   // floats of the channel-max scratch

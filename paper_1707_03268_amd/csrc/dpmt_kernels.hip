@@ -942,7 +942,9 @@ hipError_t launch_cp_corr(const CpTile* tiles, int n_tiles, const CpChunk* chunk
 //   xmax_l = max over cells |X[c][l]|                       (fp8_chanmax_*)
 //   s_r    = sum_l |U[l][r]| * xmax_l / 448 >= max_c |Z[c][r]| / 448, so
 //            Zq = e4m3(Z / s_r) never overflows             (fp8_scales)
-//   t_k    = max |G_k * s| / 448 per filter k,
+//   t_k    = max |G_k * s| / 448 per filter k, as max_r s_r M_kr / 448 with
+//            M_kr = max |G_k| over the elements of channel r (kept from the
+//            upload: rounding is monotonic, so this is the same value),
 //   Gq_k   = e4m3(G_k * s / t_k)                            (fp8_requant)
 //   resp_k = t_k * sum Gq_k Zq                               (corr epilogue)
 // Conversions round to nearest even after an explicit clamp to +-448 (the
@@ -965,8 +967,14 @@ __device__ __forceinline__ uint32_t fp8x4(float a, float b, float c, float d) {
 // partial[b][l] = max |X[c][l]| over the cells of block b's stride: thread
 // (cell row cr, channel quad l4) reads 16-byte runs, four cells in flight
 __global__ __launch_bounds__(256) void fp8_chanmax_kernel(const float* __restrict__ X, int64_t n_cells,
-                                                          float* __restrict__ partial) {
+                                                          float* __restrict__ partial, int* __restrict__ rkeys,
+                                                          int64_t n_slots) {
     __shared__ float4 sm[32][8];
+    if (rkeys != nullptr)                          // the value-range reset, folded in
+        for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n_slots; i += (int64_t)gridDim.x * 256) {
+            rkeys[i] = INT_MIN;
+            rkeys[n_slots + i] = INT_MAX;
+        }
     const int l4 = threadIdx.x & 7, cr = threadIdx.x >> 3;
     const int64_t stride = (int64_t)gridDim.x * 32;
     float4 m = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -1058,50 +1066,41 @@ __global__ __launch_bounds__(256) void project_fp8_kernel(const float* __restric
                          acc[r + 3] * sinv[r + 3]);
 }
 
-// One block per 32-filter block of a group: the FP32 master factors are laid
-// out exactly like the FP8 operand (fragment order, 4 bytes per element).
-// Pass 1: per-filter max |G * s|; pass 2: quantise with t_k folded in.
+// `split` workgroups per 32-filter block of a group, each quantising a slice
+// of its units.  The FP32 master factors are laid out exactly like the FP8
+// operand (fragment order, 4 bytes per element); chmax holds M_kr for every
+// filter slot (nch = Q * PB channels).
 __global__ __launch_bounds__(256) void fp8_requant_kernel(const RequantBlock* __restrict__ blocks,
                                                           const float* __restrict__ master,
                                                           const float* __restrict__ s, int PB,
+                                                          const float* __restrict__ chmax, int nch, int split,
                                                           uint8_t* __restrict__ G,
                                                           float* __restrict__ tk) {
-    __shared__ unsigned int tmax[32];
-    __shared__ float ss[64];                       // the channel scales (Q * PB <= 64)
-    const RequantBlock B = blocks[blockIdx.x];
-    if (threadIdx.x < 32) tmax[threadIdx.x] = 0u;
-    if (threadIdx.x < 64) ss[threadIdx.x] = s[min((int)threadIdx.x, 63)];
+    __shared__ float tsh[32];
+    __shared__ float ss[64];                       // the channel scales (nch <= 64)
+    const int rb = blockIdx.x / split, part = blockIdx.x - rb * split;
+    const RequantBlock B = blocks[rb];
+    if (threadIdx.x < 64) ss[threadIdx.x] = s[min((int)threadIdx.x, nch - 1)];
+    __syncthreads();
+    if (threadIdx.x < 32) {                        // t_k of the block's filter column threadIdx.x
+        const float* mk = chmax + (int64_t)(B.t_off + threadIdx.x) * nch;
+        float t = 0.f;
+        for (int r = 0; r < nch; ++r) t = fmaxf(t, mk[r] * ss[r]);
+        tsh[threadIdx.x] = t;
+        if (part == 0 && B.f0 + (int)threadIdx.x < B.ng) tk[B.t_off + threadIdx.x] = t > 0.f ? t / FP8_MAX : 1.f;
+    }
     __syncthreads();
     // unit = (chunk, lane): 32 consecutive elements of one filter's flattened
     // row; element e of the unit is plane byte o0 + e of plane q, channel
     // (o0 + e) % PB, stepped with a wrap instead of a division per element
     const int units = B.chunks * 64;
-    for (int u = threadIdx.x; u < units; u += 256) {
+    const int per = (units + split - 1) / split;
+    const int u1 = min(units, (part + 1) * per);
+    for (int u = part * per + threadIdx.x; u < u1; u += 256) {
         const int lane = u & 63, ch = u >> 6;
         const int sidx = (ch / B.h) % B.S;         // K-step of this chunk
         const int q = (ch / B.h) / B.S;            // plane
-        const float4* src = reinterpret_cast<const float4*>(master + B.m_off + (int64_t)u * 32);
-        int o = (64 * sidx + 32 * (lane >> 5)) % PB;
-        const float* sq = ss + q * PB;
-        float m = 0.f;
-#pragma unroll
-        for (int e4 = 0; e4 < 8; ++e4) {
-            const float4 v = src[e4];
-            const float a[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                m = fmaxf(m, fabsf(a[i] * sq[o]));
-                o = o + 1 == PB ? 0 : o + 1;
-            }
-        }
-        atomicMax(&tmax[lane & 31], __float_as_uint(m));
-    }
-    __syncthreads();
-    for (int u = threadIdx.x; u < units; u += 256) {
-        const int lane = u & 63, ch = u >> 6;
-        const int sidx = (ch / B.h) % B.S;
-        const int q = (ch / B.h) / B.S;
-        const float t = __uint_as_float(tmax[lane & 31]);
+        const float t = tsh[lane & 31];
         const float inv = t > 0.f ? FP8_MAX / t : 0.f;
         const float4* src = reinterpret_cast<const float4*>(master + B.m_off + (int64_t)u * 32);
         uint32_t* dst = reinterpret_cast<uint32_t*>(G + B.g_off + (int64_t)u * 32);
@@ -1120,21 +1119,20 @@ __global__ __launch_bounds__(256) void fp8_requant_kernel(const RequantBlock* __
             dst[e4] = fp8x4(w[0], w[1], w[2], w[3]);
         }
     }
-    if (threadIdx.x < 32 && B.f0 + (int)threadIdx.x < B.ng) {
-        const float t = __uint_as_float(tmax[threadIdx.x]);
-        tk[B.t_off + threadIdx.x] = t > 0.f ? t / FP8_MAX : 1.f;
-    }
 }
 
 hipError_t launch_fp8_prepare(const float* X, int64_t n_cells, const float* U, int RP,
                               float* partial, float* scales, const RequantBlock* blocks,
-                              int n_blocks, const float* master, uint8_t* G, float* tk,
-                              hipStream_t st) {
-    hipLaunchKernelGGL(fp8_chanmax_kernel, dim3(CHANMAX_BLOCKS), dim3(256), 0, st, X, n_cells, partial);
+                              int n_blocks, const float* master, const float* chmax, uint8_t* G,
+                              float* tk, int* rkeys, int64_t n_slots, hipStream_t st) {
+    if (RP > 32) return hipErrorInvalidValue;      // FP8 packs one plane of RP <= 32 channels
+    hipLaunchKernelGGL(fp8_chanmax_kernel, dim3(CHANMAX_BLOCKS), dim3(256), 0, st, X, n_cells, partial,
+                       rkeys, n_slots);
     hipLaunchKernelGGL(fp8_scales_kernel, dim3(1), dim3(256), 0, st, partial, CHANMAX_BLOCKS, U, RP, scales);
+    constexpr int SPLIT = 4;                       // workgroups per 32-filter block
     if (n_blocks > 0)
-        hipLaunchKernelGGL(fp8_requant_kernel, dim3(n_blocks), dim3(256), 0, st, blocks, master,
-                           scales, RP, G, tk);
+        hipLaunchKernelGGL(fp8_requant_kernel, dim3(n_blocks * SPLIT), dim3(256), 0, st, blocks, master,
+                           scales, RP, chmax, RP, SPLIT, G, tk);
     return hipGetLastError();
 }
 
