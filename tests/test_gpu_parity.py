@@ -336,6 +336,43 @@ def test_scores_fp8_within_propagated_bound(cfg, rank):
     _check_fp8_maps(wl, run, rank, range(lay.n_maps) if cfg == 1 else range(0, lay.n_maps, 7))
 
 
+class _ChannelGain:
+    """A workload whose features are another's with channel l multiplied by
+    gain[l] (different channel ranges, so different FP8 scales)."""
+
+    def __init__(self, wl, gain):
+        self._wl, self._gain = wl, np.asarray(gain, np.float32)
+
+    def __getattr__(self, name):
+        return getattr(self._wl, name)
+
+    def features(self):
+        return (self._wl.features() * self._gain).astype(np.float32)
+
+    def level_features(self, image, level):
+        return (self._wl.level_features(image, level) * self._gain).astype(np.float32)
+
+
+def test_fp8_scales_follow_the_features():
+    """The FP8 channel and filter scales are recomputed on every call: on one
+    context, a second feature set with other channel ranges scores within its
+    own propagated bound, and the first set then scores bitwise as before."""
+    from paper_1707_03268_amd import Context
+    wl = workloads.config1()
+    wl_b = _ChannelGain(wl, np.linspace(0.25, 4.0, 32))
+    note("FP8 scales per call, c1 R=16")
+    ctx = Context(0)
+    ctx.load_filters(wl.bank.filters, wl.bank.components)
+    a1 = run_gpu(wl, "tensor_fp8", 16, ctx=ctx)
+    b = run_gpu(wl_b, "tensor_fp8", 16, ctx=ctx, features=torch.from_numpy(wl_b.features()).cuda())
+    a2 = run_gpu(wl, "tensor_fp8", 16, ctx=ctx)
+    ctx.close()
+    assert np.array_equal(a1.scores.view(np.int32), a2.scores.view(np.int32))
+    assert np.array_equal(a1.offsets, a2.offsets)
+    assert not np.array_equal(a1.scores, b.scores)
+    _check_fp8_maps(wl_b, b, 16, range(b.layout.n_maps))
+
+
 def test_c5_frames_fp8_within_propagated_bound():
     """FP8 e4m3 with per-channel scales on two full-size 1920x1080 frames of the
     video workload, sampled maps, against the propagated rounding bound."""
