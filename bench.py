@@ -259,6 +259,8 @@ def main() -> None:
     ap.add_argument("--mode", default="tensor_bf16", choices=list(TOL))
     ap.add_argument("--rank", type=int, default=16)
     ap.add_argument("--no-direct", action="store_true", help="skip the direct FP32 comparison run")
+    ap.add_argument("--no-precisions", dest="precisions", action="store_false",
+                    help="skip the runs of the other tensor-form precisions (FP32, BF16, FP8)")
     ap.add_argument("--cp-rank", type=int, default=6,
                     help="rank of the per-filter CP form timed for comparison (0: skip)")
     ap.add_argument("--plant", type=int, default=1,
@@ -347,6 +349,40 @@ def main() -> None:
                   "correlation_tflops": dflops / (dstages["correlation"] * 1e-3) / 1e12,
                   "correlation_frac_fp32_mfma": dflops / (dstages["correlation"] * 1e-3) / 1e12 / PEAK_FP32_TFLOPS}
         log(f"direct_fp32: {dms:.3f} ms/step")
+
+    # the tensor form in its other operand precisions, each autotuned like the
+    # headline; score differences against the FP32 tensor form (which the GPU
+    # tests hold within 1e-4 of the FP64 oracle)
+    precisions = None
+    if args.precisions and args.mode != "direct_fp32":
+        runs = {args.mode: (ms, stages, scores)}
+        for m in ("tensor_fp32", "tensor_bf16", "tensor_fp8"):
+            if m in runs:
+                continue
+            if args.autotune:
+                s_t = torch.empty(max(lay.n_score, 1), dtype=torch.float32, device="cuda")
+                o_t = torch.empty(max(lay.n_offsets, 1), dtype=torch.int16, device="cuda")
+                ctx.autotune(m, feats, s_t, o_t, reps=3)
+                del s_t, o_t
+            mms, mstages, _, msc, _ = measure(ctx, m, feats, max(2, min(args.steps, 10)), args.warmup, torch)
+            runs[m] = (mms, mstages, msc)
+            log(f"{m}: {mms:.3f} ms/step, stages {mstages}")
+        ref = runs["tensor_fp32"][2]
+        keep = torch.isfinite(ref)
+        precisions = {}
+        for m in ("tensor_fp32", "tensor_bf16", "tensor_fp8"):
+            mms, mstages, msc = runs[m]
+            mflops, _, _ = corr_work(wl, m, args.rank)
+            peak = {"tensor_bf16": PEAK_BF16_TFLOPS, "tensor_fp8": PEAK_FP8_TFLOPS}.get(m, PEAK_FP32_TFLOPS)
+            tf = mflops / (mstages["correlation"] * 1e-3) / 1e12
+            diff = (msc - ref).abs()[keep]
+            precisions[m] = {"value": lay.n_resp / (mms * 1e-3), "ms_per_step": mms,
+                             "stages_ms": {k: round(v, 4) for k, v in mstages.items()},
+                             "tile_config": ctx.get_tile_config(m),
+                             "correlation_tflops": tf, "correlation_peak_tflops": peak,
+                             "correlation_frac_mfma": tf / peak,
+                             "max_abs_score_diff_vs_tensor_fp32": float(diff.max()) if diff.numel() else 0.0,
+                             "same_finite_pattern": bool(torch.equal(torch.isfinite(msc), keep))}
 
     cp = None
     if args.cp_rank > 0:
@@ -450,6 +486,7 @@ def main() -> None:
         "placement_roofline": rf_place,
         "direct_fp32": direct,
         "tensor_vs_direct": (value / direct["value"]) if direct else None,
+        "precisions": precisions,
         "cp_fp32": cp,
         "score_error_vs_oracle": err,
     }
