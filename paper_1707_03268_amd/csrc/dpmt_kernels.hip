@@ -1297,6 +1297,7 @@ struct PlaceGeo {
     int offA, offB;     // staging offsets of the scan's even and odd offsets (parity halves)
     int vlo, vhi, Wc;   // column window (clamped to the map +- 1 row) and its length
     int CH, SH;         // staged float4 per row, floats per parity half-row
+    int SP;             // staged row pitch (>= 2 SH)
     int lrb, RB;        // rows per round RB = 2^lrb
     int ry0, ry1, rounds;
     int X0;             // first staged column (multiple of 4)
@@ -1352,6 +1353,10 @@ __device__ __forceinline__ PlaceGeo place_geo(const MapPart& P, const MapDesc& M
     G.offB = (d & 1) ? (d + 1) >> 1 : G.SH + (d >> 1);
     int lrb = 5;                                          // up to 32 rows per round
     while (lrb > 0 && (2 * G.SH << lrb) > stage_words) --lrb;
+    // pitch 16 mod 32 floats when that keeps the rows per round: the four rows
+    // of a wavefront then start in four different 16-bank groups
+    G.SP = 2 * G.SH + ((16 - 2 * G.SH) & 31);
+    if ((G.SP << lrb) > stage_words) G.SP = 2 * G.SH;
     G.lrb = lrb;
     G.RB = 1 << lrb;
     G.ry0 = max(0, P.vy + G.vlo);
@@ -1396,7 +1401,7 @@ __device__ __forceinline__ void place_store(const PlaceGeo& G, float* stage,
             const float v1 = (unsigned)(x + 1) < (unsigned)G.Wp ? v.y : -INFINITY;
             const float v2 = (unsigned)(x + 2) < (unsigned)G.Wp ? v.z : -INFINITY;
             const float v3 = (unsigned)(x + 3) < (unsigned)G.Wp ? v.w : -INFINITY;
-            float* even = stage + __umul24(G.lrow, 2 * G.SH) + 2 * c;
+            float* even = stage + __umul24(G.lrow, G.SP) + 2 * c;
             *reinterpret_cast<float2*>(even) = make_float2(v0, v2);
             *reinterpret_cast<float2*>(even + G.SH) = make_float2(v1, v3);
         }
@@ -1502,8 +1507,8 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
                 for (int q = rr; q < G.RB; q += ROWS) {
                     const int y = yr + q;
                     if (y > G.ry1) break;
-                    const float* SE = stage + __umul24(q, 2 * G.SH) + j + G.offA;   // even offsets
-                    const float* SO = stage + __umul24(q, 2 * G.SH) + j + G.offB;   // odd offsets
+                    const float* SE = stage + __umul24(q, G.SP) + j + G.offA;   // even offsets
+                    const float* SO = stage + __umul24(q, G.SP) + j + G.offB;   // odd offsets
                     // running maximum per group of 4 offsets; the first group
                     // that reaches the maximum holds the smallest maximiser
                     float best = -INFINITY;
