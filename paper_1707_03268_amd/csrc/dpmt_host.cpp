@@ -1884,7 +1884,7 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
         pl.ctab_words = (std::max(max_Wp + 2 * (PLACE_CW - 1) + 8, 2 * (max_Hp + 1) + 1 + 4) + 3) & ~3;
         pl.max_parts = 1;
         for (const MapDesc& m : c->maps) pl.max_parts = std::max(pl.max_parts, m.n_parts);
-        if (place_lds_bytes(pl) > 160 * 1024)
+        if (place_lds_bytes(pl) > PLACE_LDS_MAX)
             return fail(c, DPMT_E_UNSUPPORTED, "score maps too tall for one placement block");
     }
 

@@ -176,6 +176,9 @@ struct PlaceLds {
     int max_parts;     // most parts of one map
 };
 size_t place_lds_bytes(const PlaceLds& l);
+// Dynamic LDS a placement block may use: 160 KB per CU, less 1 KB kept for
+// the kernel's own static LDS (checked at launch).
+constexpr size_t PLACE_LDS_MAX = 159 * 1024;
 // Row span (floats) a part of response width Wp can need in the staging
 // buffer: 2 * (PLACE_CW - 1) targets apart, plus a window clamped to the line
 // and aligned to whole 16-byte runs.

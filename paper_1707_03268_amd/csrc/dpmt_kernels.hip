@@ -1631,7 +1631,14 @@ hipError_t launch_place(const MapDesc* maps, const MapPart* parts, const int2* b
     if (lds.stage_words != PLACE_STAGE || lds.ctab_words % 4)
         return hipErrorInvalidValue;
     const size_t bytes = place_lds_bytes(lds);
-    if (bytes > 160 * 1024) return hipErrorInvalidValue;
+    if (bytes > PLACE_LDS_MAX) return hipErrorInvalidValue;
+    // the kernel's own static LDS (queried once) must fit beside the dynamic part
+    static const size_t static_lds = [] {
+        hipFuncAttributes fa;
+        return hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(place_kernel)) == hipSuccess
+                   ? fa.sharedSizeBytes : ~size_t(0);
+    }();
+    if (static_lds > 160 * 1024 - PLACE_LDS_MAX) return hipErrorInvalidValue;
     if (bytes > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(place_kernel),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);

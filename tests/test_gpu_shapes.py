@@ -130,7 +130,7 @@ def test_odd_shapes_scores(mode, rank):
 # (part level rows, cols, root level rows, cols): the widest part rows the
 # placement stages (1976 responses, plus a 72-cell window span = 2048 floats),
 # and the tallest score maps one placement block holds in its 160 KB of LDS.
-LIMITS = [("widest", 40, 1981, 20, 990), ("tallest", 1016, 40, 508, 20)]
+LIMITS = [("widest", 40, 1981, 20, 990), ("tallest", 1011, 40, 505, 20)]
 
 
 def _limit_workload(part_rows, part_cols, root_rows, root_cols):
