@@ -145,6 +145,35 @@ def test_cp_scores_against_oracle(cfg, R, every):
     ctx.close()
 
 
+@pytest.mark.parametrize("S,T", [(8, 5), (6, 6)])
+def test_cp_root_part_rank_pairs(S, T):
+    """Section 5's (S, T) rank pairs: rank S for every root filter, T for every
+    part filter (per-filter ranks), scored against the oracle on c2."""
+    wl = workloads.config2()
+    roots = {c.root for c in wl.bank.components}
+    ranks = [S if k in roots else T for k in range(len(wl.bank.filters))]
+    note(f"cp (S, T) = ({S}, {T}) scores c2")
+    ctx, fac = _cp_context(wl, ranks)
+    got_ranks, _ = ctx.get_cp(wl.bank.shapes)
+    assert list(got_ranks) == ranks
+    lay = ctx.plan(wl.pyramids)
+    feats = torch.from_numpy(wl.features()).cuda()
+    s, o = _scores(ctx, lay, feats)
+    run = GpuRun(lay, s, o, None, None)
+    cmp = Cmp()
+    cache = {}
+    for k in range(0, lay.n_maps, 3):
+        img, lvl, comp = int(lay.map_image[k]), int(lay.map_level[k]), int(lay.map_comp[k])
+        if lay.map_rows[k] == 0 or lay.map_cols[k] == 0:
+            continue
+        sm = _oracle_cp_map(wl, fac, img, lvl, comp, cache)
+        compare_map(run, wl, img, lvl, comp, sm, TOL_CP, cmp)
+    note(f"  {cmp.n_pos} positions, max |err| {cmp.max_err:.3g}, placements checked "
+         f"{cmp.n_arg_checked}/{cmp.n_arg}")
+    assert cmp.n_pos > 0
+    ctx.close()
+
+
 @pytest.mark.parametrize("prune", [False, True])
 def test_cp_launch_strategies_bitwise_equal(prune):
     wl = workloads.uneven_batch()
