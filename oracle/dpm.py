@@ -17,8 +17,8 @@ speed.  Conventions (each one is a reading of the paper, see the notes):
 * Deformation feature psi = (dx, dx^2, dy, dy^2) with dx = x' - x_anchor,
   dy = y' - y_anchor; the cost d . psi is subtracted (Section 2, the score
   formula and the placement argmax).  Coefficient order d = (d_x, d_xx, d_y, d_yy).
-* The part placement maximises over every position of the part map
-  (Section 2: "all possible part positions").  Exact ties go to the
+* The part placement maximises over the whole part map, every position
+  of it a candidate (Section 2, the placement argmax).  Exact ties go to the
   lexicographically smallest (y', x').
 * Score (Section 2): s(p0) = resp_root(p0) + sum_i D_i(2*p0 + v_i); the parts
   live one octave below the root (twice the resolution), v_i is the anchor of
@@ -35,7 +35,7 @@ Parity status of each function is pinned by tests/test_oracle_pins.py.
 from __future__ import annotations
 
 from dataclasses import dataclass
-from typing import List, Optional, Sequence, Tuple
+from typing import Callable, Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -268,27 +268,44 @@ def score_component(root_resp: np.ndarray, part_resps: Sequence[np.ndarray],
     return ScoreMap(score, offs, marg, np.asarray(root_resp, np.float64), Dall)
 
 
-def score_pyramid(levels: Sequence[np.ndarray], filters: Sequence[np.ndarray],
-                  components, octave: int, U: Optional[np.ndarray] = None
-                  ) -> List[List[ScoreMap]]:
-    """Scores of every component at every root level l >= octave of one image.
+def score_pyramid(levels, filters: Sequence[np.ndarray], components, octave: int,
+                  U: Optional[np.ndarray] = None, root_levels: Optional[Sequence[int]] = None,
+                  comps: Optional[Sequence[int]] = None,
+                  response: Optional[Callable[[np.ndarray, int], np.ndarray]] = None
+                  ) -> Dict[Tuple[int, int], ScoreMap]:
+    """Score maps of one image's pyramid: every component c at every root
+    level l >= octave, with its root filter correlated on level l and its part
+    filters on level l - octave (twice the resolution: the anchor of root
+    position p0 is 2 p0 + v_i).
 
-    ``levels``: list of (H, W, 32) feature levels.  ``components``: objects with
-    ``root``, ``parts``, ``anchors``, ``deform``.  With ``U`` given, every
-    response is the shortened (tensor-form) correlation; otherwise direct.
-    Returns out[l - octave][c].
+    ``levels``: anything indexable by level number with a length, each item an
+    (H, W, 32) feature level (a list, or a lazy mapping).  ``components``:
+    objects with ``root``, ``parts``, ``anchors``, ``deform``.  With ``U``
+    given, every response is the shortened (tensor-form) correlation;
+    otherwise direct.  ``response(X, k)``, when given, replaces both: the
+    response map of filter k on level X (e.g. a CP form's decomposed
+    correlation).  ``root_levels`` / ``comps`` restrict the output to a subset
+    (default: all).  Returns {(root level, component index): ScoreMap}.
     """
-    resp_of = (lambda X, f: correlate(X, f)) if U is None else \
-              (lambda X, f: tensor_response(X, f, U))
-    out = []
-    for l in range(octave, len(levels)):
+    if response is not None:
+        resp_of = lambda X, k: response(X, k)
+    elif U is None:
+        resp_of = lambda X, k: correlate(X, filters[k])
+    else:
+        resp_of = lambda X, k: tensor_response(X, filters[k], U)
+    L = len(levels)
+    lv_ids = range(octave, L) if root_levels is None else root_levels
+    c_ids = range(len(components)) if comps is None else comps
+    out: Dict[Tuple[int, int], ScoreMap] = {}
+    for l in lv_ids:
+        if not octave <= l < L:
+            raise ValueError(f"root level {l} outside [{octave}, {L})")
         Xr, Xp = levels[l], levels[l - octave]
-        per_comp = []
-        for c in components:
-            rr = resp_of(Xr, filters[c.root])
-            prs = [resp_of(Xp, filters[k]) for k in c.parts]
-            per_comp.append(score_component(rr, prs, c.anchors, c.deform))
-        out.append(per_comp)
+        for ci in c_ids:
+            c = components[ci]
+            rr = resp_of(Xr, c.root)
+            prs = [resp_of(Xp, k) for k in c.parts]
+            out[(l, ci)] = score_component(rr, prs, c.anchors, c.deform)
     return out
 
 
@@ -453,7 +470,7 @@ def select_rank(f: np.ndarray, e: float, r_max: int, iters: int = 200) -> Tuple[
     """Smallest r in [1, r_max] with ||f - CP(f, r)||_F < rank_bound(e, r, ...)
     (Section 4), by binary search over r (the error falls and the bound grows
     with r, so the predicate switches from false to true once); r_max when no
-    r satisfies it.  Returns (r, relative errors of the fits tried)."""
+    r satisfies it.  Returns (r, Frobenius errors of the fits tried, by r)."""
     f = np.asarray(f, np.float64)
     N, M, L = f.shape
     tried = {}

@@ -212,7 +212,7 @@ hipError_t launch_fp8_prepare(const float* X, int64_t n_cells, const float* U, i
 hipError_t launch_project_fp8(const float* X, int64_t n_cells, const float* U, int RP,
                               const float* scales, void* Z, hipStream_t st);
 constexpr int FP8_PARTIALS = 512 * 32;   // floats of the channel-max scratch
-size_t corr_lds_bytes(const CorrLaunch& cfg, int h, int S);
+size_t corr_lds_bytes(const CorrLaunch& cfg, int max_h, int S);
 hipError_t launch_range_init(int* rkeys, int64_t n_slots, hipStream_t st);
 // flags (may be NULL): the CP correlation's rejection bytes; rejected root
 // positions get score -inf and offsets 0.

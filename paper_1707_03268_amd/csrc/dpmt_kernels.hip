@@ -126,6 +126,12 @@ hipError_t launch_project(bool bf16, const float* X, int64_t n_cells, const floa
 constexpr int CORR_MAX_H = 16;
 constexpr int CORR_NBUF = 3;                   // filter-chunk staging depth of the unrolled tiles
 
+// Whether a correlation instance gives the 6-, 7- and 8-row filters fully
+// unrolled bodies (staged CORR_NBUF chunks deep); host and device agree on it.
+__host__ __device__ constexpr bool corr_unrolls(CorrKind kind, int PB, int BB, int HMAX) {
+    return kind != CORR_FP8 && HMAX >= 8 && !(PB == 32 && BB == 2);
+}
+
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u32x8 __attribute__((ext_vector_type(8)));
@@ -570,7 +576,7 @@ __global__ __launch_bounds__(64 * WY) __attribute__((amdgpu_waves_per_eu((HMAX <
         // the DPM filter heights get unrolled bodies where that costs no
         // occupancy (FP8 fragments and 64-filter tiles of 32-byte planes would
         // need too many registers)
-        constexpr bool UNROLL = KIND != CORR_FP8 && HMAX >= 8 && !(PB == 32 && BB == 2);
+        constexpr bool UNROLL = corr_unrolls(KIND, PB, BB, HMAX);
         if (UNROLL && h == 6)
             corr_tile<KIND, PB, TY, BB, WY, HMAX, 6>(t, groups, Z, G, tk, out, rmax, rmin, cell_bytes, Q, win_bytes);
         else if (UNROLL && h == 7)
@@ -585,13 +591,21 @@ __global__ __launch_bounds__(64 * WY) __attribute__((amdgpu_waves_per_eu((HMAX <
 
 static int frag_bytes(CorrKind k) { return k == CORR_FP8 ? 32 : 16; }
 
-size_t corr_lds_bytes(const CorrLaunch& cfg, int h, int S) {
+// LDS of a correlation launch whose groups have at most max_h filter rows and
+// S K-steps: the window of max_h - 1 + TY*WY rows, plus the filter staging of
+// the tallest group height the kernel may see.  An unrolled group of h <= 8
+// rows stages CORR_NBUF chunks of h rows, a rolled one 2 chunks of h rows;
+// with max_h > 8 the HMAX = 16 kernel runs both kinds, so the staging takes
+// the larger of 2 max_h and CORR_NBUF min(max_h, 8) rows.
+size_t corr_lds_bytes(const CorrLaunch& cfg, int max_h, int S) {
     const int FB = frag_bytes(cfg.kind);
     const int WC = 31 + (2 * FB * S) / cfg.pk.PB;
-    const size_t win = (size_t)(cfg.ty * cfg.wy + h - 1) * WC * cfg.pk.PB;
+    const size_t win = (size_t)(cfg.ty * cfg.wy + max_h - 1) * WC * cfg.pk.PB;
     const size_t winal = (win + 1023) & ~size_t(1023);   // whole 1 KB units (window DMA)
-    const int nb = (h <= 8 && cfg.kind != CORR_FP8) ? std::max(CORR_NBUF, 2) : 2;   // staging buffers
-    return winal + (size_t)nb * cfg.bb * h * 64 * FB;
+    const int hmax = max_h <= 8 ? 8 : CORR_MAX_H;         // the kernel instance launch_corr_t picks
+    const bool unroll = corr_unrolls(cfg.kind, cfg.pk.PB, cfg.bb, hmax) && max_h >= 6;
+    const int rows = std::max(2 * max_h, unroll ? CORR_NBUF * std::min(max_h, 8) : 0);
+    return winal + (size_t)rows * cfg.bb * 64 * FB;
 }
 
 template <CorrKind KIND, int PB, int TY, int BB, int WY, int HMAX>

@@ -27,7 +27,16 @@ class GpuRun:
     scores: np.ndarray
     offsets: np.ndarray
     sigma: Optional[np.ndarray]
-    basis: Optional[np.ndarray]
+    basis: Optional[np.ndarray]    # the oracle's own U_R (never the library's)
+
+
+def oracle_basis(filters, rank: int) -> np.ndarray:
+    """U_R of the bank computed by the oracle (Section 4 feature-mode basis).
+
+    Parity checks of the tensor form feed this to the oracle, never the basis
+    the library computed: the library's decomposition is itself under test
+    (its projector is pinned against this one on the CPU)."""
+    return oracle.decompose(filters, rank).U
 
 
 def run_gpu(wl, mode: str, rank: Optional[int] = None, ctx=None, features=None) -> GpuRun:
@@ -39,7 +48,8 @@ def run_gpu(wl, mode: str, rank: Optional[int] = None, ctx=None, features=None) 
         ctx.load_filters(wl.bank.filters, wl.bank.components)
     sigma = basis = None
     if rank is not None:
-        sigma, basis = ctx.decompose(rank)
+        sigma, _ = ctx.decompose(rank)
+        basis = oracle_basis(wl.bank.filters, rank)
     lay = ctx.plan(wl.pyramids)
     if features is None:
         features = torch.from_numpy(wl.features()).cuda()
@@ -53,22 +63,31 @@ def run_gpu(wl, mode: str, rank: Optional[int] = None, ctx=None, features=None) 
     return out
 
 
+class _LazyLevels:
+    """Feature levels of one image, generated on first use and kept in a
+    cache shared across calls (keys (image, level))."""
+
+    def __init__(self, wl, image: int, cache: Dict):
+        self._wl, self._img, self._cache = wl, image, cache
+
+    def __len__(self):
+        return len(self._wl.pyramids[self._img].levels)
+
+    def __getitem__(self, level: int):
+        key = (self._img, level)
+        if key not in self._cache:
+            self._cache[key] = self._wl.level_features(self._img, level)
+        return self._cache[key]
+
+
 def oracle_map(wl, image: int, level: int, comp: int, U: Optional[np.ndarray], cache: Dict):
-    """Oracle ScoreMap of one (image, root level, component)."""
-    pyr = wl.pyramids[image]
-    oct_ = pyr.octave
-    key = (image, level)
-    if key not in cache:
-        cache[key] = wl.level_features(image, level)
-    if (image, level - oct_) not in cache:
-        cache[(image, level - oct_)] = wl.level_features(image, level - oct_)
-    Xr, Xp = cache[key], cache[(image, level - oct_)]
-    c = wl.bank.components[comp]
-    resp = (lambda X, f: oracle.correlate(X, f)) if U is None else \
-           (lambda X, f: oracle.tensor_response(X, f, U))
-    rr = resp(Xr, wl.bank.filters[c.root])
-    prs = [resp(Xp, wl.bank.filters[k]) for k in c.parts]
-    return oracle.score_component(rr, prs, c.anchors, c.deform)
+    """Oracle ScoreMap of one (image, root level, component), through the
+    oracle's own pyramid scoring (which pairs root level l with part level
+    l - octave)."""
+    levels = _LazyLevels(wl, image, cache)
+    out = oracle.score_pyramid(levels, wl.bank.filters, wl.bank.components,
+                               wl.pyramids[image].octave, U, root_levels=[level], comps=[comp])
+    return out[(level, comp)]
 
 
 @dataclass

@@ -193,14 +193,17 @@ def test_null_pointer_rejected():
 
 
 # ------------------------------------------------------------ host-side parity
-@pytest.mark.parametrize("cfg", [1, 2])
+@pytest.mark.parametrize("cfg", [1, 2, 3, 4, 5])
 def test_decompose_matches_oracle(cfg):
+    """The library's FP64 shared basis against the oracle's on every preset
+    bank, the 1,080-filter banks of the larger workloads included."""
     wl = workloads.PRESETS[cfg]()
     ctx = Context(device=-1)
     ctx.load_filters(wl.bank.filters, wl.bank.components)
     for R in (1, 4, 8, 16, 32):
         sigma, U = ctx.decompose(R)
         dec = oracle.decompose(wl.bank.filters, R)
+        assert dec.gap > 1e-9 or R < 32, "full rank always has a gap"
         np.testing.assert_allclose(sigma, dec.sigma, rtol=1e-10, atol=1e-12 * dec.sigma[0])
         if dec.gap > 1e-9:      # the subspace is unique only with a gap at R
             np.testing.assert_allclose(U @ U.T, dec.U @ dec.U.T, atol=1e-10)
@@ -409,6 +412,25 @@ def test_select_ranks_matches_oracle():
         for f, (A, B, C), rel in zip(fs, fac, err):
             rec = oracle.cp_reconstruct(A.astype(np.float64), B.astype(np.float64), C.astype(np.float64))
             assert abs(np.linalg.norm(rec - f) / np.linalg.norm(f) - rel) < 1e-5
+    ctx.close()
+
+
+def test_select_ranks_squared_bound_hand_case():
+    """The hand-worked filter where Section 4's squared bound picks rank 2
+    and an unsquared one would pick 1 (orthogonal terms of weights 1, 1/2, ...,
+    1/32 on a 6x6x32 filter, e = 100): the library picks 2 as well."""
+    f = np.zeros((6, 6, 32), np.float32)
+    for j, w in enumerate([1, 1 / 2, 1 / 4, 1 / 8, 1 / 16, 1 / 32]):
+        f[j, j, j] = w
+    # a component needs a part: a 1x1 part rides along (rank 1 fits it exactly)
+    part = np.zeros((1, 1, 32), np.float32)
+    part[0, 0, 0] = 1.0
+    comps = [workloads.Component(0, [1], np.zeros((1, 2), np.int32),
+                                 np.array([[0.0, 0.1, 0.0, 0.1]], np.float32))]
+    ctx = Context(device=-1)
+    ctx.load_filters([f, part], comps)
+    ranks, _ = ctx.select_ranks(100.0, r_max=6, max_iters=300)
+    assert int(ranks[0]) == 2
     ctx.close()
 
 

@@ -102,14 +102,14 @@ def test_cp_random_factors_mixed_ranks_c2():
 
 
 def _oracle_cp_map(wl, fac, image, level, comp, cache):
-    pyr = wl.pyramids[image]
-    for l in (level, level - pyr.octave):
-        if (image, l) not in cache:
-            cache[(image, l)] = wl.level_features(image, l).astype(np.float64)
-    c = wl.bank.components[comp]
-    rr = oracle.cp_response(cache[(image, level)], *fac[c.root])
-    prs = [oracle.cp_response(cache[(image, level - pyr.octave)], *fac[k]) for k in c.parts]
-    return oracle.score_component(rr, prs, c.anchors, c.deform)
+    """Oracle score map of one (image, root level, component) with the CP
+    form's decomposed correlation as the response, through the oracle's
+    pyramid scoring."""
+    from _gpu_common import _LazyLevels
+    out = oracle.score_pyramid(_LazyLevels(wl, image, cache), wl.bank.filters, wl.bank.components,
+                               wl.pyramids[image].octave, root_levels=[level], comps=[comp],
+                               response=lambda X, k: oracle.cp_response(X, *fac[k]))
+    return out[(level, comp)]
 
 
 def _scores(ctx, lay, feats):

@@ -9,7 +9,7 @@ import pytest
 import oracle
 import workloads
 
-from _gpu_common import TOL, note, oracle_map
+from _gpu_common import TOL, note, oracle_basis, oracle_map
 
 pytestmark = pytest.mark.gpu
 
@@ -28,7 +28,8 @@ def _scored(wl, mode, rank):
     ctx.load_filters(wl.bank.filters, wl.bank.components)
     U = None
     if rank is not None:
-        _, U = ctx.decompose(rank)
+        ctx.decompose(rank)
+        U = oracle_basis(wl.bank.filters, rank)
     lay = ctx.plan(wl.pyramids)
     feats = torch.from_numpy(wl.features()).cuda()
     scores = torch.empty(max(lay.n_score, 1), dtype=torch.float32, device="cuda")

@@ -9,7 +9,7 @@ import pytest
 import oracle
 import workloads
 
-from _gpu_common import TOL, note
+from _gpu_common import TOL, note, oracle_basis
 
 pytestmark = pytest.mark.gpu
 
@@ -51,7 +51,8 @@ def _ctx(wl, mode, rank):
         _, fac = ctx.get_cp(wl.bank.shapes)
         ref = [tuple(m.astype(np.float64) for m in abc) for abc in fac]
     elif mode != "direct_fp32":
-        _, ref = ctx.decompose(rank)
+        ctx.decompose(rank)
+        ref = oracle_basis(wl.bank.filters, rank)
     ctx.plan(wl.pyramids)
     return ctx, ref
 
@@ -105,15 +106,14 @@ def test_odd_shapes_scores(mode, rank):
     ctx.score_pyramid(mode, feats, scores, offs)
     torch.cuda.synchronize()
     s, o = scores.cpu().numpy(), offs.cpu().numpy()
-    Xr = wl.level_features(0, 1).astype(np.float64)
-    Xp = wl.level_features(0, 0).astype(np.float64)
+    levels = [wl.level_features(0, 0).astype(np.float64), wl.level_features(0, 1).astype(np.float64)]
     tol = TOL.get(mode, 1e-4)
+    maps = oracle.score_pyramid(levels, wl.bank.filters, wl.bank.components, 1,
+                                response=lambda X, q: _ref_response(mode, X, wl.bank.filters[q].astype(np.float64), q, ref))
     for ci, c in enumerate(wl.bank.components):
         k = lay.find(0, 1, ci)
         Ho, Wo = int(lay.map_rows[k]), int(lay.map_cols[k])
-        rr = _ref_response(mode, Xr, wl.bank.filters[c.root].astype(np.float64), c.root, ref)
-        prs = [_ref_response(mode, Xp, wl.bank.filters[q].astype(np.float64), q, ref) for q in c.parts]
-        sm = oracle.score_component(rr, prs, c.anchors, c.deform)
+        sm = maps[(1, ci)]
         assert sm.score.shape == (Ho, Wo)
         g = s[lay.map_score_off[k]:lay.map_score_off[k] + Ho * Wo].reshape(Ho, Wo)
         fin = np.isfinite(sm.score)
@@ -124,6 +124,60 @@ def test_odd_shapes_scores(mode, rank):
         check = sm.margin > tol
         assert not (check[..., None] & (go != sm.offsets)).any()
     ctx.close()
+
+
+def _mixed_height_workload():
+    """Filters of 6, 7, 8, 9 and 10 rows in one bank: the taller ones select
+    the 16-row correlation instance, which still runs the 6- to 8-row groups
+    through its unrolled, three-buffer staging (the LDS must hold three chunks
+    of 8 rows as well as two of 10)."""
+    rng = workloads.seed_rng(79, 1)
+    q, _ = np.linalg.qr(rng.standard_normal((32, 32)))
+    basis = q[:, :8]
+    shapes = [(10, 6), (8, 6), (8, 6), (7, 5), (6, 6), (8, 11), (10, 4), (9, 6), (8, 8)]
+    filters = [workloads.draw_filter(rng, h, w, basis) for (h, w) in shapes]
+    comps = [workloads.Component(0, [1, 2, 3, 4], np.array([[0, 0], [12, 6], [5, 7], [14, 3]], np.int32),
+                                 np.array([[0.02, 0.05, -0.01, 0.08]] * 4, np.float32)),
+             workloads.Component(5, [6, 7, 8], np.array([[3, 18], [7, 0], [8, 14]], np.int32),
+                                 np.array([[0.05, 0.03, 0.02, 0.04]] * 3, np.float32))]
+    levels = [workloads.Level(0, 66, 95), workloads.Level(66 * 95, 33, 47)]
+    pyr = workloads.Pyramid(levels, octave=1)
+    return workloads.Workload("mixed heights", 79, [pyr], workloads.Bank(filters, comps),
+                              66 * 95 + 33 * 47, workloads.feature_seed(79), False, [(95, 66)])
+
+
+@pytest.mark.parametrize("mode,rank", [("tensor_bf16", 8), ("tensor_fp32", 4), ("tensor_bf16", 16),
+                                       ("direct_fp32", None)])
+def test_mixed_heights_8_and_10_rows(mode, rank):
+    """Responses of every filter on both levels and the score maps of both
+    components, for a bank that mixes 8-row and 10-row filters, in the modes
+    whose 16-byte planes take the 64-filter tiles with unrolled staging."""
+    from _gpu_common import Cmp, compare_map, oracle_map, run_gpu
+    wl = _mixed_height_workload()
+    note(f"mixed 8/10-row bank {mode} R={rank}")
+    ctx, ref = _ctx(wl, mode, rank)
+    feats = torch.from_numpy(wl.features()).cuda()
+    tol = TOL[mode]
+    for level in (0, 1):
+        out, total = ctx.level_responses(mode, feats, 0, level)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        X = wl.level_features(0, level).astype(np.float64)
+        off = 0
+        for k, f in enumerate(wl.bank.filters):
+            Ho, Wo = X.shape[0] - f.shape[0] + 1, X.shape[1] - f.shape[1] + 1
+            want = _ref_response(mode, X, f.astype(np.float64), k, ref)
+            g = got[off:off + Ho * Wo].reshape(Ho, Wo)
+            off += Ho * Wo
+            err = float(np.max(np.abs(g - want)))
+            assert err <= tol, f"level {level} filter {k} {f.shape[:2]}: max |err| {err:.3g} > {tol}"
+        assert off == total
+    ctx.close()
+    run = run_gpu(wl, mode, rank)
+    cmp = Cmp()
+    for ci in range(len(wl.bank.components)):
+        compare_map(run, wl, 0, 1, ci, oracle_map(wl, 0, 1, ci, run.basis, {}), tol, cmp)
+    note(f"  {cmp.n_pos} positions, max |score err| {cmp.max_err:.3g}")
 
 
 # ------------------------------------------------------------ placement limits

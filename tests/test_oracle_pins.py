@@ -9,6 +9,7 @@ import json
 import os
 
 import numpy as np
+from types import SimpleNamespace
 import pytest
 import scipy.signal
 
@@ -48,6 +49,60 @@ def test_worked_example_score_map():
     anchor_x = 2 * np.arange(Wo)[None, :] + g["anchor"][1]
     np.testing.assert_array_equal(sm.offsets[0, :, :, 0], place[:, :, 0] - anchor_y)
     np.testing.assert_array_equal(sm.offsets[0, :, :, 1], place[:, :, 1] - anchor_x)
+
+
+def _pairing_case():
+    g = _load("pyramid_pairing.json")
+    levels = []
+    for c0, c1 in zip(g["levels_ch0"], g["levels_ch1"]):
+        X = np.zeros(np.array(c0).shape + (32,))
+        X[:, :, 0] = np.array(c0)
+        X[:, :, 1] = np.array(c1)
+        levels.append(X)
+    f_root = np.zeros((1, 1, 32))
+    f_root[0, 0, 0] = 1.0
+    f_part = np.zeros((1, 1, 32))
+    f_part[0, 0, 1] = 1.0
+    comp = SimpleNamespace(root=0, parts=[1], anchors=np.array([g["anchor"]]),
+                           deform=np.array([g["deform"]], float))
+    return g, levels, [f_root, f_part], [comp]
+
+
+def test_score_pyramid_level_pairing_golden():
+    """Root level l takes its parts from level l - octave (hand-worked
+    three-level pyramid, tests/golden/pyramid_pairing.json)."""
+    g, levels, filters, comps = _pairing_case()
+    out = oracle.score_pyramid(levels, filters, comps, g["octave"])
+    assert sorted(out) == [(1, 0), (2, 0)]
+    np.testing.assert_array_equal(out[(1, 0)].score, np.array(g["score_level1"], float))
+    np.testing.assert_array_equal(out[(2, 0)].score, np.array(g["score_level2"], float))
+    np.testing.assert_array_equal(out[(1, 0)].offsets[0], np.array(g["offsets_level1"]))
+    # a subset gives the same maps; a level below the octave is refused
+    sub = oracle.score_pyramid(levels, filters, comps, g["octave"], root_levels=[2], comps=[0])
+    np.testing.assert_array_equal(sub[(2, 0)].score, out[(2, 0)].score)
+    with pytest.raises(ValueError):
+        oracle.score_pyramid(levels, filters, comps, g["octave"], root_levels=[0])
+
+
+def test_score_pyramid_worked_example_and_full_rank():
+    """The worked example as a two-level pyramid (part level 6x8 = level 0,
+    root level 3x4 = level 1, octave 1) gives its hand-derived score map, in
+    the direct form and in the tensor form at full rank (U = I)."""
+    g = _load("worked_example.json")
+    X0 = np.zeros((3, 4, 32))
+    X0[:, :, 0] = np.array(g["root_level_ch0"])
+    X1 = np.zeros(tuple(g["part_level_shape"]) + (32,))
+    for y, x, v in g["part_level_ch1_nonzero"]:
+        X1[y, x, 1] = v
+    f0 = np.zeros((2, 2, 32))
+    f0[:, :, 0] = np.array(g["root_filter_ch0"])
+    f1 = np.zeros((1, 1, 32))
+    f1[0, 0, 1] = g["part_filter_ch1"][0][0]
+    comp = SimpleNamespace(root=0, parts=[1], anchors=np.array([g["anchor"]]),
+                           deform=np.array([g["deform"]], float))
+    for U in (None, np.eye(32)):
+        out = oracle.score_pyramid([X1, X0], [f0, f1], [comp], 1, U=U)
+        np.testing.assert_array_equal(out[(1, 0)].score, np.array(g["score"], float))
 
 
 def test_dt_1d_golden():
@@ -282,6 +337,20 @@ def test_multiplication_counts_by_counting():
     assert oracle.mults_direct(Np, Mp, N, M, L) == Np * Mp * N * M * L
 
 
+def test_shared_basis_multiplication_count():
+    """The shortened correlation of Section 4 over R projected channels: one
+    multiplication per term of sum_{n,m,r} G[n,m,r] Z[y+n,x+m,r] at every
+    output (counted by enumerating the terms), and at R = L it is exactly the
+    direct count alpha."""
+    import itertools
+    Np, Mp, N, M, L, R = 3, 4, 2, 3, 5, 2
+    terms = sum(1 for _ in itertools.product(range(Np), range(Mp), range(N), range(M), range(R)))
+    assert terms == oracle.mults_shared_basis(Np, Mp, N, M, L, R)
+    assert oracle.mults_shared_basis(Np, Mp, N, M, L, L) == oracle.mults_direct(Np, Mp, N, M, L)
+    # the saving over direct is L / R, independent of the filter size
+    assert oracle.mults_direct(7, 9, 6, 6, 32) / oracle.mults_shared_basis(7, 9, 6, 6, 32, 8) == 4.0
+
+
 def test_detections_of_the_worked_example():
     """Algorithm 1's detection set on the hand-derived score map."""
     g = _load("worked_example.json")
@@ -359,10 +428,39 @@ def test_cp_response_bruteforce_tiny():
 
 # ------------------------------------------------------------ rank selection
 def test_rank_bound_closed_form():
-    # e (r (N+M+L) / (N M L))^2 at N = M = 6, L = 32, r = 6 (Section 5's example size)
-    assert oracle.rank_bound(2.0, 6, 6, 6, 32) == pytest.approx(2.0 * (6 * 44 / 1152) ** 2, rel=1e-15)
+    # Section 4's bound e (r (N+M+L) / (N M L))^2 at e = 2, r = 6, N = M = 6,
+    # L = 32: 2 (264 / 1152)^2 = 0.10503472222..., a literal worked by hand
+    assert oracle.rank_bound(2.0, 6, 6, 6, 32) == pytest.approx(0.1050347222222222, rel=1e-14)
+    # r = 1, N = M = 1, L = 2 -> e (4 / 2)^2 = 4 e
+    assert oracle.rank_bound(0.5, 1, 1, 1, 2) == pytest.approx(2.0, rel=1e-15)
     # formula (1) of Section 4 is the inverse ratio without the square
     assert oracle.gain_formula1(6, 6, 32, 6) == pytest.approx(1152 / 264, rel=1e-15)
+
+
+def _odeco(weights, N=6, M=6, L=32):
+    """sum_j w_j e_j (x) e_j (x) e_j: orthogonal rank-1 terms, so the best
+    rank-r approximation keeps the r largest and its error is the norm of the
+    rest (no ALS subtlety)."""
+    f = np.zeros((N, M, L))
+    for j, w in enumerate(weights):
+        f[j, j, j] = w
+    return f
+
+
+def test_select_rank_uses_the_squared_bound():
+    """A filter where Section 4's squared bound and an unsquared one pick
+    different ranks.  Weights (1, 1/2, 1/4, 1/8, 1/16, 1/32) on orthogonal
+    terms of a 6x6x32 filter: errors after r terms are sqrt of the tail sums,
+    0.5771, 0.2881, 0.1432 (r = 1..3).  With e = 100 the squared bound is
+    100 (44 r / 1152)^2 = 0.1459 r^2: 0.146 (r = 1) < 0.577, 0.584 (r = 2) >
+    0.288, so rank 2; the unsquared 100 (44 r / 1152) = 3.82 r accepts r = 1."""
+    f = _odeco([1, 1 / 2, 1 / 4, 1 / 8, 1 / 16, 1 / 32])
+    tail = [np.sqrt(sum(w * w for w in [1 / 2, 1 / 4, 1 / 8, 1 / 16, 1 / 32][r - 1:])) for r in (1, 2)]
+    assert tail[0] == pytest.approx(0.5771, abs=1e-4) and tail[1] == pytest.approx(0.2881, abs=1e-4)
+    r, errs = oracle.select_rank(f, 100.0, 6, iters=300)
+    assert r == 2, (r, errs)
+    # the binary search tried r = 3, 2, 1; their fits are the exact truncations
+    assert errs[0] == pytest.approx(tail[0], rel=1e-9) and errs[1] == pytest.approx(tail[1], rel=1e-9)
 
 
 def test_select_rank_finds_planted_rank():
