@@ -284,6 +284,26 @@ dpmt_status dpmt_distance_transform(const float* resp_dev, int32_t rows, int32_t
                                     const float* deform_host, float* d_dev, int32_t* arg_y_dev,
                                     int32_t* arg_x_dev, void* hip_stream);
 
+/* dpmt_distance_transform for callers that cannot allocate memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, kernels and results, but the scratch the transform needs
+ * (line maxima and the row pass's values and argmax, 16 MiB + 64 KiB) lives
+ * in a static device array of the library that each GPU holds from its first
+ * use until the process ends; the call allocates nothing.  Runs on the
+ * current HIP device (hip_stream must belong to it); the first call on a
+ * device looks up that device's copy of the array.  Limits:
+ * rows <= DPMT_DT_NOALLOC_MAX_SIDE, cols <= DPMT_DT_NOALLOC_MAX_SIDE and
+ * rows * cols <= DPMT_DT_NOALLOC_MAX_CELLS, else DPMT_E_UNSUPPORTED before
+ * anything is enqueued.  Every call on a GPU uses that GPU's one array, so
+ * calls that overlap on one GPU (other streams, other threads) race: order
+ * them on one stream or synchronise between them. */
+#define DPMT_DT_NOALLOC_MAX_SIDE 16384
+#define DPMT_DT_NOALLOC_MAX_CELLS 2097152
+dpmt_status dpmt_distance_transform_noalloc(const float* resp_dev, int32_t rows, int32_t cols,
+                                            int32_t ld, const float* deform_host, float* d_dev,
+                                            int32_t* arg_y_dev, int32_t* arg_x_dev,
+                                            void* hip_stream);
+
 /* Per-stage GPU timing from HIP events recorded on the launch stream around
  * each stage of dpmt_score_pyramid.  dpmt_set_profiling(ctx, 1) starts
  * recording (and clears what was gathered); every later score call adds one

@@ -15,6 +15,9 @@ DPMT_E_NOMEM = -4
 DPMT_E_DEVICE = -5
 DPMT_E_UNSUPPORTED = -6
 
+DT_NOALLOC_MAX_SIDE = 16384        # DPMT_DT_NOALLOC_MAX_SIDE
+DT_NOALLOC_MAX_CELLS = 2097152     # DPMT_DT_NOALLOC_MAX_CELLS
+
 DIRECT_FP32 = 0
 TENSOR_FP32 = 1
 TENSOR_BF16 = 2
@@ -83,6 +86,8 @@ SIGNATURES = {
                                        c_int64, POINTER(c_int64), c_void_p]),
     "dpmt_distance_transform": (c_int32, [c_void_p, c_int32, c_int32, c_int32, POINTER(c_float),
                                           c_void_p, c_void_p, c_void_p, c_void_p]),
+    "dpmt_distance_transform_noalloc": (c_int32, [c_void_p, c_int32, c_int32, c_int32, POINTER(c_float),
+                                                  c_void_p, c_void_p, c_void_p, c_void_p]),
     "dpmt_set_profiling": (c_int32, [c_void_p, c_int32]),
     "dpmt_stage_times": (c_int32, [c_void_p, POINTER(c_float), c_int32, POINTER(c_int32)]),
     "dpmt_set_launch": (c_int32, [c_void_p, c_int32]),

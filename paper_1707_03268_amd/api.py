@@ -371,9 +371,11 @@ def tile_config_name(config: int) -> Optional[str]:
     return r.decode() if r is not None else None
 
 
-def distance_transform(resp, deform, out=None, arg_y=None, arg_x=None, stream=None):
+def distance_transform(resp, deform, out=None, arg_y=None, arg_x=None, stream=None, noalloc=False):
     """Generalised distance transform of one 2D float32 CUDA map for every
-    target cell; returns (D, arg_y, arg_x)."""
+    target cell; returns (D, arg_y, arg_x).  noalloc: call
+    dpmt_distance_transform_noalloc (the library's static scratch, no
+    allocation inside the call; outputs must then be given)."""
     import torch
     if resp.dim() != 2:
         raise ValueError("resp must be 2D")
@@ -390,9 +392,10 @@ def distance_transform(resp, deform, out=None, arg_y=None, arg_x=None, stream=No
     d = (c_float * 4)(*[float(v) for v in deform])
     if not resp.is_cuda or resp.dtype != torch.float32:
         raise TypeError("resp must be a float32 CUDA tensor")
-    _check(_lib().dpmt_distance_transform(
+    fn = _lib().dpmt_distance_transform_noalloc if noalloc else _lib().dpmt_distance_transform
+    _check(fn(
         c_void_p(resp.data_ptr()), rows, cols, ld, d,
         _dev_ptr(out, torch.float32, "out"), _dev_ptr(arg_y, torch.int32, "arg_y"),
         _dev_ptr(arg_x, torch.int32, "arg_x"), _stream_ptr(stream)), None,
-        "dpmt_distance_transform")
+        "dpmt_distance_transform_noalloc" if noalloc else "dpmt_distance_transform")
     return out, arg_y, arg_x

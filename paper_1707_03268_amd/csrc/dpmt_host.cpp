@@ -2233,9 +2233,13 @@ dpmt_status dpmt_level_responses(dpmt_ctx* c, dpmt_mode mode, const float* featu
     return DPMT_OK;
 }
 
-dpmt_status dpmt_distance_transform(const float* resp_dev, int32_t rows, int32_t cols, int32_t ld,
-                                    const float* deform_host, float* d_dev, int32_t* arg_y_dev,
-                                    int32_t* arg_x_dev, void* hip_stream) {
+}  // extern "C"
+
+namespace {
+// Arguments of the single-map transform (both entry points).
+dpmt_status check_dt_args(const float* resp_dev, int32_t rows, int32_t cols, int32_t ld,
+                          const float* deform_host, const float* d_dev, const int32_t* arg_y_dev,
+                          const int32_t* arg_x_dev) {
     if (!resp_dev || !deform_host || !d_dev) return fail(nullptr, DPMT_E_INVALID, "resp_dev, deform_host and d_dev are required");
     if (rows < 1 || cols < 1 || ld < cols) return fail(nullptr, DPMT_E_INVALID, "need rows >= 1, cols >= 1, ld >= cols");
     if ((arg_y_dev == nullptr) != (arg_x_dev == nullptr)) return fail(nullptr, DPMT_E_INVALID, "arg_y_dev and arg_x_dev must both be given or both NULL");
@@ -2243,6 +2247,17 @@ dpmt_status dpmt_distance_transform(const float* resp_dev, int32_t rows, int32_t
         if (!std::isfinite(deform_host[t])) return fail(nullptr, DPMT_E_INVALID, "non-finite deformation coefficient");
     if (!(deform_host[1] > 0.f) || !(deform_host[3] > 0.f)) return fail(nullptr, DPMT_E_INVALID, "quadratic deformation coefficients must be > 0");
     if ((int64_t)rows * cols > (int64_t)1 << 30) return fail(nullptr, DPMT_E_UNSUPPORTED, "map larger than 2^30 cells");
+    return DPMT_OK;
+}
+}  // namespace
+
+extern "C" {
+
+dpmt_status dpmt_distance_transform(const float* resp_dev, int32_t rows, int32_t cols, int32_t ld,
+                                    const float* deform_host, float* d_dev, int32_t* arg_y_dev,
+                                    int32_t* arg_x_dev, void* hip_stream) {
+    const dpmt_status chk = check_dt_args(resp_dev, rows, cols, ld, deform_host, d_dev, arg_y_dev, arg_x_dev);
+    if (chk != DPMT_OK) return chk;
     hipStream_t st = static_cast<hipStream_t>(hip_stream);
     const int64_t n = (int64_t)rows * cols;
     float* lmax = nullptr;
@@ -2256,6 +2271,21 @@ dpmt_status dpmt_distance_transform(const float* resp_dev, int32_t rows, int32_t
     if (r1v) (void)hipFreeAsync(r1v, st);
     if (r1a) (void)hipFreeAsync(r1a, st);
     if (e != hipSuccess) return hip_fail(nullptr, e, "distance transform");
+    return DPMT_OK;
+}
+
+dpmt_status dpmt_distance_transform_noalloc(const float* resp_dev, int32_t rows, int32_t cols,
+                                            int32_t ld, const float* deform_host, float* d_dev,
+                                            int32_t* arg_y_dev, int32_t* arg_x_dev, void* hip_stream) {
+    const dpmt_status chk = check_dt_args(resp_dev, rows, cols, ld, deform_host, d_dev, arg_y_dev, arg_x_dev);
+    if (chk != DPMT_OK) return chk;
+    if (rows > DT_NOALLOC_MAX_SIDE || cols > DT_NOALLOC_MAX_SIDE)
+        return fail(nullptr, DPMT_E_UNSUPPORTED, "allocation-free transform: rows and cols must be <= 16384");
+    if ((int64_t)rows * cols > DT_NOALLOC_MAX_CELLS)
+        return fail(nullptr, DPMT_E_UNSUPPORTED, "allocation-free transform: map larger than 2^21 cells");
+    const hipError_t e = launch_dt_single_noalloc(resp_dev, rows, cols, ld, deform_host, d_dev, arg_y_dev,
+                                                  arg_x_dev, static_cast<hipStream_t>(hip_stream));
+    if (e != hipSuccess) return hip_fail(nullptr, e, "allocation-free distance transform");
     return DPMT_OK;
 }
 

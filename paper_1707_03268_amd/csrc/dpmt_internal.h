@@ -230,5 +230,13 @@ hipError_t launch_detect(const float* scores, int64_t n, float tau, const MapDes
 hipError_t launch_dt_single(const float* resp, int rows, int cols, int ld, const float* d,
                             float* lmax, float* r1v, int32_t* r1a, float* out, int32_t* ay,
                             int32_t* ax, hipStream_t st);
+// The same transform with its scratch (line maxima, row-pass values and
+// argmax) in a file-scope device array of the kernels' source instead of
+// allocations: maps up to DT_NOALLOC_MAX_CELLS cells and DT_NOALLOC_MAX_SIDE
+// rows and columns (the caller checks), on the current device.
+constexpr int DT_NOALLOC_MAX_SIDE = 16384;
+constexpr int64_t DT_NOALLOC_MAX_CELLS = (int64_t)1 << 21;
+hipError_t launch_dt_single_noalloc(const float* resp, int rows, int cols, int ld, const float* d,
+                                    float* out, int32_t* ay, int32_t* ax, hipStream_t st);
 
 }  // namespace dpmt

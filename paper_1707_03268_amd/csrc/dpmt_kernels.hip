@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <cfloat>
 #include <climits>
+#include <mutex>
 
 namespace dpmt {
 
@@ -1883,6 +1884,55 @@ hipError_t launch_dt_single(const float* resp, int rows, int cols, int ld, const
     hipLaunchKernelGGL(dt1_col_kernel, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, r1v,
                        r1a, rows, cols, lmax, d[3], d[2], out, ay, ax);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// allocation-free single-map transform: the scratch of launch_dt_single (line
+// maxima, then the row pass's values and argmax) lives in this file-scope
+// array.  Every kernel writes each scratch element it later reads, so nothing
+// needs clearing between calls.  Each GPU holds its own copy at its own
+// address; host code uses that address (found once per device with
+// hipGetSymbolAddress), never the array's name.  Calls on one GPU share the
+// array, so calls that overlap on one GPU race.
+// ---------------------------------------------------------------------------
+constexpr size_t DT_NA_LMAX = (size_t)DT_NOALLOC_MAX_SIDE * sizeof(float);   // 64 KiB
+constexpr size_t DT_NA_PLANE = (size_t)DT_NOALLOC_MAX_CELLS * sizeof(float); // 8 MiB
+constexpr int DT_NA_MAX_DEVICES = 64;
+static __device__ __align__(256) char scratch[DT_NA_LMAX + 2 * DT_NA_PLANE];
+
+// Device address of the current device's scratch, looked up on the first call
+// on that device (with it current) and kept.
+static hipError_t dt_noalloc_scratch(char** out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= DT_NA_MAX_DEVICES) return hipErrorInvalidDevice;
+    static std::mutex mu;
+    static char* addr[DT_NA_MAX_DEVICES] = {};
+    std::lock_guard<std::mutex> lock(mu);
+    if (addr[dev] == nullptr) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (p == nullptr) return hipErrorInvalidSymbol;
+        addr[dev] = static_cast<char*>(p);
+    }
+    *out = addr[dev];
+    return hipSuccess;
+}
+
+hipError_t launch_dt_single_noalloc(const float* resp, int rows, int cols, int ld, const float* d,
+                                    float* out, int32_t* ay, int32_t* ax, hipStream_t st) {
+    if (rows > DT_NOALLOC_MAX_SIDE || cols > DT_NOALLOC_MAX_SIDE ||
+        (int64_t)rows * cols > DT_NOALLOC_MAX_CELLS)
+        return hipErrorInvalidValue;
+    char* base = nullptr;
+    hipError_t e = dt_noalloc_scratch(&base);
+    if (e != hipSuccess) return e;
+    float* lmax = reinterpret_cast<float*>(base);
+    float* r1v = reinterpret_cast<float*>(base + DT_NA_LMAX);
+    int32_t* r1a = reinterpret_cast<int32_t*>(base + DT_NA_LMAX + DT_NA_PLANE);
+    return launch_dt_single(resp, rows, cols, ld, d, lmax, r1v, r1a, out, ay, ax, st);
 }
 
 }  // namespace dpmt

@@ -489,3 +489,19 @@ def test_fit_thresholds_matches_oracle_and_validates():
     assert e.value.status == _abi.DPMT_E_INVALID
     ctx.set_thresholds(None)
     ctx.close()
+
+
+def test_noalloc_distance_transform_limits_host_only():
+    """The allocation-free transform rejects maps beyond its static scratch
+    (either side > 16384, or more than 2^21 cells) before touching a device;
+    dummy non-NULL pointers suffice since nothing is enqueued."""
+    lib = _abi.load()
+    d = (ctypes.c_float * 4)(0.0, 0.1, 0.0, 0.1)
+    fake = ctypes.c_void_p(4096)
+    for rows, cols in ((16385, 1), (1, 16385), (1449, 1449)):
+        rc = lib.dpmt_distance_transform_noalloc(fake, rows, cols, cols, d, fake, None, None, None)
+        assert rc == _abi.DPMT_E_UNSUPPORTED, (rows, cols, rc)
+        assert b"allocation-free" in lib.dpmt_last_error(None)
+    bad = (ctypes.c_float * 4)(0.0, 0.0, 0.0, 0.1)
+    assert lib.dpmt_distance_transform_noalloc(fake, 4, 4, 4, bad, fake, None, None, None) == _abi.DPMT_E_INVALID
+    assert _abi.DT_NOALLOC_MAX_CELLS == 1 << 21 and _abi.DT_NOALLOC_MAX_SIDE == 16384
