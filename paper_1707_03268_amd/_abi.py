@@ -5,7 +5,9 @@ import ctypes
 import os
 from ctypes import POINTER, c_double, c_float, c_int16, c_int32, c_int64, c_void_p, c_char_p
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdpmt.so")
+# DPMT_LIBRARY names another build of the library (the sanitizer build of the
+# host runtime that the CPU tests load); the default is the in-tree build.
+LIB_PATH = os.environ.get("DPMT_LIBRARY") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdpmt.so")
 
 DPMT_OK = 0
 DPMT_E_INVALID = -1

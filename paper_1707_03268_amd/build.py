@@ -2,8 +2,13 @@
 
     python -m paper_1707_03268_amd.build
 
-Compiles the host runtime and the HIP kernels into one shared library next
-to this file.  Packed FP32 instructions are disabled for all device code.
+Compiles the host runtime and the HIP kernels to objects under _build/ and
+links them into one shared library next to this file.  Packed FP32
+instructions are disabled for all device code.
+
+build_host_sanitized() links a second copy whose host runtime is built with
+AddressSanitizer and UndefinedBehaviorSanitizer (host code only; the kernels'
+object is the normal one), for the CPU tests of the host-only paths.
 """
 from __future__ import annotations
 
@@ -15,8 +20,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdpmt.so")
-SOURCES = [os.path.join(CSRC, "dpmt_host.cpp"), os.path.join(CSRC, "dpmt_kernels.hip")]
+BUILD_DIR = os.path.join(ROOT, "_build")
+HOST_SRC = os.path.join(CSRC, "dpmt_host.cpp")
+KERNEL_SRC = os.path.join(CSRC, "dpmt_kernels.hip")
 ARCH = "gfx950"
+COMMON = ["-std=c++17", "-fPIC", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
+NOISE = "is not a recognized feature for this target"
 
 
 def hipcc() -> str:
@@ -24,24 +34,76 @@ def hipcc() -> str:
     return os.path.join(rocm, "bin", "hipcc")
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
-           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           "-Wall", "-Wno-unused-function", "-Wno-unused-result",
-           *SOURCES, "-o", tmp]
+def _includes():
+    return ["-I", os.path.join(ROOT, "include"), "-I", CSRC]
+
+
+def _run(cmd, verbose: bool) -> None:
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
-    noise = "is not a recognized feature for this target"
-    msgs = "\n".join(l for l in (res.stdout + res.stderr).splitlines() if noise not in l)
+    msgs = "\n".join(l for l in (res.stdout + res.stderr).splitlines() if NOISE not in l)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed ({res.returncode}):\n{msgs}")
     if verbose and msgs.strip():
         print(msgs)
+
+
+def _kernels_object(verbose: bool) -> str:
+    obj = os.path.join(BUILD_DIR, "dpmt_kernels.o")
+    _run([hipcc(), f"--offload-arch={ARCH}", "-O3", *COMMON, *_includes(), "-c", KERNEL_SRC,
+          "-o", obj], verbose)
+    return obj
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    kobj = _kernels_object(verbose)
+    hobj = os.path.join(BUILD_DIR, "dpmt_host.o")
+    _run([hipcc(), f"--offload-arch={ARCH}", "-O3", *COMMON, *_includes(), "-c", HOST_SRC,
+          "-o", hobj], verbose)
+    tmp = LIB + ".tmp"
+    _run([hipcc(), f"--offload-arch={ARCH}", "-shared", kobj, hobj, "-o", tmp], verbose)
     os.replace(tmp, LIB)
     return LIB
+
+
+def build_host_sanitized(out_dir: str, verbose: bool = False) -> str:
+    """libdpmt with the host runtime under ASan + UBSan (every UB report
+    fatal), linked with the kernels' object of the in-tree build (compiled
+    here if missing or older than its sources).  Returns the library path; it
+    needs the ASan runtime preloaded (asan_runtime())."""
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    kobj = os.path.join(BUILD_DIR, "dpmt_kernels.o")
+    newest = max(os.path.getmtime(p) for p in (KERNEL_SRC, os.path.join(CSRC, "dpmt_internal.h")))
+    if not os.path.exists(kobj) or os.path.getmtime(kobj) < newest:
+        kobj = _kernels_object(verbose)
+    os.makedirs(out_dir, exist_ok=True)
+    hobj = os.path.join(out_dir, "dpmt_host_san.o")
+    san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+           "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer"]
+    _run([hipcc(), "--cuda-host-only", "-O1", "-g", *COMMON, *san, *_includes(), "-c", HOST_SRC,
+          "-o", hobj], verbose)
+    lib = os.path.join(out_dir, "libdpmt_san.so")
+    _run([hipcc(), f"--offload-arch={ARCH}", "-shared", *san, kobj, hobj, "-o", lib], verbose)
+    return lib
+
+
+def asan_runtime() -> str:
+    """Path of the compiler's shared ASan runtime (it carries the UBSan
+    handlers too)."""
+    res = subprocess.run([hipcc(), "--print-file-name=libclang_rt.asan-x86_64.so"],
+                         capture_output=True, text=True)
+    path = res.stdout.strip().splitlines()[-1] if res.stdout.strip() else ""
+    if not os.path.isabs(path) or not os.path.exists(path):
+        rocm = os.environ.get("ROCM_PATH", "/opt/rocm")
+        base = os.path.join(rocm, "llvm", "lib", "clang")
+        for v in sorted(os.listdir(base)) if os.path.isdir(base) else []:
+            cand = os.path.join(base, v, "lib", "linux", "libclang_rt.asan-x86_64.so")
+            if os.path.exists(cand):
+                return cand
+        raise FileNotFoundError("libclang_rt.asan-x86_64.so not found")
+    return path
 
 
 if __name__ == "__main__":
