@@ -320,6 +320,18 @@ class Context:
         rec = rec[:m]
         return rec, rec[:, 3].contiguous().view(torch.float32), n
 
+    def detect_into(self, scores, tau: float, records, count, stream=None) -> None:
+        """Enqueue dpmt_detect into caller buffers without waiting: ``records``
+        an int32 CUDA tensor of shape (capacity, 4), ``count`` an int64 CUDA
+        tensor of at least one element (receives the full count)."""
+        import torch
+        if records.dim() != 2 or records.shape[1] != 4:
+            raise ValueError("records must have shape (capacity, 4)")
+        _check(_lib().dpmt_detect(self._h, _dev_ptr(scores, torch.float32, "scores"), float(tau),
+                                  _dev_ptr(records, torch.int32, "records"), int(records.shape[0]),
+                                  _dev_ptr(count, torch.int64, "count"), _stream_ptr(stream)),
+               self._h, "dpmt_detect")
+
     # ------------------------------------------------------ launch strategy
     def set_launch(self, launch) -> None:
         """'batched' (default), 'per_level' or 'graph' (see dpmt_launch)."""

@@ -161,6 +161,82 @@ def level_values(lv: Level, seed: int, padded: bool) -> np.ndarray:
     return vals
 
 
+def _i64(c: int) -> int:
+    """A 64-bit constant as the signed value torch's int64 arithmetic uses."""
+    return c - (1 << 64) if c >= (1 << 63) else c
+
+
+def _splitmix64_torch(z):
+    """splitmix64 on a torch int64 tensor (two's-complement wrap-around, logical
+    shifts by masking the arithmetic ones); the same bits as ``splitmix64``."""
+    import torch  # noqa: F401
+
+    def lsr(v, k):
+        return (v >> k) & ((1 << (64 - k)) - 1)
+    z = z + _i64(_GOLDEN)
+    z = (z ^ lsr(z, 30)) * _i64(_M1)
+    z = (z ^ lsr(z, 27)) * _i64(_M2)
+    return z ^ lsr(z, 31)
+
+
+def _image_cell_range(pyr: Pyramid) -> Tuple[int, int]:
+    first = pyr.levels[0].cell_offset
+    last = pyr.levels[-1]
+    return first, last.cell_offset + last.rows * last.cols
+
+
+def _padding_mask(pyr: Pyramid, padded: bool):
+    """Boolean mask over an image's cells (relative to its first cell): True
+    in the padding band of every level."""
+    first, end = _image_cell_range(pyr)
+    mask = np.zeros(end - first, dtype=bool)
+    if padded:
+        for lv in pyr.levels:
+            m = np.ones((lv.rows, lv.cols), dtype=bool)
+            m[PAD_ROWS:lv.rows - PAD_ROWS, PAD_COLS:lv.cols - PAD_COLS] = False
+            mask[lv.cell_offset - first:lv.cell_offset - first + lv.rows * lv.cols] = m.ravel()
+    return mask
+
+
+def features_device(wl: "Workload", device, out=None, cell_base: int = 0, images=None):
+    """The packed feature buffer generated on a torch device, bit for bit the
+    values of ``Workload.features()`` (the same counter hash of the global
+    element index, the same float32 scaling and padding), one image at a
+    time, so that large batches need no host copy.  ``images`` (default all)
+    selects a contiguous run of images; ``cell_base`` is the global cell index
+    of ``out``'s first row (default 0: ``out`` holds the whole buffer).
+    Returns ``out`` (allocated when None)."""
+    import torch
+    imgs = range(len(wl.pyramids)) if images is None else images
+    if out is None:
+        lo = _image_cell_range(wl.pyramids[imgs[0]])[0]
+        hi = _image_cell_range(wl.pyramids[imgs[-1]])[1]
+        out = torch.empty((hi - lo, N_CHANNELS), dtype=torch.float32, device=device)
+        cell_base = lo
+    scale = torch.full((N_CHANNELS,), 0.2, dtype=torch.float32, device=device)
+    scale[27:31] = 0.4
+    scale[31] = 0.0
+    pad_row = torch.zeros(N_CHANNELS, dtype=torch.float32, device=device)
+    pad_row[31] = 1.0
+    seed = _i64(wl.feat_seed & _MASK)
+    masks = {}
+    for i in imgs:
+        pyr = wl.pyramids[i]
+        first, end = _image_cell_range(pyr)
+        key = tuple((lv.cell_offset - first, lv.rows, lv.cols) for lv in pyr.levels)
+        if key not in masks:
+            masks[key] = torch.from_numpy(_padding_mask(pyr, wl.padded)).to(device)
+        n = end - first
+        idx = torch.arange(n * N_CHANNELS, dtype=torch.int64, device=device) + first * N_CHANNELS
+        outer = _splitmix64_torch(_splitmix64_torch(idx) ^ seed)
+        u = ((outer >> 40) & ((1 << 24) - 1)).to(torch.float32) * (2.0 ** -24)
+        vals = u.view(n, N_CHANNELS) * scale
+        vals[masks[key]] = pad_row
+        out[first - cell_base:end - cell_base] = vals
+        del idx, outer, u, vals
+    return out
+
+
 def pyramid_level_sizes(width: int, height: int) -> List[Tuple[int, int]]:
     """Unpadded (rows, cols) of every level: 10 levels per octave, level 0 at 2x.
 
