@@ -1375,7 +1375,10 @@ __device__ __forceinline__ PlaceGeo place_geo(const MapPart& P, const MapDesc& M
     G.lrb = lrb;
     G.RB = 1 << lrb;
     G.ry0 = max(0, P.vy + G.vlo);
-    G.ry1 = min(P.Hp - 1, 2 * (M.Ho - 1) + P.vy + G.vhi);
+    // the column pass reads up to 3 rows past the last target's window (its
+    // offsets go in groups of 4): those rows are row-pass rows too when they
+    // lie in the map, and the -inf pad rows beyond it
+    G.ry1 = min(P.Hp - 1, 2 * (M.Ho - 1) + P.vy + G.vhi + 3);
     G.rounds = (G.live && G.ry1 >= G.ry0) ? (G.ry1 - G.ry0 + G.RB) >> lrb : 0;
     G.X0 = G.tx0 + ulo - d;
     G.tpr = 256 >> lrb;

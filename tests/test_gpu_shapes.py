@@ -220,3 +220,37 @@ def test_placement_limits_scores(name, pr, pc, rr, rc, mode, rank):
     compare_map(run, wl, 0, 1, 0, sm, TOL[mode], cmp)
     note(f"  {cmp.n_pos} positions, max |score err| {cmp.max_err:.3g}, argmax checked "
          f"{cmp.n_arg_checked}/{cmp.n_arg}")
+
+
+# ------------------------------------------------- part maps taller than needed
+def _tall_part_level_workload():
+    """A part level far taller than its root level needs (60 rows of parts for
+    a 7-row score map): the column pass's last groups of 4 window offsets then
+    reach part rows below every target's window.  The first part (weak
+    vertical deformation, anchor row 6, a filter 5x the norm of the others)
+    has large row-pass values on those rows; the second (strong vertical
+    deformation, anchor row 0) must not see them."""
+    rng = workloads.seed_rng(79, 1)
+    q, _ = np.linalg.qr(rng.standard_normal((32, 32)))
+    basis = q[:, :8]
+    root = workloads.draw_filter(rng, 6, 11, basis)
+    pa = 5.0 * workloads.draw_filter(rng, 6, 6, basis)
+    pb = workloads.draw_filter(rng, 6, 6, basis)
+    comps = [workloads.Component(0, [1, 2], np.array([[6, 3], [0, 8]], np.int32),
+                                 np.array([[0.0, 0.05, 0.0, 1e-4], [0.01, 0.05, 0.0, 2.0]], np.float32))]
+    levels = [workloads.Level(0, 60, 40), workloads.Level(60 * 40, 12, 20)]
+    pyr = workloads.Pyramid(levels, octave=1)
+    return workloads.Workload("tall part level", 79, [pyr], workloads.Bank([root, pa, pb], comps),
+                              60 * 40 + 12 * 20, workloads.feature_seed(79), False, [(40, 60)])
+
+
+@pytest.mark.parametrize("mode,rank", [("direct_fp32", None), ("tensor_fp32", 32)])
+def test_part_level_taller_than_the_windows(mode, rank):
+    from _gpu_common import Cmp, compare_map, oracle_map, run_gpu
+    wl = _tall_part_level_workload()
+    note(f"tall part level, {mode}")
+    run = run_gpu(wl, mode, rank)
+    cmp = Cmp()
+    sm = oracle_map(wl, 0, 1, 0, run.basis, {})
+    compare_map(run, wl, 0, 1, 0, sm, TOL[mode], cmp)
+    assert cmp.n_pos == 7 * 10
