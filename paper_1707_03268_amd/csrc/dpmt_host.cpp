@@ -21,22 +21,31 @@ namespace {
 thread_local std::string g_free_error;   // errors of calls without a context
 
 // Correlation tile configurations the autotuner chooses from: output rows per
-// wave, 32-filter blocks per wave, waves per workgroup, resident grid.  All of
-// them accumulate every response in the same order, so they give equal bits.
+// wave, 32-filter blocks per wave, waves per workgroup, resident grid, groups
+// of filter blocks walked over one window, and how many of the waves sit side
+// by side along x (the rest stacked along rows).  All of them accumulate
+// every response in the same order, so they give equal bits.  Wider
+// workgroup tiles write longer runs of every response row: the FP32
+// responses leave in 128-byte runs per filter row with one wave along x, in
+// 512- or 1024-byte runs with 4 or 8.
 struct TileCfg {
     int ty, bb, wy, persistent;
     int nfb;           // groups of bb filter blocks a tile walks over one window
     const char* name;
+    int wx;            // waves along x
 };
 constexpr TileCfg TILE_CFGS[] = {
-    {4, 2, 4, 0, 1, "16 rows x 32 cols x 64 filters, 256 threads, one workgroup per tile"},
-    {4, 2, 4, 1, 1, "16 rows x 32 cols x 64 filters, 256 threads, resident grid"},
-    {2, 2, 4, 0, 1, "8 rows x 32 cols x 64 filters, 256 threads, one workgroup per tile"},
-    {4, 1, 4, 0, 1, "16 rows x 32 cols x 32 filters, 256 threads, one workgroup per tile"},
-    {2, 2, 4, 1, 1, "8 rows x 32 cols x 64 filters, 256 threads, resident grid"},
-    {4, 1, 4, 0, 6, "16 rows x 32 cols x 6 x 32 filters over one window, 256 threads"},
-    {4, 1, 4, 0, 3, "16 rows x 32 cols x 3 x 32 filters over one window, 256 threads"},
-    {4, 2, 4, 0, 3, "16 rows x 32 cols x 3 x 64 filters over one window, 256 threads"},
+    {4, 2, 4, 0, 1, "16 rows x 32 cols x 64 filters, 256 threads, one workgroup per tile", 1},
+    {4, 2, 4, 1, 1, "16 rows x 32 cols x 64 filters, 256 threads, resident grid", 1},
+    {2, 2, 4, 0, 1, "8 rows x 32 cols x 64 filters, 256 threads, one workgroup per tile", 1},
+    {4, 1, 4, 0, 1, "16 rows x 32 cols x 32 filters, 256 threads, one workgroup per tile", 1},
+    {2, 2, 4, 1, 1, "8 rows x 32 cols x 64 filters, 256 threads, resident grid", 1},
+    {4, 1, 4, 0, 6, "16 rows x 32 cols x 6 x 32 filters over one window, 256 threads", 1},
+    {4, 1, 4, 0, 3, "16 rows x 32 cols x 3 x 32 filters over one window, 256 threads", 1},
+    {4, 2, 4, 0, 3, "16 rows x 32 cols x 3 x 64 filters over one window, 256 threads", 1},
+    {4, 1, 4, 0, 1, "4 rows x 128 cols x 32 filters, 256 threads, one workgroup per tile", 4},
+    {4, 1, 8, 0, 1, "4 rows x 256 cols x 32 filters, 512 threads, one workgroup per tile", 8},
+    {4, 1, 4, 0, 3, "4 rows x 128 cols x 3 x 32 filters over one window, 256 threads", 4},
 };
 constexpr int N_TILE_CFGS = (int)(sizeof(TILE_CFGS) / sizeof(TILE_CFGS[0]));
 constexpr int MAX_BB = 2;                 // most filter blocks per tile over TILE_CFGS
@@ -81,8 +90,11 @@ struct ModeData {
         int n_tiles = 0;
         std::vector<std::array<int, 4>> lvl;   // (image, level, begin, end)
         std::vector<std::array<int, 2>> chunk; // (begin, end) into dTilesChunk per chunk
+        // per order list (cost, level, chunk): runs of tiles whose groups have
+        // the same filter height, (begin, end, height, most K-steps)
+        std::array<std::vector<std::array<int, 4>>, 3> runs;
     };
-    std::map<std::array<int, 3>, TileSet> tilesets;
+    std::map<std::array<int, 4>, TileSet> tilesets;
     // CP mode: chunk table and packed factors, first chunk of every group,
     // and its tiles (cost order, (image, level) order, chunk order)
     CpChunk* dCpChunks = nullptr;
@@ -839,12 +851,12 @@ void build_groups(dpmt_ctx* c) {
 }
 
 void add_tiles(std::vector<CorrTile>& tiles, const GroupDesc& gd, int group, int64_t z_cell,
-               int64_t out_off, int rng, int H, int W, int rows, int bb, int nfb) {
+               int64_t out_off, int rng, int H, int W, int rows, int cols, int bb, int nfb) {
     const int Ho = H - gd.h + 1, Wo = W - gd.w + 1;
     if (Ho <= 0 || Wo <= 0) return;
     const int nblk = (gd.ng + 31) / 32;
     for (int y0 = 0; y0 < Ho; y0 += rows)
-        for (int x0 = 0; x0 < Wo; x0 += 32)
+        for (int x0 = 0; x0 < Wo; x0 += cols)
             for (int fb = 0; fb < nblk; fb += bb * nfb) {
                 CorrTile t{};
                 t.z_cell = z_cell;
@@ -868,7 +880,7 @@ void add_tiles(std::vector<CorrTile>& tiles, const GroupDesc& gd, int group, int
 dpmt_status prepare_tiles(dpmt_ctx* c, dpmt_mode mode, ModeData::TileSet** out) {
     ModeData& md = c->modes[mode];
     const TileCfg& tc = TILE_CFGS[md.tile_cfg];
-    const std::array<int, 3> key{tc.ty * tc.wy, tc.bb, tc.nfb};
+    const std::array<int, 4> key{tc.ty * (tc.wy / tc.wx), tc.bb, tc.nfb, 32 * tc.wx};
     ModeData::TileSet& ts = md.tilesets[key];
     *out = &ts;
     if (ts.plan_id == c->plan_id && (ts.dTiles || ts.n_tiles == 0)) return DPMT_OK;
@@ -881,7 +893,7 @@ dpmt_status prepare_tiles(dpmt_ctx* c, dpmt_mode mode, ModeData::TileSet** out) 
         const LevelInfo& lv = c->pyr[k.img][k.level];
         const size_t b0 = tiles.size();
         add_tiles(tiles, md.groups[k.group], k.group, lv.cell_offset, kv.second.off,
-                  (int)kv.second.rng, lv.rows, lv.cols, key[0], key[1], key[2]);
+                  (int)kv.second.rng, lv.rows, lv.cols, key[0], key[3], key[1], key[2]);
         if (tiles.size() == b0) continue;
         if (!ts.lvl.empty() && ts.lvl.back()[0] == k.img && ts.lvl.back()[1] == k.level)
             ts.lvl.back()[3] = (int)tiles.size();
@@ -889,6 +901,21 @@ dpmt_status prepare_tiles(dpmt_ctx* c, dpmt_mode mode, ModeData::TileSet** out) 
             ts.lvl.push_back({k.img, k.level, (int)b0, (int)tiles.size()});
     }
     if (tiles.size() > (size_t)INT32_MAX) return fail(c, DPMT_E_UNSUPPORTED, "batch too large for one launch");
+    // runs of consecutive tiles with equal filter height in one order list
+    auto height_runs = [&](const std::vector<CorrTile>& tl) {
+        std::vector<std::array<int, 4>> r;
+        for (size_t i = 0; i < tl.size(); ++i) {
+            const GroupDesc& gd = md.groups[tl[i].group];
+            if (!r.empty() && r.back()[2] == gd.h && r.back()[1] == (int)i) {
+                r.back()[1] = (int)i + 1;
+                r.back()[3] = std::max(r.back()[3], gd.S);
+            } else {
+                r.push_back({(int)i, (int)i + 1, gd.h, gd.S});
+            }
+        }
+        return r;
+    };
+    ts.runs[1] = height_runs(tiles);
     HIP_TRY(c, upload(&ts.dTilesLvl, tiles), "upload tiles");
     {   // chunk order for the overlapped strategy, most expensive first within a chunk
         std::vector<std::pair<int, CorrTile>> keyed;
@@ -905,24 +932,30 @@ dpmt_status prepare_tiles(dpmt_ctx* c, dpmt_mode mode, ModeData::TileSet** out) 
             if (a.first != b.first) return a.first < b.first;
             const GroupDesc& ga = md.groups[a.second.group];
             const GroupDesc& gb = md.groups[b.second.group];
+            if (ga.h != gb.h) return ga.h > gb.h;
             return (int64_t)ga.h * ga.S > (int64_t)gb.h * gb.S;
         });
         std::vector<CorrTile> ct;
         ct.reserve(keyed.size());
+        // within a chunk, taller filters first, then the longer K loops
         ts.chunk.assign(std::max(c->n_chunks, 1), {0, 0});
         for (size_t i = 0; i < keyed.size(); ++i) {
             if (i == 0 || keyed[i].first != keyed[i - 1].first) ts.chunk[keyed[i].first][0] = (int)i;
             ts.chunk[keyed[i].first][1] = (int)i + 1;
             ct.push_back(keyed[i].second);
         }
+        ts.runs[2] = height_runs(ct);
         HIP_TRY(c, upload(&ts.dTilesChunk, ct), "upload tiles");
     }
-    // most expensive groups first so that the tail of the batched launch is short tiles
+    // taller filters first, then the most expensive groups, so that the tail of
+    // the batched launch is short tiles and every filter height is one run
     std::stable_sort(tiles.begin(), tiles.end(), [&](const CorrTile& a, const CorrTile& b) {
         const GroupDesc& ga = md.groups[a.group];
         const GroupDesc& gb = md.groups[b.group];
+        if (ga.h != gb.h) return ga.h > gb.h;
         return (int64_t)ga.h * ga.S > (int64_t)gb.h * gb.S;
     });
+    ts.runs[0] = height_runs(tiles);
     HIP_TRY(c, upload(&ts.dTiles, tiles), "upload tiles");
     ts.n_tiles = (int)tiles.size();
     ts.plan_id = c->plan_id;
@@ -1081,12 +1114,12 @@ dpmt_status score_prepare(dpmt_ctx* c, dpmt_mode mode, hipStream_t st) {
 ModeData::TileSet& current_tiles(dpmt_ctx* c, dpmt_mode mode) {
     ModeData& md = c->modes[mode];
     const TileCfg& tc = TILE_CFGS[md.tile_cfg];
-    return md.tilesets[{tc.ty * tc.wy, tc.bb, tc.nfb}];
+    return md.tilesets[{tc.ty * (tc.wy / tc.wx), tc.bb, tc.nfb, 32 * tc.wx}];
 }
 
 CorrLaunch corr_launch(const ModeData& md) {
     const TileCfg& tc = TILE_CFGS[md.tile_cfg];
-    return CorrLaunch{md.kind, md.pk, tc.ty, tc.bb, tc.wy, tc.persistent};
+    return CorrLaunch{md.kind, md.pk, tc.ty, tc.bb, tc.wy, tc.persistent, tc.wx, 0};
 }
 
 // Correlation of the tiles [b, e) of one order of the current tile set
@@ -1103,8 +1136,18 @@ hipError_t corr_tiles(dpmt_ctx* c, dpmt_mode mode, int order, int b, int e, cons
     ModeData::TileSet& ts = current_tiles(c, mode);
     const CorrTile* t = order == 0 ? ts.dTiles : order == 1 ? ts.dTilesLvl : ts.dTilesChunk;
     const void* Z = is_tensor(mode) ? c->d_Z : static_cast<const void*>(X);
-    return launch_corr(corr_launch(md), t + b, e - b, md.dGroups, Z, md.dG, md.dTk, c->d_resp, c->d_rkeys,
-                       c->n_slots, md.max_h, md.max_S, st);
+    // one launch per run of equal filter height: the kernel built for that
+    // height alone, with the LDS that height needs
+    CorrLaunch cl = corr_launch(md);
+    for (const auto& r : ts.runs[order]) {
+        const int rb = std::max(b, r[0]), re = std::min(e, r[1]);
+        if (rb >= re) continue;
+        cl.hs = r[2];
+        const hipError_t err = launch_corr(cl, t + rb, re - rb, md.dGroups, Z, md.dG, md.dTk, c->d_resp,
+                                           c->d_rkeys, c->n_slots, r[2], r[3], st);
+        if (err != hipSuccess) return err;
+    }
+    return hipSuccess;
 }
 
 int n_corr_tiles(dpmt_ctx* c, dpmt_mode mode) {
@@ -2043,7 +2086,7 @@ dpmt_status dpmt_set_tile_config(dpmt_ctx* c, dpmt_mode mode, int32_t config) {
     const TileCfg& tc = TILE_CFGS[config];
     int max_h = 0;
     for (const auto& sh : c->shapes) max_h = std::max(max_h, sh.h);
-    if (!corr_shape_supported(tc.ty, tc.bb, tc.wy, max_h))
+    if (!corr_shape_supported(tc.ty, tc.bb, tc.wy, tc.wx, max_h))
         return fail(c, DPMT_E_UNSUPPORTED, "tile configuration does not support filters of " + std::to_string(max_h) + " rows");
     c->modes[mode].tile_cfg = config;
     return DPMT_OK;
@@ -2074,7 +2117,7 @@ dpmt_status dpmt_autotune(dpmt_ctx* c, dpmt_mode mode, const float* features_dev
     for (int k = 0; k < N_TILE_CFGS && err == hipSuccess; ++k) {
         if (ms_out) ms_out[k] = -1.f;
         const TileCfg& tc = TILE_CFGS[k];
-        if (!corr_shape_supported(tc.ty, tc.bb, tc.wy, max_h)) continue;
+        if (!corr_shape_supported(tc.ty, tc.bb, tc.wy, tc.wx, max_h)) continue;
         if (mode == DPMT_CP_FP32 && k != 0) continue;
         md.tile_cfg = k;
         if ((s = score_prepare(c, mode, st)) != DPMT_OK) break;
@@ -2177,7 +2220,7 @@ dpmt_status dpmt_level_responses(dpmt_ctx* c, dpmt_mode mode, const float* featu
             add_cp_tiles(cp_tiles, hg, md.cp_chunk0[g], lv.cell_offset, blk_total, -1, lv.rows, lv.cols);
         } else {
             const GroupDesc& gd = md.groups[g];
-            add_tiles(tiles, gd, (int)g, 0, blk_total, -1, lv.rows, lv.cols, 16, 2, 1);
+            add_tiles(tiles, gd, (int)g, 0, blk_total, -1, lv.rows, lv.cols, 16, 32, 2, 1);
             max_S = std::max(max_S, gd.S);
         }
         gblocks.push_back({(int)g, blk_total, Ho, Wo, pitch_of(Wo)});
@@ -2214,7 +2257,7 @@ dpmt_status dpmt_level_responses(dpmt_ctx* c, dpmt_mode mode, const float* featu
         if (e == hipSuccess) e = launch_cp_corr(dcp, (int)cp_tiles.size(), md.dCpChunks, features_dev, md.dCpFac, dblk, nullptr, 0, nullptr, lds, st);
     } else {
         if (e == hipSuccess) e = upload(&dtiles, tiles);
-        CorrLaunch cl{md.kind, md.pk, 4, 2, 4, 0};
+        CorrLaunch cl{md.kind, md.pk, 4, 2, 4, 0, 1, 0};
         if (e == hipSuccess) e = launch_corr(cl, dtiles, (int)tiles.size(), md.dGroups, Zsrc, md.dG, md.dTk, dblk, nullptr, 0, max_h, max_S, st);
     }
     for (const auto& gb : gblocks) {

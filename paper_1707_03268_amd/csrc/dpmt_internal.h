@@ -139,12 +139,15 @@ struct CorrLaunch {
     Packing pk;
     int ty;            // output rows per wave
     int bb;            // 32-filter blocks per wave
-    int wy;            // waves per workgroup (stacked along rows)
+    int wy;            // waves per workgroup
     int persistent;    // 0: one workgroup per tile; 1: resident grid striding the tiles
+    int wx;            // of them side by side along x (wy / wx stacked along rows)
+    int hs;            // every tile has filters of exactly hs rows (6, 7, 8), or 0: any
 };
-// Tile shapes the correlation kernel is built for (ty, bb, wy); filters taller
-// than 8 rows only with (4, 2, 4).
-bool corr_shape_supported(int ty, int bb, int wy, int max_h);
+// Tile shapes the correlation kernel is built for (ty, bb, wy, wx); filters
+// taller than 8 rows only with (4, 2, 4, 1).  A workgroup tile covers
+// ty * wy / wx output rows x 32 * wx output columns.
+bool corr_shape_supported(int ty, int bb, int wy, int wx, int max_h);
 
 // Placement kernel geometry.  A block owns PLACE_CW consecutive root columns
 // of one score map; its LDS holds the score accumulator, the row-pass tile of

@@ -190,13 +190,14 @@ __device__ __forceinline__ typename FragT<KIND>::type lds_frag(const char* p, in
 // pitch is a multiple of 4, so a run that starts inside the map ends inside
 // the pitch).  The value range of every plane over its valid positions goes to
 // the range slots.
-template <CorrKind KIND, int TY, int BB, int WY>
+template <CorrKind KIND, int TY, int BB, int WY, int WX>
 __device__ __forceinline__ void corr_epilogue(const CorrTile& t, const GroupDesc& g, int fbb,
                                               const v16f (&acc)[TY][BB],
                                               const float* __restrict__ tk, float* __restrict__ out,
                                               int* __restrict__ rmax, int* __restrict__ rmin) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int p = lane & 31, j = lane >> 5;
+    const int wr = wv / WX, x0 = t.x0 + 32 * (wv % WX);   // the wave's rows and columns
     float vmax[BB], vmin[BB];
 #pragma unroll
     for (int b = 0; b < BB; ++b) {
@@ -205,17 +206,17 @@ __device__ __forceinline__ void corr_epilogue(const CorrTile& t, const GroupDesc
     }
 #pragma unroll
     for (int i = 0; i < TY; ++i) {
-        const int y = t.y0 + wv * TY + i;
+        const int y = t.y0 + wr * TY + i;
         if (y >= t.Ho) continue;
 #pragma unroll
         for (int b = 0; b < BB; ++b) {
             const int f = (fbb + b) * 32 + p;
             if (f >= g.ng) continue;
-            float* orow = out + t.out_off + ((int64_t)f * t.Ho + y) * t.ld + t.x0 + 4 * j;
+            float* orow = out + t.out_off + ((int64_t)f * t.Ho + y) * t.ld + x0 + 4 * j;
             const float sc = (KIND == CORR_FP8) ? tk[g.t_off + f] : 1.f;
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
-                const int x = t.x0 + 8 * m + 4 * j;
+                const int x = x0 + 8 * m + 4 * j;
                 if (x >= t.Wo) continue;
                 float4 v;
                 v.x = acc[i][b][4 * m + 0] * sc;
@@ -252,7 +253,7 @@ __device__ __forceinline__ void corr_epilogue(const CorrTile& t, const GroupDesc
 // HS > 0: the tile's filters have exactly HS rows, and the filter-row loop is
 // fully unrolled over a static ring of A fragments (no register rotation, exact
 // LDS waits); HS = 0: any height up to HMAX with a rolled loop.
-template <CorrKind KIND, int PB, int TY, int BB, int WY, int HMAX, int HS>
+template <CorrKind KIND, int PB, int TY, int BB, int WY, int WX, int HMAX, int HS>
 __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __restrict__ groups,
                                           const char* __restrict__ Z, const char* __restrict__ G,
                                           const float* __restrict__ tk, float* __restrict__ out,
@@ -260,7 +261,8 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
                                           int cell_bytes, int Q, int win_bytes) {
     extern __shared__ __align__(16) char smem[];
     constexpr int NT = 64 * WY;
-    constexpr int TYWG = TY * WY;
+    static_assert(WY % WX == 0, "waves along x must divide the workgroup");
+    constexpr int TYWG = TY * (WY / WX);           // output rows of the workgroup tile
     constexpr int CH = PB >= 16 ? 16 : 8;          // window copy granule
     constexpr int FB = FragT<KIND>::bytes;         // fragment bytes per lane
     constexpr int KS = 2 * FB;                     // flattened row bytes per K-step
@@ -271,7 +273,7 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
 
     const GroupDesc g = groups[t.group];
     const int h = HS > 0 ? HS : g.h, S = g.S;
-    const int WC = 31 + (KS * S) / PB;             // window cells per row
+    const int WC = 32 * WX - 1 + (KS * S) / PB;    // window cells per row
     const int pitch = WC * PB;
     const int nrows = TYWG + h - 1;
     char* win = smem;
@@ -480,7 +482,7 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
         }
 
         const u32x4* gb = DMA ? gbuf(bi) : ((gs & 1) ? gbuf1 : gbuf0);
-        const char* abase = win + (wv * TY) * pitch + p * PB + KS * s + FB * j;
+        const char* abase = win + ((wv / WX) * TY) * pitch + (32 * (wv % WX) + p) * PB + KS * s + FB * j;
         const char* gbb = reinterpret_cast<const char*>(gb) + lane * FB;
         if constexpr (HS > 0) {
             // window row n + i feeds output row i at filter row n; the TY live
@@ -544,7 +546,7 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
             for (int k = 0; k < PFMAX; ++k) nb[pf_dst[k]] = pf[k];
         }
         if (step == total - 1) {
-            corr_epilogue<KIND, TY, BB, WY>(t, g, t.fb0 + fbi * BB, acc, tk, out, rmax, rmin);
+            corr_epilogue<KIND, TY, BB, WY, WX>(t, g, t.fb0 + fbi * BB, acc, tk, out, rmax, rmin);
 #pragma unroll
             for (int i = 0; i < TY; ++i)
 #pragma unroll
@@ -560,8 +562,11 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
 }
 
 // One workgroup per tile (grid = tiles), or a persistent grid that strides
-// over the cost-sorted tile list; both produce the same bits.
-template <CorrKind KIND, int PB, int TY, int BB, int WY, int HMAX>
+// over the cost-sorted tile list; both produce the same bits.  HSO > 0: every
+// tile's filters have HSO rows, and only that unrolled body is built (a
+// kernel with one body needs far fewer registers than one that can take any
+// height, so more wavefronts fit each SIMD).
+template <CorrKind KIND, int PB, int TY, int BB, int WY, int WX, int HMAX, int HSO>
 __global__ __launch_bounds__(64 * WY) __attribute__((amdgpu_waves_per_eu((HMAX <= 8 && KIND != CORR_FP8) ? 2 : 1))) void corr_kernel(const CorrTile* __restrict__ tiles, int n_tiles,
                                                        const GroupDesc* __restrict__ groups,
                                                        const char* __restrict__ Z,
@@ -573,19 +578,23 @@ __global__ __launch_bounds__(64 * WY) __attribute__((amdgpu_waves_per_eu((HMAX <
                                                        int Q, int win_bytes) {
     for (int i = blockIdx.x; i < n_tiles; i += gridDim.x) {
         const CorrTile t = tiles[i];
-        const int h = groups[t.group].h;
-        // the DPM filter heights get unrolled bodies where that costs no
-        // occupancy (FP8 fragments and 64-filter tiles of 32-byte planes would
-        // need too many registers)
-        constexpr bool UNROLL = corr_unrolls(KIND, PB, BB, HMAX);
-        if (UNROLL && h == 6)
-            corr_tile<KIND, PB, TY, BB, WY, HMAX, 6>(t, groups, Z, G, tk, out, rmax, rmin, cell_bytes, Q, win_bytes);
-        else if (UNROLL && h == 7)
-            corr_tile<KIND, PB, TY, BB, WY, HMAX, 7>(t, groups, Z, G, tk, out, rmax, rmin, cell_bytes, Q, win_bytes);
-        else if (UNROLL && h == 8)
-            corr_tile<KIND, PB, TY, BB, WY, HMAX, 8>(t, groups, Z, G, tk, out, rmax, rmin, cell_bytes, Q, win_bytes);
-        else
-            corr_tile<KIND, PB, TY, BB, WY, HMAX, 0>(t, groups, Z, G, tk, out, rmax, rmin, cell_bytes, Q, win_bytes);
+        if constexpr (HSO > 0) {
+            corr_tile<KIND, PB, TY, BB, WY, WX, HMAX, HSO>(t, groups, Z, G, tk, out, rmax, rmin, cell_bytes, Q, win_bytes);
+        } else {
+            const int h = groups[t.group].h;
+            // the DPM filter heights get unrolled bodies where that costs no
+            // occupancy (FP8 fragments and 64-filter tiles of 32-byte planes
+            // would need too many registers)
+            constexpr bool UNROLL = corr_unrolls(KIND, PB, BB, HMAX);
+            if (UNROLL && h == 6)
+                corr_tile<KIND, PB, TY, BB, WY, WX, HMAX, 6>(t, groups, Z, G, tk, out, rmax, rmin, cell_bytes, Q, win_bytes);
+            else if (UNROLL && h == 7)
+                corr_tile<KIND, PB, TY, BB, WY, WX, HMAX, 7>(t, groups, Z, G, tk, out, rmax, rmin, cell_bytes, Q, win_bytes);
+            else if (UNROLL && h == 8)
+                corr_tile<KIND, PB, TY, BB, WY, WX, HMAX, 8>(t, groups, Z, G, tk, out, rmax, rmin, cell_bytes, Q, win_bytes);
+            else
+                corr_tile<KIND, PB, TY, BB, WY, WX, HMAX, 0>(t, groups, Z, G, tk, out, rmax, rmin, cell_bytes, Q, win_bytes);
+        }
         if (i + (int)gridDim.x < n_tiles) __syncthreads();   // LDS reused by the next tile
     }
 }
@@ -593,15 +602,16 @@ __global__ __launch_bounds__(64 * WY) __attribute__((amdgpu_waves_per_eu((HMAX <
 static int frag_bytes(CorrKind k) { return k == CORR_FP8 ? 32 : 16; }
 
 // LDS of a correlation launch whose groups have at most max_h filter rows and
-// S K-steps: the window of max_h - 1 + TY*WY rows, plus the filter staging of
-// the tallest group height the kernel may see.  An unrolled group of h <= 8
-// rows stages CORR_NBUF chunks of h rows, a rolled one 2 chunks of h rows;
-// with max_h > 8 the HMAX = 16 kernel runs both kinds, so the staging takes
-// the larger of 2 max_h and CORR_NBUF min(max_h, 8) rows.
+// S K-steps: the window of max_h - 1 + ty * wy / wx rows of 32 * wx - 1 + S
+// steps of cells, plus the filter staging of the tallest group height the
+// kernel may see.  An unrolled group of h <= 8 rows stages CORR_NBUF chunks of
+// h rows, a rolled one 2 chunks of h rows; with max_h > 8 the HMAX = 16
+// kernel runs both kinds, so the staging takes the larger of 2 max_h and
+// CORR_NBUF min(max_h, 8) rows.
 size_t corr_lds_bytes(const CorrLaunch& cfg, int max_h, int S) {
     const int FB = frag_bytes(cfg.kind);
-    const int WC = 31 + (2 * FB * S) / cfg.pk.PB;
-    const size_t win = (size_t)(cfg.ty * cfg.wy + max_h - 1) * WC * cfg.pk.PB;
+    const int WC = 32 * cfg.wx - 1 + (2 * FB * S) / cfg.pk.PB;
+    const size_t win = (size_t)(cfg.ty * (cfg.wy / cfg.wx) + max_h - 1) * WC * cfg.pk.PB;
     const size_t winal = (win + 1023) & ~size_t(1023);   // whole 1 KB units (window DMA)
     const int hmax = max_h <= 8 ? 8 : CORR_MAX_H;         // the kernel instance launch_corr_t picks
     const bool unroll = corr_unrolls(cfg.kind, cfg.pk.PB, cfg.bb, hmax) && max_h >= 6;
@@ -609,18 +619,18 @@ size_t corr_lds_bytes(const CorrLaunch& cfg, int max_h, int S) {
     return winal + (size_t)rows * cfg.bb * 64 * FB;
 }
 
-template <CorrKind KIND, int PB, int TY, int BB, int WY, int HMAX>
-static hipError_t launch_corr_h(const CorrLaunch& cfg, const CorrTile* tiles, int n_tiles,
+template <CorrKind KIND, int PB, int TY, int BB, int WY, int WX, int HMAX, int HSO>
+static hipError_t launch_corr_k(const CorrLaunch& cfg, const CorrTile* tiles, int n_tiles,
                                 const GroupDesc* groups, const void* Z, const void* G,
                                 const float* tk, float* out, int* rkeys, int64_t n_slots,
                                 int cell_bytes, int max_h, int max_S, hipStream_t st) {
     const size_t lds = corr_lds_bytes(cfg, max_h, max_S);
     const int FB = FragT<KIND>::bytes;
-    const int WC = 31 + (2 * FB * max_S) / PB;
-    const size_t win = (size_t)(TY * WY + max_h - 1) * WC * PB;
+    const int WC = 32 * WX - 1 + (2 * FB * max_S) / PB;
+    const size_t win = (size_t)(TY * (WY / WX) + max_h - 1) * WC * PB;
     const int win_bytes = (int)((win + 1023) & ~size_t(1023));
     if (lds > 160 * 1024) return hipErrorInvalidValue;
-    auto kern = corr_kernel<KIND, PB, TY, BB, WY, HMAX>;
+    auto kern = corr_kernel<KIND, PB, TY, BB, WY, WX, HMAX, HSO>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -641,20 +651,43 @@ static hipError_t launch_corr_h(const CorrLaunch& cfg, const CorrTile* tiles, in
     return hipGetLastError();
 }
 
+// Tiles whose filters all have 6, 7 or 8 rows go to a kernel built for that
+// height alone when the kind unrolls it; others to the kernel that takes any
+// height up to HMAX.
+template <CorrKind KIND, int PB, int TY, int BB, int WY, int WX, int HMAX>
+static hipError_t launch_corr_h(const CorrLaunch& cfg, const CorrTile* tiles, int n_tiles,
+                                const GroupDesc* groups, const void* Z, const void* G,
+                                const float* tk, float* out, int* rkeys, int64_t n_slots,
+                                int cell_bytes, int max_h, int max_S, hipStream_t st) {
+    if constexpr (HMAX == 8 && corr_unrolls(KIND, PB, BB, 8)) {
+        if (cfg.hs == 6 && max_h == 6)
+            return launch_corr_k<KIND, PB, TY, BB, WY, WX, HMAX, 6>(cfg, tiles, n_tiles, groups, Z, G, tk, out,
+                                                                    rkeys, n_slots, cell_bytes, max_h, max_S, st);
+        if (cfg.hs == 7 && max_h == 7)
+            return launch_corr_k<KIND, PB, TY, BB, WY, WX, HMAX, 7>(cfg, tiles, n_tiles, groups, Z, G, tk, out,
+                                                                    rkeys, n_slots, cell_bytes, max_h, max_S, st);
+        if (cfg.hs == 8 && max_h == 8)
+            return launch_corr_k<KIND, PB, TY, BB, WY, WX, HMAX, 8>(cfg, tiles, n_tiles, groups, Z, G, tk, out,
+                                                                    rkeys, n_slots, cell_bytes, max_h, max_S, st);
+    }
+    return launch_corr_k<KIND, PB, TY, BB, WY, WX, HMAX, 0>(cfg, tiles, n_tiles, groups, Z, G, tk, out, rkeys,
+                                                            n_slots, cell_bytes, max_h, max_S, st);
+}
+
 // Filters of at most 8 rows (every DPM root and part shape) get a kernel whose
 // chunk prefetch needs half the registers; taller filters only the default tile.
-template <CorrKind KIND, int PB, int TY, int BB, int WY>
+template <CorrKind KIND, int PB, int TY, int BB, int WY, int WX>
 static hipError_t launch_corr_t(const CorrLaunch& cfg, const CorrTile* tiles, int n_tiles,
                                 const GroupDesc* groups, const void* Z, const void* G,
                                 const float* tk, float* out, int* rkeys, int64_t n_slots,
                                 int cell_bytes, int max_h, int max_S, hipStream_t st) {
     if (max_h <= 8)
-        return launch_corr_h<KIND, PB, TY, BB, WY, 8>(cfg, tiles, n_tiles, groups, Z, G, tk, out,
-                                                      rkeys, n_slots, cell_bytes, max_h, max_S, st);
-    if constexpr (TY == 4 && BB == 2 && WY == 4)
-        return launch_corr_h<KIND, PB, TY, BB, WY, CORR_MAX_H>(cfg, tiles, n_tiles, groups, Z, G, tk,
-                                                               out, rkeys, n_slots, cell_bytes,
-                                                               max_h, max_S, st);
+        return launch_corr_h<KIND, PB, TY, BB, WY, WX, 8>(cfg, tiles, n_tiles, groups, Z, G, tk, out,
+                                                          rkeys, n_slots, cell_bytes, max_h, max_S, st);
+    if constexpr (TY == 4 && BB == 2 && WY == 4 && WX == 1)
+        return launch_corr_h<KIND, PB, TY, BB, WY, WX, CORR_MAX_H>(cfg, tiles, n_tiles, groups, Z, G, tk,
+                                                                   out, rkeys, n_slots, cell_bytes,
+                                                                   max_h, max_S, st);
     return hipErrorInvalidValue;
 }
 
@@ -663,22 +696,25 @@ static hipError_t launch_corr_p(const CorrLaunch& cfg, const CorrTile* tiles, in
                                 const GroupDesc* groups, const void* Z, const void* G,
                                 const float* tk, float* out, int* rkeys, int64_t n_slots,
                                 int cell_bytes, int max_h, int max_S, hipStream_t st) {
-#define DPMT_SHAPE(A, B, C)                                                                      \
-    if (cfg.ty == A && cfg.bb == B && cfg.wy == C)                                               \
-        return launch_corr_t<KIND, PB, A, B, C>(cfg, tiles, n_tiles, groups, Z, G, tk, out, rkeys, \
-                                                n_slots, cell_bytes, max_h, max_S, st);
-    DPMT_SHAPE(4, 2, 4)
-    DPMT_SHAPE(2, 2, 4)
-    DPMT_SHAPE(4, 1, 4)
+#define DPMT_SHAPE(A, B, C, D)                                                                       \
+    if (cfg.ty == A && cfg.bb == B && cfg.wy == C && cfg.wx == D)                                    \
+        return launch_corr_t<KIND, PB, A, B, C, D>(cfg, tiles, n_tiles, groups, Z, G, tk, out, rkeys, \
+                                                   n_slots, cell_bytes, max_h, max_S, st);
+    DPMT_SHAPE(4, 2, 4, 1)
+    DPMT_SHAPE(2, 2, 4, 1)
+    DPMT_SHAPE(4, 1, 4, 1)
+    DPMT_SHAPE(4, 1, 4, 4)
+    DPMT_SHAPE(4, 1, 8, 8)
 #undef DPMT_SHAPE
     return hipErrorInvalidValue;
 }
 
-bool corr_shape_supported(int ty, int bb, int wy, int max_h) {
-    const bool listed = (ty == 4 && bb == 2 && wy == 4) || (ty == 2 && bb == 2 && wy == 4) ||
-                        (ty == 4 && bb == 1 && wy == 4);
+bool corr_shape_supported(int ty, int bb, int wy, int wx, int max_h) {
+    const bool listed = (ty == 4 && bb == 2 && wy == 4 && wx == 1) || (ty == 2 && bb == 2 && wy == 4 && wx == 1) ||
+                        (ty == 4 && bb == 1 && wy == 4 && wx == 1) || (ty == 4 && bb == 1 && wy == 4 && wx == 4) ||
+                        (ty == 4 && bb == 1 && wy == 8 && wx == 8);
     if (!listed || max_h > CORR_MAX_H) return false;
-    return max_h <= 8 || (ty == 4 && bb == 2 && wy == 4);
+    return max_h <= 8 || (ty == 4 && bb == 2 && wy == 4 && wx == 1);
 }
 
 hipError_t launch_corr(const CorrLaunch& cfg, const CorrTile* tiles, int n_tiles,
@@ -686,7 +722,7 @@ hipError_t launch_corr(const CorrLaunch& cfg, const CorrTile* tiles, int n_tiles
                        float* out, int* rkeys, int64_t n_slots, int max_h, int max_S,
                        hipStream_t st) {
     if (n_tiles <= 0) return hipSuccess;
-    if (!corr_shape_supported(cfg.ty, cfg.bb, cfg.wy, max_h)) return hipErrorInvalidValue;
+    if (!corr_shape_supported(cfg.ty, cfg.bb, cfg.wy, cfg.wx, max_h)) return hipErrorInvalidValue;
     const int cb = cfg.pk.RP * cfg.pk.esz;
 #define DPMT_CORR(K, P) \
     case P: return launch_corr_p<K, P>(cfg, tiles, n_tiles, groups, Z, G, tk, out, rkeys, n_slots, cb, max_h, max_S, st);
