@@ -46,6 +46,8 @@ constexpr TileCfg TILE_CFGS[] = {
     {4, 1, 4, 0, 1, "4 rows x 128 cols x 32 filters, 256 threads, one workgroup per tile", 4},
     {4, 1, 8, 0, 1, "4 rows x 256 cols x 32 filters, 512 threads, one workgroup per tile", 8},
     {4, 1, 4, 0, 3, "4 rows x 128 cols x 3 x 32 filters over one window, 256 threads", 4},
+    {4, 1, 8, 0, 1, "8 rows x 128 cols x 32 filters, 512 threads, one workgroup per tile", 4},
+    {4, 1, 8, 0, 3, "8 rows x 128 cols x 3 x 32 filters over one window, 512 threads", 4},
 };
 constexpr int N_TILE_CFGS = (int)(sizeof(TILE_CFGS) / sizeof(TILE_CFGS[0]));
 constexpr int MAX_BB = 2;                 // most filter blocks per tile over TILE_CFGS

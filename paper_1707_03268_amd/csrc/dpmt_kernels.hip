@@ -127,6 +127,13 @@ hipError_t launch_project(bool bf16, const float* X, int64_t n_cells, const floa
 constexpr int CORR_MAX_H = 16;
 constexpr int CORR_NBUF = 3;                   // filter-chunk staging depth of the unrolled tiles
 
+// Filter-chunk buffers of a tile: CORR_NBUF with direct global-to-LDS
+// staging, two (plain double buffering) for the wide tiles, whose windows
+// take the LDS, and for staging through registers.
+__host__ __device__ constexpr int corr_chunk_buffers(bool dma, int wx) {
+    return dma && wx == 1 ? CORR_NBUF : 2;
+}
+
 // Whether a correlation instance gives the 6-, 7- and 8-row filters fully
 // unrolled bodies (staged CORR_NBUF chunks deep); host and device agree on it.
 __host__ __device__ constexpr bool corr_unrolls(CorrKind kind, int PB, int BB, int HMAX) {
@@ -285,7 +292,7 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
     // units of a chunk.  Other tiles stage through registers, two buffers.
     constexpr bool DMA = HS > 0 && FragT<KIND>::bytes == 16;
     constexpr int UPW = DMA ? (BB * HS + WY - 1) / WY : 1;
-    constexpr int NB = DMA ? CORR_NBUF : 2;
+    constexpr int NB = corr_chunk_buffers(DMA, WX);
     static_assert(!DMA || (NB - 2) * UPW <= 15, "outstanding chunk loads must fit the vmcnt immediate");
     auto gbuf = [&](int k) { return gbuf0 + k * (BB * h * CU); };
 
@@ -615,7 +622,7 @@ size_t corr_lds_bytes(const CorrLaunch& cfg, int max_h, int S) {
     const size_t winal = (win + 1023) & ~size_t(1023);   // whole 1 KB units (window DMA)
     const int hmax = max_h <= 8 ? 8 : CORR_MAX_H;         // the kernel instance launch_corr_t picks
     const bool unroll = corr_unrolls(cfg.kind, cfg.pk.PB, cfg.bb, hmax) && max_h >= 6;
-    const int rows = std::max(2 * max_h, unroll ? CORR_NBUF * std::min(max_h, 8) : 0);
+    const int rows = std::max(2 * max_h, unroll ? corr_chunk_buffers(true, cfg.wx) * std::min(max_h, 8) : 0);
     return winal + (size_t)rows * cfg.bb * 64 * FB;
 }
 
@@ -705,6 +712,7 @@ static hipError_t launch_corr_p(const CorrLaunch& cfg, const CorrTile* tiles, in
     DPMT_SHAPE(4, 1, 4, 1)
     DPMT_SHAPE(4, 1, 4, 4)
     DPMT_SHAPE(4, 1, 8, 8)
+    DPMT_SHAPE(4, 1, 8, 4)
 #undef DPMT_SHAPE
     return hipErrorInvalidValue;
 }
@@ -712,7 +720,7 @@ static hipError_t launch_corr_p(const CorrLaunch& cfg, const CorrTile* tiles, in
 bool corr_shape_supported(int ty, int bb, int wy, int wx, int max_h) {
     const bool listed = (ty == 4 && bb == 2 && wy == 4 && wx == 1) || (ty == 2 && bb == 2 && wy == 4 && wx == 1) ||
                         (ty == 4 && bb == 1 && wy == 4 && wx == 1) || (ty == 4 && bb == 1 && wy == 4 && wx == 4) ||
-                        (ty == 4 && bb == 1 && wy == 8 && wx == 8);
+                        (ty == 4 && bb == 1 && wy == 8 && wx == 8) || (ty == 4 && bb == 1 && wy == 8 && wx == 4);
     if (!listed || max_h > CORR_MAX_H) return false;
     return max_h <= 8 || (ty == 4 && bb == 2 && wy == 4 && wx == 1);
 }
