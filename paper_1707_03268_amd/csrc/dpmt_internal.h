@@ -225,8 +225,12 @@ hipError_t launch_place(const MapDesc* maps, const MapPart* parts, const int2* b
                         hipStream_t st);
 hipError_t launch_planes_to_maps(const float* planes, int ng, int Ho, int Wo, int ld,
                                  const int64_t* dst_off, float* out, hipStream_t st);
-// Detections: counts holds det_blocks(n) int64 of scratch.
-constexpr int64_t det_blocks(int64_t n) { return (n + 1023) / 1024; }
+// Detections: counts holds det_blocks(n) int64 of scratch: one count per
+// block of 1024 positions, then one sum per segment of DET_SEG such counts.
+constexpr int64_t DET_SEG = 1024;
+constexpr int64_t det_blocks(int64_t n) {
+    return (n + 1023) / 1024 + ((n + 1023) / 1024 + DET_SEG - 1) / DET_SEG;
+}
 hipError_t launch_detect(const float* scores, int64_t n, float tau, const MapDesc* maps, int n_maps,
                          int64_t* counts, int64_t* count, Detection* dets, int64_t capacity,
                          hipStream_t st);

@@ -1714,8 +1714,9 @@ hipError_t launch_place(const MapDesc* maps, const MapPart* parts, const int2* b
 // ---------------------------------------------------------------------------
 // Detections (Algorithm 1: keep every hypothesis with score >= tau), as a
 // deterministic stream compaction over the concatenated score maps: counts per
-// block of DET_SPAN positions, an exclusive scan of the counts, then every
-// block writes its detections in position order at its offset.
+// block of DET_SPAN positions, an exclusive scan of the counts in two levels
+// (within segments of DET_SEG counts in parallel, then of the segment sums),
+// then every block writes its detections in position order at its offset.
 // ---------------------------------------------------------------------------
 constexpr int DET_PER_THREAD = 4;
 constexpr int DET_SPAN = 256 * DET_PER_THREAD;
@@ -1754,7 +1755,32 @@ __global__ __launch_bounds__(256) void detect_count_kernel(const float* __restri
     if (threadIdx.x == 0) counts[blockIdx.x] = total;
 }
 
-// Exclusive scan of the block counts in place (one workgroup, chunks of 256),
+// Exclusive scan of the block counts within every segment of DET_SEG of them
+// (one workgroup per segment, 4 counts per thread), the segment's total to
+// sums[segment].
+__global__ __launch_bounds__(256) void detect_segscan_kernel(int64_t* __restrict__ counts, int nb,
+                                                             int64_t* __restrict__ sums) {
+    static_assert(DET_SEG == 4 * 256, "a segment is 4 counts per thread");
+    __shared__ int sh[4];
+    const int64_t i0 = (int64_t)blockIdx.x * DET_SEG + 4 * threadIdx.x;
+    int v[4];
+    int c = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        v[k] = i0 + k < nb ? (int)counts[i0 + k] : 0;      // each at most DET_SPAN
+        c += v[k];
+    }
+    int total;
+    int ex = block_exclusive_scan(c, sh, total);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (i0 + k < nb) counts[i0 + k] = ex;
+        ex += v[k];
+    }
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// Exclusive scan of the segment sums in place (one workgroup, chunks of 256),
 // total count to *count.
 __global__ __launch_bounds__(256) void detect_scan_kernel(int64_t* __restrict__ counts, int nb,
                                                           int64_t* __restrict__ count) {
@@ -1762,7 +1788,7 @@ __global__ __launch_bounds__(256) void detect_scan_kernel(int64_t* __restrict__ 
     int64_t carry = 0;
     for (int base = 0; base < nb; base += 256) {
         const int i = base + (int)threadIdx.x;
-        const int v = i < nb ? (int)counts[i] : 0;     // at most DET_SPAN
+        const int v = i < nb ? (int)counts[i] : 0;     // at most DET_SEG * DET_SPAN
         int total;
         const int ex = block_exclusive_scan(v, sh, total);
         if (i < nb) counts[i] = carry + ex;
@@ -1773,6 +1799,7 @@ __global__ __launch_bounds__(256) void detect_scan_kernel(int64_t* __restrict__ 
 
 __global__ __launch_bounds__(256) void detect_write_kernel(const float* __restrict__ scores, int64_t n,
                                                            float tau, const int64_t* __restrict__ counts,
+                                                           const int64_t* __restrict__ sums,
                                                            const MapDesc* __restrict__ maps, int n_maps,
                                                            Detection* __restrict__ dets, int64_t capacity) {
     __shared__ int sh[4];
@@ -1787,7 +1814,7 @@ __global__ __launch_bounds__(256) void detect_write_kernel(const float* __restri
         c += hit[k] ? 1 : 0;
     }
     int total;
-    int64_t out = counts[blockIdx.x] + block_exclusive_scan(c, sh, total);
+    int64_t out = sums[blockIdx.x / DET_SEG] + counts[blockIdx.x] + block_exclusive_scan(c, sh, total);
 #pragma unroll
     for (int k = 0; k < DET_PER_THREAD; ++k) {
         if (!hit[k]) continue;
@@ -1816,13 +1843,17 @@ hipError_t launch_detect(const float* scores, int64_t n, float tau, const MapDes
                          int64_t* counts, int64_t* count, Detection* dets, int64_t capacity,
                          hipStream_t st) {
     const int64_t nb = (n + DET_SPAN - 1) / DET_SPAN;
+    const int64_t nseg = (nb + DET_SEG - 1) / DET_SEG;
     if (nb > INT32_MAX) return hipErrorInvalidValue;
-    if (nb > 0)
+    int64_t* sums = counts + nb;                       // det_blocks(n) = nb + nseg
+    if (nb > 0) {
         hipLaunchKernelGGL(detect_count_kernel, dim3((unsigned)nb), dim3(256), 0, st, scores, n, tau, counts);
-    hipLaunchKernelGGL(detect_scan_kernel, dim3(1), dim3(256), 0, st, counts, (int)nb, count);
+        hipLaunchKernelGGL(detect_segscan_kernel, dim3((unsigned)nseg), dim3(256), 0, st, counts, (int)nb, sums);
+    }
+    hipLaunchKernelGGL(detect_scan_kernel, dim3(1), dim3(256), 0, st, sums, (int)nseg, count);
     if (nb > 0 && capacity > 0)
         hipLaunchKernelGGL(detect_write_kernel, dim3((unsigned)nb), dim3(256), 0, st, scores, n, tau,
-                           counts, maps, n_maps, dets, capacity);
+                           counts, sums, maps, n_maps, dets, capacity);
     return hipGetLastError();
 }
 
