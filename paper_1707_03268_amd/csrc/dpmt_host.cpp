@@ -229,7 +229,12 @@ struct dpmt_ctx {
     int n_chunks = 0;
     std::vector<int2> place_blk_chunk;            // placement blocks in chunk order
     std::vector<std::array<int, 2>> place_chunk;  // (begin, end) per chunk
-    PlaceLds place_lds{};
+    PlaceLds place_lds{};                         // every map of the plan (the plan's limit check)
+    // LDS of each launch, sized by its own maps: the batched launch is split
+    // into runs of blocks of equal workgroups per CU (place_runs, (begin,
+    // end) into place_blk); per-level launches and chunks get their own
+    std::vector<std::array<int, 2>> place_runs;
+    std::vector<PlaceLds> place_runs_lds, place_lvl_lds, place_chunk_lds;
     dpmt_layout layout{};
 
     // device workspace
@@ -1162,6 +1167,42 @@ const std::vector<std::array<int, 2>>& corr_chunks(dpmt_ctx* c, dpmt_mode mode) 
     return mode == DPMT_CP_FP32 ? c->modes[mode].cp.chunk : current_tiles(c, mode).chunk;
 }
 
+// Placement LDS for the maps of n blocks: the tallest map, the tallest and
+// widest part map and the most parts among them.
+PlaceLds place_lds_of(const dpmt_ctx* c, const int2* blk, size_t n) {
+    int max_Ho = 0, max_Hp = 0, max_Wp = 0, max_np = 1;
+    int last = -1;
+    for (size_t b = 0; b < n; ++b) {
+        if (blk[b].x == last) continue;
+        last = blk[b].x;
+        const MapDesc& md = c->maps[blk[b].x];
+        max_Ho = std::max(max_Ho, md.Ho);
+        max_np = std::max(max_np, md.n_parts);
+        for (int sl = 0; sl < md.n_parts; ++sl) {
+            const MapPart& mp = c->map_parts[md.part_base + sl];
+            max_Hp = std::max(max_Hp, mp.Hp);
+            max_Wp = std::max(max_Wp, mp.Wp);
+        }
+    }
+    PlaceLds pl;
+    pl.acc_rows = std::max(max_Ho, 1);
+    pl.r1_rows = max_Hp + 2 * PLACE_PAD;
+    pl.stage_words = PLACE_STAGE;
+    // row table: window of at most Wp + 2 (CW - 1) + 3 (alignment) + 1 offsets,
+    // rounded up to 4; column table: at most 2 (Hp + 1) + 1 offsets plus 4
+    pl.ctab_words = (std::max(max_Wp + 2 * (PLACE_CW - 1) + 8, 2 * (max_Hp + 1) + 1 + 4) + 3) & ~3;
+    pl.max_parts = max_np;
+    return pl;
+}
+
+// Placement workgroups one CU holds by LDS (at most PLACE_WG_PER_CU, the
+// register limit), for a block that needs `bytes` of dynamic LDS.
+int place_wg_per_cu(size_t bytes) {
+    const size_t gran = 512, lds = 160 * 1024 - 1024;      // 1 KB kept for the static LDS
+    const size_t per = (bytes + gran - 1) / gran * gran;
+    return (int)std::min<size_t>(PLACE_WG_PER_CU, per ? lds / per : PLACE_WG_PER_CU);
+}
+
 // The whole call as one launch per stage: value-range reset, projection of
 // every level, correlation of every tile, placement of every score map.
 hipError_t enqueue_batched(dpmt_ctx* c, dpmt_mode mode, const float* X, float* scores,
@@ -1176,10 +1217,10 @@ hipError_t enqueue_batched(dpmt_ctx* c, dpmt_mode mode, const float* X, float* s
     if (e == hipSuccess && ev) e = hipEventRecord(ev[1], st);
     if (e == hipSuccess) e = corr_tiles(c, mode, 0, 0, n_corr_tiles(c, mode), X, st);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[2], st);
-    if (e == hipSuccess)
-        e = launch_place(c->d_maps, c->d_parts, c->d_place_blk, (int)c->place_blk.size(), c->d_resp,
-                         c->d_rkeys, c->n_slots, scores, offs, c->place_lds,
-                         pruning(c, mode) ? c->d_flags : nullptr, st);
+    for (size_t k = 0; k < c->place_runs.size() && e == hipSuccess; ++k)
+        e = launch_place(c->d_maps, c->d_parts, c->d_place_blk + c->place_runs[k][0],
+                         c->place_runs[k][1] - c->place_runs[k][0], c->d_resp, c->d_rkeys, c->n_slots,
+                         scores, offs, c->place_runs_lds[k], pruning(c, mode) ? c->d_flags : nullptr, st);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[3], st);
     return e;
 }
@@ -1209,10 +1250,10 @@ hipError_t enqueue_per_level(dpmt_ctx* c, dpmt_mode mode, const float* X, float*
         e = corr_tiles(c, mode, 1, r[2], r[3], X, st);
     }
     if (e == hipSuccess && ev) e = hipEventRecord(ev[2], st);
-    for (const auto& r : c->place_lvl) {
-        if (e != hipSuccess) break;
+    for (size_t k = 0; k < c->place_lvl.size() && e == hipSuccess; ++k) {
+        const auto& r = c->place_lvl[k];
         e = launch_place(c->d_maps, c->d_parts, c->d_place_blk_lvl + r[2], r[3] - r[2], c->d_resp,
-                         c->d_rkeys, c->n_slots, scores, offs, c->place_lds,
+                         c->d_rkeys, c->n_slots, scores, offs, c->place_lvl_lds[k],
                          pruning(c, mode) ? c->d_flags : nullptr, st);
     }
     if (e == hipSuccess && ev) e = hipEventRecord(ev[3], st);
@@ -1244,7 +1285,7 @@ hipError_t enqueue_overlap(dpmt_ctx* c, dpmt_mode mode, const float* X, float* s
         if (e == hipSuccess)
             e = launch_place(c->d_maps, c->d_parts, c->d_place_blk_chunk + c->place_chunk[k][0],
                              c->place_chunk[k][1] - c->place_chunk[k][0], c->d_resp, c->d_rkeys,
-                             c->n_slots, scores, offs, c->place_lds,
+                             c->n_slots, scores, offs, c->place_chunk_lds[k],
                              pruning(c, mode) ? c->d_flags : nullptr, c->aux_stream);
     }
     if (e == hipSuccess && ev) e = hipEventRecord(ev[2], st);
@@ -1931,6 +1972,38 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
         for (const MapDesc& m : c->maps) pl.max_parts = std::max(pl.max_parts, m.n_parts);
         if (place_lds_bytes(pl) > PLACE_LDS_MAX)
             return fail(c, DPMT_E_UNSUPPORTED, "score maps too tall for one placement block");
+        // batched launch: blocks regrouped (stably, so largest work first
+        // within a run) into runs of equal workgroups per CU, fewest first;
+        // each run's LDS sized by its own maps, so that short maps are not
+        // held to the occupancy of the tallest
+        {
+            std::vector<std::pair<int, int2>> cls;
+            cls.reserve(c->place_blk.size());
+            std::map<int, int> wg_of;                     // map -> workgroups per CU
+            for (const int2& b : c->place_blk) {
+                auto it = wg_of.find(b.x);
+                if (it == wg_of.end())
+                    it = wg_of.emplace(b.x, place_wg_per_cu(place_lds_bytes(place_lds_of(c, &b, 1)))).first;
+                cls.push_back({it->second, b});
+            }
+            std::stable_sort(cls.begin(), cls.end(),
+                             [](const std::pair<int, int2>& a, const std::pair<int, int2>& b) { return a.first < b.first; });
+            c->place_runs.clear();
+            c->place_runs_lds.clear();
+            for (size_t b = 0; b < cls.size(); ++b) {
+                c->place_blk[b] = cls[b].second;
+                if (b == 0 || cls[b].first != cls[b - 1].first) c->place_runs.push_back({(int)b, (int)b + 1});
+                else c->place_runs.back()[1] = (int)b + 1;
+            }
+            for (const auto& r : c->place_runs)
+                c->place_runs_lds.push_back(place_lds_of(c, c->place_blk.data() + r[0], (size_t)(r[1] - r[0])));
+            c->place_lvl_lds.clear();
+            for (const auto& r : c->place_lvl)
+                c->place_lvl_lds.push_back(place_lds_of(c, c->place_blk_lvl.data() + r[2], (size_t)(r[3] - r[2])));
+            c->place_chunk_lds.clear();
+            for (const auto& r : c->place_chunk)
+                c->place_chunk_lds.push_back(place_lds_of(c, c->place_blk_chunk.data() + r[0], (size_t)(r[1] - r[0])));
+        }
     }
 
     dpmt_layout& lay = c->layout;

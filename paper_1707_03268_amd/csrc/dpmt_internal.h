@@ -159,6 +159,9 @@ constexpr int PLACE_RPW = 64 / PLACE_CW;  // rows per wavefront
 // window clamp spans its PLACE_RPW target rows, plus 3 for the unroll by 4
 constexpr int PLACE_PAD = 2 * (PLACE_RPW - 1) + 3;
 constexpr int PLACE_STAGE = 2048;         // floats of the staging buffer (32 rows of 64)
+// Workgroups of 256 threads a CU holds by registers: the kernel's 78 VGPRs
+// (granules of 8, 80 allocated) allow 6 wavefronts per SIMD.
+constexpr int PLACE_WG_PER_CU = 6;
 // Workgroups are dealt to the 8 XCDs (each with its own L2) round-robin by
 // launch index.  The placement's neighbouring strips stage overlapping
 // response rows, so it remaps the launch index: clusters of 2^xcl consecutive

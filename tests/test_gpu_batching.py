@@ -147,3 +147,39 @@ def test_autotune_picks_a_timed_config(batch):
     np.testing.assert_array_equal(s, ref_s)
     np.testing.assert_array_equal(o, ref_o)
     ctx.close()
+
+
+def _mixed_sizes_workload():
+    """One 1920x1080 frame beside two small images, one class model: the
+    frame's tallest score maps need several times the LDS of the small
+    images' maps, so the batched placement runs as several launches whose LDS
+    each run's own maps size (fewer workgroups per CU for the tall maps)."""
+    sizes = [(1920, 1080), (320, 240), (400, 300)]
+    pyrs, total = workloads.build_pyramids(sizes)
+    bank = workloads.build_bank(5, 1)
+    return workloads.Workload("mixed sizes: one 1920x1080 frame, two small images, 1 class", 5, pyrs,
+                              bank, total, workloads.feature_seed(5), True, sizes)
+
+
+def test_placement_runs_by_occupancy():
+    from _gpu_common import GpuRun
+    wl = _mixed_sizes_workload()
+    note("placement runs by occupancy: batched vs per level, oracle on the tallest and a small map")
+    feats = torch.from_numpy(wl.features()).cuda()
+    ctx, lay, U = _context(wl, 16)
+    ref_s, ref_o = _score(ctx, "tensor_bf16", feats, lay)
+    for launch in ("per_level", "overlap"):
+        ctx.set_launch(launch)
+        s, o = _score(ctx, "tensor_bf16", feats, lay)
+        np.testing.assert_array_equal(s, ref_s, err_msg=launch)
+        np.testing.assert_array_equal(o, ref_o, err_msg=launch)
+    ctx.set_launch("batched")
+    run = GpuRun(lay, ref_s, ref_o, None, U)
+    cmp, cache = Cmp(), {}
+    oct0 = wl.pyramids[0].octave
+    for img, level, comp in ((0, oct0, 0), (1, wl.pyramids[1].octave, 5)):
+        sm = oracle_map(wl, img, level, comp, U, cache)
+        compare_map(run, wl, img, level, comp, sm, TOL["tensor_bf16"], cmp)
+    note(f"  {cmp.n_pos} positions, max |err| {cmp.max_err:.3g}")
+    assert cmp.n_pos > 0
+    ctx.close()
