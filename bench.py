@@ -483,6 +483,29 @@ def rank_sweep(torch, workers, steps: int, n_comps: int = 24):
 
 
 # ----------------------------------------------------------------------------
+def hog_leg(torch, ctx, wl, score_ms_per_image: float, reps: int = 10):
+    """HOG feature pyramid of image 0 (a synthetic image of its size, every
+    level of its pyramid), timed like the steps, beside the scoring time per
+    image (the paper finds score estimation about 20x the feature extraction,
+    Section 1)."""
+    import workloads
+    w, h = wl.image_sizes[0]
+    pyr = wl.pyramids[0]
+    base = pyr.levels[0].cell_offset
+    levels = [(off - base, r, c, pr, pc, cell, inv)
+              for (off, r, c, pr, pc, cell, inv) in workloads.hog_levels(pyr)]
+    n = sum(r * c for _, r, c, *_ in levels)
+    pixels = sum((r - 2 * pr) * cell * (c - 2 * pc) * cell for _, r, c, pr, pc, cell, _ in levels)
+    img = torch.from_numpy(workloads.synthetic_image(0, w, h)).cuda()
+    out = torch.empty((n, 32), dtype=torch.float32, device="cuda")
+    ms, pct = run_steps(torch, lambda st: ctx.hog_pyramid(img, levels, out, stream=st), reps, 2)
+    del out, img
+    return {"image": f"{w}x{h}", "levels": len(levels), "cells": n, "resized_pixels": pixels,
+            "ms_per_image": ms, "mpixels_per_s": pixels / (ms * 1e-3) / 1e6, **pct,
+            "score_ms_per_image": score_ms_per_image,
+            "score_over_features": score_ms_per_image / ms if ms > 0 else None}
+
+
 def legs(torch, wl, args, n_images, feats_all):
     """The other forms on the first n_images images / frames, in a context of
     their own: direct FP32, the tensor form in its three operand precisions
@@ -629,6 +652,8 @@ def main() -> None:
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="keep the default correlation tile configuration instead of timing them all")
     ap.add_argument("--tile-config", type=int, default=None, help="correlation tile configuration index")
+    ap.add_argument("--no-hog", dest="hog", action="store_false",
+                    help="skip timing the HOG feature pyramid of one image")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device to device three times (a known-size copy kernel "
                          "for scaling hardware byte counters)")
@@ -705,6 +730,11 @@ def main() -> None:
             log(f"launch {launch}: {lms:.3f} ms per chunk")
         ctx.set_launch("batched")
 
+    hog = None
+    if args.hog and wl.padded:
+        hog = hog_leg(torch, ctx, wl, ms / n_img)
+        log(f"hog: {hog}")
+
     # roofline of each kernel (per launch = per chunk); the headline object is the dominant one
     pyrs = wl.pyramids[:chunk]
     shapes, comps = wl.bank.shapes, wl.bank.components
@@ -778,6 +808,7 @@ def main() -> None:
         "precisions": (leg or {}).get("precisions"),
         "cp_fp32": (leg or {}).get("cp_fp32"),
         "score_error_vs_oracle": err,
+        "hog_features": hog,
         "rank_sweep": sweep,
         "paper_context": "the paper reports up to 4.5x fewer convolutions than DPM v5 at matched detection "
                          "quality, on hardware it does not state",

@@ -263,6 +263,43 @@ typedef struct {
 dpmt_status dpmt_detect(dpmt_ctx* ctx, const float* scores_dev, float tau, dpmt_detection* dets_dev,
                         int64_t capacity, int64_t* count_dev, void* hip_stream);
 
+/* One level of a HOG feature pyramid: rows x cols cells (padding included)
+ * starting at cell cell_offset of a packed float32 HWC buffer of 32 channels.
+ * The rows - 2 pad_rows x cols - 2 pad_cols interior cells cover the image
+ * resized by 1 / inv_scale, cell x cell resized pixels each; the padding band
+ * of pad_rows rows and pad_cols columns on every side gets channel 31 = 1 and
+ * the other channels 0. */
+typedef struct {
+    int64_t cell_offset;
+    int32_t rows, cols;
+    int32_t pad_rows, pad_cols;
+    int32_t cell;        /* 4 or 8 */
+    float   inv_scale;   /* source pixels per resized pixel, finite, > 0 */
+} dpmt_hog_level;
+
+/* HOG features of an image, level by level: the feature map phi the scores
+ * are computed on (Section 2), 32 values per cell (Section 5, L = 32), in
+ * the 32-value variant of Felzenszwalb et al. (PAMI 2010, Section 6).  Each
+ * level samples the image bilinearly at its scale; per pixel the colour
+ * channel with the largest centred gradient votes for the nearest of 18
+ * directions, its magnitude spread bilinearly over the 4 nearest cells; the
+ * cell histograms are normalised by the 4 2x2-cell blocks around each cell,
+ * truncated at 0.2 and projected to 18 contrast-sensitive, 9 insensitive and
+ * 4 texture channels (channel 31 zero inside the image).
+ * image_dev: height x width x 3 uint8 (RGB, row-major, no pitch).
+ * levels_host: n_levels descriptors (copied); their cell ranges must not
+ * overlap (DPMT_E_INVALID).  features_dev receives every level's cells; cells
+ * outside the levels are not written.  Sides: image up to DPMT_HOG_MAX_SIDE
+ * pixels, levels up to 16384 cells (DPMT_E_UNSUPPORTED beyond).  Needs a
+ * context with a device (nothing loaded or planned); the context keeps the
+ * level tables and a histogram scratch of 76 bytes per interior cell, which
+ * grows when a call needs more (such a call first waits for the stream).
+ * Asynchronous on hip_stream; calls on one context must not overlap. */
+#define DPMT_HOG_MAX_SIDE 65536
+dpmt_status dpmt_hog_pyramid(dpmt_ctx* ctx, const uint8_t* image_dev, int32_t height, int32_t width,
+                             int32_t n_levels, const dpmt_hog_level* levels_host, float* features_dev,
+                             void* hip_stream);
+
 /* Filter responses of every filter of the bank on one planned level (for
  * checking the correlation stage on its own).  out_dev receives, for filter
  * k = 0 .. n_filters-1 in order, its (rows - h_k + 1) x (cols - w_k + 1)

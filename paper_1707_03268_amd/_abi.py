@@ -19,6 +19,7 @@ DPMT_E_UNSUPPORTED = -6
 
 DT_NOALLOC_MAX_SIDE = 16384        # DPMT_DT_NOALLOC_MAX_SIDE
 DT_NOALLOC_MAX_CELLS = 2097152     # DPMT_DT_NOALLOC_MAX_CELLS
+HOG_MAX_SIDE = 65536               # DPMT_HOG_MAX_SIDE
 
 DIRECT_FP32 = 0
 TENSOR_FP32 = 1
@@ -52,6 +53,12 @@ class LevelDesc(ctypes.Structure):
 
 class PyramidDesc(ctypes.Structure):
     _fields_ = [("n_levels", c_int32), ("levels", POINTER(LevelDesc)), ("octave", c_int32)]
+
+
+class HogLevel(ctypes.Structure):
+    _fields_ = [("cell_offset", c_int64), ("rows", c_int32), ("cols", c_int32),
+                ("pad_rows", c_int32), ("pad_cols", c_int32), ("cell", c_int32),
+                ("inv_scale", c_float)]
 
 
 class Hypothesis(ctypes.Structure):
@@ -100,6 +107,8 @@ SIGNATURES = {
     "dpmt_autotune": (c_int32, [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_int32,
                                 POINTER(c_float), POINTER(c_int32), c_void_p]),
     "dpmt_detect": (c_int32, [c_void_p, c_void_p, c_float, c_void_p, c_int64, c_void_p, c_void_p]),
+    "dpmt_hog_pyramid": (c_int32, [c_void_p, c_void_p, c_int32, c_int32, c_int32, POINTER(HogLevel),
+                                   c_void_p, c_void_p]),
     "dpmt_status_string": (c_char_p, [c_int32]),
     "dpmt_last_error": (c_char_p, [c_void_p]),
 }

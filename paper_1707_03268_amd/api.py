@@ -332,6 +332,25 @@ class Context:
                                   _dev_ptr(count, torch.int64, "count"), _stream_ptr(stream)),
                self._h, "dpmt_detect")
 
+    # ------------------------------------------------------ HOG features
+    def hog_pyramid(self, image, levels, features, stream=None) -> None:
+        """Enqueue dpmt_hog_pyramid: ``image`` a uint8 CUDA tensor (H, W, 3),
+        ``levels`` a sequence of (cell_offset, rows, cols, pad_rows, pad_cols,
+        cell, inv_scale) tuples, ``features`` a float32 CUDA tensor holding
+        every level's cells (32 floats per cell)."""
+        import torch
+        if image.dim() != 3 or image.shape[2] != 3:
+            raise ValueError("image must have shape (H, W, 3)")
+        n = len(levels)
+        arr = (_abi.HogLevel * max(n, 1))()
+        for k, lv in enumerate(levels):
+            off, rows, cols, pr, pc, cell, inv = lv
+            arr[k] = _abi.HogLevel(int(off), int(rows), int(cols), int(pr), int(pc), int(cell), float(inv))
+        _check(_lib().dpmt_hog_pyramid(self._h, _dev_ptr(image, torch.uint8, "image"), int(image.shape[0]),
+                                       int(image.shape[1]), n, arr,
+                                       _dev_ptr(features, torch.float32, "features"), _stream_ptr(stream)),
+               self._h, "dpmt_hog_pyramid")
+
     # ------------------------------------------------------ launch strategy
     def set_launch(self, launch) -> None:
         """'batched' (default), 'per_level' or 'graph' (see dpmt_launch)."""

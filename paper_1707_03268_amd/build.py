@@ -22,7 +22,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdpmt.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 HOST_SRC = os.path.join(CSRC, "dpmt_host.cpp")
-KERNEL_SRC = os.path.join(CSRC, "dpmt_kernels.hip")
+KERNEL_SRCS = [os.path.join(CSRC, "dpmt_kernels.hip"), os.path.join(CSRC, "dpmt_hog.hip")]
 ARCH = "gfx950"
 COMMON = ["-std=c++17", "-fPIC", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wall", "-Wno-unused-function", "-Wno-unused-result"]
@@ -49,35 +49,47 @@ def _run(cmd, verbose: bool) -> None:
         print(msgs)
 
 
-def _kernels_object(verbose: bool) -> str:
-    obj = os.path.join(BUILD_DIR, "dpmt_kernels.o")
-    _run([hipcc(), f"--offload-arch={ARCH}", "-O3", *COMMON, *_includes(), "-c", KERNEL_SRC,
-          "-o", obj], verbose)
-    return obj
+def _object(src: str) -> str:
+    return os.path.join(BUILD_DIR, os.path.splitext(os.path.basename(src))[0] + ".o")
+
+
+def _compile_all(cmds, verbose: bool) -> None:
+    """Run the compile commands side by side; raise on the first failure."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=len(cmds)) as ex:
+        for f in [ex.submit(_run, cmd, verbose) for cmd in cmds]:
+            f.result()
+
+
+def _kernel_cmd(src: str):
+    return [hipcc(), f"--offload-arch={ARCH}", "-O3", *COMMON, *_includes(), "-c", src, "-o", _object(src)]
 
 
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD_DIR, exist_ok=True)
-    kobj = _kernels_object(verbose)
     hobj = os.path.join(BUILD_DIR, "dpmt_host.o")
-    _run([hipcc(), f"--offload-arch={ARCH}", "-O3", *COMMON, *_includes(), "-c", HOST_SRC,
-          "-o", hobj], verbose)
+    _compile_all([_kernel_cmd(s) for s in KERNEL_SRCS] +
+                 [[hipcc(), f"--offload-arch={ARCH}", "-O3", *COMMON, *_includes(), "-c", HOST_SRC,
+                   "-o", hobj]], verbose)
     tmp = LIB + ".tmp"
-    _run([hipcc(), f"--offload-arch={ARCH}", "-shared", kobj, hobj, "-o", tmp], verbose)
+    _run([hipcc(), f"--offload-arch={ARCH}", "-shared", *[_object(s) for s in KERNEL_SRCS], hobj,
+          "-o", tmp], verbose)
     os.replace(tmp, LIB)
     return LIB
 
 
 def build_host_sanitized(out_dir: str, verbose: bool = False) -> str:
     """libdpmt with the host runtime under ASan + UBSan (every UB report
-    fatal), linked with the kernels' object of the in-tree build (compiled
-    here if missing or older than its sources).  Returns the library path; it
-    needs the ASan runtime preloaded (asan_runtime())."""
+    fatal), linked with the kernels' objects of the in-tree build (compiled
+    here if missing or older than their sources).  Returns the library path;
+    it needs the ASan runtime preloaded (asan_runtime())."""
     os.makedirs(BUILD_DIR, exist_ok=True)
-    kobj = os.path.join(BUILD_DIR, "dpmt_kernels.o")
-    newest = max(os.path.getmtime(p) for p in (KERNEL_SRC, os.path.join(CSRC, "dpmt_internal.h")))
-    if not os.path.exists(kobj) or os.path.getmtime(kobj) < newest:
-        kobj = _kernels_object(verbose)
+    hdr = os.path.getmtime(os.path.join(CSRC, "dpmt_internal.h"))
+    stale = [s for s in KERNEL_SRCS
+             if not os.path.exists(_object(s)) or os.path.getmtime(_object(s)) < max(hdr, os.path.getmtime(s))]
+    if stale:
+        _compile_all([_kernel_cmd(s) for s in stale], verbose)
+    kobjs = [_object(s) for s in KERNEL_SRCS]
     os.makedirs(out_dir, exist_ok=True)
     hobj = os.path.join(out_dir, "dpmt_host_san.o")
     san = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
@@ -85,7 +97,7 @@ def build_host_sanitized(out_dir: str, verbose: bool = False) -> str:
     _run([hipcc(), "--cuda-host-only", "-O1", "-g", *COMMON, *san, *_includes(), "-c", HOST_SRC,
           "-o", hobj], verbose)
     lib = os.path.join(out_dir, "libdpmt_san.so")
-    _run([hipcc(), f"--offload-arch={ARCH}", "-shared", *san, kobj, hobj, "-o", lib], verbose)
+    _run([hipcc(), f"--offload-arch={ARCH}", "-shared", *san, *kobjs, hobj, "-o", lib], verbose)
     return lib
 
 

@@ -268,6 +268,18 @@ struct dpmt_ctx {
     GraphKey graph_key;
     hipGraphExec_t graph_exec = nullptr;
 
+    // HOG pyramid: level table and work lists of the last geometry, and the
+    // histogram scratch (grown as needed)
+    std::vector<HogLevelDesc> hog_levels;
+    std::vector<int4> hog_tiles;
+    std::vector<int2> hog_blocks;
+    int hog_H = -1, hog_W = -1;
+    HogLevelDesc* d_hog_levels = nullptr;
+    int4* d_hog_tiles = nullptr;
+    int2* d_hog_blocks = nullptr;
+    float* d_hog_hist = nullptr;
+    int64_t hog_hist_cells = 0;
+
     // profiling: one set of events per profiled call
     bool prof = false;
     std::vector<std::array<hipEvent_t, N_EVENTS>> ev_sets;
@@ -1350,6 +1362,10 @@ void dpmt_destroy(dpmt_ctx* c) {
         (void)hipDeviceSynchronize();
         free_plan(c);
         for (auto& m : c->modes) free_mode(m);
+        dfree(c->d_hog_levels);
+        dfree(c->d_hog_tiles);
+        dfree(c->d_hog_blocks);
+        dfree(c->d_hog_hist);
         if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
         if (c->aux_stream) (void)hipStreamDestroy(c->aux_stream);
         for (hipEvent_t e : c->chunk_ev) (void)hipEventDestroy(e);
@@ -2245,6 +2261,113 @@ dpmt_status dpmt_detect(dpmt_ctx* c, const float* scores_dev, float tau, dpmt_de
     HIP_TRY(c, launch_detect(scores_dev, c->layout.n_score, tau, c->d_maps, (int)c->maps.size(),
                              c->d_det_counts, count_dev, reinterpret_cast<Detection*>(dets_dev), capacity, st),
             "detection launch");
+    return DPMT_OK;
+}
+
+dpmt_status dpmt_hog_pyramid(dpmt_ctx* c, const uint8_t* image_dev, int32_t height, int32_t width,
+                             int32_t n_levels, const dpmt_hog_level* levels, float* features_dev,
+                             void* hip_stream) {
+    if (!c) return fail(nullptr, DPMT_E_INVALID, "ctx is NULL");
+    if (height < 1 || width < 1 || height > DPMT_HOG_MAX_SIDE || width > DPMT_HOG_MAX_SIDE)
+        return fail(c, DPMT_E_INVALID, "image sides must be in [1, DPMT_HOG_MAX_SIDE]");
+    if (n_levels < 0 || (n_levels > 0 && !levels)) return fail(c, DPMT_E_INVALID, "need levels for n_levels > 0");
+    if (n_levels > 0 && (!image_dev || !features_dev))
+        return fail(c, DPMT_E_INVALID, "image_dev and features_dev are required");
+    std::vector<HogLevelDesc> lv((size_t)n_levels);
+    std::vector<std::pair<int64_t, int64_t>> spans;
+    int64_t hist_cells = 0;
+    for (int l = 0; l < n_levels; ++l) {
+        const dpmt_hog_level& h = levels[l];
+        const std::string at = "level " + std::to_string(l) + ": ";
+        if (h.cell != 4 && h.cell != 8) return fail(c, DPMT_E_INVALID, at + "cell must be 4 or 8");
+        if (!std::isfinite(h.inv_scale) || !(h.inv_scale > 0.f)) return fail(c, DPMT_E_INVALID, at + "inv_scale must be finite and > 0");
+        if (h.cell_offset < 0 || h.pad_rows < 0 || h.pad_cols < 0 || h.rows < 2 * (int64_t)h.pad_rows ||
+            h.cols < 2 * (int64_t)h.pad_cols)
+            return fail(c, DPMT_E_INVALID, at + "needs cell_offset >= 0 and rows, cols >= twice the padding");
+        if (h.rows > 16384 || h.cols > 16384)
+            return fail(c, DPMT_E_UNSUPPORTED, at + "sides up to 16384 cells");
+        HogLevelDesc& d = lv[l];
+        d.cell_offset = h.cell_offset;
+        d.rows = h.rows;
+        d.cols = h.cols;
+        d.pad_rows = h.pad_rows;
+        d.pad_cols = h.pad_cols;
+        d.nr = h.rows - 2 * h.pad_rows;
+        d.nc = h.cols - 2 * h.pad_cols;
+        d.cell = h.cell;
+        d.inv_scale = h.inv_scale;
+        d.hist_off = hist_cells;
+        hist_cells += (int64_t)d.nr * d.nc;
+        if ((int64_t)h.rows * h.cols > 0) spans.push_back({h.cell_offset, h.cell_offset + (int64_t)h.rows * h.cols});
+    }
+    std::sort(spans.begin(), spans.end());
+    for (size_t k = 1; k < spans.size(); ++k)
+        if (spans[k].first < spans[k - 1].second) return fail(c, DPMT_E_INVALID, "levels overlap in the feature buffer");
+    if (!c->has_device()) return fail(c, DPMT_E_STATE, "host-only context cannot extract features");
+    HIP_TRY(c, hipSetDevice(c->device), "hipSetDevice");
+    hipStream_t st = hip_stream ? static_cast<hipStream_t>(hip_stream) : c->stream;
+    if (n_levels == 0) return DPMT_OK;
+
+    std::vector<int4> tiles;
+    std::vector<int2> blocks;
+    for (int l = 0; l < n_levels; ++l) {
+        const HogLevelDesc& d = lv[l];
+        const int T = HOG_TILE_PIXELS / d.cell;
+        for (int ty = 0; ty < (d.nr + T - 1) / T; ++ty)
+            for (int tx = 0; tx < (d.nc + T - 1) / T; ++tx) tiles.push_back(make_int4(l, ty, tx, 0));
+        for (int64_t p = 0; p < (int64_t)d.rows * d.cols; p += 256) blocks.push_back(make_int2(l, (int)p));
+    }
+    if (tiles.size() > (size_t)INT32_MAX || blocks.size() > (size_t)INT32_MAX)
+        return fail(c, DPMT_E_UNSUPPORTED, "pyramid too large for one launch");
+    auto same = [](const void* a, const void* b, size_t n) { return n == 0 || std::memcmp(a, b, n) == 0; };
+    const bool changed = height != c->hog_H || width != c->hog_W || lv.size() != c->hog_levels.size() ||
+                         tiles.size() != c->hog_tiles.size() || blocks.size() != c->hog_blocks.size() ||
+                         !same(lv.data(), c->hog_levels.data(), lv.size() * sizeof(HogLevelDesc)) ||
+                         !same(tiles.data(), c->hog_tiles.data(), tiles.size() * sizeof(int4)) ||
+                         !same(blocks.data(), c->hog_blocks.data(), blocks.size() * sizeof(int2));
+    if (changed || hist_cells > c->hog_hist_cells) {
+        // earlier calls on the stream may still read the old tables and scratch
+        HIP_TRY(c, hipStreamSynchronize(st), "hipStreamSynchronize");
+    }
+    if (changed) {
+        dfree(c->d_hog_levels); c->d_hog_levels = nullptr;
+        dfree(c->d_hog_tiles); c->d_hog_tiles = nullptr;
+        dfree(c->d_hog_blocks); c->d_hog_blocks = nullptr;
+        c->hog_levels.clear();
+        c->hog_tiles.clear();
+        c->hog_blocks.clear();
+        c->hog_H = c->hog_W = -1;
+        auto put = [&](void** dst, const void* src, size_t bytes, const char* what) -> dpmt_status {
+            if (bytes == 0) return DPMT_OK;
+            hipError_t e = hipMalloc(dst, bytes);
+            if (e == hipSuccess) e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+            return e == hipSuccess ? DPMT_OK : hip_fail(c, e, what);
+        };
+        dpmt_status s;
+        if ((s = put((void**)&c->d_hog_levels, lv.data(), lv.size() * sizeof(HogLevelDesc), "upload HOG levels")) != DPMT_OK) return s;
+        if ((s = put((void**)&c->d_hog_tiles, tiles.data(), tiles.size() * sizeof(int4), "upload HOG tiles")) != DPMT_OK) return s;
+        if ((s = put((void**)&c->d_hog_blocks, blocks.data(), blocks.size() * sizeof(int2), "upload HOG blocks")) != DPMT_OK) return s;
+        c->hog_levels = lv;
+        c->hog_tiles = tiles;
+        c->hog_blocks = blocks;
+        c->hog_H = height;
+        c->hog_W = width;
+    }
+    if (hist_cells > c->hog_hist_cells) {
+        dfree(c->d_hog_hist); c->d_hog_hist = nullptr; c->hog_hist_cells = 0;
+        HIP_TRY(c, hipMalloc((void**)&c->d_hog_hist, (size_t)hist_cells * 19 * sizeof(float)), "allocate HOG scratch");
+        c->hog_hist_cells = hist_cells;
+    }
+    HogTable tab;
+    for (int o = 0; o < 9; ++o) {
+        tab.u[o] = (float)std::cos(o * M_PI / 9.0);
+        tab.v[o] = (float)std::sin(o * M_PI / 9.0);
+    }
+    float* hist = c->d_hog_hist;
+    float* energy = hist ? hist + c->hog_hist_cells * 18 : nullptr;
+    HIP_TRY(c, launch_hog(image_dev, height, width, c->d_hog_levels, c->d_hog_tiles, (int)tiles.size(),
+                          c->d_hog_blocks, (int)blocks.size(), tab, hist, energy, features_dev, st),
+            "HOG launch");
     return DPMT_OK;
 }
 

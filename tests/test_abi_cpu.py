@@ -505,3 +505,39 @@ def test_noalloc_distance_transform_limits_host_only():
     bad = (ctypes.c_float * 4)(0.0, 0.0, 0.0, 0.1)
     assert lib.dpmt_distance_transform_noalloc(fake, 4, 4, 4, bad, fake, None, None, None) == _abi.DPMT_E_INVALID
     assert _abi.DT_NOALLOC_MAX_CELLS == 1 << 21 and _abi.DT_NOALLOC_MAX_SIDE == 16384
+
+
+def test_hog_arguments_host_only():
+    """dpmt_hog_pyramid validates every argument before it needs a device:
+    bad geometry is DPMT_E_INVALID (or DPMT_E_UNSUPPORTED past the size
+    limits); valid arguments on a host-only context are DPMT_E_STATE."""
+    lib = _abi.load()
+    ctx = Context(device=-1)
+    img, out = ctypes.c_void_p(16), ctypes.c_void_p(16)
+
+    def call(levels, h=30, w=40, image=img, feats=out, handle=None):
+        arr = (_abi.HogLevel * max(len(levels), 1))(*[_abi.HogLevel(*lv) for lv in levels])
+        return lib.dpmt_hog_pyramid(ctx._h if handle is None else handle, image, h, w, len(levels), arr,
+                                    feats, None)
+
+    ok = [(0, 10, 12, 1, 2, 4, 1.0), (120, 6, 9, 3, 4, 8, 2.5)]
+    assert call(ok) == _abi.DPMT_E_STATE
+    assert b"host-only" in lib.dpmt_last_error(ctx._h)
+    assert call([]) == _abi.DPMT_E_STATE
+    assert ctypes.sizeof(_abi.HogLevel) == 32
+    for bad in ([(0, 10, 12, 1, 2, 5, 1.0)],                        # cell
+                [(0, 10, 12, 6, 2, 4, 1.0)],                        # padding rows
+                [(0, 10, 12, 1, 7, 4, 1.0)],                        # padding cols
+                [(0, 10, 12, -1, 2, 4, 1.0)],
+                [(-5, 10, 12, 1, 2, 4, 1.0)],
+                [(0, 10, 12, 1, 2, 4, 0.0)],
+                [(0, 10, 12, 1, 2, 4, -2.0)],
+                [(0, 10, 12, 1, 2, 4, float("nan"))],
+                [(0, 10, 12, 1, 2, 4, 1.0), (119, 6, 9, 3, 4, 8, 2.5)]):   # overlap by one cell
+        assert call(bad) == _abi.DPMT_E_INVALID, bad
+    assert call(ok, h=0) == _abi.DPMT_E_INVALID
+    assert call(ok, w=_abi.HOG_MAX_SIDE + 1) == _abi.DPMT_E_INVALID
+    assert call(ok, image=None) == _abi.DPMT_E_INVALID
+    assert call(ok, feats=None) == _abi.DPMT_E_INVALID
+    assert call([(0, 16385, 12, 1, 2, 4, 1.0)]) == _abi.DPMT_E_UNSUPPORTED
+    assert lib.dpmt_hog_pyramid(None, img, 30, 40, 0, None, out, None) == _abi.DPMT_E_INVALID

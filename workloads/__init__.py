@@ -268,6 +268,46 @@ def build_pyramids(image_sizes: Sequence[Tuple[int, int]]) -> Tuple[List[Pyramid
     return pyrs, off
 
 
+def hog_levels(pyr: Pyramid, pad_rows: int = PAD_ROWS, pad_cols: int = PAD_COLS):
+    """Geometry of a pyramid's levels for HOG extraction, one tuple
+    (cell_offset, rows, cols, pad_rows, pad_cols, cell, inv_scale) per level.
+    Level l of the first octave takes cells of 4 resized pixels on the image
+    scaled by 2^(-l/10); later levels cells of CELL pixels on the image scaled
+    by 2^(1 - l/10).  Both give the level's floor(side * 2^(1 - l/10) / CELL)
+    interior cells (the image covers them: those cells span at most the
+    resized image)."""
+    out = []
+    for l, lv in enumerate(pyr.levels):
+        cell = CELL // 2 if l < pyr.octave else CELL
+        inv = 2.0 ** (l / pyr.octave) if l < pyr.octave else 2.0 ** (l / pyr.octave - 1.0)
+        out.append((lv.cell_offset, lv.rows, lv.cols, pad_rows, pad_cols, cell, inv))
+    return out
+
+
+def synthetic_image(seed: int, width: int, height: int, n_shapes: int = 24,
+                    noise: float = 6.0) -> np.ndarray:
+    """Seeded uint8 (height, width, 3) RGB test image: a smooth colour
+    gradient, n_shapes filled ellipses and rotated rectangles of random
+    colours and sizes, and Gaussian pixel noise, so that edges of every
+    orientation and scale reach the HOG stage."""
+    rng = np.random.default_rng(np.random.SeedSequence([1707, 3268, 99, seed]))
+    y, x = np.mgrid[0:height, 0:width].astype(np.float32)
+    c0, c1 = rng.uniform(40, 215, 3), rng.uniform(40, 215, 3)
+    t = (x / max(width - 1, 1) * rng.uniform(0.2, 1.0) + y / max(height - 1, 1) * rng.uniform(0.2, 1.0))
+    t = t / max(float(t.max()), 1e-6)
+    img = c0[None, None, :] * (1.0 - t[..., None]) + c1[None, None, :] * t[..., None]
+    for k in range(n_shapes):
+        cx, cy = rng.uniform(0, width), rng.uniform(0, height)
+        a, b = rng.uniform(0.03, 0.25) * width, rng.uniform(0.03, 0.25) * height
+        th = rng.uniform(0, np.pi)
+        u = (x - cx) * np.cos(th) + (y - cy) * np.sin(th)
+        v = -(x - cx) * np.sin(th) + (y - cy) * np.cos(th)
+        inside = (u / a) ** 2 + (v / b) ** 2 <= 1.0 if k % 2 == 0 else (np.abs(u) <= a) & (np.abs(v) <= b)
+        img[inside] = rng.uniform(0, 255, 3)
+    img += rng.normal(0.0, noise, img.shape)
+    return np.clip(np.rint(img), 0, 255).astype(np.uint8)
+
+
 # --------------------------------------------------------------------------
 # filters, components
 # --------------------------------------------------------------------------
