@@ -506,6 +506,27 @@ def hog_leg(torch, ctx, wl, score_ms_per_image: float, reps: int = 10):
             "score_over_features": score_ms_per_image / ms if ms > 0 else None}
 
 
+def dt_methods(torch, reps: int = 10):
+    """Single-map distance transform, window scans against lower envelopes,
+    on a 1920x1080 frame's largest part map (277 x 497) and a 1024 x 1024
+    map, with the workloads' deformation (0.05) and a weak one (0.001)."""
+    from paper_1707_03268_amd import distance_transform
+    out = {}
+    rng = np.random.default_rng(0)
+    for rows, cols in ((277, 497), (1024, 1024)):
+        resp = torch.from_numpy(rng.standard_normal((rows, cols)).astype(np.float32)).cuda()
+        D = torch.empty((rows, cols), dtype=torch.float32, device="cuda")
+        ay = torch.empty((rows, cols), dtype=torch.int32, device="cuda")
+        ax = torch.empty_like(ay)
+        for q in (0.05, 0.001):
+            d = [0.02, q, -0.01, q]
+            for method in ("window", "envelope"):
+                ms, _ = run_steps(torch, lambda st: distance_transform(resp, d, D, ay, ax, stream=st, method=method),
+                                  reps, 2)
+                out[f"{rows}x{cols} d={q} {method}"] = ms
+    return out
+
+
 def legs(torch, wl, args, n_images, feats_all):
     """The other forms on the first n_images images / frames, in a context of
     their own: direct FP32, the tensor form in its three operand precisions
@@ -652,6 +673,8 @@ def main() -> None:
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="keep the default correlation tile configuration instead of timing them all")
     ap.add_argument("--tile-config", type=int, default=None, help="correlation tile configuration index")
+    ap.add_argument("--no-dt-methods", dest="dt_methods", action="store_false",
+                    help="skip timing the single-map transform's two methods")
     ap.add_argument("--no-hog", dest="hog", action="store_false",
                     help="skip timing the HOG feature pyramid of one image")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -734,6 +757,9 @@ def main() -> None:
     if args.hog and wl.padded:
         hog = hog_leg(torch, ctx, wl, ms / n_img)
         log(f"hog: {hog}")
+    dtm = dt_methods(torch) if args.dt_methods else None
+    if dtm:
+        log(f"distance transform methods (ms): {dtm}")
 
     # roofline of each kernel (per launch = per chunk); the headline object is the dominant one
     pyrs = wl.pyramids[:chunk]
@@ -809,6 +835,7 @@ def main() -> None:
         "cp_fp32": (leg or {}).get("cp_fp32"),
         "score_error_vs_oracle": err,
         "hog_features": hog,
+        "distance_transform_ms": dtm,
         "rank_sweep": sweep,
         "paper_context": "the paper reports up to 4.5x fewer convolutions than DPM v5 at matched detection "
                          "quality, on hardware it does not state",

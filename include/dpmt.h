@@ -321,6 +321,25 @@ dpmt_status dpmt_distance_transform(const float* resp_dev, int32_t rows, int32_t
                                     const float* deform_host, float* d_dev, int32_t* arg_y_dev,
                                     int32_t* arg_x_dev, void* hip_stream);
 
+/* dpmt_distance_transform with a choice of method: DPMT_DT_WINDOW is
+ * dpmt_distance_transform itself (exact scans of the window that the line's
+ * value range allows, work growing with sqrt(range / d_xx) per target);
+ * DPMT_DT_ENVELOPE finds the same maximum along each line from the upper
+ * envelope of the candidates' cost parabolas (Section 2 placement argmax,
+ * computed as in Felzenszwalb and Huttenlocher's distance transform of
+ * sampled functions), in time linear in the line length whatever the
+ * deformation, one GPU thread per line.  The envelope is built in FP64 and
+ * the maximiser is decided in FP32 among the envelope's candidates with the
+ * window scan's formula and tie rule, so both methods agree wherever the
+ * FP32 values of the top two candidates differ.  Inputs finite or -inf (an
+ * all -inf line gives -inf).  Other arguments as dpmt_distance_transform;
+ * an unknown method is DPMT_E_INVALID. */
+#define DPMT_DT_WINDOW 0
+#define DPMT_DT_ENVELOPE 1
+dpmt_status dpmt_distance_transform_method(const float* resp_dev, int32_t rows, int32_t cols, int32_t ld,
+                                           const float* deform_host, float* d_dev, int32_t* arg_y_dev,
+                                           int32_t* arg_x_dev, int32_t method, void* hip_stream);
+
 /* dpmt_distance_transform for callers that cannot allocate memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
  * same arguments, kernels and results, but the scratch the transform needs

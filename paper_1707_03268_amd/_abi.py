@@ -20,6 +20,9 @@ DPMT_E_UNSUPPORTED = -6
 DT_NOALLOC_MAX_SIDE = 16384        # DPMT_DT_NOALLOC_MAX_SIDE
 DT_NOALLOC_MAX_CELLS = 2097152     # DPMT_DT_NOALLOC_MAX_CELLS
 HOG_MAX_SIDE = 65536               # DPMT_HOG_MAX_SIDE
+DT_WINDOW = 0                      # DPMT_DT_WINDOW
+DT_ENVELOPE = 1                    # DPMT_DT_ENVELOPE
+DT_METHODS = {"window": DT_WINDOW, "envelope": DT_ENVELOPE}
 
 DIRECT_FP32 = 0
 TENSOR_FP32 = 1
@@ -97,6 +100,8 @@ SIGNATURES = {
                                           c_void_p, c_void_p, c_void_p, c_void_p]),
     "dpmt_distance_transform_noalloc": (c_int32, [c_void_p, c_int32, c_int32, c_int32, POINTER(c_float),
                                                   c_void_p, c_void_p, c_void_p, c_void_p]),
+    "dpmt_distance_transform_method": (c_int32, [c_void_p, c_int32, c_int32, c_int32, POINTER(c_float),
+                                                 c_void_p, c_void_p, c_void_p, c_int32, c_void_p]),
     "dpmt_set_profiling": (c_int32, [c_void_p, c_int32]),
     "dpmt_stage_times": (c_int32, [c_void_p, POINTER(c_float), c_int32, POINTER(c_int32)]),
     "dpmt_set_launch": (c_int32, [c_void_p, c_int32]),

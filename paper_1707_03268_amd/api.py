@@ -402,11 +402,14 @@ def tile_config_name(config: int) -> Optional[str]:
     return r.decode() if r is not None else None
 
 
-def distance_transform(resp, deform, out=None, arg_y=None, arg_x=None, stream=None, noalloc=False):
+def distance_transform(resp, deform, out=None, arg_y=None, arg_x=None, stream=None, noalloc=False,
+                       method: str = "window"):
     """Generalised distance transform of one 2D float32 CUDA map for every
     target cell; returns (D, arg_y, arg_x).  noalloc: call
     dpmt_distance_transform_noalloc (the library's static scratch, no
-    allocation inside the call; outputs must then be given)."""
+    allocation inside the call; outputs must then be given).  method:
+    "window" (windowed scans) or "envelope" (lower envelopes, through
+    dpmt_distance_transform_method)."""
     import torch
     if resp.dim() != 2:
         raise ValueError("resp must be 2D")
@@ -423,10 +426,17 @@ def distance_transform(resp, deform, out=None, arg_y=None, arg_x=None, stream=No
     d = (c_float * 4)(*[float(v) for v in deform])
     if not resp.is_cuda or resp.dtype != torch.float32:
         raise TypeError("resp must be a float32 CUDA tensor")
+    if method not in _abi.DT_METHODS:
+        raise ValueError(f"method must be one of {sorted(_abi.DT_METHODS)}")
+    ptrs = (c_void_p(resp.data_ptr()), rows, cols, ld, d, _dev_ptr(out, torch.float32, "out"),
+            _dev_ptr(arg_y, torch.int32, "arg_y"), _dev_ptr(arg_x, torch.int32, "arg_x"))
+    if method != "window":
+        if noalloc:
+            raise ValueError("the allocation-free transform uses windowed scans")
+        _check(_lib().dpmt_distance_transform_method(*ptrs, _abi.DT_METHODS[method], _stream_ptr(stream)),
+               None, "dpmt_distance_transform_method")
+        return out, arg_y, arg_x
     fn = _lib().dpmt_distance_transform_noalloc if noalloc else _lib().dpmt_distance_transform
-    _check(fn(
-        c_void_p(resp.data_ptr()), rows, cols, ld, d,
-        _dev_ptr(out, torch.float32, "out"), _dev_ptr(arg_y, torch.int32, "arg_y"),
-        _dev_ptr(arg_x, torch.int32, "arg_x"), _stream_ptr(stream)), None,
-        "dpmt_distance_transform_noalloc" if noalloc else "dpmt_distance_transform")
+    _check(fn(*ptrs, _stream_ptr(stream)), None,
+           "dpmt_distance_transform_noalloc" if noalloc else "dpmt_distance_transform")
     return out, arg_y, arg_x

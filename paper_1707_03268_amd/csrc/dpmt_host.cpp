@@ -2515,6 +2515,36 @@ dpmt_status dpmt_distance_transform(const float* resp_dev, int32_t rows, int32_t
     return DPMT_OK;
 }
 
+dpmt_status dpmt_distance_transform_method(const float* resp_dev, int32_t rows, int32_t cols, int32_t ld,
+                                           const float* deform_host, float* d_dev, int32_t* arg_y_dev,
+                                           int32_t* arg_x_dev, int32_t method, void* hip_stream) {
+    if (method == DPMT_DT_WINDOW)
+        return dpmt_distance_transform(resp_dev, rows, cols, ld, deform_host, d_dev, arg_y_dev, arg_x_dev,
+                                       hip_stream);
+    if (method != DPMT_DT_ENVELOPE) return fail(nullptr, DPMT_E_INVALID, "unknown distance transform method");
+    const dpmt_status chk = check_dt_args(resp_dev, rows, cols, ld, deform_host, d_dev, arg_y_dev, arg_x_dev);
+    if (chk != DPMT_OK) return chk;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    const int64_t n = (int64_t)rows * cols;
+    float* r1v = nullptr;
+    int32_t* r1a = nullptr;
+    int32_t* hx = nullptr;
+    double* hz = nullptr;
+    int32_t* ayw = nullptr;
+    hipError_t e = hipMallocAsync((void**)&r1v, (size_t)n * 4, st);
+    if (e == hipSuccess) e = hipMallocAsync((void**)&r1a, (size_t)n * 4, st);
+    if (e == hipSuccess) e = hipMallocAsync((void**)&hx, (size_t)n * 4, st);
+    if (e == hipSuccess) e = hipMallocAsync((void**)&hz, (size_t)n * 8, st);
+    if (e == hipSuccess && !arg_y_dev) e = hipMallocAsync((void**)&ayw, (size_t)n * 4, st);
+    if (e == hipSuccess)
+        e = launch_dt_envelope(resp_dev, rows, cols, ld, deform_host, r1v, r1a, hx, hz, d_dev,
+                               arg_y_dev ? arg_y_dev : ayw, arg_x_dev, st);
+    for (void* p : {(void*)r1v, (void*)r1a, (void*)hx, (void*)hz, (void*)ayw})
+        if (p) (void)hipFreeAsync(p, st);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "distance transform (lower envelopes)");
+    return DPMT_OK;
+}
+
 dpmt_status dpmt_distance_transform_noalloc(const float* resp_dev, int32_t rows, int32_t cols,
                                             int32_t ld, const float* deform_host, float* d_dev,
                                             int32_t* arg_y_dev, int32_t* arg_x_dev, void* hip_stream) {

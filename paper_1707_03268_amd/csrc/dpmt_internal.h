@@ -270,6 +270,12 @@ hipError_t launch_dt_single(const float* resp, int rows, int cols, int ld, const
 // rows and columns (the caller checks), on the current device.
 constexpr int DT_NOALLOC_MAX_SIDE = 16384;
 constexpr int64_t DT_NOALLOC_MAX_CELLS = (int64_t)1 << 21;
+// Single-map transform by lower envelopes (one thread per line).  hx, hz:
+// rows * cols int32 / double of scratch; ay is required (the column pass's
+// argmax), ax optional.
+hipError_t launch_dt_envelope(const float* resp, int rows, int cols, int ld, const float* d, float* r1v,
+                              int32_t* r1a, int32_t* hx, double* hz, float* out, int32_t* ay, int32_t* ax,
+                              hipStream_t st);
 hipError_t launch_dt_single_noalloc(const float* resp, int rows, int cols, int ld, const float* d,
                                     float* out, int32_t* ay, int32_t* ax, hipStream_t st);
 

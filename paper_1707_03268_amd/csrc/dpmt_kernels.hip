@@ -1965,6 +1965,120 @@ hipError_t launch_dt_single(const float* resp, int rows, int cols, int ld, const
 }
 
 // ---------------------------------------------------------------------------
+// single-map distance transform by lower envelopes: the same result for every
+// target, found in time linear in the line length whatever the deformation.
+// Along a line, v[x] - c(x - t) = h_x + 2 a t x - a t^2 + b t with
+// h_x = v[x] - a x^2 - b x, so the best x for target t is the line of largest
+// value at t among the lines h_x + 2 a x t, whose slopes grow with x: their
+// upper envelope is built in one pass over x (a stack; line x beats the top p
+// for t > s = (h_p - h_x) / (2 a (x - p)); p leaves the stack when that
+// happens at or before the point where p itself took over), and targets in
+// increasing order walk it with one pointer.  The envelope is built in FP64
+// (for lines up to 2^14 cells a x^2 and b x are exact there, so h_x carries
+// a single FP64 rounding), and the answer is decided in FP32 among the
+// envelope line found and its two neighbours, with the same value formula
+// and tie rule (smallest x) as the window scan, so that the two methods pick
+// the same maximiser wherever the FP32 values differ.  One thread per line;
+// the envelope of line i lives in scratch element [k][i] (index k, line i
+// fastest), so that the threads of a wavefront touch consecutive words.
+// ---------------------------------------------------------------------------
+template <class Load>
+__device__ __forceinline__ void env_line(const Load& load, int n, int nl, int line, float a, float b,
+                                         int32_t* __restrict__ hx, double* __restrict__ hz,
+                                         float* __restrict__ ov, int64_t ostride, int32_t* __restrict__ oa) {
+    const double A = a, B = b;
+    // envelope: line hx[j] is the best from hz[j] on (hz[0] = -inf); -inf
+    // values never win and are left out
+    int m = 0;
+    double htop = 0.0;
+    for (int x = 0; x < n; ++x) {
+        const float vx = load(x);
+        if (vx == -INFINITY) continue;
+        const double h = (double)vx - (A * x) * x - B * x;
+        double s = -INFINITY;
+        while (m > 0) {
+            const int p = hx[(int64_t)(m - 1) * nl + line];
+            s = (htop - h) / (2.0 * A * (double)(x - p));     // x beats p for t > s
+            if (m > 1 && s <= hz[(int64_t)(m - 1) * nl + line]) {
+                --m;                                           // p is never the smallest best
+                const int q = hx[(int64_t)(m - 1) * nl + line];
+                htop = (double)load(q) - (A * q) * q - B * q;
+                continue;
+            }
+            break;
+        }
+        hx[(int64_t)m * nl + line] = x;
+        hz[(int64_t)m * nl + line] = m == 0 ? -INFINITY : s;
+        ++m;
+        htop = h;
+    }
+    int k = 0;
+    for (int t = 0; t < n; ++t) {
+        float best = -INFINITY;
+        int arg = t;                                   // a line of -inf only
+        if (m > 0) {
+            while (k + 1 < m && hz[(int64_t)(k + 1) * nl + line] < (double)t) ++k;
+            // decided in FP32 among the envelope line and its neighbours,
+            // in increasing x: the first of equal values wins
+            const int j0 = max(k - 1, 0), j1 = min(k + 1, m - 1);
+            arg = hx[(int64_t)j0 * nl + line];
+            for (int j = j0; j <= j1; ++j) {
+                const int x = hx[(int64_t)j * nl + line];
+                const float u = (float)(x - t);
+                const float e = load(x) - u * fmaf(a, u, b);
+                if (e > best) { best = e; arg = x; }
+            }
+        }
+        ov[(int64_t)t * ostride] = best;
+        oa[(int64_t)t * ostride] = arg;
+    }
+}
+
+__global__ __launch_bounds__(256) void dt1_env_row_kernel(const float* __restrict__ v, int rows, int cols,
+                                                          int64_t ld, float a, float b,
+                                                          int32_t* __restrict__ hx, double* __restrict__ hz,
+                                                          float* __restrict__ ov, int32_t* __restrict__ oa) {
+    const int y = blockIdx.x * 256 + threadIdx.x;
+    if (y >= rows) return;
+    const float* row = v + y * ld;
+    env_line([&](int x) { return row[x]; }, cols, rows, y, a, b, hx, hz, ov + (int64_t)y * cols, 1,
+             oa + (int64_t)y * cols);
+}
+
+__global__ __launch_bounds__(256) void dt1_env_col_kernel(const float* __restrict__ r1v,
+                                                          const int32_t* __restrict__ r1a, int rows,
+                                                          int cols, float a, float b,
+                                                          int32_t* __restrict__ hx, double* __restrict__ hz,
+                                                          float* __restrict__ out, int32_t* __restrict__ ay) {
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    if (x >= cols) return;
+    env_line([&](int y) { return r1v[(int64_t)y * cols + x]; }, rows, cols, x, a, b, hx, hz, out + x, cols,
+             ay + x);
+}
+
+__global__ void dt1_env_ax_kernel(const int32_t* __restrict__ ay, const int32_t* __restrict__ r1a, int rows,
+                                  int cols, int32_t* __restrict__ ax) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= (int64_t)rows * cols) return;
+    const int x = (int)(i % cols);
+    ax[i] = r1a[(int64_t)ay[i] * cols + x];
+}
+
+hipError_t launch_dt_envelope(const float* resp, int rows, int cols, int ld, const float* d, float* r1v,
+                              int32_t* r1a, int32_t* hx, double* hz, float* out, int32_t* ay, int32_t* ax,
+                              hipStream_t st) {
+    if ((int64_t)rows * cols <= 0) return hipSuccess;
+    hipLaunchKernelGGL(dt1_env_row_kernel, dim3((rows + 255) / 256), dim3(256), 0, st, resp, rows, cols,
+                       (int64_t)ld, d[1], d[0], hx, hz, r1v, r1a);
+    hipLaunchKernelGGL(dt1_env_col_kernel, dim3((cols + 255) / 256), dim3(256), 0, st, r1v, r1a, rows, cols,
+                       d[3], d[2], hx, hz, out, ay);
+    if (ax)
+        hipLaunchKernelGGL(dt1_env_ax_kernel, dim3((unsigned)(((int64_t)rows * cols + 255) / 256)), dim3(256), 0,
+                           st, ay, r1a, rows, cols, ax);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // allocation-free single-map transform: the scratch of launch_dt_single (line
 // maxima, then the row pass's values and argmax) lives in this file-scope
 // array.  Every kernel writes each scratch element it later reads, so nothing

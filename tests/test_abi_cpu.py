@@ -541,3 +541,16 @@ def test_hog_arguments_host_only():
     assert call(ok, feats=None) == _abi.DPMT_E_INVALID
     assert call([(0, 16385, 12, 1, 2, 4, 1.0)]) == _abi.DPMT_E_UNSUPPORTED
     assert lib.dpmt_hog_pyramid(None, img, 30, 40, 0, None, out, None) == _abi.DPMT_E_INVALID
+
+
+def test_distance_transform_method_validation():
+    """An unknown method is DPMT_E_INVALID; the envelope method checks its
+    arguments like the window method (no device needed to reject them)."""
+    lib = _abi.load()
+    d = (ctypes.c_float * 4)(0.0, 0.1, 0.0, 0.1)
+    p = ctypes.c_void_p(16)
+    assert lib.dpmt_distance_transform_method(p, 4, 4, 4, d, p, p, p, 7, None) == _abi.DPMT_E_INVALID
+    assert lib.dpmt_distance_transform_method(p, 4, 4, 3, d, p, p, p, _abi.DT_ENVELOPE, None) == _abi.DPMT_E_INVALID
+    bad = (ctypes.c_float * 4)(0.0, 0.0, 0.0, 0.1)
+    assert lib.dpmt_distance_transform_method(p, 4, 4, 4, bad, p, p, p, _abi.DT_ENVELOPE, None) == _abi.DPMT_E_INVALID
+    assert lib.dpmt_distance_transform_method(p, 4, 4, 4, d, p, p, None, _abi.DT_ENVELOPE, None) == _abi.DPMT_E_INVALID

@@ -62,6 +62,70 @@ def test_distance_transform_integer_ties(seed):
     np.testing.assert_array_equal(ax.cpu().numpy(), ref.arg_x)
 
 
+@pytest.mark.parametrize("shape", DT_CASES)
+def test_distance_transform_envelope_random(shape):
+    """The lower-envelope method against the oracle, and against the window
+    scans: the same maxima, the same maximisers wherever the oracle's margin
+    exceeds the tolerance."""
+    from paper_1707_03268_amd import distance_transform
+    rows, cols = shape
+    note(f"DT envelope random {shape}")
+    rng = np.random.default_rng(rows * 1000 + cols + 7)
+    resp = rng.standard_normal((rows, cols)).astype(np.float32)
+    d = np.array([rng.uniform(-0.3, 0.3), rng.uniform(0.01, 0.2), rng.uniform(-0.3, 0.3), rng.uniform(0.01, 0.2)], np.float32)
+    t = torch.from_numpy(resp).cuda()
+    D, ay, ax = distance_transform(t, d, method="envelope")
+    Dw, ayw, axw = distance_transform(t, d)
+    torch.cuda.synchronize()
+    ref = oracle.distance_transform(resp, d)
+    np.testing.assert_allclose(D.cpu().numpy(), ref.D, atol=2e-5, rtol=0)
+    ok = ref.margin > 1e-4
+    np.testing.assert_array_equal(ay.cpu().numpy()[ok], ref.arg_y[ok])
+    np.testing.assert_array_equal(ax.cpu().numpy()[ok], ref.arg_x[ok])
+    np.testing.assert_array_equal(ay.cpu().numpy()[ok], ayw.cpu().numpy()[ok])
+    np.testing.assert_allclose(D.cpu().numpy(), Dw.cpu().numpy(), atol=1e-6, rtol=0)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_distance_transform_envelope_integer_ties(seed):
+    """Exact FP32 data: every value and every maximiser, ties included, equal
+    to the oracle's (the envelope keeps the smallest of tied candidates)."""
+    from paper_1707_03268_amd import distance_transform
+    note(f"DT envelope integer ties seed {seed}")
+    rng = np.random.default_rng(60 + seed)
+    rows, cols = 29, 41
+    resp = rng.integers(-4, 5, size=(rows, cols)).astype(np.float32)
+    d = np.array([rng.integers(-1, 2), rng.choice([0.25, 0.5, 1.0]), rng.integers(-1, 2), rng.choice([0.25, 1.0])], np.float32)
+    D, ay, ax = distance_transform(torch.from_numpy(resp).cuda(), d, method="envelope")
+    torch.cuda.synchronize()
+    ref = oracle.distance_transform(resp, d)
+    np.testing.assert_array_equal(D.cpu().numpy(), ref.D)
+    np.testing.assert_array_equal(ay.cpu().numpy(), ref.arg_y)
+    np.testing.assert_array_equal(ax.cpu().numpy(), ref.arg_x)
+
+
+@pytest.mark.parametrize("dq", [0.001, 1e-5])
+def test_distance_transform_weak_deformation_both_methods(dq):
+    """Weak deformation (the windows grow to whole lines): both methods equal
+    the oracle; -inf cells never win."""
+    from paper_1707_03268_amd import distance_transform
+    note(f"DT weak deformation {dq}")
+    rng = np.random.default_rng(int(1 / dq))
+    rows, cols = 96, 211
+    resp = rng.standard_normal((rows, cols)).astype(np.float32)
+    resp[rng.random((rows, cols)) < 0.05] = -np.inf
+    d = np.array([0.002, dq, -0.001, dq], np.float32)
+    ref = oracle.distance_transform(resp, d)
+    ok = ref.margin > 1e-4
+    t = torch.from_numpy(resp).cuda()
+    for method in ("envelope", "window"):
+        D, ay, ax = distance_transform(t, d, method=method)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(D.cpu().numpy(), ref.D, atol=2e-5, rtol=0, err_msg=method)
+        np.testing.assert_array_equal(ay.cpu().numpy()[ok], ref.arg_y[ok], err_msg=method)
+        np.testing.assert_array_equal(ax.cpu().numpy()[ok], ref.arg_x[ok], err_msg=method)
+
+
 def test_distance_transform_pitched_input():
     from paper_1707_03268_amd import distance_transform
     note("DT pitched input")
