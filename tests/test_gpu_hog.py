@@ -135,3 +135,68 @@ def test_invalid_levels_are_rejected_before_any_write(ctx):
             ctx.hog_pyramid(img, levels, feats)
     torch.cuda.synchronize()
     assert torch.isnan(feats).all()
+
+
+def test_scores_from_images_end_to_end():
+    """Algorithm 1 from pixels: the GPU's HOG pyramid of two images is scored
+    on the GPU (BF16 tensor form) and compared with the oracle's scores of the
+    oracle's HOG pyramid of the same images: scores within the BF16 tolerance
+    plus what the features' float32 error can move them, placements equal
+    above the margin, and the detection set at a threshold equal to the
+    thresholding of the GPU's own scores."""
+    import oracle
+    from paper_1707_03268_amd import Context
+    from _gpu_common import oracle_basis
+    sizes = [(200, 150), (160, 136)]
+    pyrs, total = workloads.build_pyramids(sizes)
+    bank = workloads.build_bank(2, 1)
+    imgs = [workloads.synthetic_image(40 + i, w, h) for i, (w, h) in enumerate(sizes)]
+    note("scores from images: 2 images, 54 filters, HOG on the GPU")
+    feats = torch.full((total, 32), float("nan"), dtype=torch.float32, device="cuda")
+    ctx = Context(0)
+    for img, pyr in zip(imgs, pyrs):
+        ctx.hog_pyramid(torch.from_numpy(img).cuda(), workloads.hog_levels(pyr), feats)
+    ctx.load_filters(bank.filters, bank.components)
+    ctx.decompose(16)
+    U = oracle_basis(bank.filters, 16)
+    lay = ctx.plan(pyrs)
+    scores = torch.empty(lay.n_score, dtype=torch.float32, device="cuda")
+    offs = torch.empty(lay.n_offsets, dtype=torch.int16, device="cuda")
+    ctx.score_pyramid("tensor_bf16", feats, scores, offs)
+    torch.cuda.synchronize()
+    s, o = scores.cpu().numpy(), offs.cpu().numpy()
+    # the oracle's own HOG levels, scored by the oracle
+    # the BF16 target, doubled because the HOG channels reach about twice the
+    # synthetic features' range, plus the features' float32 error carried by 9
+    # unit-norm filters of at most 8 x 15 x 32 taps: 9 * 2e-5 * sqrt(3840)
+    tol = 2e-2 + 9 * 2e-5 * 3840 ** 0.5
+    worst = 0.0
+    checked = 0
+    for i, (img, pyr) in enumerate(zip(imgs, pyrs)):
+        levels = [hog.hog_level(img, hog.HogLevel(r - 2 * pr, c - 2 * pc, cell, inv, pr, pc))
+                  for (_, r, c, pr, pc, cell, inv) in workloads.hog_levels(pyr)]
+        ref = oracle.score_pyramid(levels, bank.filters, bank.components, pyr.octave, U)
+        for (lvl, comp), sm in ref.items():
+            k = lay.find(i, lvl, comp)
+            Ho, Wo = int(lay.map_rows[k]), int(lay.map_cols[k])
+            if Ho * Wo == 0:
+                continue
+            g = s[lay.map_score_off[k]:lay.map_score_off[k] + Ho * Wo].reshape(Ho, Wo)
+            fin = np.isfinite(sm.score)
+            assert np.array_equal(np.isfinite(g), fin)
+            if fin.any():
+                e = float(np.max(np.abs(g[fin] - sm.score[fin])))
+                worst = max(worst, e)
+                assert e <= tol, (i, lvl, comp, e)
+            npart = len(bank.components[comp].parts)
+            go = o[lay.map_offs_off[k]:lay.map_offs_off[k] + Ho * Wo * npart * 2].reshape(npart, Ho, Wo, 2)
+            ok = sm.margin > tol
+            checked += int(ok.sum())
+            assert np.array_equal(go[ok], sm.offsets[ok]), (i, lvl, comp)
+    note(f"  max |score err| {worst:.3g}, {checked} placements checked")
+    assert checked > 0
+    fin = s[np.isfinite(s)]
+    tau = float(np.quantile(fin, 0.999))
+    rec, sc, n = ctx.detect(scores, tau)
+    assert n == int((fin >= tau).sum()) and n > 0
+    ctx.close()
