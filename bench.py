@@ -192,10 +192,40 @@ class Stream:
     def chunk_features(self, k: int):
         return self.feats[k * self.cells:(k + 1) * self.cells]
 
+    def add_pipeline(self, ctx2) -> None:
+        """A second context (same filters, decomposition and tile
+        configuration, planned here for the same chunk) with its own score,
+        offset and workspace buffers and its own stream: chunks then alternate
+        between the two, so that one chunk's placement (VALU-bound) can run
+        while the next chunk's correlation (MFMA- and store-bound) runs."""
+        torch = self.torch
+        lay2 = ctx2.plan(self.wl.pyramids[:self.chunk])
+        assert lay2.n_score == self.lay.n_score and lay2.n_offsets == self.lay.n_offsets
+        self.ctx2 = ctx2
+        self.scores2 = torch.empty_like(self.scores)
+        self.offs2 = torch.empty_like(self.offs)
+        self.side = [torch.cuda.Stream(), torch.cuda.Stream()]     # default priority
+
     def step(self, mode: str, stream) -> None:
+        if getattr(self, "ctx2", None) is None:
+            for k in range(self.n_chunks):
+                self.ctx.score_pyramid(mode, self.chunk_features(k), self.scores, self.offs, stream=stream)
+                self.ctx.detect_into(self.scores, self.tau, self.dets[k], self.counts[k], stream=stream)
+            return
+        torch = self.torch
+        start = torch.cuda.Event()
+        start.record(stream)
+        for s in self.side:
+            s.wait_event(start)
         for k in range(self.n_chunks):
-            self.ctx.score_pyramid(mode, self.chunk_features(k), self.scores, self.offs, stream=stream)
-            self.ctx.detect_into(self.scores, self.tau, self.dets[k], self.counts[k], stream=stream)
+            c = k % 2
+            ctx, sc, of = (self.ctx, self.scores, self.offs) if c == 0 else (self.ctx2, self.scores2, self.offs2)
+            ctx.score_pyramid(mode, self.chunk_features(k), sc, of, stream=self.side[c])
+            ctx.detect_into(sc, self.tau, self.dets[k], self.counts[k], stream=self.side[c])
+        for s in self.side:
+            done = torch.cuda.Event()
+            done.record(s)
+            stream.wait_event(done)
 
     def score_chunk(self, mode: str, k: int = 0) -> None:
         self.ctx.score_pyramid(mode, self.chunk_features(k), self.scores, self.offs)
@@ -673,6 +703,8 @@ def main() -> None:
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="keep the default correlation tile configuration instead of timing them all")
     ap.add_argument("--tile-config", type=int, default=None, help="correlation tile configuration index")
+    ap.add_argument("--contexts", type=int, default=1, choices=[1, 2],
+                    help="contexts the stream's chunks alternate between, each on its own stream")
     ap.add_argument("--no-dt-methods", dest="dt_methods", action="store_false",
                     help="skip timing the single-map transform's two methods")
     ap.add_argument("--no-hog", dest="hog", action="store_false",
@@ -728,15 +760,33 @@ def main() -> None:
         ctx.set_tile_config(args.mode, args.tile_config)
     S.score_chunk(args.mode, 0)
     S.tau = pick_tau(torch, S.scores)
+    if args.contexts == 2 and S.n_chunks > 1:
+        ctx2 = Context(0)
+        ctx2.load_filters(wl.bank.filters, wl.bank.components)
+        if args.mode != "direct_fp32":
+            ctx2.decompose(args.rank)
+        ctx2.set_tile_config(args.mode, ctx.get_tile_config(args.mode))
+        S.add_pipeline(ctx2)
+        log("pipeline: chunks alternate between two contexts on two streams")
 
     def step(st):
         S.step(args.mode, st)
 
     ctx.set_launch(args.launch)
+    # the stage split runs the chunks one after another on one context (the
+    # kernels alone), also when the timed steps alternate two contexts
+    pipe, S.ctx2 = getattr(S, "ctx2", None), None
     stages = stage_split(torch, ctx, step, 1) if args.launch != "graph" else {}
+    S.ctx2 = pipe
     ms, pct = run_steps(torch, step, args.steps, args.warmup)
     ctx.set_launch("batched")
     counts = S.counts.cpu().numpy().ravel()
+    n_ctx = 2 if getattr(S, "ctx2", None) is not None else 1
+    if n_ctx == 2:                                   # free the second workspace for the other legs
+        S.ctx2.close()
+        S.ctx2 = None
+        del S.scores2, S.offs2
+        torch.cuda.empty_cache()
     value = n_resp / (ms * 1e-3)
     log(f"{args.mode} ({args.launch}): {ms:.3f} ms/step, {value:.4g} resp/s, stages per chunk {stages}, "
         f"detections per step {int(counts.sum())} (tau {S.tau:.4g})")
@@ -823,6 +873,7 @@ def main() -> None:
         "step_ms_percentiles": pct,
         "detections_per_step": int(counts.sum()),
         "launch": args.launch,
+        "contexts": n_ctx,
         "launch_strategies": launches,
         "tile_config": tuning if tuning else {"chosen": args.tile_config},
         "correlation": corr,
