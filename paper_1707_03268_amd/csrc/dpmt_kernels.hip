@@ -299,6 +299,10 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
     const int tid = threadIdx.x;
     const int lane = tid & 63, wv = tid >> 6;
     const int p = lane & 31, j = lane >> 5;
+    // in a tile of several wavefronts along x, a wavefront whose 32 columns
+    // all lie right of the map (the last tile of a level rarely fills all of
+    // 32 * WX) loads and waits with the others but issues no MFMA
+    const bool xlive = WX == 1 || t.x0 + 32 * (__builtin_amdgcn_readfirstlane(wv) % WX) < t.Wo;
 
     v16f acc[TY][BB];
 #pragma unroll
@@ -508,11 +512,13 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
                         Br[(n + 1) & 1][b] = *reinterpret_cast<const Frag*>(gbb + (b * HS + n + 1) * chunk_bytes);
                     Ar[(n + TY) % (TY + 1)] = lds_frag<KIND>(abase + (n + TY) * pitch, PB);
                 }
+                if (xlive) {
 #pragma unroll
-                for (int i = 0; i < TY; ++i)
+                    for (int i = 0; i < TY; ++i)
 #pragma unroll
-                    for (int b = 0; b < BB; ++b)
-                        acc[i][b] = mfma_step<KIND>(Ar[(n + i) % (TY + 1)], Br[n & 1][b], acc[i][b]);
+                        for (int b = 0; b < BB; ++b)
+                            acc[i][b] = mfma_step<KIND>(Ar[(n + i) % (TY + 1)], Br[n & 1][b], acc[i][b]);
+                }
                 // keep the source order: the next row's LDS reads are issued
                 // ahead of this row's MFMAs and their latency hides behind them
                 __builtin_amdgcn_sched_barrier(0);
@@ -533,10 +539,12 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
                         Bn[b] = *reinterpret_cast<const Frag*>(gbb + (b * h + n + 1) * chunk_bytes);
                     An = lds_frag<KIND>(abase + (n + TY) * pitch, PB);
                 }
+                if (xlive) {
 #pragma unroll
-                for (int i = 0; i < TY; ++i)
+                    for (int i = 0; i < TY; ++i)
 #pragma unroll
-                    for (int b = 0; b < BB; ++b) acc[i][b] = mfma_step<KIND>(A[i], B[b], acc[i][b]);
+                        for (int b = 0; b < BB; ++b) acc[i][b] = mfma_step<KIND>(A[i], B[b], acc[i][b]);
+                }
                 if (nx) {
 #pragma unroll
                     for (int i = 0; i + 1 < TY; ++i) A[i] = A[i + 1];
