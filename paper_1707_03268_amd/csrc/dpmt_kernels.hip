@@ -136,8 +136,10 @@ __host__ __device__ constexpr int corr_chunk_buffers(bool dma, int wx) {
 
 // Whether a correlation instance gives the 6-, 7- and 8-row filters fully
 // unrolled bodies (staged CORR_NBUF chunks deep); host and device agree on it.
+// FP8 fragments are twice as wide, so FP8 unrolls with one filter block per
+// wavefront only.
 __host__ __device__ constexpr bool corr_unrolls(CorrKind kind, int PB, int BB, int HMAX) {
-    return kind != CORR_FP8 && HMAX >= 8 && !(PB == 32 && BB == 2);
+    return HMAX >= 8 && !(PB == 32 && BB == 2) && (kind != CORR_FP8 || BB == 1);
 }
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
@@ -288,12 +290,14 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
     u32x4* gbuf1 = gbuf0 + BB * h * CU;
     // Unrolled heights stage the filter chunks with direct global-to-LDS loads,
     // CORR_NBUF buffers deep (the chunks of steps gs + 1 .. gs + CORR_NBUF - 1
-    // are in flight while step gs computes); each wavefront loads UPW 1 KB
-    // units of a chunk.  Other tiles stage through registers, two buffers.
-    constexpr bool DMA = HS > 0 && FragT<KIND>::bytes == 16;
+    // are in flight while step gs computes); each wavefront loads UPW units
+    // of a chunk, a unit (one filter row of one block: 64 fragments) being
+    // LPU loads of 1 KB.  Other tiles stage through registers, two buffers.
+    constexpr bool DMA = HS > 0;
     constexpr int UPW = DMA ? (BB * HS + WY - 1) / WY : 1;
+    constexpr int LPU = FB / 16;                   // 1 KB loads per unit
     constexpr int NB = corr_chunk_buffers(DMA, WX);
-    static_assert(!DMA || (NB - 2) * UPW <= 15, "outstanding chunk loads must fit the vmcnt immediate");
+    static_assert(!DMA || (NB - 2) * UPW * LPU <= 15, "outstanding chunk loads must fit the vmcnt immediate");
     auto gbuf = [&](int k) { return gbuf0 + k * (BB * h * CU); };
 
     const int tid = threadIdx.x;
@@ -346,7 +350,8 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
     const int wx = t.x0 + wcc;
 
     // chunk cidx = group * BB * total + step: unit (b, n) of the packed operand
-    // of block fb0 + b lies at ((fb0 + b) * total + cidx) * h + n units of 1 KB
+    // of block fb0 + b lies at ((fb0 + b) * total + cidx) * h + n units of
+    // chunk_bytes (64 fragments: 1 KB, 2 KB for FP8)
     const int wvu = __builtin_amdgcn_readfirstlane(wv);
     auto dma_chunk = [&](int cidx, u32x4* dst) {
 #pragma unroll
@@ -354,10 +359,12 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
             const int u = min(wvu + WY * m, BB * HS - 1);  // surplus waves reload the last unit
             const int b = u / (HS > 0 ? HS : 1), n = u - b * (HS > 0 ? HS : 1);
             const char* src = G + g.g_off +
-                              ((int64_t)((t.fb0 + b) * total + cidx) * (HS > 0 ? HS : 1) + n) * 1024 + lane * 16;
-            __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void*)src,
-                                             (__attribute__((address_space(3))) void*)(reinterpret_cast<char*>(dst) + u * 1024),
-                                             16, 0, 0);
+                              ((int64_t)((t.fb0 + b) * total + cidx) * (HS > 0 ? HS : 1) + n) * chunk_bytes + lane * 16;
+#pragma unroll
+            for (int k = 0; k < LPU; ++k)
+                __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void*)(src + k * 1024),
+                                                 (__attribute__((address_space(3))) void*)(reinterpret_cast<char*>(dst) + u * chunk_bytes + k * 1024),
+                                                 16, 0, 0);
         }
     };
 
@@ -459,8 +466,8 @@ __device__ __forceinline__ void corr_tile(const CorrTile& t, const GroupDesc* __
             // chunk already issued (gs + 1 .. gs + NB - 2) are outstanding;
             // vmcnt(N) keeps expcnt and lgkmcnt at their maxima
             const int later = min(NB - 2, nsteps - 1 - gs);
-            if (NB >= 4 && later >= 2) __builtin_amdgcn_s_waitcnt(0xF70 | (2 * UPW));
-            else if (later >= 1) __builtin_amdgcn_s_waitcnt(0xF70 | UPW);
+            if (NB >= 4 && later >= 2) __builtin_amdgcn_s_waitcnt(0xF70 | (2 * UPW * LPU));
+            else if (later >= 1) __builtin_amdgcn_s_waitcnt(0xF70 | (UPW * LPU));
             else __builtin_amdgcn_s_waitcnt(0xF70);
         }
         __syncthreads();                           // window and chunk `step` visible
