@@ -16,13 +16,13 @@
 // for this file), so the decisions are a fixed function of the inputs.  Ties
 // go to the first channel and the first direction.
 //
-// Two kernels per call.  hog_hist_kernel: one workgroup per tile of 64 x 64
-// resized pixels (16 x 16 cells of 4 pixels, or 8 x 8 cells of 8); the
+// Two kernels per call.  hog_hist_kernel: one workgroup per tile of 32 x 32
+// resized pixels (8 x 8 cells of 4 pixels, or 4 x 4 cells of 8); the
 // sampled tile with its halo, the per-pixel votes and per-thread partial
 // histograms live in LDS; it writes the tile's 18-bin cell histograms and
 // their energies.  hog_feat_kernel: one thread per padded cell; it reads its
 // histogram and the 9 energies around it and writes the cell's 32 floats.
-#include "dpmt_internal.h"
+#include "dpmt_hog.h"
 
 #include <cmath>
 
@@ -34,7 +34,7 @@ namespace dpmt {
 
 namespace {
 
-constexpr int HOG_TILE = 64;                       // resized pixels per tile side
+constexpr int HOG_TILE = HOG_TILE_PIXELS;          // resized pixels per tile side
 constexpr int HOG_MAX_CELL = 8;
 constexpr int HOG_S = HOG_TILE + HOG_MAX_CELL + 2; // sampled side: votes + gradient halo
 constexpr int HOG_V = HOG_TILE + HOG_MAX_CELL;     // vote side: the cells' 2c windows
@@ -126,16 +126,16 @@ __global__ __launch_bounds__(256) void hog_hist_kernel(const uint8_t* __restrict
     }
     __syncthreads();
 
-    // 4. votes: thread t owns quadrant items t * qpt .. t * qpt + qpt - 1
-    // (item = 4 * cell + quadrant); a cell's window is its 2c x 2c pixels,
-    // the upper-left quadrant taking the pixels whose upper-left cell centre
-    // is this cell's upper-left neighbour
-    const int qpt = 4 * T * T / 256;                               // 4 (c = 4) or 1 (c = 8)
+    // 4. votes: thread t < 4 T^2 owns quadrant item t (item = 4 * cell +
+    // quadrant); a cell's window is its 2c x 2c pixels, the upper-left
+    // quadrant taking the pixels whose upper-left cell centre is this cell's
+    // upper-left neighbour
+    const int items = 4 * T * T;                                   // 256 (c = 4) or 64 (c = 8)
     float* mine = part + tid * HOG_BINS;
-    for (int b = 0; b < HOG_BINS; ++b) mine[b] = 0.f;
     const float invc = 1.f / (float)c;                             // exact (power of two)
-    for (int it = 0; it < qpt; ++it) {
-        const int item = tid * qpt + it, cell = item >> 2, quad = item & 3;
+    if (tid < items) {
+        for (int b = 0; b < HOG_BINS; ++b) mine[b] = 0.f;
+        const int item = tid, cell = item >> 2, quad = item & 3;
         const int ci = cell / T, cj = cell - ci * T;
         const int gi = Y0 / c + ci, gj = X0 / c + cj;              // level cell
         const int r0 = ci * c + (quad >> 1) * c, q0 = cj * c + (quad & 1) * c;
@@ -156,21 +156,18 @@ __global__ __launch_bounds__(256) void hog_hist_kernel(const uint8_t* __restrict
     }
     __syncthreads();
 
-    // cell totals (quadrant partials in order when c = 8), histogram and energy out
+    // cell totals (the 4 quadrant partials in order), histogram and energy out
     const int cells = T * T;
     for (int cell = tid; cell < cells; cell += 256) {
         const int ci = cell / T, cj = cell - ci * T;
         const int gi = Y0 / c + ci, gj = X0 / c + cj;
         if (gi >= L.nr || gj >= L.nc) continue;
         float h[HOG_BINS];
-        const int t0 = qpt == 4 ? cell : 4 * cell;                 // first thread holding the cell
-        const int nt = qpt == 4 ? 1 : 4;
+        const int t0 = 4 * cell;                                   // the 4 threads holding its quadrants
 #pragma unroll
-        for (int b = 0; b < HOG_BINS; ++b) {
-            float s = part[t0 * HOG_BINS + b];
-            for (int k = 1; k < nt; ++k) s += part[(t0 + k) * HOG_BINS + b];
-            h[b] = s;
-        }
+        for (int b = 0; b < HOG_BINS; ++b)
+            h[b] = ((part[t0 * HOG_BINS + b] + part[(t0 + 1) * HOG_BINS + b]) + part[(t0 + 2) * HOG_BINS + b]) +
+                   part[(t0 + 3) * HOG_BINS + b];
         float e = 0.f;
 #pragma unroll
         for (int o = 0; o < 9; ++o) {
@@ -254,6 +251,7 @@ hipError_t launch_hog(const uint8_t* img, int H, int W, const HogLevelDesc* leve
                       int n_tiles, const int2* blocks, int n_blocks, const HogTable& tab, float* hist,
                       float* energy, float* feats, hipStream_t st) {
     static_assert(256 * HOG_BINS <= 3 * HOG_S * HOG_S, "partial histograms fit in the sampled tile");
+    static_assert(4 * (HOG_TILE / 4) * (HOG_TILE / 4) <= 256, "one quadrant item per thread");
     const size_t bytes = hog_lds_bytes();
     if (n_tiles > 0) {
         if (bytes > 65536) {

@@ -2,6 +2,7 @@
 // filter bank, operand packing, planning of work lists, and the launch
 // sequence of dpmt_score_pyramid.  Kernels live in dpmt_kernels.hip.
 #include "dpmt.h"
+#include "dpmt_hog.h"
 #include "dpmt_internal.h"
 
 #include <algorithm>
