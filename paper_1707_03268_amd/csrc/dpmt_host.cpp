@@ -1208,13 +1208,10 @@ PlaceLds place_lds_of(const dpmt_ctx* c, const int2* blk, size_t n) {
     return pl;
 }
 
-// Placement workgroups one CU holds by LDS (at most PLACE_WG_PER_CU, the
-// register limit), for a block that needs `bytes` of dynamic LDS.
-int place_wg_per_cu(size_t bytes) {
-    const size_t gran = 512, lds = 160 * 1024 - 1024;      // 1 KB kept for the static LDS
-    const size_t per = (bytes + gran - 1) / gran * gran;
-    return (int)std::min<size_t>(PLACE_WG_PER_CU, per ? lds / per : PLACE_WG_PER_CU);
-}
+// Placement workgroups of 256 threads one CU holds by LDS (at most
+// PLACE_WG_PER_CU, the register limit), for a block that needs `bytes` of
+// dynamic LDS.
+int place_wg_per_cu(size_t bytes) { return place_blocks_per_cu(bytes, 256); }
 
 // The whole call as one launch per stage: value-range reset, projection of
 // every level, correlation of every tile, placement of every score map.

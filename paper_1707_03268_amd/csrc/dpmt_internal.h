@@ -185,6 +185,15 @@ size_t place_lds_bytes(const PlaceLds& l);
 // Dynamic LDS a placement block may use: 160 KB per CU, less 1 KB kept for
 // the kernel's own static LDS (checked at launch).
 constexpr size_t PLACE_LDS_MAX = 159 * 1024;
+// Placement workgroups of nt threads (256 or 512) one CU holds, for blocks of
+// `bytes` dynamic LDS: by LDS (allocated in 512-byte granules) and by
+// registers (6 wavefronts per SIMD).
+inline int place_blocks_per_cu(size_t bytes, int nt) {
+    const size_t per = (bytes + 511) / 512 * 512;
+    const int by_regs = PLACE_WG_PER_CU * 256 / nt;
+    const size_t by_lds = per ? PLACE_LDS_MAX / per : (size_t)by_regs;
+    return by_lds < (size_t)by_regs ? (int)by_lds : by_regs;
+}
 // Row span (floats) a part of response width Wp can need in the staging
 // buffer: 2 * (PLACE_CW - 1) targets apart, plus a window clamped to the line
 // and aligned to whole 16-byte runs.

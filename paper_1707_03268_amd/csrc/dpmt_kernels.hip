@@ -1348,7 +1348,9 @@ size_t place_lds_bytes(const PlaceLds& l) {
            (size_t)16 * l.max_parts;
 }
 
-constexpr int PLACE_LOADS = PLACE_STAGE / 1024;        // staged float4 per thread and round
+// staged float4 per thread and round, for workgroups of NT threads
+template <int NT>
+constexpr int place_loads() { return PLACE_STAGE / (4 * NT); }
 
 // Window of a line from its value range with the reciprocal 1/(2a) given;
 // the hardware square root is within a few ulp, which the 1-cell margins of
@@ -1393,7 +1395,9 @@ __device__ __forceinline__ int4 part_windows(const MapPart& P, const int* __rest
     return make_int4(ulo, uhi, max(vlo, -(P.Hp + 1)), min(vhi, P.Hp + 1));
 }
 
-// win: the part's part_windows, read from LDS by every lane (made uniform here).
+// win: the part's part_windows, read from LDS by every lane (made uniform
+// here).  NT: threads of the workgroup (2^LNT).
+template <int NT>
 __device__ __forceinline__ PlaceGeo place_geo(const MapPart& P, const MapDesc& M, int xs, int4 win,
                                               int stage_words) {
     constexpr int CW = PLACE_CW;
@@ -1440,9 +1444,11 @@ __device__ __forceinline__ PlaceGeo place_geo(const MapPart& P, const MapDesc& M
     G.ry1 = min(P.Hp - 1, 2 * (M.Ho - 1) + P.vy + G.vhi + 3);
     G.rounds = (G.live && G.ry1 >= G.ry0) ? (G.ry1 - G.ry0 + G.RB) >> lrb : 0;
     G.X0 = G.tx0 + ulo - d;
-    G.tpr = 256 >> lrb;
-    G.nq = (G.CH + G.tpr - 1) >> (8 - lrb);               // <= PLACE_LOADS since RB * CH <= 512
-    G.lrow = (int)threadIdx.x >> (8 - lrb);
+    constexpr int LNT = NT == 512 ? 9 : 8;
+    static_assert(NT == 1 << LNT, "256 or 512 threads");
+    G.tpr = NT >> lrb;
+    G.nq = (G.CH + G.tpr - 1) >> (LNT - lrb);             // <= place_loads<NT>() since RB * CH <= 512
+    G.lrow = (int)threadIdx.x >> (LNT - lrb);
     G.lcol = (int)threadIdx.x & (G.tpr - 1);
     return G;
 }
@@ -1452,12 +1458,13 @@ __device__ __forceinline__ PlaceGeo place_geo(const MapPart& P, const MapDesc& M
 // aligned address with nothing depending on it until the store, so that all
 // of them are in flight together; out-of-map columns are masked at the store
 // (a clamped run lies wholly outside the map).
+template <int LD>
 __device__ __forceinline__ void place_load(const PlaceGeo& G, const float* __restrict__ resp,
-                                           int round, float4 (&pf)[PLACE_LOADS]) {
+                                           int round, float4 (&pf)[LD]) {
     const int y = min(G.ry0 + (round << G.lrb) + G.lrow, G.ry1);
     const float* base = resp + G.plane + __umul24(y, G.ld);     // full-rate 24-bit product
 #pragma unroll
-    for (int q = 0; q < PLACE_LOADS; ++q) {
+    for (int q = 0; q < LD; ++q) {
         const int x = G.X0 + 4 * (G.lcol + q * G.tpr);
         pf[q] = *reinterpret_cast<const float4*>(base + min(max(x, 0), G.ld - 4));
     }
@@ -1465,11 +1472,11 @@ __device__ __forceinline__ void place_load(const PlaceGeo& G, const float* __res
 
 // Store of a loaded round into the staging buffer, [row][parity][SH]: the
 // run x, x+1, x+2, x+3 (x even) goes to even[x/2 .. x/2+1], odd[x/2 .. x/2+1].
-__device__ __forceinline__ void place_store(const PlaceGeo& G, float* stage,
-                                            const float4 (&pf)[PLACE_LOADS]) {
+template <int LD>
+__device__ __forceinline__ void place_store(const PlaceGeo& G, float* stage, const float4 (&pf)[LD]) {
     if (G.lrow >= G.RB) return;
 #pragma unroll
-    for (int q = 0; q < PLACE_LOADS; ++q) {
+    for (int q = 0; q < LD; ++q) {
         const int c = G.lcol + q * G.tpr;
         if (q < G.nq && c < G.CH) {
             const int x = G.X0 + 4 * c;
@@ -1485,7 +1492,8 @@ __device__ __forceinline__ void place_store(const PlaceGeo& G, float* stage,
     }
 }
 
-__global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ maps,
+template <int NT>
+__global__ __launch_bounds__(NT) void place_kernel(const MapDesc* __restrict__ maps,
                                                     const MapPart* __restrict__ parts,
                                                     const int2* __restrict__ blkmap,
                                                     const float* __restrict__ resp,
@@ -1495,7 +1503,8 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
                                                     int16_t* __restrict__ offs, PlaceLds L,
                                                     int n_blocks, const uint8_t* __restrict__ flags) {
     constexpr int CW = PLACE_CW, PAD = PLACE_PAD, RPW = PLACE_RPW;
-    constexpr int ROWS = 256 / CW;                         // row slots of the workgroup
+    constexpr int ROWS = NT / CW;                          // row slots of the workgroup
+    constexpr int LD = place_loads<NT>();
     extern __shared__ __align__(16) float psm[];
     float* acc = psm;                                      // [acc_rows][CW]
     float* r1v = acc + L.acc_rows * CW;                    // [r1_rows][CW], row y' at y' + PAD
@@ -1548,21 +1557,21 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
         }
     }
 
-    for (int s = tid; s < M.n_parts; s += 256) win[s] = part_windows(parts[M.part_base + s], rmax, rmin);
+    for (int s = tid; s < M.n_parts; s += NT) win[s] = part_windows(parts[M.part_base + s], rmax, rmin);
     __syncthreads();
 
-    float4 pf[PLACE_LOADS];
-    PlaceGeo G = place_geo(parts[M.part_base], M, xs, win[0], L.stage_words);
+    float4 pf[LD];
+    PlaceGeo G = place_geo<NT>(parts[M.part_base], M, xs, win[0], L.stage_words);
     if (G.rounds > 0) place_load(G, resp, 0, pf);
 
     int pad_hp = -1;                                       // part height the -inf pad rows are at
     for (int s = 0; s < M.n_parts; ++s) {
         // pf holds round 0 of part s (when it has rows)
         if (G.live) {
-            for (int e = tid; e < G.Wq; e += 256) crow[e] = e < G.Wr ? quad_cost(G.ax, G.bx, G.ulo + e) : INFINITY;
-            for (int e = tid; e < G.Wc + 4; e += 256) ccol[e] = e < G.Wc ? quad_cost(G.ay, G.by, G.vlo + e) : INFINITY;
+            for (int e = tid; e < G.Wq; e += NT) crow[e] = e < G.Wr ? quad_cost(G.ax, G.bx, G.ulo + e) : INFINITY;
+            for (int e = tid; e < G.Wc + 4; e += NT) ccol[e] = e < G.Wc ? quad_cost(G.ay, G.by, G.vlo + e) : INFINITY;
             if (G.Hp != pad_hp) {                          // the row pass writes rows [0, Hp) only
-                for (int i = tid; i < 2 * PAD * CW; i += 256) {
+                for (int i = tid; i < 2 * PAD * CW; i += NT) {
                     const int r = i / CW;
                     r1v[(r < PAD ? r : G.Hp + r) * CW + (i - r * CW)] = -INFINITY;
                 }
@@ -1573,7 +1582,7 @@ __global__ __launch_bounds__(256) void place_kernel(const MapDesc* __restrict__ 
         __syncthreads();                                   // tables, pads, round 0 staged
         const bool has_next = s + 1 < M.n_parts;
         PlaceGeo Gn = G;
-        if (has_next) Gn = place_geo(parts[M.part_base + s + 1], M, xs, win[s + 1], L.stage_words);
+        if (has_next) Gn = place_geo<NT>(parts[M.part_base + s + 1], M, xs, win[s + 1], L.stage_words);
         if (G.live) {
             // row pass
             for (int r = 0; r < G.rounds; ++r) {
@@ -1709,20 +1718,30 @@ hipError_t launch_place(const MapDesc* maps, const MapPart* parts, const int2* b
         return hipErrorInvalidValue;
     const size_t bytes = place_lds_bytes(lds);
     if (bytes > PLACE_LDS_MAX) return hipErrorInvalidValue;
+    // A block's LDS does not grow with its threads: where LDS caps a CU below
+    // the register limit, blocks of 512 threads give it more wavefronts.
+    const bool wide = 8 * place_blocks_per_cu(bytes, 512) > 4 * place_blocks_per_cu(bytes, 256);
+    const void* fn = wide ? reinterpret_cast<const void*>(place_kernel<512>)
+                          : reinterpret_cast<const void*>(place_kernel<256>);
     // the kernel's own static LDS (queried once) must fit beside the dynamic part
     static const size_t static_lds = [] {
-        hipFuncAttributes fa;
-        return hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(place_kernel)) == hipSuccess
-                   ? fa.sharedSizeBytes : ~size_t(0);
+        hipFuncAttributes fa, fb;
+        return hipFuncGetAttributes(&fa, reinterpret_cast<const void*>(place_kernel<256>)) == hipSuccess &&
+                       hipFuncGetAttributes(&fb, reinterpret_cast<const void*>(place_kernel<512>)) == hipSuccess
+                   ? std::max(fa.sharedSizeBytes, fb.sharedSizeBytes) : ~size_t(0);
     }();
     if (static_lds > 160 * 1024 - PLACE_LDS_MAX) return hipErrorInvalidValue;
     if (bytes > 65536) {
-        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(place_kernel),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(place_kernel, dim3(xcd_grid(n_blocks, PLACE_XCL)), dim3(256), bytes, st, maps, parts,
-                       blkmap, resp, rkeys, rkeys + n_slots, scores, offs, lds, n_blocks, flags);
+    const dim3 grid(xcd_grid(n_blocks, PLACE_XCL));
+    if (wide)
+        hipLaunchKernelGGL(place_kernel<512>, grid, dim3(512), bytes, st, maps, parts, blkmap, resp, rkeys,
+                           rkeys + n_slots, scores, offs, lds, n_blocks, flags);
+    else
+        hipLaunchKernelGGL(place_kernel<256>, grid, dim3(256), bytes, st, maps, parts, blkmap, resp, rkeys,
+                           rkeys + n_slots, scores, offs, lds, n_blocks, flags);
     return hipGetLastError();
 }
 
