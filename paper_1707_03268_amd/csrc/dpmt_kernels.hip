@@ -1314,7 +1314,9 @@ __device__ __forceinline__ void line_window(float a, float b, float range, int n
 // Placement: the distance transform evaluated at the part anchors of every
 // root position, and the score assembly, in one kernel.
 //
-// Block = (score map, PLACE_CW consecutive root columns x0).  For each part i
+// Block = (score map, PLACE_CW consecutive root columns x0) of NT threads:
+// 256, or 512 where LDS rather than registers limits the blocks per CU (tall
+// maps), which gives such a CU twice the wavefronts.  For each part i
 // of the map's component (anchor v, cost d) the block
 //   1. row pass: for every part-map row y' it needs and every column of the
 //      strip, R1[y'][x0] = max over x' of resp_i[y'][x'] - c_x(x' - t_x) with
