@@ -230,12 +230,11 @@ struct dpmt_ctx {
     int n_chunks = 0;
     std::vector<int2> place_blk_chunk;            // placement blocks in chunk order
     std::vector<std::array<int, 2>> place_chunk;  // (begin, end) per chunk
-    PlaceLds place_lds{};                         // every map of the plan (the plan's limit check)
     // LDS of each launch, sized by its own maps: the batched launch is split
     // into runs of blocks of equal workgroups per CU (place_runs, (begin,
     // end) into place_blk); per-level launches and chunks get their own
     std::vector<std::array<int, 2>> place_runs;
-    std::vector<PlaceLds> place_runs_lds, place_lvl_lds, place_chunk_lds;
+    std::vector<size_t> place_runs_lds, place_lvl_lds, place_chunk_lds;   // dynamic LDS per launch
     dpmt_layout layout{};
 
     // device workspace
@@ -1182,30 +1181,17 @@ const std::vector<std::array<int, 2>>& corr_chunks(dpmt_ctx* c, dpmt_mode mode) 
 
 // Placement LDS for the maps of n blocks: the tallest map, the tallest and
 // widest part map and the most parts among them.
-PlaceLds place_lds_of(const dpmt_ctx* c, const int2* blk, size_t n) {
-    int max_Ho = 0, max_Hp = 0, max_Wp = 0, max_np = 1;
+// Dynamic LDS of a placement launch over these blocks: every block lays out
+// its own map's buffers, so the launch needs the largest of its maps'.
+size_t place_bytes_of(const dpmt_ctx* c, const int2* blk, size_t n) {
+    size_t bytes = 0;
     int last = -1;
     for (size_t b = 0; b < n; ++b) {
         if (blk[b].x == last) continue;
         last = blk[b].x;
-        const MapDesc& md = c->maps[blk[b].x];
-        max_Ho = std::max(max_Ho, md.Ho);
-        max_np = std::max(max_np, md.n_parts);
-        for (int sl = 0; sl < md.n_parts; ++sl) {
-            const MapPart& mp = c->map_parts[md.part_base + sl];
-            max_Hp = std::max(max_Hp, mp.Hp);
-            max_Wp = std::max(max_Wp, mp.Wp);
-        }
+        bytes = std::max(bytes, place_lds_bytes(place_lds_of_map(c->maps[last])));
     }
-    PlaceLds pl;
-    pl.acc_rows = std::max(max_Ho, 1);
-    pl.r1_rows = max_Hp + 2 * PLACE_PAD;
-    pl.stage_words = PLACE_STAGE;
-    // row table: window of at most Wp + 2 (CW - 1) + 3 (alignment) + 1 offsets,
-    // rounded up to 4; column table: at most 2 (Hp + 1) + 1 offsets plus 4
-    pl.ctab_words = (std::max(max_Wp + 2 * (PLACE_CW - 1) + 8, 2 * (max_Hp + 1) + 1 + 4) + 3) & ~3;
-    pl.max_parts = max_np;
-    return pl;
+    return bytes;
 }
 
 // Placement workgroups of 256 threads one CU holds by LDS (at most
@@ -1835,7 +1821,7 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
     c->m_image.clear(); c->m_level.clear(); c->m_comp.clear(); c->m_rows.clear(); c->m_cols.clear();
     c->m_score_off.clear(); c->m_offs_off.clear(); c->maps.clear(); c->map_parts.clear();
     int64_t score_off = 0, offs_off = 0;
-    int max_Ho = 0, max_Hp = 0, max_Wp = 0;
+    int max_Wp = 0;
     for (int i = 0; i < n_images; ++i) {
         const int L = (int)c->pyr[i].size(), oct = c->octave[i];
         for (int l = oct; l < L; ++l) {
@@ -1846,6 +1832,7 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
                 const int Ho = std::max(lv.rows - rs.h + 1, 0), Wo = std::max(lv.cols - rs.w + 1, 0);
                 const int np = (int)cm.parts.size();
                 MapDesc md{};
+                int map_Hp = 0, map_Wp = 0;               // tallest and widest part map
                 md.score_off = score_off;
                 md.offs_off = offs_off;
                 md.Ho = Ho;
@@ -1875,13 +1862,13 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
                     mp.inv2ax = (float)(0.5 / (double)mp.d[1]);
                     mp.inv2ay = (float)(0.5 / (double)mp.d[3]);
                     mp.bb4a = (float)((double)mp.d[0] * mp.d[0] / (4.0 * mp.d[1]));
-                    if (Ho > 0 && Wo > 0) {
-                        max_Hp = std::max(max_Hp, mp.Hp);
-                        max_Wp = std::max(max_Wp, mp.Wp);
-                    }
+                    if (Ho > 0 && Wo > 0) max_Wp = std::max(max_Wp, mp.Wp);
+                    map_Hp = std::max(map_Hp, mp.Hp);
+                    map_Wp = std::max(map_Wp, mp.Wp);
                     c->map_parts.push_back(mp);
                 }
-                if (Ho > 0 && Wo > 0) max_Ho = std::max(max_Ho, Ho);
+                md.r1_rows = map_Hp + 2 * PLACE_PAD;
+                md.ctab_words = place_ctab_words(map_Hp, map_Wp);
                 c->maps.push_back(md);
                 c->m_image.push_back(i);
                 c->m_level.push_back(l);
@@ -1975,16 +1962,7 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
         const int span = place_span_max(max_Wp);
         if (span > PLACE_STAGE)
             return fail(c, DPMT_E_UNSUPPORTED, "part level wider than the placement staging supports");
-        PlaceLds& pl = c->place_lds;
-        pl.acc_rows = std::max(max_Ho, 1);
-        pl.r1_rows = max_Hp + 2 * PLACE_PAD;
-        pl.stage_words = PLACE_STAGE;
-        // row table: window of at most Wp + 2 (CW - 1) + 3 (alignment) + 1 offsets,
-        // rounded up to 4; column table: at most 2 (Hp + 1) + 1 offsets plus 4
-        pl.ctab_words = (std::max(max_Wp + 2 * (PLACE_CW - 1) + 8, 2 * (max_Hp + 1) + 1 + 4) + 3) & ~3;
-        pl.max_parts = 1;
-        for (const MapDesc& m : c->maps) pl.max_parts = std::max(pl.max_parts, m.n_parts);
-        if (place_lds_bytes(pl) > PLACE_LDS_MAX)
+        if (place_bytes_of(c, c->place_blk.data(), c->place_blk.size()) > PLACE_LDS_MAX)
             return fail(c, DPMT_E_UNSUPPORTED, "score maps too tall for one placement block");
         // batched launch: blocks regrouped (stably, so largest work first
         // within a run) into runs of equal workgroups per CU, fewest first;
@@ -1997,7 +1975,7 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
             for (const int2& b : c->place_blk) {
                 auto it = wg_of.find(b.x);
                 if (it == wg_of.end())
-                    it = wg_of.emplace(b.x, place_wg_per_cu(place_lds_bytes(place_lds_of(c, &b, 1)))).first;
+                    it = wg_of.emplace(b.x, place_wg_per_cu(place_lds_bytes(place_lds_of_map(c->maps[b.x])))).first;
                 cls.push_back({it->second, b});
             }
             std::stable_sort(cls.begin(), cls.end(),
@@ -2010,13 +1988,13 @@ dpmt_status dpmt_plan(dpmt_ctx* c, int32_t n_images, const dpmt_pyramid* pyrs, c
                 else c->place_runs.back()[1] = (int)b + 1;
             }
             for (const auto& r : c->place_runs)
-                c->place_runs_lds.push_back(place_lds_of(c, c->place_blk.data() + r[0], (size_t)(r[1] - r[0])));
+                c->place_runs_lds.push_back(place_bytes_of(c, c->place_blk.data() + r[0], (size_t)(r[1] - r[0])));
             c->place_lvl_lds.clear();
             for (const auto& r : c->place_lvl)
-                c->place_lvl_lds.push_back(place_lds_of(c, c->place_blk_lvl.data() + r[2], (size_t)(r[3] - r[2])));
+                c->place_lvl_lds.push_back(place_bytes_of(c, c->place_blk_lvl.data() + r[2], (size_t)(r[3] - r[2])));
             c->place_chunk_lds.clear();
             for (const auto& r : c->place_chunk)
-                c->place_chunk_lds.push_back(place_lds_of(c, c->place_blk_chunk.data() + r[0], (size_t)(r[1] - r[0])));
+                c->place_chunk_lds.push_back(place_bytes_of(c, c->place_blk_chunk.data() + r[0], (size_t)(r[1] - r[0])));
         }
     }
 

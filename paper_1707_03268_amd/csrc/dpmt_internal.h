@@ -80,6 +80,8 @@ struct MapDesc {
     int32_t ldr;       // root plane row pitch
     int32_t n_parts;
     int32_t part_base; // first MapPart of the map
+    int32_t r1_rows;   // placement row-pass tile rows: tallest part map + 2 * PLACE_PAD
+    int32_t ctab_words;// placement floats per cost table (multiple of 4)
     int32_t pad;
 };
 
@@ -174,14 +176,27 @@ inline int xcd_grid(int n, int xcl) {
     const int g = N_XCD << xcl;
     return (n + g - 1) / g * g;
 }
+// LDS of one placement block, laid out from its own map: score accumulator,
+// row-pass tile, staging, the two cost tables, row-pass argmax, rejection
+// flags, part windows.  A launch gives every block the largest of its maps'.
 struct PlaceLds {
-    int acc_rows;      // largest map height
-    int r1_rows;       // largest part map height + 2 * PLACE_PAD
+    int acc_rows;      // map height
+    int r1_rows;       // tallest part map + 2 * PLACE_PAD
     int stage_words;   // floats of the staging buffer (PLACE_STAGE)
     int ctab_words;    // floats per cost table (multiple of 4)
-    int max_parts;     // most parts of one map
+    int max_parts;     // parts of the map
 };
 size_t place_lds_bytes(const PlaceLds& l);
+// Cost table floats for part maps of at most Hp x Wp: the row window spans
+// at most Wp + 2 (CW - 1) + 3 (alignment) + 1 offsets, rounded up to 4; the
+// column window at most 2 (Hp + 1) + 1 offsets, plus 4.
+inline int place_ctab_words(int Hp, int Wp) {
+    const int row = Wp + 2 * (PLACE_CW - 1) + 8, col = 2 * (Hp + 1) + 1 + 4;
+    return ((row > col ? row : col) + 3) & ~3;
+}
+inline PlaceLds place_lds_of_map(const MapDesc& m) {
+    return PlaceLds{m.Ho, m.r1_rows, PLACE_STAGE, m.ctab_words, m.n_parts};
+}
 // Dynamic LDS a placement block may use: 160 KB per CU, less 1 KB kept for
 // the kernel's own static LDS (checked at launch).
 constexpr size_t PLACE_LDS_MAX = 159 * 1024;
@@ -233,7 +248,7 @@ hipError_t launch_range_init(int* rkeys, int64_t n_slots, hipStream_t st);
 // positions get score -inf and offsets 0.
 hipError_t launch_place(const MapDesc* maps, const MapPart* parts, const int2* blkmap,
                         int n_blocks, const float* resp, const int* rkeys, int64_t n_slots,
-                        float* scores, int16_t* offs, const PlaceLds& lds, const uint8_t* flags,
+                        float* scores, int16_t* offs, size_t lds_bytes, const uint8_t* flags,
                         hipStream_t st);
 hipError_t launch_planes_to_maps(const float* planes, int ng, int Ho, int Wo, int ld,
                                  const int64_t* dst_off, float* out, hipStream_t st);

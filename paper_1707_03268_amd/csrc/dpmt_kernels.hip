@@ -1502,25 +1502,26 @@ __global__ __launch_bounds__(NT) void place_kernel(const MapDesc* __restrict__ m
                                                     const int* __restrict__ rmax,
                                                     const int* __restrict__ rmin,
                                                     float* __restrict__ scores,
-                                                    int16_t* __restrict__ offs, PlaceLds L,
-                                                    int n_blocks, const uint8_t* __restrict__ flags) {
+                                                    int16_t* __restrict__ offs, int n_blocks,
+                                                    const uint8_t* __restrict__ flags) {
     constexpr int CW = PLACE_CW, PAD = PLACE_PAD, RPW = PLACE_RPW;
     constexpr int ROWS = NT / CW;                          // row slots of the workgroup
     constexpr int LD = place_loads<NT>();
     extern __shared__ __align__(16) float psm[];
-    float* acc = psm;                                      // [acc_rows][CW]
-    float* r1v = acc + L.acc_rows * CW;                    // [r1_rows][CW], row y' at y' + PAD
-    float* stage = r1v + L.r1_rows * CW;                   // [stage_words]
-    float* crow = stage + L.stage_words;                   // row-pass cost table
-    float* ccol = crow + L.ctab_words;                     // column-pass cost table
-    int16_t* r1a = reinterpret_cast<int16_t*>(ccol + L.ctab_words);   // [r1_rows][CW]
-    uint8_t* rej = reinterpret_cast<uint8_t*>(r1a + L.r1_rows * CW); // [acc_rows][CW] rejected
-    int4* win = reinterpret_cast<int4*>(rej + L.acc_rows * CW);       // [max_parts] part_windows
 
     const int item = xcd_item<PLACE_XCL>(blockIdx.x);
     if (item >= n_blocks) return;
     const int2 bm = blkmap[item];                          // (map, strip)
     const MapDesc M = maps[bm.x];
+    // LDS laid out for this map (every offset a multiple of 16 bytes, CW = 16)
+    float* acc = psm;                                      // [Ho][CW]
+    float* r1v = acc + M.Ho * CW;                          // [r1_rows][CW], row y' at y' + PAD
+    float* stage = r1v + M.r1_rows * CW;                   // [PLACE_STAGE]
+    float* crow = stage + PLACE_STAGE;                     // row-pass cost table
+    float* ccol = crow + M.ctab_words;                     // column-pass cost table
+    int16_t* r1a = reinterpret_cast<int16_t*>(ccol + M.ctab_words);   // [r1_rows][CW]
+    uint8_t* rej = reinterpret_cast<uint8_t*>(r1a + M.r1_rows * CW); // [Ho][CW] rejected
+    int4* win = reinterpret_cast<int4*>(rej + M.Ho * CW);             // [n_parts] part_windows
     const int xs = bm.y * CW;
     const int ncol = min(CW, M.Wo - xs);
     const int tid = threadIdx.x;
@@ -1563,7 +1564,7 @@ __global__ __launch_bounds__(NT) void place_kernel(const MapDesc* __restrict__ m
     __syncthreads();
 
     float4 pf[LD];
-    PlaceGeo G = place_geo<NT>(parts[M.part_base], M, xs, win[0], L.stage_words);
+    PlaceGeo G = place_geo<NT>(parts[M.part_base], M, xs, win[0], PLACE_STAGE);
     if (G.rounds > 0) place_load(G, resp, 0, pf);
 
     int pad_hp = -1;                                       // part height the -inf pad rows are at
@@ -1584,7 +1585,7 @@ __global__ __launch_bounds__(NT) void place_kernel(const MapDesc* __restrict__ m
         __syncthreads();                                   // tables, pads, round 0 staged
         const bool has_next = s + 1 < M.n_parts;
         PlaceGeo Gn = G;
-        if (has_next) Gn = place_geo<NT>(parts[M.part_base + s + 1], M, xs, win[s + 1], L.stage_words);
+        if (has_next) Gn = place_geo<NT>(parts[M.part_base + s + 1], M, xs, win[s + 1], PLACE_STAGE);
         if (G.live) {
             // row pass
             for (int r = 0; r < G.rounds; ++r) {
@@ -1713,13 +1714,10 @@ hipError_t launch_range_init(int* rkeys, int64_t n_slots, hipStream_t st) {
 
 hipError_t launch_place(const MapDesc* maps, const MapPart* parts, const int2* blkmap,
                         int n_blocks, const float* resp, const int* rkeys, int64_t n_slots,
-                        float* scores, int16_t* offs, const PlaceLds& lds, const uint8_t* flags,
+                        float* scores, int16_t* offs, size_t bytes, const uint8_t* flags,
                         hipStream_t st) {
     if (n_blocks <= 0) return hipSuccess;
-    if (lds.stage_words != PLACE_STAGE || lds.ctab_words % 4)
-        return hipErrorInvalidValue;
-    const size_t bytes = place_lds_bytes(lds);
-    if (bytes > PLACE_LDS_MAX) return hipErrorInvalidValue;
+    if (bytes == 0 || bytes > PLACE_LDS_MAX) return hipErrorInvalidValue;
     // A block's LDS does not grow with its threads: where LDS caps a CU below
     // the register limit, blocks of 512 threads give it more wavefronts.
     const bool wide = 8 * place_blocks_per_cu(bytes, 512) > 4 * place_blocks_per_cu(bytes, 256);
@@ -1740,10 +1738,10 @@ hipError_t launch_place(const MapDesc* maps, const MapPart* parts, const int2* b
     const dim3 grid(xcd_grid(n_blocks, PLACE_XCL));
     if (wide)
         hipLaunchKernelGGL(place_kernel<512>, grid, dim3(512), bytes, st, maps, parts, blkmap, resp, rkeys,
-                           rkeys + n_slots, scores, offs, lds, n_blocks, flags);
+                           rkeys + n_slots, scores, offs, n_blocks, flags);
     else
         hipLaunchKernelGGL(place_kernel<256>, grid, dim3(256), bytes, st, maps, parts, blkmap, resp, rkeys,
-                           rkeys + n_slots, scores, offs, lds, n_blocks, flags);
+                           rkeys + n_slots, scores, offs, n_blocks, flags);
     return hipGetLastError();
 }
 
