@@ -169,9 +169,11 @@ constexpr int PLACE_WG_PER_CU = 6;
 // response rows, so it remaps the launch index: clusters of 2^xcl consecutive
 // strips run on one XCD, while the clusters still interleave over the XCDs in
 // work order; the grid is padded to a multiple of 8 * 2^xcl and the padding
-// exits.  (Clusters of 4 halve the kernel's HBM fetch.)
+// exits.  Clusters of 16 strips span a 1080p root map's width: the fetch is
+// then 1.13x the responses the kernel reads (1.25x with clusters of 8, 1.47x
+// with clusters of 4).
 constexpr int N_XCD = 8;
-constexpr int PLACE_XCL = 2;
+constexpr int PLACE_XCL = 4;
 inline int xcd_grid(int n, int xcl) {
     const int g = N_XCD << xcl;
     return (n + g - 1) / g * g;
